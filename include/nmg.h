@@ -1,0 +1,246 @@
+/*
+ * nmg.h - C ABI of the MI355X (gfx950) neural multigrid library.
+ *
+ * The library solves the regularised convolution system
+ *     (K^T K + alpha I) u = b
+ * arising from a convolution-type integral equation with a truncated
+ * Gaussian kernel (paper Sec. 2.1; 2D Kronecker form K2 = K (x) K of Sec. 4.2)
+ * by V-cycles whose smoothers are learned per-level CNNs (Algorithms 2-4),
+ * with full-weighting restriction, linear interpolation, Galerkin coarse
+ * operators (Algorithm 1) and a Cholesky solve on the coarsest grid.
+ *
+ * Conventions shared by every entry point
+ *  - Grids have n = 2^k - 1 interior points per axis, mesh h = 1/(n+1),
+ *    zero boundary values.  Level l+1 has (n_l - 1)/2 points per axis.
+ *  - Batched device arrays are contiguous [B][n] (dim 1) or [B][n][n]
+ *    (dim 2, row-major [row][col]); per right-hand-side scalars are [B].
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library
+ *    owns everything it allocates inside a handle and frees it in
+ *    nmg_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Work is enqueued asynchronously unless an entry point says it
+ *    synchronises.
+ *  - Errors: every call returns an nmg_status; negative values are errors
+ *    and leave outputs unspecified, NMG_NOT_CONVERGED is a warning with the
+ *    last iterate written.  All argument and shape checks happen on the host
+ *    before any launch.  nmg_last_error() gives a thread-local message.
+ *  - A handle is not thread-safe; use one handle per host thread/stream.
+ */
+#ifndef NMG_H
+#define NMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmg_ctx* nmg_handle;
+
+typedef enum {
+    NMG_OK = 0,
+    NMG_NOT_CONVERGED = 1,
+    NMG_ERR_ARG = -1,        /* bad argument value or NULL pointer        */
+    NMG_ERR_SHAPE = -2,      /* n, levels, batch or layer shapes invalid  */
+    NMG_ERR_OOM = -3,        /* device allocation failed                  */
+    NMG_ERR_NOT_SPD = -4,    /* coarse Cholesky met a non-positive pivot  */
+    NMG_ERR_NONFINITE = -5,  /* NaN/Inf in an input or a residual         */
+    NMG_ERR_HIP = -6,        /* HIP runtime error                         */
+    NMG_ERR_BUDGET = -7,     /* request exceeds the handle's HBM budget   */
+    NMG_ERR_STATE = -8       /* call out of order (e.g. no weights yet)   */
+} nmg_status;
+
+/* Arithmetic of a cycle.
+ *  NMG_FP64  : everything in FP64 (parity path).
+ *  NMG_FP32  : plain FP32 cycle and FP32 smoother; FP64 coarse solve.
+ *  NMG_MIXED : BF16 smoother on MFMA with FP32 accumulation, FP32 residuals
+ *              and transfers, FP64 coarse solve; nmg_solve wraps it in FP64
+ *              iterative refinement. */
+typedef enum { NMG_FP64 = 0, NMG_FP32 = 1, NMG_MIXED = 2 } nmg_precision;
+
+typedef enum { NMG_MASK_BAND = 0, NMG_MASK_RAMP = 1 } nmg_mask_kind;
+
+#define NMG_MAX_LAYERS 7
+
+/* Problem and smoother architecture fixed for the lifetime of a handle. */
+typedef struct {
+    int dim;                         /* 1 or 2                                   */
+    int n;                           /* interior points per axis, 2^k - 1        */
+    double s;                        /* Gaussian width, unit-interval units      */
+    double trunc;                    /* truncation radius in units of s (e.g. 4) */
+    int levels;                      /* L >= 1; n_L >= 1                         */
+    int max_batch;                   /* right-hand sides per call                */
+    int n_layers;                    /* smoother conv layers, 1..NMG_MAX_LAYERS  */
+    int channels[NMG_MAX_LAYERS + 1];/* channels[0] = channels[n_layers] = 1     */
+    int ksize;                       /* odd convolution kernel size              */
+    int n_weight_sets;               /* independent smoother sets per level      */
+} nmg_problem;
+
+/* Options of one V(nu1, nu2) cycle (Algorithm 1 with the neural smoothing
+ * step of Algorithms 2-4; use_fprime enables the filter F'_l of Algorithms 3
+ * and 4 on every smoother output). */
+typedef struct {
+    int nu1;
+    int nu2;
+    int use_fprime;
+    nmg_precision precision;
+} nmg_cycle_opts;
+
+/* ---- setup ------------------------------------------------------------- */
+
+/* Builds the grid hierarchy (Sec. 2.3 / Algorithm 1): Gaussian taps, the
+ * banded factor G_1 = K^T K, the Galerkin factors M_l, G_l of
+ * A_l = alpha M_l (x) M_l + G_l (x) G_l, device copies and workspaces for
+ * max_batch right-hand sides.  Synchronises.  *out receives the handle.
+ * Errors: NMG_ERR_SHAPE (n not 2^k-1, too many levels, bad channels),
+ * NMG_ERR_ARG, NMG_ERR_OOM, NMG_ERR_HIP. */
+nmg_status nmg_setup_hierarchy(const nmg_problem* problem, nmg_handle* out);
+
+/* Frees every device and host resource of the handle (NULL is ignored). */
+void nmg_destroy(nmg_handle h);
+
+/* Thread-local description of the last error returned on this thread. */
+const char* nmg_last_error(void);
+
+/* Copies the CNN weights of smoother N_theta_l (level 0-based, l < L-1) of
+ * weight set `weight_set` from host memory.  Layout: all layers
+ * concatenated, layer i as [C_{i+1}][C_i][k] (dim 1) or [C_{i+1}][C_i][k][k]
+ * (dim 2), cross-correlation, no bias (Algorithm 2's smoother, Appendix A's
+ * convolution operator W).  `count` must equal the total weight count.
+ * Selects the neural smoother for that level.  Synchronises. */
+nmg_status nmg_load_smoother_weights(nmg_handle h, int level, int weight_set,
+                                     const float* weights_host, size_t count);
+
+/* Copies the current FP32 weights of (level, weight_set) back to the host. */
+nmg_status nmg_get_smoother_weights(nmg_handle h, int level, int weight_set,
+                                    float* weights_host, size_t count);
+
+/* Selects the weighted Jacobi smoother h = omega D_l^{-1} b of Sec. 2.2 on
+ * level `level` (omega > 0), in place of the neural smoother. */
+nmg_status nmg_set_jacobi_smoother(nmg_handle h, int level, double omega);
+
+/* Per right-hand-side coarse factorisation: for every slot b < batch forms
+ * A_L = alpha[b] M_L (x) M_L + G_L (x) G_L and its FP64 Cholesky factor
+ * (Algorithm 1, exact coarsest solve).  alpha: device double[batch].
+ * Must precede nmg_vcycle for those alphas (nmg_solve calls it itself).
+ * Synchronises to report NMG_ERR_NOT_SPD. */
+nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha_dev, void* stream);
+
+/* ---- operators ---------------------------------------------------------- */
+
+/* y = A_l x on level `level` for every right-hand side (alpha device
+ * double[batch]).  x, y: device [B][n_l]([n_l]) of type double (NMG_FP64)
+ * or float (otherwise).  Used to form b = A u* and training pairs. */
+nmg_status nmg_apply_operator(nmg_handle h, int level, int batch, const double* alpha_dev,
+                              const void* x, void* y, nmg_precision precision, void* stream);
+
+/* h = ||b||_2 N_theta_l(b / ||b||_2) per right-hand side: the neural
+ * smoothing step of Algorithm 2 / Algorithm 4 on level `level` (l < L-1),
+ * or omega D_l^{-1} b if that level uses weighted Jacobi (Sec. 2.2).  b, h:
+ * device [B][n_l]([n_l]); double for NMG_FP64, float otherwise (NMG_MIXED
+ * runs the BF16 MFMA network).  alpha_dev is only read by Jacobi.  A zero b
+ * gives h = 0. */
+nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* alpha_dev,
+                              const int* weight_set_dev, const void* b, void* h_out,
+                              nmg_precision precision, void* stream);
+
+/* ---- the cycle ---------------------------------------------------------- */
+
+/* x <- MG(x, y): one V(nu1, nu2) cycle on the finest level with initial
+ * guess x (Algorithm 1 skeleton with the neural smoothing step
+ * b = y - A x, h = ||b|| N(b/||b||), x += F'(h) of Algorithms 2-4, Galerkin
+ * coarse levels, Cholesky coarsest solve).  x, y: device, double for
+ * NMG_FP64, float otherwise.  weight_set_dev: device int[batch] choosing the
+ * smoother set per right-hand side, or NULL for set 0.  Requires
+ * nmg_prepare for the same alphas. */
+nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
+                      const void* y, void* x, const nmg_cycle_opts* opts, void* stream);
+
+/* Outer iteration x^{t+1} = MG(x^t, b) from x^0 = 0 until
+ * ||b - A x||_2 / ||b||_2 <= rtol per right-hand side or max_cycles
+ * (Sec. 2.3; stopping rule of Sec. 4).  b, x: device double[B][n]([n]).
+ * NMG_FP64 / NMG_MIXED iterate in FP64 with d = MG(0, r/||r||) computed in
+ * the cycle precision (residual-driven form of the same iteration);
+ * NMG_FP32 iterates in plain FP32 and converts at the end.  Converged
+ * right-hand sides are frozen.  cycles_host (int[batch], may be NULL)
+ * receives cycles used; history_host (double[batch][max_cycles+1], may be
+ * NULL) receives the relative residual before each cycle (unused entries
+ * set to -1).  Synchronises.  Returns NMG_NOT_CONVERGED if any
+ * right-hand side missed rtol, NMG_ERR_NONFINITE on NaN/Inf residuals. */
+nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
+                     const double* b_dev, double* x_dev, double rtol, int max_cycles,
+                     const nmg_cycle_opts* opts, int* cycles_host, double* history_host,
+                     void* stream);
+
+/* ---- training (Sec. 3.2 eq. loss_2_modified / Sec. 3.3 eq. loss_3,
+ *      Algorithm 5) ----------------------------------------------------- */
+
+/* Level-wise losses and their gradients for one batch of true solutions
+ * e (device, [B][n]([n]), double for NMG_FP64 else float):
+ * y = A e, one pre-smoothing-only cycle from zero recording b_l, then
+ * L_l = (1/B) sum_i || mask_l (.) DCT2(e - sum_{k<l} I_k^1 F'_k(h_k) - I_l^1 h_l) ||^2
+ * and dL_l/dtheta_l (earlier levels held fixed).  alpha_dev: double[batch].
+ * losses_host: double[L-1] (may be NULL).  The gradients are accumulated
+ * into the handle's gradient buffers of `weight_set` (zeroed first when
+ * zero_grad != 0).  Precision NMG_FP64 computes everything in FP64;
+ * otherwise FP32 arithmetic with BF16 MFMA smoother forward.  Synchronises. */
+nmg_status nmg_loss_grad(nmg_handle h, int weight_set, int batch, const double* alpha_dev,
+                         const void* e_dev, nmg_mask_kind mask, int use_fprime,
+                         nmg_precision precision, int zero_grad, double* losses_host, void* stream);
+
+/* Copies the gradient of (level, weight_set) filled by the last
+ * nmg_loss_grad to the host as doubles (layout as nmg_load_smoother_weights). */
+nmg_status nmg_get_gradient(nmg_handle h, int level, int weight_set, double* grad_host, size_t count);
+
+/* One bias-corrected Adam step (beta1, beta2, eps as given; no weight decay)
+ * on every level of `weight_set` from the accumulated gradients; updates the
+ * FP32 master weights and the FP64 / BF16 copies. */
+nmg_status nmg_adam_step(nmg_handle h, int weight_set, double lr, double beta1, double beta2,
+                         double eps, void* stream);
+
+/* nmg_loss_grad followed by nmg_adam_step (Algorithm 5, one training step). */
+nmg_status nmg_train_step(nmg_handle h, int weight_set, int batch, const double* alpha_dev,
+                          const void* e_dev, nmg_mask_kind mask, int use_fprime,
+                          nmg_precision precision, double lr, double* losses_host, void* stream);
+
+/* ---- profiling ------------------------------------------------------------ */
+
+/* Kernel families timed by the built-in profiler. */
+typedef enum {
+    NMG_K_SMOOTHER = 0, NMG_K_OPERATOR = 1, NMG_K_RESTRICT = 2, NMG_K_PROLONG = 3,
+    NMG_K_COARSE = 4, NMG_K_FPRIME = 5, NMG_K_REFINE = 6, NMG_K_NORM = 7
+} nmg_kernel_kind;
+
+/* Turns HIP-event timing of every cycle/solve launch on (1) or off (0) and
+ * clears the accumulated times.  Events are recorded on the caller's stream
+ * around each launch. */
+nmg_status nmg_profile_enable(nmg_handle h, int on);
+
+/* Accumulated device time (ms) and launch count of one kernel family on one
+ * level (level -1 sums all levels).  Synchronises the recorded events. */
+nmg_status nmg_profile_query(nmg_handle h, int kind, int level, double* total_ms, int* launches);
+
+/* ---- introspection ------------------------------------------------------ */
+
+/* Grid size of level `level` (0-based). */
+int nmg_level_size(nmg_handle h, int level);
+
+/* Integer index maps of the 1D transfers between level and level+1 as the
+ * kernels use them.  kind 0 = restriction: idx int32[n_{l+1}][3], w float
+ * same shape (fine indices read by each coarse node).  kind 1 =
+ * interpolation: idx int32[n_l][2], w float[n_l][2] (coarse indices read by
+ * each fine node, -1 where absent). */
+nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* idx, float* w);
+
+/* Copies the banded Galerkin factor rows of level `level` to the host:
+ * which 0 = M_l, 1 = G_l; out double[n_l][2 r + 1], *radius receives r
+ * (call with out == NULL to query the radius). */
+nmg_status nmg_debug_factor(nmg_handle h, int level, int which, double* out, int* radius);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMG_H */

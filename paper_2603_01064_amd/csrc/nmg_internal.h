@@ -1,0 +1,207 @@
+// Internal declarations of the neural multigrid library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nmg.h"
+
+namespace nmg {
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every internal call returns nmg_status; messages go to a
+// thread-local string read by nmg_last_error().
+// ---------------------------------------------------------------------------
+nmg_status fail(nmg_status code, const std::string& msg);
+nmg_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define NMG_HIP(...)                                                         \
+    do {                                                                     \
+        hipError_t _e = (__VA_ARGS__);                                       \
+        if (_e != hipSuccess) return ::nmg::hip_fail(_e, #__VA_ARGS__, __FILE__, __LINE__); \
+    } while (0)
+
+#define NMG_TRY(...)                                                         \
+    do {                                                                     \
+        nmg_status _s = (__VA_ARGS__);                                       \
+        if (_s < 0) return _s;                                               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Host-side hierarchy (FP64): banded Galerkin factors of
+// A_l = alpha M_l (x) M_l + G_l (x) G_l  (1D: alpha M_l + G_l).
+// ---------------------------------------------------------------------------
+struct Band {
+    int n = 0;   // rows
+    int r = 0;   // radius
+    std::vector<double> a;  // a[i*(2r+1) + (j - i + r)]
+    double get(int i, int j) const {
+        int d = j - i;
+        if (i < 0 || j < 0 || i >= n || j >= n || d < -r || d > r) return 0.0;
+        return a[(size_t)i * (2 * r + 1) + (d + r)];
+    }
+};
+
+struct HostLevel {
+    int n = 0;
+    Band M, G;
+};
+
+// Builds taps, G_1 = K K, M_1 = I and the Galerkin chain; returns false with
+// a message on invalid input.
+bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector<HostLevel>& out,
+                          int* taps_radius, std::string& err);
+
+// ---------------------------------------------------------------------------
+// Device-side state
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LevelBuffers {
+    T* x = nullptr;   // iterate / correction on this level
+    T* y = nullptr;   // right-hand side on this level
+    T* b = nullptr;   // residual work
+    T* h = nullptr;   // smoother output (for F')
+    T* t1 = nullptr;  // axis-pass temporary
+    T* t2 = nullptr;  // axis-pass temporary
+};
+
+template <typename T>
+struct Work {
+    bool ready = false;
+    std::vector<LevelBuffers<T>> lv;
+    T* act0 = nullptr;   // conv activations ping
+    T* act1 = nullptr;   // conv activations pong
+    T* Gd = nullptr;     // per level band tables, concatenated
+    T* Md = nullptr;
+    std::vector<size_t> g_off, m_off;
+    T* dct = nullptr;    // per level DCT-II matrices [n][n], concatenated
+    std::vector<size_t> dct_off;
+    T* wts = nullptr;    // smoother weights in this precision [L-1][sets][count]
+};
+
+struct Ctx {
+    nmg_problem p{};
+    int L = 0;
+    int ny0 = 0;                       // rows of the finest grid (n or 1)
+    std::vector<int> n;                // points per axis per level
+    std::vector<HostLevel> host;
+    int taps_radius = 0;
+    // smoother description
+    int wcount = 0;                    // weights per (level, set)
+    std::vector<int> layer_off;        // offset of each layer in a weight block
+    int cmax = 1;                      // widest layer
+    std::vector<int> kind;             // per level: 0 neural, 1 jacobi, -1 unset
+    std::vector<double> omega;
+    std::vector<std::vector<char>> loaded;  // [level][set]
+    // FP32 master weights, gradients and Adam moments [L-1][sets][wcount]
+    float* w32 = nullptr;
+    float* g32 = nullptr;
+    double* g64 = nullptr;
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    std::vector<int> adam_step;        // per set
+    uint16_t* wbf = nullptr;           // BF16 MFMA-packed weights
+    size_t wbf_stride = 0;             // per (level, set)
+    // coarse solve
+    int nc = 0;                        // coarse unknowns n_L^dim
+    double* Mc = nullptr;              // dense n_L x n_L
+    double* Gc = nullptr;
+    double* chol = nullptr;            // [max_batch][nc][nc] lower factor, row-major
+    double* cholT = nullptr;           // [max_batch][nc][nc] its transpose
+    int* flags = nullptr;              // [max_batch] non-SPD / non-finite flags
+    double* alpha_prepared = nullptr;  // [max_batch] device copy of factored alphas
+    // norms and scratch
+    double* nrm = nullptr;             // [max_batch] per right-hand-side norms
+    double* nrm2 = nullptr;            // [max_batch] second norm slot
+    double* x64 = nullptr;             // [max_batch][ny][n] refinement scratch
+    double* r64 = nullptr;
+    double* hist_dev = nullptr;        // [max_batch] residual snapshot
+    int* active = nullptr;             // [max_batch]
+    // training scratch
+    double* loss_dev = nullptr;        // [L-1]
+    Work<double> w64;
+    Work<float> w32b;
+    bool grad_is_fp64 = false;         // which gradient buffer the last loss_grad filled
+    // profiler
+    bool prof_on = false;
+    struct ProfEv { hipEvent_t a, b; int kind, level; };
+    std::vector<ProfEv> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[8][16] = {};
+    int prof_cnt[8][16] = {};
+};
+
+// Records a start event on construction and a stop event on destruction
+// when profiling is on.
+struct ProfScope {
+    Ctx* c;
+    hipStream_t s;
+    int kind, level;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const Ctx* cc, hipStream_t ss, int k, int l);
+    ~ProfScope();
+};
+nmg_status prof_resolve(Ctx* c);
+
+template <typename T>
+Work<T>& work_of(Ctx* c);
+template <typename T>
+nmg_status ensure_work(Ctx* c);
+void release_training(const Ctx* c);
+
+size_t level_elems(const Ctx* c, int l);  // ny_l * n_l
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+// mode 0: out = y - A x ; mode 1: out = A x
+template <typename T>
+nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y,
+                           T* out, int mode, Work<T>& w, hipStream_t s);
+template <typename T>
+nmg_status launch_sumsq(int batch, size_t elems, const T* v, double* out, hipStream_t s);
+template <typename T>
+nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s);
+template <typename T>
+nmg_status launch_prolong_transpose(const Ctx* c, int l, int batch, const T* g, T* out, hipStream_t s);
+template <typename T>
+nmg_status launch_dense_axis(const T* in, T* out, const T* C, int n, int ny, int batch, int col_axis, int inverse,
+                             hipStream_t s);
+template <typename T>
+nmg_status launch_prolong_add(const Ctx* c, int l, int batch, const T* e, T* x, hipStream_t s);
+template <typename T>
+nmg_status launch_axpy(int batch, size_t elems, const T* src, T* dst, int accumulate, hipStream_t s);
+template <typename T>
+nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, const T* b, const double* nrm2,
+                                T* dst, int accumulate, Work<T>& w, hipStream_t s);
+nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b,
+                                const double* nrm2, float* dst, int accumulate, Work<float>& w, hipStream_t s);
+template <typename T>
+nmg_status launch_jacobi(const Ctx* c, int l, int batch, const double* alpha, double omega, const T* b, T* dst,
+                         int accumulate, Work<T>& w, hipStream_t s);
+template <typename T>
+nmg_status launch_fprime(const Ctx* c, int l, int batch, const T* h, T* dst, int accumulate, Work<T>& w,
+                         hipStream_t s);
+nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
+nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStream_t s);
+template <typename T>
+nmg_status launch_coarse_solve(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);
+template <typename T>
+nmg_status launch_zero(T* p, size_t count, hipStream_t s);
+template <typename A, typename B>
+nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s);
+template <typename R, typename T>
+nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
+                               double rtol, int* active, hipStream_t s);
+template <typename X, typename T>
+nmg_status launch_refine_update(int batch, size_t per, X* x, const T* d, const double* rn2, const int* active,
+                                hipStream_t s);
+nmg_status repack_bf16(Ctx* c, int level, int weight_set);
+
+}  // namespace nmg
+
+struct nmg_ctx : public nmg::Ctx {};

@@ -1,0 +1,735 @@
+// C ABI entry points: hierarchy setup, weights, the V-cycle and the solve.
+//
+// The cycle follows Algorithm 1 with the neural smoothing step of
+// Algorithms 2-4: on each level above the coarsest, nu1 times
+//   b = y - A x ;  h = ||b|| N(b/||b||) ;  x += F'(h)  (F' optional)
+// then restriction of y - A x, a recursive cycle from zero on the next
+// level, interpolation and correction, and nu2 post-smoothing steps with
+// the same smoother; the coarsest level is solved exactly by Cholesky.
+// The recursion is unrolled on the host into a fixed launch sequence.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "nmg_internal.h"
+
+namespace nmg {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+nmg_status dev_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return NMG_OK;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(NMG_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return NMG_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+nmg_status fail(nmg_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+nmg_status hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "HIP error %s (%d) in %s at %s:%d", hipGetErrorString(e), (int)e, what, file,
+                  line);
+    g_last_error = buf;
+    return NMG_ERR_HIP;
+}
+
+static hipEvent_t prof_event(Ctx* c) {
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+ProfScope::ProfScope(const Ctx* cc, hipStream_t ss, int k, int l) : c(const_cast<Ctx*>(cc)), s(ss), kind(k), level(l) {
+    if (!c->prof_on) return;
+    a = prof_event(c);
+    b = prof_event(c);
+    if (a && b) (void)hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_pending.push_back({a, b, kind, level});
+}
+
+nmg_status prof_resolve(Ctx* c) {
+    for (auto& ev : c->prof_pending) {
+        NMG_HIP(hipEventSynchronize(ev.b));
+        float ms = 0.f;
+        NMG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        const int k = ev.kind & 7, l = ev.level < 0 ? 0 : (ev.level > 15 ? 15 : ev.level);
+        c->prof_ms[k][l] += ms;
+        c->prof_cnt[k][l] += 1;
+        c->prof_pool.push_back(ev.a);
+        c->prof_pool.push_back(ev.b);
+    }
+    c->prof_pending.clear();
+    return NMG_OK;
+}
+
+namespace {
+
+// Orthonormal DCT-II of size n: C[k][i] = c_k cos(pi k (2 i + 1) / (2 n)).
+std::vector<double> dct2(int n) {
+    std::vector<double> C((size_t)n * n);
+    for (int k = 0; k < n; ++k) {
+        const double ck = k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+        for (int i = 0; i < n; ++i) C[(size_t)k * n + i] = ck * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n));
+    }
+    return C;
+}
+
+template <typename T>
+nmg_status upload(T* dst, const std::vector<double>& src) {
+    std::vector<T> tmp(src.begin(), src.end());
+    NMG_HIP(hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+    return NMG_OK;
+}
+
+}  // namespace
+
+template <>
+Work<double>& work_of<double>(Ctx* c) {
+    return c->w64;
+}
+template <>
+Work<float>& work_of<float>(Ctx* c) {
+    return c->w32b;
+}
+
+template <typename T>
+nmg_status ensure_work(Ctx* c) {
+    Work<T>& w = work_of<T>(c);
+    if (w.ready) return NMG_OK;
+    const int B = c->p.max_batch;
+    w.lv.assign((size_t)c->L, LevelBuffers<T>{});
+    for (int l = 0; l < c->L; ++l) {
+        const size_t cnt = (size_t)B * level_elems(c, l);
+        LevelBuffers<T>& lb = w.lv[(size_t)l];
+        NMG_TRY(dev_alloc(&lb.x, cnt));
+        NMG_TRY(dev_alloc(&lb.y, cnt));
+        NMG_TRY(dev_alloc(&lb.b, cnt));
+        NMG_TRY(dev_alloc(&lb.h, cnt));
+        NMG_TRY(dev_alloc(&lb.t1, cnt));
+        NMG_TRY(dev_alloc(&lb.t2, cnt));
+    }
+    const size_t act = (size_t)B * c->cmax * level_elems(c, 0);
+    NMG_TRY(dev_alloc(&w.act0, act));
+    NMG_TRY(dev_alloc(&w.act1, act));
+    // band tables and DCT matrices
+    std::vector<double> G, M, D;
+    w.g_off.clear();
+    w.m_off.clear();
+    w.dct_off.clear();
+    for (int l = 0; l < c->L; ++l) {
+        w.g_off.push_back(G.size());
+        G.insert(G.end(), c->host[(size_t)l].G.a.begin(), c->host[(size_t)l].G.a.end());
+        w.m_off.push_back(M.size());
+        M.insert(M.end(), c->host[(size_t)l].M.a.begin(), c->host[(size_t)l].M.a.end());
+        w.dct_off.push_back(D.size());
+        std::vector<double> C = dct2(c->n[(size_t)l]);
+        D.insert(D.end(), C.begin(), C.end());
+    }
+    NMG_TRY(dev_alloc(&w.Gd, G.size()));
+    NMG_TRY(dev_alloc(&w.Md, M.size()));
+    NMG_TRY(dev_alloc(&w.dct, D.size()));
+    NMG_TRY(upload(w.Gd, G));
+    NMG_TRY(upload(w.Md, M));
+    NMG_TRY(upload(w.dct, D));
+    if (std::is_same<T, double>::value) {
+        const size_t wn = (size_t)std::max(1, c->L - 1) * c->p.n_weight_sets * c->wcount;
+        NMG_TRY(dev_alloc(&w.wts, wn));
+        NMG_TRY(launch_convert<float, T>(c->w32, w.wts, wn, nullptr));
+    } else {
+        w.wts = reinterpret_cast<T*>(c->w32);
+    }
+    NMG_HIP(hipDeviceSynchronize());
+    w.ready = true;
+    return NMG_OK;
+}
+
+template nmg_status ensure_work<float>(Ctx*);
+template nmg_status ensure_work<double>(Ctx*);
+
+namespace {
+
+template <typename T>
+void free_work(Ctx* c, Work<T>& w) {
+    for (auto& lb : w.lv) {
+        dev_free(lb.x);
+        dev_free(lb.y);
+        dev_free(lb.b);
+        dev_free(lb.h);
+        dev_free(lb.t1);
+        dev_free(lb.t2);
+    }
+    dev_free(w.act0);
+    dev_free(w.act1);
+    dev_free(w.Gd);
+    dev_free(w.Md);
+    dev_free(w.dct);
+    if (std::is_same<T, double>::value) dev_free(w.wts);
+    w.wts = nullptr;
+    w.ready = false;
+    (void)c;
+}
+
+nmg_status check_handle(nmg_handle h) {
+    if (!h) return fail(NMG_ERR_ARG, "null handle");
+    return NMG_OK;
+}
+
+nmg_status check_batch(const Ctx* c, int batch) {
+    if (batch < 1 || batch > c->p.max_batch) return fail(NMG_ERR_SHAPE, "batch must be in [1, max_batch]");
+    return NMG_OK;
+}
+
+nmg_status check_opts(const Ctx* c, const nmg_cycle_opts* o) {
+    if (!o) return fail(NMG_ERR_ARG, "null cycle options");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 16) return fail(NMG_ERR_ARG, "nu1/nu2 out of range");
+    if (o->precision != NMG_FP64 && o->precision != NMG_FP32 && o->precision != NMG_MIXED)
+        return fail(NMG_ERR_ARG, "unknown precision");
+    for (int l = 0; l + 1 < c->L; ++l) {
+        if (c->kind[(size_t)l] < 0) return fail(NMG_ERR_STATE, "no smoother set for level " + std::to_string(l));
+    }
+    return NMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The cycle
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CycleArgs {
+    Ctx* c;
+    Work<T>* w;
+    int batch;
+    const double* alpha;
+    const int* ws;
+    nmg_cycle_opts o;
+    hipStream_t s;
+};
+
+template <typename T>
+nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
+    Ctx* c = a.c;
+    Work<T>& w = *a.w;
+    const size_t per = level_elems(c, l);
+    const T* bres = y;
+    if (!x_zero) {
+        ProfScope ps(c, a.s, NMG_K_OPERATOR, l);
+        NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, w.lv[(size_t)l].b, 0, w, a.s));
+        bres = w.lv[(size_t)l].b;
+    }
+    T* target = a.o.use_fprime ? w.lv[(size_t)l].h : x;
+    const int acc = a.o.use_fprime ? 0 : (x_zero ? 0 : 1);
+    if (c->kind[(size_t)l] == 1) {
+        ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
+        NMG_TRY(launch_jacobi<T>(c, l, a.batch, a.alpha, c->omega[(size_t)l], bres, target, acc, w, a.s));
+    } else {
+        {
+            ProfScope ps(c, a.s, NMG_K_NORM, l);
+            NMG_TRY(launch_sumsq<T>(a.batch, per, bres, c->nrm, a.s));
+        }
+        ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
+        if (a.o.precision == NMG_MIXED) {
+            NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->nrm,
+                                         reinterpret_cast<float*>(target), acc, *reinterpret_cast<Work<float>*>(&w),
+                                         a.s));
+        } else {
+            NMG_TRY(launch_conv_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
+        }
+    }
+    if (a.o.use_fprime) {
+        ProfScope ps(c, a.s, NMG_K_FPRIME, l);
+        NMG_TRY(launch_fprime<T>(c, l, a.batch, w.lv[(size_t)l].h, x, x_zero ? 0 : 1, w, a.s));
+    }
+    return NMG_OK;
+}
+
+template <typename T>
+nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
+    Ctx* c = a.c;
+    Work<T>& w = *a.w;
+    if (l == c->L - 1) {
+        ProfScope ps(c, a.s, NMG_K_COARSE, l);
+        return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
+    }
+    const size_t per = level_elems(c, l);
+    if (x_zero && a.o.nu1 == 0) {
+        NMG_TRY(launch_zero<T>(x, (size_t)a.batch * per, a.s));
+    }
+    for (int k = 0; k < a.o.nu1; ++k) {
+        NMG_TRY(smooth_step<T>(a, l, x, y, x_zero));
+        x_zero = false;
+    }
+    LevelBuffers<T>& lb = w.lv[(size_t)l];
+    {
+        ProfScope ps(c, a.s, NMG_K_OPERATOR, l);
+        NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, lb.b, 0, w, a.s));
+    }
+    {
+        ProfScope ps(c, a.s, NMG_K_RESTRICT, l);
+        NMG_TRY(launch_restrict<T>(c, l, a.batch, lb.b, w.lv[(size_t)l + 1].y, a.s));
+    }
+    NMG_TRY(cycle<T>(a, l + 1, w.lv[(size_t)l + 1].x, w.lv[(size_t)l + 1].y, true));
+    {
+        ProfScope ps(c, a.s, NMG_K_PROLONG, l);
+        NMG_TRY(launch_prolong_add<T>(c, l, a.batch, w.lv[(size_t)l + 1].x, x, a.s));
+    }
+    for (int k = 0; k < a.o.nu2; ++k) NMG_TRY(smooth_step<T>(a, l, x, y, false));
+    return NMG_OK;
+}
+
+template <typename T>
+nmg_status run_cycle(Ctx* c, int batch, const double* alpha, const int* ws, const T* y, T* x, bool x_zero,
+                     const nmg_cycle_opts& o, hipStream_t s) {
+    NMG_TRY(ensure_work<T>(c));
+    CycleArgs<T> a{c, &work_of<T>(c), batch, alpha, ws, o, s};
+    return cycle<T>(a, 0, x, y, x_zero);
+}
+
+}  // namespace
+
+}  // namespace nmg
+
+using namespace nmg;
+
+
+extern "C" {
+
+const char* nmg_last_error(void) { return nmg::g_last_error.c_str(); }
+
+nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
+    if (!p || !out) return fail(NMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (p->dim != 1 && p->dim != 2) return fail(NMG_ERR_SHAPE, "dim must be 1 or 2");
+    if (p->levels < 1 || p->levels > 16) return fail(NMG_ERR_SHAPE, "levels must be in [1, 16]");
+    if (p->max_batch < 1 || p->max_batch > 4096) return fail(NMG_ERR_SHAPE, "max_batch must be in [1, 4096]");
+    if (p->n_layers < 1 || p->n_layers > NMG_MAX_LAYERS) return fail(NMG_ERR_SHAPE, "n_layers out of range");
+    if (p->channels[0] != 1 || p->channels[p->n_layers] != 1)
+        return fail(NMG_ERR_SHAPE, "first and last channel counts must be 1");
+    for (int i = 0; i <= p->n_layers; ++i)
+        if (p->channels[i] < 1 || p->channels[i] > 256) return fail(NMG_ERR_SHAPE, "channel count out of range");
+    if (p->ksize < 1 || (p->ksize & 1) == 0 || p->ksize > 15) return fail(NMG_ERR_SHAPE, "ksize must be odd, <= 15");
+    if (p->n_weight_sets < 1 || p->n_weight_sets > 64) return fail(NMG_ERR_SHAPE, "n_weight_sets out of range");
+    std::unique_ptr<nmg_ctx> c(new nmg_ctx());
+    c->p = *p;
+    std::string err;
+    if (!build_host_hierarchy(p->n, p->s, p->trunc, p->levels, c->host, &c->taps_radius, err))
+        return fail(NMG_ERR_SHAPE, err);
+    c->L = p->levels;
+    for (auto& hl : c->host) c->n.push_back(hl.n);
+    c->ny0 = p->dim == 2 ? p->n : 1;
+    const int nl = c->n.back();
+    c->nc = p->dim == 2 ? nl * nl : nl;
+    if (c->nc > 1024) return fail(NMG_ERR_SHAPE, "coarsest grid too large for the dense Cholesky (n_L^dim > 1024)");
+    // smoother layout
+    const int kk = p->dim == 2 ? p->ksize * p->ksize : p->ksize;
+    c->wcount = 0;
+    c->cmax = 1;
+    for (int i = 0; i < p->n_layers; ++i) {
+        c->layer_off.push_back(c->wcount);
+        c->wcount += p->channels[i] * p->channels[i + 1] * kk;
+        c->cmax = std::max(c->cmax, p->channels[i + 1]);
+    }
+    const int nsm = std::max(1, c->L - 1);
+    c->kind.assign((size_t)nsm, -1);
+    c->omega.assign((size_t)nsm, 0.0);
+    c->loaded.assign((size_t)nsm, std::vector<char>((size_t)p->n_weight_sets, 0));
+    c->adam_step.assign((size_t)p->n_weight_sets, 0);
+    const size_t wn = (size_t)nsm * p->n_weight_sets * c->wcount;
+    const int B = p->max_batch;
+    NMG_TRY(dev_alloc(&c->w32, wn));
+    NMG_TRY(dev_alloc(&c->g32, wn));
+    NMG_TRY(dev_alloc(&c->g64, wn));
+    NMG_TRY(dev_alloc(&c->adam_m, wn));
+    NMG_TRY(dev_alloc(&c->adam_v, wn));
+    NMG_HIP(hipMemset(c->w32, 0, wn * sizeof(float)));
+    NMG_HIP(hipMemset(c->g32, 0, wn * sizeof(float)));
+    NMG_HIP(hipMemset(c->g64, 0, wn * sizeof(double)));
+    NMG_HIP(hipMemset(c->adam_m, 0, wn * sizeof(float)));
+    NMG_HIP(hipMemset(c->adam_v, 0, wn * sizeof(float)));
+    // coarse factors
+    std::vector<double> Mc((size_t)nl * nl), Gc((size_t)nl * nl);
+    const HostLevel& hc = c->host.back();
+    for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j) {
+            Mc[(size_t)i * nl + j] = hc.M.get(i, j);
+            Gc[(size_t)i * nl + j] = hc.G.get(i, j);
+        }
+    NMG_TRY(dev_alloc(&c->Mc, Mc.size()));
+    NMG_TRY(dev_alloc(&c->Gc, Gc.size()));
+    NMG_TRY(upload(c->Mc, Mc));
+    NMG_TRY(upload(c->Gc, Gc));
+    NMG_TRY(dev_alloc(&c->chol, (size_t)B * c->nc * c->nc));
+    NMG_TRY(dev_alloc(&c->cholT, (size_t)B * c->nc * c->nc));
+    NMG_TRY(dev_alloc(&c->flags, (size_t)B));
+    NMG_TRY(dev_alloc(&c->alpha_prepared, (size_t)B));
+    NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
+    NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
+    NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
+    NMG_TRY(dev_alloc(&c->active, (size_t)B));
+    NMG_TRY(dev_alloc(&c->x64, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->loss_dev, (size_t)nsm));
+    NMG_HIP(hipDeviceSynchronize());
+    *out = c.release();
+    return NMG_OK;
+}
+
+void nmg_destroy(nmg_handle h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    nmg::Ctx* c = h;
+    (void)prof_resolve(c);
+    for (auto e : c->prof_pool) (void)hipEventDestroy(e);
+    c->prof_pool.clear();
+    release_training(c);
+    free_work(c, c->w64);
+    free_work(c, c->w32b);
+    dev_free(c->w32);
+    dev_free(c->g32);
+    dev_free(c->g64);
+    dev_free(c->adam_m);
+    dev_free(c->adam_v);
+    dev_free(c->wbf);
+    dev_free(c->Mc);
+    dev_free(c->Gc);
+    dev_free(c->chol);
+    dev_free(c->cholT);
+    dev_free(c->flags);
+    dev_free(c->alpha_prepared);
+    dev_free(c->nrm);
+    dev_free(c->nrm2);
+    dev_free(c->hist_dev);
+    dev_free(c->active);
+    dev_free(c->x64);
+    dev_free(c->r64);
+    dev_free(c->loss_dev);
+    delete h;
+}
+
+int nmg_level_size(nmg_handle h, int level) {
+    if (!h || level < 0 || level >= h->L) return -1;
+    return h->n[(size_t)level];
+}
+
+nmg_status nmg_load_smoother_weights(nmg_handle h, int level, int weight_set, const float* w, size_t count) {
+    NMG_TRY(check_handle(h));
+    if (!w) return fail(NMG_ERR_ARG, "null weights");
+    if (level < 0 || level >= h->L - 1) return fail(NMG_ERR_ARG, "level must be in [0, L-2]");
+    if (weight_set < 0 || weight_set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight_set out of range");
+    if (count != (size_t)h->wcount)
+        return fail(NMG_ERR_SHAPE, "weight count " + std::to_string(count) + " != expected " +
+                                       std::to_string(h->wcount));
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(w[i])) return fail(NMG_ERR_NONFINITE, "non-finite weight");
+    const size_t off = ((size_t)level * h->p.n_weight_sets + weight_set) * h->wcount;
+    NMG_HIP(hipMemcpy(h->w32 + off, w, count * sizeof(float), hipMemcpyHostToDevice));
+    if (h->w64.ready) NMG_TRY(launch_convert<float, double>(h->w32 + off, h->w64.wts + off, count, nullptr));
+    NMG_HIP(hipDeviceSynchronize());
+    h->kind[(size_t)level] = 0;
+    h->loaded[(size_t)level][(size_t)weight_set] = 1;
+    NMG_TRY(repack_bf16(h, level, weight_set));
+    return NMG_OK;
+}
+
+nmg_status nmg_get_smoother_weights(nmg_handle h, int level, int weight_set, float* w, size_t count) {
+    NMG_TRY(check_handle(h));
+    if (!w) return fail(NMG_ERR_ARG, "null weights");
+    if (level < 0 || level >= h->L - 1) return fail(NMG_ERR_ARG, "level must be in [0, L-2]");
+    if (weight_set < 0 || weight_set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight_set out of range");
+    if (count != (size_t)h->wcount) return fail(NMG_ERR_SHAPE, "weight count mismatch");
+    const size_t off = ((size_t)level * h->p.n_weight_sets + weight_set) * h->wcount;
+    NMG_HIP(hipDeviceSynchronize());
+    NMG_HIP(hipMemcpy(w, h->w32 + off, count * sizeof(float), hipMemcpyDeviceToHost));
+    return NMG_OK;
+}
+
+nmg_status nmg_set_jacobi_smoother(nmg_handle h, int level, double omega) {
+    NMG_TRY(check_handle(h));
+    if (level < 0 || level >= h->L - 1) return fail(NMG_ERR_ARG, "level must be in [0, L-2]");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(NMG_ERR_ARG, "omega must be positive");
+    h->kind[(size_t)level] = 1;
+    h->omega[(size_t)level] = omega;
+    return NMG_OK;
+}
+
+nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha, void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    if (!alpha) return fail(NMG_ERR_ARG, "null alpha");
+    hipStream_t s = (hipStream_t)stream;
+    NMG_HIP(hipMemcpyAsync(h->alpha_prepared, alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NMG_TRY(launch_coarse_factor(h, batch, h->alpha_prepared, s));
+    std::vector<int> flags((size_t)batch);
+    std::vector<double> al((size_t)batch);
+    NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
+    NMG_HIP(hipMemcpyAsync(al.data(), alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < batch; ++b) {
+        if (!std::isfinite(al[(size_t)b]) || !(al[(size_t)b] > 0.0))
+            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(b) + ")");
+        if (flags[(size_t)b]) return fail(NMG_ERR_NOT_SPD, "coarse Cholesky failed for slot " + std::to_string(b));
+    }
+    return NMG_OK;
+}
+
+nmg_status nmg_apply_operator(nmg_handle h, int level, int batch, const double* alpha, const void* x, void* y,
+                              nmg_precision prec, void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    if (!alpha || !x || !y) return fail(NMG_ERR_ARG, "null pointer");
+    if (level < 0 || level >= h->L) return fail(NMG_ERR_ARG, "level out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == NMG_FP64) {
+        NMG_TRY(ensure_work<double>(h));
+        return launch_operator<double>(h, level, batch, alpha, (const double*)x, nullptr, (double*)y, 1, h->w64, s);
+    }
+    NMG_TRY(ensure_work<float>(h));
+    return launch_operator<float>(h, level, batch, alpha, (const float*)x, nullptr, (float*)y, 1, h->w32b, s);
+}
+
+nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* alpha, const int* ws, const void* b,
+                              void* out, nmg_precision prec, void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    if (!b || !out) return fail(NMG_ERR_ARG, "null pointer");
+    if (level < 0 || level >= h->L - 1) return fail(NMG_ERR_ARG, "level must be in [0, L-2]");
+    if (h->kind[(size_t)level] < 0) return fail(NMG_ERR_STATE, "no smoother set for this level");
+    if (h->kind[(size_t)level] == 1 && !alpha) return fail(NMG_ERR_ARG, "Jacobi needs alpha");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t per = level_elems(h, level);
+    if (prec == NMG_FP64) {
+        NMG_TRY(ensure_work<double>(h));
+        const double* bb = (const double*)b;
+        double* oo = (double*)out;
+        if (h->kind[(size_t)level] == 1)
+            return launch_jacobi<double>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w64, s);
+        NMG_TRY(launch_sumsq<double>(batch, per, bb, h->nrm, s));
+        return launch_conv_smoother<double>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w64, s);
+    }
+    NMG_TRY(ensure_work<float>(h));
+    const float* bb = (const float*)b;
+    float* oo = (float*)out;
+    if (h->kind[(size_t)level] == 1)
+        return launch_jacobi<float>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w32b, s);
+    NMG_TRY(launch_sumsq<float>(batch, per, bb, h->nrm, s));
+    if (prec == NMG_MIXED) return launch_mfma_smoother(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
+    return launch_conv_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
+}
+
+nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* ws, const void* y, void* x,
+                      const nmg_cycle_opts* o, void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    NMG_TRY(check_opts(h, o));
+    if (!alpha || !y || !x) return fail(NMG_ERR_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (o->precision == NMG_FP64)
+        return run_cycle<double>(h, batch, alpha, ws, (const double*)y, (double*)x, false, *o, s);
+    return run_cycle<float>(h, batch, alpha, ws, (const float*)y, (float*)x, false, *o, s);
+}
+
+nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws, const double* b, double* x,
+                     double rtol, int max_cycles, const nmg_cycle_opts* o, int* cycles_host, double* history_host,
+                     void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    NMG_TRY(check_opts(h, o));
+    if (!alpha || !b || !x) return fail(NMG_ERR_ARG, "null pointer");
+    if (!(rtol > 0.0) || max_cycles < 0) return fail(NMG_ERR_ARG, "rtol must be > 0 and max_cycles >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    NMG_TRY(nmg_prepare(h, batch, alpha, stream));
+    const size_t per = level_elems(h, 0);
+    const size_t cnt = (size_t)batch * per;
+    NMG_TRY(ensure_work<double>(h));
+    const bool plain32 = o->precision == NMG_FP32;
+    if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
+    float* xs = h->w32b.ready ? h->w32b.lv[0].h : nullptr;  // plain FP32 iterate
+    float* bs = h->w32b.ready ? h->w32b.lv[0].b : nullptr;  // plain FP32 right-hand side
+    float* r32 = h->w32b.ready ? h->w32b.lv[0].t1 : nullptr;
+    (void)r32;
+    // plain FP32 keeps its own iterate; the residual buffer of level 0 is reused
+    float* rs = nullptr;
+    if (plain32) {
+        NMG_TRY(launch_convert<double, float>(b, bs, cnt, s));
+        NMG_TRY(launch_zero<float>(xs, cnt, s));
+        rs = reinterpret_cast<float*>(h->r64);  // r64 has room for cnt doubles
+    } else {
+        NMG_TRY(launch_zero<double>(x, cnt, s));
+    }
+    NMG_TRY(launch_sumsq<double>(batch, per, b, h->nrm2, s));
+    std::vector<double> bn2((size_t)batch), rn2((size_t)batch);
+    NMG_HIP(hipMemcpyAsync(bn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    double* bn2_dev = h->hist_dev;
+    NMG_HIP(hipMemcpyAsync(bn2_dev, h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < batch; ++i)
+        if (!std::isfinite(bn2[(size_t)i])) return fail(NMG_ERR_NONFINITE, "non-finite right-hand side");
+    if (history_host)
+        for (size_t i = 0; i < (size_t)batch * (max_cycles + 1); ++i) history_host[i] = -1.0;
+    std::vector<int> cyc((size_t)batch, 0);
+    std::vector<char> done((size_t)batch, 0);
+    bool nonfinite = false;
+    const double tol2 = rtol * rtol;
+    for (int it = 0; it <= max_cycles; ++it) {
+        // residual and its norm in the outer precision
+        {
+            ProfScope ps(h, s, NMG_K_REFINE, 0);
+            if (plain32) {
+                NMG_TRY(launch_operator<float>(h, 0, batch, alpha, xs, bs, rs, 0, h->w32b, s));
+                NMG_TRY(launch_sumsq<float>(batch, per, rs, h->nrm2, s));
+            } else {
+                NMG_TRY(launch_operator<double>(h, 0, batch, alpha, x, b, h->r64, 0, h->w64, s));
+                NMG_TRY(launch_sumsq<double>(batch, per, h->r64, h->nrm2, s));
+            }
+        }
+        NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+        NMG_HIP(hipStreamSynchronize(s));
+        if (h->prof_on) NMG_TRY(prof_resolve(h));
+        bool any = false;
+        for (int i = 0; i < batch; ++i) {
+            if (done[(size_t)i]) continue;
+            const double r = rn2[(size_t)i], bb = bn2[(size_t)i];
+            if (!std::isfinite(r)) {
+                nonfinite = true;
+                done[(size_t)i] = 1;
+                continue;
+            }
+            if (history_host) history_host[(size_t)i * (max_cycles + 1) + it] = bb > 0 ? std::sqrt(r / bb) : 0.0;
+            if (!(r > tol2 * bb)) {
+                done[(size_t)i] = 1;
+                continue;
+            }
+            if (it == max_cycles) continue;
+            any = true;
+        }
+        if (!any) break;
+        // d = MG(0, r / ||r||) for active right-hand sides; converged ones get a zero input
+        if (plain32) {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<float, float>(batch, per, rs, w.lv[0].y, h->nrm2, bn2_dev, rtol, h->active, s));
+            NMG_TRY(run_cycle<float>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<float, float>(batch, per, xs, w.lv[0].x, h->nrm2, h->active, s));
+        } else if (o->precision == NMG_FP64) {
+            Work<double>& w = h->w64;
+            NMG_TRY(launch_refine_scale<double, double>(batch, per, h->r64, w.lv[0].y, h->nrm2, bn2_dev, rtol,
+                                                        h->active, s));
+            NMG_TRY(run_cycle<double>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<double, double>(batch, per, x, w.lv[0].x, h->nrm2, h->active, s));
+        } else {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<double, float>(batch, per, h->r64, w.lv[0].y, h->nrm2, bn2_dev, rtol,
+                                                       h->active, s));
+            NMG_TRY(run_cycle<float>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<double, float>(batch, per, x, w.lv[0].x, h->nrm2, h->active, s));
+        }
+        for (int i = 0; i < batch; ++i)
+            if (!done[(size_t)i]) cyc[(size_t)i] += 1;
+    }
+    if (plain32) NMG_TRY(launch_convert<float, double>(xs, x, cnt, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    if (cycles_host)
+        for (int i = 0; i < batch; ++i) cycles_host[i] = cyc[(size_t)i];
+    if (nonfinite) return fail(NMG_ERR_NONFINITE, "non-finite residual");
+    for (int i = 0; i < batch; ++i) {
+        const double r = rn2[(size_t)i], bb = bn2[(size_t)i];
+        if (r > tol2 * bb) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
+    }
+    return NMG_OK;
+}
+
+nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* idx, float* w) {
+    NMG_TRY(check_handle(h));
+    if (level < 0 || level >= h->L - 1) return fail(NMG_ERR_ARG, "level must be in [0, L-2]");
+    if (!idx || !w) return fail(NMG_ERR_ARG, "null output");
+    if (kind != 0 && kind != 1) return fail(NMG_ERR_ARG, "kind must be 0 or 1");
+    const int cnt = kind == 0 ? h->n[(size_t)level + 1] : h->n[(size_t)level];
+    const int per = kind == 0 ? 3 : 2;
+    int32_t* di = nullptr;
+    float* dw = nullptr;
+    NMG_TRY(dev_alloc(&di, (size_t)cnt * per));
+    nmg_status st = dev_alloc(&dw, (size_t)cnt * per);
+    if (st == NMG_OK) st = launch_export_maps(h, level, kind, di, dw, nullptr);
+    if (st == NMG_OK) {
+        hipError_t e1 = hipMemcpy(idx, di, (size_t)cnt * per * sizeof(int32_t), hipMemcpyDeviceToHost);
+        hipError_t e2 = hipMemcpy(w, dw, (size_t)cnt * per * sizeof(float), hipMemcpyDeviceToHost);
+        if (e1 != hipSuccess) st = hip_fail(e1, "hipMemcpy", __FILE__, __LINE__);
+        else if (e2 != hipSuccess) st = hip_fail(e2, "hipMemcpy", __FILE__, __LINE__);
+    }
+    dev_free(di);
+    dev_free(dw);
+    return st;
+}
+
+nmg_status nmg_profile_enable(nmg_handle h, int on) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(prof_resolve(h));
+    h->prof_on = on != 0;
+    for (auto& row : h->prof_ms)
+        for (auto& v : row) v = 0.0;
+    for (auto& row : h->prof_cnt)
+        for (auto& v : row) v = 0;
+    return NMG_OK;
+}
+
+nmg_status nmg_profile_query(nmg_handle h, int kind, int level, double* total_ms, int* launches) {
+    NMG_TRY(check_handle(h));
+    if (kind < 0 || kind > 7) return fail(NMG_ERR_ARG, "unknown kernel kind");
+    if (level < -1 || level >= 16) return fail(NMG_ERR_ARG, "level out of range");
+    NMG_TRY(prof_resolve(h));
+    double ms = 0.0;
+    int cnt = 0;
+    for (int l = 0; l < 16; ++l)
+        if (level < 0 || l == level) {
+            ms += h->prof_ms[kind][l];
+            cnt += h->prof_cnt[kind][l];
+        }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = cnt;
+    return NMG_OK;
+}
+
+nmg_status nmg_debug_factor(nmg_handle h, int level, int which, double* out, int* radius) {
+    NMG_TRY(check_handle(h));
+    if (level < 0 || level >= h->L) return fail(NMG_ERR_ARG, "level out of range");
+    if (which != 0 && which != 1) return fail(NMG_ERR_ARG, "which must be 0 or 1");
+    const Band& B = which == 0 ? h->host[(size_t)level].M : h->host[(size_t)level].G;
+    if (radius) *radius = B.r;
+    if (out) std::memcpy(out, B.a.data(), B.a.size() * sizeof(double));
+    return NMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""Offline training of per-level smoother weights on the GPU (Algorithm 5).
+
+Each weight set belongs to one operator (grid, kernel width, alpha): the
+paper trains smoothers for a fixed coefficient matrix and retrains when it
+changes.  Training uses the library's own ``train_step`` (level-wise loss,
+hand-written adjoint, Adam) on batches of i.i.d. N(0,1) error vectors, an
+optional rollout of k in 1..K cycles of the current smoothers before each
+batch (Algorithm 5, DataGeneration) and a curriculum over alpha (weights of
+a larger alpha initialise the next smaller one, Sec. 4.1).
+
+Usage: python -m paper_2603_01064_amd.train_weights --n 255 --s 0.01 --levels 5 \
+           --alphas 1e-2 1e-3 1e-4 --steps 1500 --out paper_2603_01064_amd/weights/grid255_s0.01.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import inputs
+from . import nmg
+
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def save_weights(path: str, meta: dict, sets: list) -> None:
+    """``sets[k][l]`` is the flat FP32 weight vector of level l of set k."""
+    arrs = {f"set{k}_level{l}": np.asarray(w, dtype=np.float32) for k, s in enumerate(sets) for l, w in enumerate(s)}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8), **arrs)
+
+
+def load_weights(path: str):
+    """Returns ``(meta, sets)`` written by :func:`save_weights`."""
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["meta"]).decode())
+        sets = []
+        k = 0
+        while f"set{k}_level0" in z:
+            lv = []
+            l = 0
+            while f"set{k}_level{l}" in z:
+                lv.append(np.array(z[f"set{k}_level{l}"]))
+                l += 1
+            sets.append(lv)
+            k += 1
+    return meta, sets
+
+
+def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: torch.Generator,
+            precision: str) -> torch.Tensor:
+    """DataGeneration of Algorithm 5: each sample is run through k ~ U{0..K}
+    cycles of the current smoothers (e <- e - NMG(0, A e)) without gradients;
+    samples are rescaled to unit RMS so every batch has the same scale."""
+    if K <= 0:
+        return e
+    B = e.shape[0]
+    ks = torch.randint(0, K + 1, (B,), generator=gen).to(e.device)
+    h.prepare(alpha)
+    for j in range(K):
+        y = h.apply_operator(0, e, alpha, precision="fp32")
+        d = torch.zeros_like(e)
+        h.vcycle(y, d, alpha, nu1=1, nu2=0, precision=precision)
+        upd = (ks > j).to(e.dtype).reshape(B, 1, 1)
+        e = e - upd * d
+    rms = e.reshape(B, -1).norm(dim=1) / (e[0].numel() ** 0.5)
+    return e / rms.clamp_min(1e-30).reshape(B, 1, 1)
+
+
+def train_set(h: nmg.Handle, alpha_value: float, steps: int, batch: int, lr: float, mask: str, seed: int,
+              rollout_K: int = 0, log_every: int = 100, precision: str = "fp32"):
+    dev = torch.device("cuda:0")
+    n = h.problem.n
+    alpha = torch.full((batch,), alpha_value, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    for step in range(steps):
+        e = torch.randn((batch, n, n), generator=gen, dtype=torch.float32).to(dev)
+        e = rollout(h, e, alpha, rollout_K, gen, "mixed" if precision == "mixed" else "fp32")
+        cur_lr = lr * (0.1 ** (step / max(1, steps)))  # decays by 10x over the run
+        losses = h.train_step(e, alpha, mask=mask, precision=precision, lr=cur_lr)
+        hist.append(losses.tolist())
+        if log_every and step % log_every == 0:
+            print(f"  alpha={alpha_value:g} step {step} losses {np.array2string(losses, precision=3)} "
+                  f"({time.time() - t0:.1f}s)", flush=True)
+    return hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--s", type=float, default=0.01)
+    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--channels", type=int, nargs="+", default=[1, 32, 32, 1])
+    ap.add_argument("--alphas", type=float, nargs="+", default=[1e-2, 1e-3, 1e-4])
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--mask", default="ramp", choices=["ramp", "band"])
+    ap.add_argument("--rollout", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--seed", type=int, default=7000)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    nmg.load_library()
+    prob = nmg.Problem(n=a.n, s=a.s, levels=a.levels, dim=2, max_batch=a.batch, channels=tuple(a.channels),
+                       ksize=3, n_weight_sets=1)
+    h = nmg.setup_hierarchy(prob)
+    L = a.levels
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, inputs.he_normal_weights(tuple(a.channels), 3, 2, a.seed + 10 * l))
+    sets = []
+    for k, av in enumerate(sorted(a.alphas, reverse=True)):
+        print(f"training alpha={av:g} ({a.steps} steps, batch {a.batch}, mask {a.mask})", flush=True)
+        train_set(h, av, a.steps, a.batch, a.lr, a.mask, a.seed + 1000 * k, a.rollout, precision=a.precision)
+        sets.append([h.get_smoother_weights(l) for l in range(L - 1)])
+    meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=sorted(a.alphas, reverse=True),
+                steps=a.steps, batch=a.batch, lr=a.lr, mask=a.mask, rollout=a.rollout, precision=a.precision,
+                seed=a.seed, use_fprime=False)
+    save_weights(a.out, meta, sets)
+    print(f"wrote {a.out}", flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,94 @@
+"""BF16 MFMA smoother: checked against a BF16-rounding emulation of the same
+network (tight) and against the FP64 oracle (error stated, loose bound)."""
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _bf(x):
+    return x.to(torch.bfloat16).to(DT)
+
+
+def _emulated_smoother(W, b):
+    """Same network with every operand the kernel rounds to BF16 rounded the
+    same way (input b/||b||, weights, hidden activations); sums in FP64."""
+    nrm = torch.sqrt((b * b).sum(dim=(1, 2)))
+    z = _bf(b / nrm[:, None, None]).unsqueeze(1)
+    for i, w in enumerate(W):
+        z = torch.nn.functional.conv2d(z, _bf(w), padding=1)
+        if i + 1 < len(W):
+            z = _bf(torch.relu(z))
+    return z.squeeze(1) * nrm[:, None, None]
+
+
+def _rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+@pytest.mark.parametrize("n,ch,B", [(63, (1, 32, 32, 1), 3), (255, (1, 32, 32, 1), 2),
+                                    (31, (1, 32, 32, 32, 1), 2), (15, (1, 32, 32, 1), 1)])
+def test_mfma_smoother_matches_bf16_emulation(n, ch, B):
+    print(f"case mfma smoother n={n} layers={len(ch) - 1} B={B}", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    levels = {255: 5, 63: 3, 31: 2, 15: 2}[n]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=0.02, levels=levels, max_batch=B, channels=ch, ksize=3))
+    W = [torch.tensor(w).float().double() for w in inputs.he_normal_weights(ch, 3, 2, 7100)]
+    h.load_smoother_weights(0, 0, [w.numpy() for w in W])
+    b = torch.randn(B, n, n, dtype=DT, generator=torch.Generator().manual_seed(50)) * 3.0
+    b[0, :5, :] = 0.0  # zero rows next to the boundary
+    got = h.apply_smoother(0, b.float().to(dev), precision="mixed").cpu().double()
+    emul = _emulated_smoother(W, b.float().double())
+    e_emul = _rel(got, emul)
+    ref = O.neural_smoother(W, 2)(None, 0, b, None)
+    e_ref = _rel(got, ref)
+    print(f"  vs bf16 emulation {e_emul:.2e}   vs fp64 oracle {e_ref:.2e}", flush=True)
+    assert e_emul < 2e-4
+    assert e_ref < 5e-2
+    # fp32 and fp64 direct paths of the same entry point
+    g32 = h.apply_smoother(0, b.float().to(dev), precision="fp32").cpu().double()
+    g64 = h.apply_smoother(0, b.to(dev), precision="fp64").cpu()
+    assert _rel(g64, ref) < 1e-12 and _rel(g32, ref) < 1e-5
+    h.close()
+
+
+def test_mfma_zero_input_gives_zero():
+    print("case mfma zero input", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    ch = (1, 32, 32, 1)
+    h = nmg.setup_hierarchy(nmg.Problem(n=31, s=0.02, levels=2, max_batch=2, channels=ch, ksize=3))
+    h.load_smoother_weights(0, 0, inputs.he_normal_weights(ch, 3, 2, 7200))
+    b = torch.zeros(2, 31, 31, dtype=torch.float32, device=dev)
+    out = h.apply_smoother(0, b, precision="mixed")
+    assert int(torch.count_nonzero(out)) == 0 and bool(torch.isfinite(out).all())
+    h.close()
+
+
+def test_mixed_vcycle_error_stated():
+    """Mixed-precision cycle vs FP64 oracle on 63x63 with 4 levels (error stated)."""
+    print("case mixed vcycle 63", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    n, s, L, ch = 63, 0.04, 4, (1, 32, 32, 1)
+    W = [[torch.tensor(w).float().double() for w in inputs.he_normal_weights(ch, 3, 2, 7000 + 10 * l)] for l in range(L - 1)]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=2, channels=ch, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [w.numpy() for w in W[l]])
+    H = O.build_hierarchy(n, s, L, dim=2)
+    alpha = torch.tensor([1e-2, 1e-3], dtype=DT)
+    y = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(51))
+    ref = O.vcycle(H, [O.neural_smoother(w, 2) for w in W], torch.zeros_like(y), y, alpha, 1, 1, True)
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    x = torch.zeros(2, n, n, dtype=torch.float32, device=dev)
+    h.vcycle(y.float().to(dev), x, ad, nu1=1, nu2=1, use_fprime=True, precision="mixed")
+    err = _rel(x.cpu().double(), ref)
+    print(f"  mixed V(1,1)+F' vs fp64 oracle: {err:.2e}", flush=True)
+    assert err < 5e-2
+    h.close()

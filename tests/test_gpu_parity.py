@@ -1,0 +1,302 @@
+"""GPU-vs-oracle parity of the hierarchy, transfers, operator, coarse solve and
+the V-cycle (FP64: 1e-12 relative, FP32: 1e-5 relative, norm-wise per cycle).
+
+Every case prints its name before touching the GPU so a failure is
+attributable from the log alone.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DT = torch.float64
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _nmg():
+    from paper_2603_01064_amd import nmg
+    nmg.load_library()
+    return nmg
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float((a - b).norm() / max(float(b.norm()), 1e-300))
+
+
+def _weights(channels, k, dim, L, base=7000):
+    return [[torch.tensor(w).float().double() for w in inputs.he_normal_weights(channels, k, dim, base + 10 * l)]
+            for l in range(L - 1)]
+
+
+def _handle(n, s, L, dim=2, B=2, channels=(1, 8, 8, 1), k=3, sets=1, W=None):
+    nmg = _nmg()
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, dim=dim, max_batch=B, channels=channels, ksize=k,
+                                        n_weight_sets=sets))
+    if W is not None:
+        for l, lw in enumerate(W):
+            h.load_smoother_weights(l, 0, [w.numpy() for w in lw])
+    return h
+
+
+# --------------------------------------------------------------------------
+# Hierarchy and transfers
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n,s,L", [(255, 0.01, 5), (63, 0.04, 4), (127, 2.5 / 128, 4)])
+def test_galerkin_factors_match_oracle(n, s, L):
+    print(f"case factors n={n} s={s} L={L}", flush=True)
+    h = _handle(n, s, L)
+    H = O.build_hierarchy(n, s, L, dim=2)
+    for l in range(L):
+        for which, ref in ((0, H.levels[l].M), (1, H.levels[l].G)):
+            band, r = h.debug_factor(l, which)
+            nl = ref.shape[0]
+            dense = np.zeros((nl, nl))
+            for i in range(nl):
+                for d in range(-r, r + 1):
+                    if 0 <= i + d < nl:
+                        dense[i, i + d] = band[i, d + r]
+            scale = float(ref.abs().max())
+            assert np.abs(dense - ref.numpy()).max() <= 1e-14 * scale, (l, which)
+    h.close()
+
+
+@pytest.mark.parametrize("n,L", [(255, 5), (31, 3), (7, 2)])
+def test_transfer_index_maps_bit_exact(n, L):
+    print(f"case index maps n={n} L={L}", flush=True)
+    h = _handle(n, 0.05, L)
+    for l in range(L - 1):
+        nf = h.level_size(l)
+        nc = h.level_size(l + 1)
+        rmap, pmap = O.transfer_index_maps(nc)
+        idx, w = h.debug_transfer_map(l, 0)
+        for i in range(nc):
+            assert [(int(a), float(b)) for a, b in zip(idx[i], w[i])] == rmap[i]
+        idx, w = h.debug_transfer_map(l, 1)
+        for p in range(nf):
+            got = [(int(a), float(b)) for a, b in zip(idx[p], w[p]) if a >= 0]
+            assert got == pmap[p]
+    h.close()
+
+
+@pytest.mark.parametrize("dim,n,s,L", [(2, 255, 0.01, 5), (2, 63, 0.04, 4), (1, 255, 0.02, 4)])
+def test_operator_every_level(dim, n, s, L):
+    print(f"case operator dim={dim} n={n} L={L}", flush=True)
+    dev = _dev()
+    h = _handle(n, s, L, dim=dim, B=3)
+    H = O.build_hierarchy(n, s, L, dim=dim)
+    alpha = torch.tensor([1e-2, 1e-3, 1e-4], dtype=DT)
+    g = torch.Generator().manual_seed(21)
+    for l in range(L):
+        nl = H.levels[l].n
+        x = torch.randn((3,) + (nl,) * dim, dtype=DT, generator=g)
+        ref = O.apply_operator(H, l, x, alpha)
+        got = h.apply_operator(l, x.to(dev), alpha.to(dev), "fp64").cpu()
+        assert _rel(got, ref) < FP64_TOL, l
+        got32 = h.apply_operator(l, x.float().to(dev), alpha.to(dev), "fp32").cpu().double()
+        assert _rel(got32, ref) < FP32_TOL, l
+    h.close()
+
+
+def test_one_level_is_coarse_cholesky_solve():
+    print("case L=1 direct solve 15x15", flush=True)
+    dev = _dev()
+    n, s = 15, 0.05
+    h = _handle(n, s, 1)
+    H = O.build_hierarchy(n, s, 1, dim=2)
+    alpha = torch.tensor([1e-3, 1e-4], dtype=DT)
+    y = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(22))
+    ref = O.coarse_solve(H, y, alpha)
+    x = torch.zeros_like(y).to(dev)
+    h.prepare(alpha.to(dev))
+    h.vcycle(y.to(dev), x, alpha.to(dev), precision="fp64")
+    assert _rel(x.cpu(), ref) < 1e-11
+    h.close()
+
+
+def test_non_spd_alpha_rejected():
+    print("case alpha <= 0 rejected", flush=True)
+    dev = _dev()
+    nmg = _nmg()
+    h = _handle(15, 0.05, 2)
+    with pytest.raises(nmg.NMGError):
+        h.prepare(torch.tensor([-1.0, 1e-3], dtype=DT, device=dev))
+    h.close()
+
+
+# --------------------------------------------------------------------------
+# The cycle
+# --------------------------------------------------------------------------
+
+
+def _cycle_case(dim, n, s, L, ch, k, nu1, nu2, use_fp, alphas, cycles, seed=31, prec="fp64"):
+    dev = _dev()
+    B = len(alphas)
+    W = _weights(ch, k, dim, L)
+    h = _handle(n, s, L, dim=dim, B=B, channels=ch, k=k, W=W)
+    H = O.build_hierarchy(n, s, L, dim=dim)
+    S = [O.neural_smoother(w, dim) for w in W]
+    alpha = torch.tensor(alphas, dtype=DT)
+    g = torch.Generator().manual_seed(seed)
+    y = torch.randn((B,) + (n,) * dim, dtype=DT, generator=g)
+    x = torch.zeros_like(y)
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    yd, xd = y.to(dt).to(dev), x.to(dt).to(dev)
+    errs = []
+    for c in range(cycles):
+        x = O.vcycle(H, S, x, y, alpha, nu1, nu2, use_fp)
+        h.vcycle(yd, xd, ad, nu1=nu1, nu2=nu2, use_fprime=use_fp, precision=prec)
+        for b in range(B):
+            errs.append(_rel(xd[b].cpu().double(), x[b]))
+    h.close()
+    return errs
+
+
+@pytest.mark.parametrize("nu1,nu2,use_fp", [(1, 1, False), (1, 0, True), (2, 1, True), (0, 1, False)])
+def test_vcycle_fp64_2d(nu1, nu2, use_fp):
+    print(f"case vcycle fp64 2D 63 nu=({nu1},{nu2}) fprime={use_fp}", flush=True)
+    errs = _cycle_case(2, 63, 0.04, 4, (1, 8, 8, 1), 3, nu1, nu2, use_fp, [1e-2, 1e-4], 3)
+    assert max(errs) < FP64_TOL, errs
+
+
+def test_vcycle_fp32_2d():
+    print("case vcycle fp32 2D 63", flush=True)
+    errs = _cycle_case(2, 63, 0.04, 4, (1, 8, 8, 1), 3, 1, 1, True, [1e-2, 1e-3], 3, prec="fp32")
+    assert max(errs) < FP32_TOL, errs
+
+
+def test_vcycle_1d_ten_cycles_fp64_and_fp32():
+    """1D n=255, s=0.02, alpha=1e-3, 4 levels, Conv1d 1->16->16->1 k5, He-normal
+    weights, u* = sinusoids + steps, 10 V(1,1) cycles compared every cycle."""
+    print("case 1D n=255 ten V(1,1) cycles", flush=True)
+    dev = _dev()
+    n, s, L, ch, k = 255, 0.02, 4, (1, 16, 16, 1), 5
+    W = _weights(ch, k, 1, L)
+    H = O.build_hierarchy(n, s, L, dim=1)
+    S = [O.neural_smoother(w, 1) for w in W]
+    alpha = torch.tensor([1e-3], dtype=DT)
+    u = torch.tensor(inputs.sinusoids_and_steps_1d(n, 1000)).unsqueeze(0)
+    y = O.apply_operator(H, 0, u, alpha)
+    h = _handle(n, s, L, dim=1, B=1, channels=ch, k=k, W=W)
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    x = torch.zeros_like(y)
+    x64 = torch.zeros_like(y).to(dev)
+    x32 = torch.zeros_like(y).float().to(dev)
+    y64, y32 = y.to(dev), y.float().to(dev)
+    for c in range(10):
+        x = O.vcycle(H, S, x, y, alpha, 1, 1, False)
+        h.vcycle(y64, x64, ad, nu1=1, nu2=1, precision="fp64")
+        h.vcycle(y32, x32, ad, nu1=1, nu2=1, precision="fp32")
+        e64 = _rel(x64.cpu(), x)
+        e32 = _rel(x32.cpu().double(), x)
+        print(f"  cycle {c + 1}: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
+        assert e64 < FP64_TOL and e32 < FP32_TOL
+    h.close()
+
+
+def test_vcycle_ragged_tile_sizes():
+    """Sizes that do not divide any launch tile: 31 and 127 with 3 levels."""
+    for n, s in ((31, 0.05), (127, 0.02)):
+        print(f"case ragged n={n}", flush=True)
+        errs = _cycle_case(2, n, s, 3, (1, 4, 4, 1), 3, 1, 1, True, [1e-3], 2)
+        assert max(errs) < FP64_TOL, (n, errs)
+
+
+def test_jacobi_mode_equals_oracle():
+    print("case damped Jacobi V-cycle 63", flush=True)
+    dev = _dev()
+    n, s, L = 63, 0.04, 4
+    H = O.build_hierarchy(n, s, L, dim=2)
+    alpha = torch.tensor([1e-2], dtype=DT)
+    omegas = []
+    for l in range(L - 1):
+        d = torch.diagonal(O.dense_operator(H, l, 1e-2))
+        A = O.dense_operator(H, l, 1e-2)
+        omegas.append(1.0 / float(torch.linalg.eigvals(A / d[:, None]).abs().max()))
+    h = _handle(n, s, L, B=1)
+    for l in range(L - 1):
+        h.set_jacobi_smoother(l, omegas[l])
+    y = torch.randn(1, n, n, dtype=DT, generator=torch.Generator().manual_seed(41))
+    x = torch.zeros_like(y)
+    xd = x.clone().to(dev)
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    for _ in range(3):
+        x = O.vcycle(H, [O.jacobi_smoother(omegas)] * (L - 1), x, y, alpha, 1, 1)
+        h.vcycle(y.to(dev), xd, ad, precision="fp64")
+    assert _rel(xd.cpu(), x) < FP64_TOL
+    h.close()
+
+
+def test_mixed_weight_sets_per_rhs():
+    """Each right-hand side picks its own smoother set; results equal solo runs."""
+    print("case per-RHS weight sets", flush=True)
+    dev = _dev()
+    nmg = _nmg()
+    n, s, L, ch = 63, 0.04, 3, (1, 4, 4, 1)
+    Wa = _weights(ch, 3, 2, L, base=100)
+    Wb = _weights(ch, 3, 2, L, base=200)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=2, channels=ch, n_weight_sets=2))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [w.numpy() for w in Wa[l]])
+        h.load_smoother_weights(l, 1, [w.numpy() for w in Wb[l]])
+    H = O.build_hierarchy(n, s, L, dim=2)
+    alpha = torch.tensor([1e-3, 1e-2], dtype=DT)
+    y = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(42))
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    xd = torch.zeros(2, n, n, dtype=DT, device=dev)
+    h.vcycle(y.to(dev), xd, ad, weight_set=torch.tensor([1, 0], dtype=torch.int32, device=dev))
+    for b, W in ((0, Wb), (1, Wa)):
+        ref = O.vcycle(H, [O.neural_smoother(w, 2) for w in W], torch.zeros(1, n, n, dtype=DT), y[b:b + 1],
+                       alpha[b:b + 1], 1, 1)
+        assert _rel(xd[b:b + 1].cpu(), ref) < FP64_TOL
+    h.close()
+
+
+# --------------------------------------------------------------------------
+# Solve
+# --------------------------------------------------------------------------
+
+
+def test_solve_fp64_history_matches_oracle_and_dense_solution():
+    print("case solve fp64 Jacobi 31", flush=True)
+    dev = _dev()
+    n, s, L, alpha_v = 31, 0.04, 3, 1e-1
+    H = O.build_hierarchy(n, s, L, dim=2)
+    omegas = []
+    for l in range(L - 1):
+        A = O.dense_operator(H, l, alpha_v)
+        d = torch.diagonal(A)
+        omegas.append(1.0 / float(torch.linalg.eigvals(A / d[:, None]).abs().max()))
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2000 + i) for i in range(2)]))
+    alpha = torch.tensor([alpha_v, alpha_v], dtype=DT)
+    y = O.apply_operator(H, 0, u, alpha)
+    ref = O.solve(H, [O.jacobi_smoother(omegas)] * (L - 1), y, alpha, tol=1e-10, max_cycles=400)
+    h = _handle(n, s, L)
+    for l in range(L - 1):
+        h.set_jacobi_smoother(l, omegas[l])
+    x, cycles, hist, st = h.solve(y.to(dev), alpha.to(dev), rtol=1e-10, max_cycles=400, precision="fp64",
+                                  history=True)
+    assert st == 0
+    assert list(cycles) == [int(c) for c in ref.cycles]
+    for k, hr in enumerate(ref.history):
+        for b in range(2):
+            if hist[b, k] >= 0:
+                assert abs(hist[b, k] - float(hr[b])) <= 1e-9 * float(hr[b]) + 1e-14
+    dense = torch.linalg.solve(O.dense_operator(H, 0, alpha_v), y.reshape(2, -1).T).T.reshape(y.shape)
+    assert _rel(x.cpu(), dense) < 1e-8

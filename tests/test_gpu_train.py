@@ -1,0 +1,152 @@
+"""Hand-written adjoint of the level-wise spectral loss (eq. loss_3) vs the
+oracle's autograd gradient, central finite differences and Adam."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _setup(n=31, s=0.04, L=4, ch=(1, 32, 32, 1), B=3, seed=7300):
+    from paper_2603_01064_amd import nmg
+    W = [[torch.tensor(w).float().double() for w in inputs.he_normal_weights(ch, 3, 2, seed + 10 * l)]
+         for l in range(L - 1)]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=ch, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [w.numpy() for w in W[l]])
+    H = O.build_hierarchy(n, s, L, dim=2)
+    return h, H, W
+
+
+def _flat(ws):
+    return torch.cat([w.reshape(-1) for w in ws])
+
+
+@pytest.mark.parametrize("mask,use_fp", [("ramp", False), ("band", False), ("ramp", True)])
+def test_fp64_loss_and_gradient_match_oracle_autograd(mask, use_fp):
+    print(f"case loss grad fp64 31x31 mask={mask} fprime={use_fp}", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, W = _setup()
+    B, n = 3, 31
+    e = torch.tensor(inputs.iid_normal((B, n, n), 3000))
+    alpha = torch.full((B,), 1e-3, dtype=DT)
+    ref_l, ref_g = O.level_loss_grads(H, W, e, alpha, mask, use_fp)
+    got_l = h.loss_grad(e.to(dev), alpha.to(dev), mask=mask, use_fprime=use_fp, precision="fp64")
+    for l in range(H.L - 1):
+        assert abs(got_l[l] - float(ref_l[l])) <= 1e-12 * abs(float(ref_l[l])), (l, got_l[l], float(ref_l[l]))
+        g = torch.tensor(h.get_gradient(l))
+        r = _flat(ref_g[l])
+        err = float((g - r).norm() / r.norm())
+        print(f"  level {l}: loss {got_l[l]:.6e} grad rel err {err:.2e}", flush=True)
+        assert err < 1e-10
+    h.close()
+
+
+def test_fp64_gradient_central_differences():
+    """Central differences of the GPU FP64 loss against the GPU adjoint for a
+    few parameters of every level, at eps = 1e-3 and eps = 1e-5.  The loss is
+    piecewise quadratic in each weight (ReLU kinks), so central differences
+    are exact unless the interval crosses a kink; each parameter must agree
+    at one of the two step sizes."""
+    print("case central differences eps=1e-3 / 1e-5", flush=True)
+    dev = torch.device("cuda:0")
+    B, n, L = 2, 31, 4
+    h, H, W = _setup(B=B, L=L)
+    e = torch.tensor(inputs.iid_normal((B, n, n), 3001)).to(dev)
+    alpha = torch.full((B,), 1e-3, dtype=DT, device=dev)
+    h.loss_grad(e, alpha, mask="ramp", precision="fp64")
+    grads = [h.get_gradient(l) for l in range(L - 1)]
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    agree_1e3 = 0
+    total = 0
+    for l in range(L - 1):
+        base = np.concatenate([w.numpy().reshape(-1) for w in W[l]])
+        gscale = np.abs(grads[l]).max()
+        for idx in rng.integers(0, base.size, size=4):
+            rels = []
+            for eps in (1e-3, 1e-5):
+                vals, pts = [], []
+                for sgn in (1, -1):
+                    wv = base.copy()
+                    wv[idx] = np.float32(base[idx] + sgn * eps)  # the ABI stores FP32 weights
+                    pts.append(float(wv[idx]))
+                    h.load_smoother_weights(l, 0, [wv])
+                    vals.append(h.loss_grad(e, alpha, mask="ramp", precision="fp64")[l])
+                h.load_smoother_weights(l, 0, [base])
+                fd = (vals[0] - vals[1]) / (pts[0] - pts[1])
+                g = grads[l][idx]
+                rels.append(abs(fd - g) / max(abs(g), 1e-3 * gscale))
+                print(f"  level {l} w[{idx}] eps {eps:g}: fd {fd:.6e} adjoint {g:.6e} rel {rels[-1]:.1e}", flush=True)
+            total += 1
+            agree_1e3 += rels[0] < 1e-6
+            worst = max(worst, min(rels))
+    assert worst < 1e-4
+    assert agree_1e3 >= total // 2
+    h.close()
+
+
+def test_fp32_gradient_close_to_oracle():
+    print("case loss grad fp32", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, W = _setup()
+    B, n = 3, 31
+    e = torch.tensor(inputs.iid_normal((B, n, n), 3002))
+    alpha = torch.full((B,), 1e-2, dtype=DT)
+    ref_l, ref_g = O.level_loss_grads(H, W, e, alpha, "ramp", False)
+    got_l = h.loss_grad(e.float().to(dev), alpha.to(dev), mask="ramp", precision="fp32")
+    for l in range(H.L - 1):
+        assert abs(got_l[l] - float(ref_l[l])) <= 1e-5 * abs(float(ref_l[l]))
+        g = torch.tensor(h.get_gradient(l))
+        r = _flat(ref_g[l])
+        err = float((g - r).norm() / r.norm())
+        print(f"  level {l}: grad rel err {err:.2e}", flush=True)
+        assert err < 1e-4
+    h.close()
+
+
+def test_adam_step_matches_oracle_update():
+    print("case adam", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, W = _setup(L=3)
+    B, n = 3, 31
+    e = torch.tensor(inputs.iid_normal((B, n, n), 3003))
+    alpha = torch.full((B,), 1e-3, dtype=DT)
+    params = [_flat(W[l]) for l in range(2)]
+    m = [torch.zeros_like(p) for p in params]
+    v = [torch.zeros_like(p) for p in params]
+    for step in range(1, 4):
+        h.loss_grad(e.to(dev), alpha.to(dev), mask="ramp", precision="fp64")
+        for l in range(2):
+            g = torch.tensor(h.get_gradient(l))
+            params[l], m[l], v[l] = O.adam_update(params[l], g, m[l], v[l], step, 1e-3)
+        h.adam_step(0, lr=1e-3)
+        for l in range(2):
+            got = torch.tensor(h.get_smoother_weights(l).astype(np.float64))
+            assert float((got - params[l]).abs().max()) < 2e-6  # FP32 master weights
+    h.close()
+
+
+def test_training_reduces_the_loss():
+    print("case 30 training steps fp32", flush=True)
+    dev = torch.device("cuda:0")
+    B, n, L = 16, 63, 4
+    from paper_2603_01064_amd import nmg
+    ch = (1, 32, 32, 1)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=0.04, levels=L, max_batch=B, channels=ch, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, inputs.he_normal_weights(ch, 3, 2, 7400 + 10 * l))
+    alpha = torch.full((B,), 1e-3, dtype=DT, device=dev)
+    first = None
+    for step in range(30):
+        e = torch.tensor(inputs.iid_normal((B, n, n), 5000 + step), dtype=torch.float32, device=dev)
+        losses = h.train_step(e, alpha, mask="ramp", precision="fp32", lr=1e-3)
+        if first is None:
+            first = losses.copy()
+    print(f"  first {first} last {losses}", flush=True)
+    assert losses[0] < first[0]
+    h.close()
