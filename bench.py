@@ -1,0 +1,264 @@
+"""Benchmark: V-cycle solves/s to 1e-6 relative residual on 255x255 (256^2
+cells) with a batch of 64 right-hand sides, plus p50/p99 solve latency.
+
+One step = one batched solve of 64 synthetic deblurring problems
+b = A u* (u* = 20 random boxes + N(0, 0.01) noise, alpha per right-hand side
+drawn from {1e-2, 1e-3, 1e-4}) to relative residual 1e-6 with the
+mixed-precision neural V-cycle (BF16 MFMA smoother, FP32 cycle, FP64
+refinement and coarse Cholesky).  Inputs of every step are resident on the
+GPU before the timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "V-cycle solves/s to 1e-6 rel. residual, 256^2 batch 64; p50/p99 solve latency"
+N, S, LEVELS, BATCH = 255, 0.01, 5, 64
+CHANNELS = (1, 32, 32, 1)
+ALPHAS = (1e-2, 1e-3, 1e-4)
+FLOP_PER_PX = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)  # 19,584: three 3x3 layers
+BF16_PEAK_TFLOPS = 2500.0
+WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s0.01.npz")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_mfma_grid255_b64_pmc.txt")
+SMOOTHER_SRC = os.path.join(ROOT, "paper_2603_01064_amd", "csrc", "mfma_smoother.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    want = source_hash(SMOOTHER_SRC)
+    if f"kernel_source_sha256_16: {want}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("hbm_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
+
+
+def make_inputs(steps, seed0=20000):
+    from paper_2603_01064_amd import inputs
+    out = []
+    for k in range(steps):
+        alpha = inputs.alpha_mix(BATCH, seed0 + k)
+        u = np.stack([inputs.boxes_image(N, 2000 + 1000 * k + i) for i in range(BATCH)])
+        out.append((alpha, u))
+    return out
+
+
+def cpu_baseline(meta, mean_cycles, budget_s=20.0):
+    """The FP64 oracle's V-cycle on one right-hand side of the same workload,
+    timed on the host cores; converted to solves/s with the GPU's mean cycle
+    count (the oracle's per-cycle cost does not depend on the weight values,
+    so seeded He-normal weights are used)."""
+    import torch
+
+    import oracle as O
+    from paper_2603_01064_amd import inputs
+    H = O.build_hierarchy(N, S, LEVELS, dim=2)
+    W = [[torch.tensor(w) for w in inputs.he_normal_weights(CHANNELS, 3, 2, 7000 + 10 * l)] for l in range(LEVELS - 1)]
+    Sm = [O.neural_smoother(w, 2) for w in W]
+    u = torch.tensor(inputs.boxes_image(N, 1)).unsqueeze(0)
+    alpha = torch.tensor([1e-3], dtype=torch.float64)
+    y = O.apply_operator(H, 0, u, alpha)
+    x = torch.zeros_like(y)
+    nu1, nu2, fp = meta["cycle"]["nu1"], meta["cycle"]["nu2"], meta["cycle"]["use_fprime"]
+    t0 = time.perf_counter()
+    cycles = 0
+    while True:
+        x = O.vcycle(H, Sm, x, y, alpha, nu1, nu2, fp)
+        cycles += 1
+        if time.perf_counter() - t0 > budget_s or cycles >= 50:
+            break
+    dt = (time.perf_counter() - t0) / cycles
+    return {
+        "value": 1.0 / (dt * mean_cycles),
+        "unit": "solves/s",
+        "cores": int(torch.get_num_threads()),
+        "kind": "oracle",
+        "sample": f"{cycles} FP64 oracle V({nu1},{nu2}){'+F' if fp else ''} cycles on one 255x255 right-hand side "
+                  f"({dt:.2f} s/cycle) x {mean_cycles:.1f} cycles per solve (the GPU run's mean)",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--max-cycles", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serial-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); every right-hand side is "
+              f"independent, see the sharding notes in DESIGN.md", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2603_01064_amd import nmg
+    from paper_2603_01064_amd.train_weights import load_weights
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    nmg.load_library()
+    meta, sets = load_weights(a.weights)
+    assert meta["n"] == N and abs(meta["s"] - S) < 1e-12 and meta["levels"] == LEVELS
+    cyc_cfg = meta.get("cycle", {"nu1": 1, "nu2": 1, "use_fprime": bool(meta.get("use_fprime", False))})
+    meta["cycle"] = cyc_cfg
+    set_alphas = list(meta["alphas"])
+    h = nmg.setup_hierarchy(nmg.Problem(n=N, s=S, levels=LEVELS, max_batch=BATCH, channels=CHANNELS, ksize=3,
+                                        n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(LEVELS - 1):
+            h.load_smoother_weights(l, k, [ws[l]])
+
+    # ---- inputs, resident on the GPU before timing
+    log(f"generating {a.warmup + a.steps} batches of {BATCH} right-hand sides")
+    host = make_inputs(a.warmup + a.steps)
+    batches = []
+    for alpha_np, u in host:
+        alpha = torch.tensor(alpha_np, dtype=torch.float64, device=dev)
+        ws = torch.tensor([set_alphas.index(min(set_alphas, key=lambda s: abs(math.log(s / v)))) for v in alpha_np],
+                          dtype=torch.int32, device=dev)
+        b = h.apply_operator(0, torch.tensor(u, device=dev), alpha, "fp64")
+        batches.append((alpha, ws, b, torch.empty_like(b)))
+    torch.cuda.synchronize()
+
+    def run(batch):
+        alpha, ws, b, x = batch
+        done = np.full(BATCH, -1.0)
+        _, cyc, _, st = h.solve(b, alpha, weight_set=ws, rtol=1e-6, max_cycles=a.max_cycles, nu1=cyc_cfg["nu1"],
+                                nu2=cyc_cfg["nu2"], use_fprime=cyc_cfg["use_fprime"], precision="mixed", x=x,
+                                done_ms=done)
+        return cyc, done, st
+
+    for k in range(a.warmup):
+        log(f"warmup {k + 1}/{a.warmup}")
+        run(batches[k])
+    # ---- timed region
+    h.profile_enable(("smoother",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles, lat, status = [], [], []
+    for k in range(a.steps):
+        cyc, done, st = run(batches[a.warmup + k])
+        cycles.append(cyc)
+        lat.append(done)
+        status.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sm_ms, sm_n = h.profile_query("smoother", 0)
+    h.profile_enable(())
+    log(f"timed {a.steps} steps in {elapsed:.3f} s")
+    cycles = np.concatenate(cycles)
+    lat = np.concatenate(lat)
+    alphas_all = np.concatenate([host[a.warmup + k][0] for k in range(a.steps)])
+    converged = lat >= 0
+    value = BATCH * a.steps / elapsed
+    by_alpha = {f"{av:g}": float(cycles[np.isclose(alphas_all, av)].mean()) for av in ALPHAS
+                if np.isclose(alphas_all, av).any()}
+    flops_launch = FLOP_PER_PX * N * N * BATCH
+    avg_ms = sm_ms / max(sm_n, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(),
+            "kernel": "k_smoother_mfma<3> (level-1 BF16 smoother, 255x255 x 64)",
+            "avg_launch_ms": round(avg_ms, 4), "launches": sm_n, "flop_per_launch": flops_launch}
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(1e3 * elapsed / a.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {
+            "workload": "2D deblurring solve, 255x255 unknowns (256^2 cells), Gaussian s=0.01 truncated at 4s, "
+                        "alpha per RHS in {1e-2,1e-3,1e-4}, 5 levels to 15x15, CNN 1-32-32-1 3x3 smoothers, "
+                        "batch 64, rtol 1e-6",
+            "global_batch": BATCH, "grid": N, "levels": LEVELS,
+            "cycle": f"V({cyc_cfg['nu1']},{cyc_cfg['nu2']})" + ("+F'" if cyc_cfg["use_fprime"] else ""),
+            "precision": "BF16 smoother on MFMA (FP32 accumulate), FP32 cycle, FP64 refinement + coarse Cholesky",
+            "p50_ms": round(float(np.percentile(lat[converged], 50)), 3) if converged.any() else None,
+            "p99_ms": round(float(np.percentile(lat[converged], 99)), 3) if converged.any() else None,
+            "mean_cycles": round(float(cycles.mean()), 2), "cycles_by_alpha": by_alpha,
+            "converged": int(converged.sum()), "solves": int(len(lat)),
+        },
+        "roofline": roof,
+    }
+    if not a.no_serial_baseline:
+        res["serial_fp32_gpu"] = serial_fp32(nmg, sets, set_alphas, cyc_cfg, host[a.warmup][0], host[a.warmup][1],
+                                             a.max_cycles)
+        if res["serial_fp32_gpu"]["value"] > 0:
+            res["serial_fp32_gpu"]["speedup_solves_per_s"] = round(value / res["serial_fp32_gpu"]["value"], 1)
+            if res["config"]["p99_ms"] and res["serial_fp32_gpu"]["p99_ms"]:
+                res["serial_fp32_gpu"]["p99_ratio"] = round(res["serial_fp32_gpu"]["p99_ms"] / res["config"]["p99_ms"], 2)
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle")
+        res["cpu_baseline"] = cpu_baseline(meta, float(cycles.mean()))
+    print(json.dumps(res), flush=True)
+    h.close()
+    return 0
+
+
+def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8):
+    """Plain FP32 V-cycle solving one right-hand side at a time (no batching,
+    no BF16, no refinement) on the first `count` problems of a batch."""
+    import torch
+    dev = torch.device("cuda:0")
+    h1 = nmg.setup_hierarchy(nmg.Problem(n=N, s=S, levels=LEVELS, max_batch=1, channels=CHANNELS, ksize=3,
+                                         n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(LEVELS - 1):
+            h1.load_smoother_weights(l, k, [ws[l]])
+    probs = []
+    for i in range(count):
+        alpha = torch.tensor([alpha_np[i]], dtype=torch.float64, device=dev)
+        wsi = set_alphas.index(min(set_alphas, key=lambda s: abs(math.log(s / alpha_np[i]))))
+        ws = torch.tensor([wsi], dtype=torch.int32, device=dev)
+        b = h1.apply_operator(0, torch.tensor(u[i:i + 1], device=dev), alpha, "fp64")
+        probs.append((alpha, ws, b))
+    torch.cuda.synchronize()
+    lat, cyc_all, ok = [], [], 0
+    t0 = time.perf_counter()
+    for alpha, ws, b in probs:
+        t1 = time.perf_counter()
+        try:
+            _, cyc, _, st = h1.solve(b, alpha, weight_set=ws, rtol=1e-6, max_cycles=max_cycles,
+                                     nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"], use_fprime=cyc_cfg["use_fprime"],
+                                     precision="fp32")
+            ok += int(st == 0)
+            cyc_all.append(int(cyc[0]))
+        except nmg.NMGError:
+            cyc_all.append(-1)
+        lat.append(1e3 * (time.perf_counter() - t1))
+    elapsed = time.perf_counter() - t0
+    h1.close()
+    return {"value": round(count / elapsed, 3), "unit": "solves/s", "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2), "converged": ok, "solves": count, "cycles": cyc_all,
+            "note": "one request at a time, plain FP32 cycle and FP32 direct-convolution smoother"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

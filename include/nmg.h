@@ -146,6 +146,14 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
                               const int* weight_set_dev, const void* b, void* h_out,
                               nmg_precision precision, void* stream);
 
+/* out = F'_l(in) = C^T (m'_l .* (C in C^T)) C on level `level` (the filter
+ * of Algorithm 3 / Algorithm 4 with the DCT-II basis of a zero-boundary
+ * grid and m'_l = sqrt(max(k1, k2) / n_l)).  in, out: device, double for
+ * NMG_FP64, float otherwise; NMG_MIXED runs the four transforms on BF16
+ * MFMA with FP32 accumulation.  in and out must not overlap. */
+nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, void* out,
+                            nmg_precision precision, void* stream);
+
 /* ---- the cycle ---------------------------------------------------------- */
 
 /* x <- MG(x, y): one V(nu1, nu2) cycle on the finest level with initial
@@ -167,12 +175,15 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const in
  * right-hand sides are frozen.  cycles_host (int[batch], may be NULL)
  * receives cycles used; history_host (double[batch][max_cycles+1], may be
  * NULL) receives the relative residual before each cycle (unused entries
- * set to -1).  Synchronises.  Returns NMG_NOT_CONVERGED if any
- * right-hand side missed rtol, NMG_ERR_NONFINITE on NaN/Inf residuals. */
+ * set to -1); done_ms_host (double[batch], may be NULL) receives the host
+ * time in ms from entry to the residual check that found each right-hand
+ * side converged (-1 if it never did).  Synchronises once per cycle.
+ * Returns NMG_NOT_CONVERGED if any right-hand side missed rtol,
+ * NMG_ERR_NONFINITE on NaN/Inf residuals. */
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
                      const double* b_dev, double* x_dev, double rtol, int max_cycles,
                      const nmg_cycle_opts* opts, int* cycles_host, double* history_host,
-                     void* stream);
+                     double* done_ms_host, void* stream);
 
 /* ---- training (Sec. 3.2 eq. loss_2_modified / Sec. 3.3 eq. loss_3,
  *      Algorithm 5) ----------------------------------------------------- */
@@ -213,10 +224,10 @@ typedef enum {
     NMG_K_COARSE = 4, NMG_K_FPRIME = 5, NMG_K_REFINE = 6, NMG_K_NORM = 7
 } nmg_kernel_kind;
 
-/* Turns HIP-event timing of every cycle/solve launch on (1) or off (0) and
- * clears the accumulated times.  Events are recorded on the caller's stream
- * around each launch. */
-nmg_status nmg_profile_enable(nmg_handle h, int on);
+/* Turns HIP-event timing on for the kernel families in kind_mask (bit k =
+ * nmg_kernel_kind k; 0 turns it off) and clears the accumulated times.
+ * Events are recorded on the caller's stream around each timed launch. */
+nmg_status nmg_profile_enable(nmg_handle h, int kind_mask);
 
 /* Accumulated device time (ms) and launch count of one kernel family on one
  * level (level -1 sums all levels).  Synchronises the recorded events. */

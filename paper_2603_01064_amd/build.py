@@ -19,7 +19,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
-SOURCES = ["hierarchy.cpp", "stencil.hip", "smoother.hip", "coarse.hip", "fprime.hip",
+SOURCES = ["hierarchy.cpp", "stencil.hip", "smoother.hip", "coarse.hip", "fprime.hip", "fprime_mfma.hip",
            "refine.hip", "mfma_smoother.hip", "train.hip", "runtime.hip"]
 
 

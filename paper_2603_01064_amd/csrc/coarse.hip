@@ -3,9 +3,12 @@
 // Per right-hand-side slot the dense matrix
 //   A_L = alpha M_L (x) M_L + G_L (x) G_L   (1D: alpha M_L + G_L)
 // is assembled from the dense Galerkin factors and factored by Cholesky,
-// A_L = L L^T; each cycle then performs the forward and back substitutions.
-// One workgroup owns one slot.  The factor is stored twice (L and L^T,
-// row-major) so both sweeps read contiguous rows.
+// A_L = L L^T.  The FP64 cycle then performs the forward and back
+// substitutions (one workgroup per slot; the factor is stored twice, L and
+// L^T row-major, so both sweeps read contiguous rows).  FP32 and mixed
+// cycles instead apply the FP64 inverse L^{-T} L^{-1}, formed once per
+// factorisation, as a batched matrix-vector product: the substitutions are
+// 2 n_L^2 dependent steps per cycle, the product has no serial chain.
 #include "nmg_internal.h"
 
 namespace nmg {
@@ -98,7 +101,70 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restric
     for (int i = threadIdx.x; i < N; i += kBlock) x[(size_t)b * N + i] = (T)z[i];
 }
 
+// W = L^{-1} by forward substitution on the identity, one column per thread
+// (column c of W lives in W[.][c], so a row of W is read coalesced).
+__global__ void __launch_bounds__(kBlock) k_lower_inverse(const double* __restrict__ chol, double* __restrict__ W,
+                                                          int N) {
+    const int b = blockIdx.x;
+    const double* Lr = chol + (size_t)b * N * N;
+    double* Wb = W + (size_t)b * N * N;
+    for (int c = threadIdx.x; c < N; c += kBlock) {
+        for (int j = 0; j < N; ++j) {
+            double acc = (j == c) ? 1.0 : 0.0;
+            for (int k = c; k < j; ++k) acc -= Lr[(size_t)j * N + k] * Wb[(size_t)k * N + c];
+            Wb[(size_t)j * N + c] = (j < c) ? 0.0 : acc / Lr[(size_t)j * N + j];
+        }
+    }
+}
+
+// Ainv = W^T W (symmetric), Ainv[i][j] = sum_{k >= max(i,j)} W[k][i] W[k][j].
+__global__ void __launch_bounds__(kBlock) k_gram(const double* __restrict__ W, double* __restrict__ Ainv, int N) {
+    const int b = blockIdx.y;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= N * N) return;
+    const int i = e / N, j = e % N;
+    const double* Wb = W + (size_t)b * N * N;
+    double acc = 0.0;
+    for (int k = i > j ? i : j; k < N; ++k) acc += Wb[(size_t)k * N + i] * Wb[(size_t)k * N + j];
+    Ainv[(size_t)b * N * N + e] = acc;
+}
+
+// x = Ainv y per right-hand side; Ainv is symmetric, so thread i reads column
+// i (contiguous across threads for each k).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restrict__ Ainv, const T* __restrict__ y,
+                                                          T* __restrict__ x, int N) {
+    extern __shared__ double yv[];
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < N; i += kBlock) yv[i] = (double)y[(size_t)b * N + i];
+    __syncthreads();
+    const double* A = Ainv + (size_t)b * N * N;
+    for (int i = threadIdx.x; i < N; i += kBlock) {
+        double acc = 0.0;
+        for (int k = 0; k < N; ++k) acc += A[(size_t)k * N + i] * yv[k];
+        x[(size_t)b * N + i] = (T)acc;
+    }
+}
+
 }  // namespace
+
+nmg_status launch_coarse_inverse(Ctx* c, int batch, hipStream_t s) {
+    const int N = c->nc;
+    hipLaunchKernelGGL(k_lower_inverse, dim3(batch), dim3(kBlock), 0, s, c->chol, c->cwork, N);
+    hipLaunchKernelGGL(k_gram, dim3((N * N + kBlock - 1) / kBlock, batch), dim3(kBlock), 0, s, c->cwork, c->cinv, N);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+
+template <typename T>
+nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
+    const int N = c->nc;
+    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv, y, x, N);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_coarse_apply_inverse<float>(const Ctx*, int, const float*, float*, hipStream_t);
+template nmg_status launch_coarse_apply_inverse<double>(const Ctx*, int, const double*, double*, hipStream_t);
 
 nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStream_t s) {
     const int nl = c->n[c->L - 1];

@@ -9,6 +9,7 @@
 // G_{l+1} = R1 G_l P1 for the 1D transfers R1 = P1^T / 2 (full weighting)
 // and P1 (linear interpolation).  Every factor is a band matrix; its rows
 // near the boundary differ from the interior, so rows are stored one by one.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -61,6 +62,39 @@ Band galerkin(const Band& B) {
 
 }  // namespace
 
+bool split_toeplitz(const Band& B, ToeplitzSplit& out) {
+    out = ToeplitzSplit{};
+    const int n = B.n, r = B.r;
+    if (n < 2 * r + 1) return false;
+    const int mid = n / 2;
+    out.r = r;
+    out.t.assign((size_t)(2 * r + 1), 0.0);
+    for (int d = -r; d <= r; ++d) out.t[(size_t)(d + r)] = B.get(mid, mid + d);
+    int rc_top = 0, rc_bot = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(0, i - r); j <= std::min(n - 1, i + r); ++j) {
+            const double dv = B.get(i, j) - out.t[(size_t)(j - i + r)];
+            if (dv == 0.0) continue;
+            if (i < mid && j < mid) rc_top = std::max(rc_top, std::max(i, j) + 1);
+            else if (i >= mid && j >= mid) rc_bot = std::max(rc_bot, n - std::min(i, j));
+            else return false;
+        }
+    const int rc = std::max(rc_top, rc_bot);
+    if (rc > r) return false;
+    out.rc = rc;
+    out.dtl.assign((size_t)rc * rc, 0.0);
+    out.dbr.assign((size_t)rc * rc, 0.0);
+    for (int i = 0; i < rc; ++i)
+        for (int j = 0; j < rc; ++j) {
+            const double tij = std::abs(j - i) <= r ? out.t[(size_t)(j - i + r)] : 0.0;
+            out.dtl[(size_t)i * rc + j] = B.get(i, j) - tij;
+            const int bi = n - rc + i, bj = n - rc + j;
+            out.dbr[(size_t)i * rc + j] = B.get(bi, bj) - tij;
+        }
+    out.ok = true;
+    return true;
+}
+
 bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector<HostLevel>& out,
                           int* taps_radius, std::string& err) {
     if (n < 1) {
@@ -106,6 +140,10 @@ bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector
         c.G = galerkin(out.back().G);
         c.n = c.M.n;
         out.push_back(std::move(c));
+    }
+    for (auto& hl : out) {
+        split_toeplitz(hl.M, hl.Ms);
+        split_toeplitz(hl.G, hl.Gs);
     }
     return true;
 }

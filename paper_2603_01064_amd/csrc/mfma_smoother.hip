@@ -2,7 +2,7 @@
 // (the smoothing line of Algorithm 4; N = Conv2d 1->32->...->32->1, 3x3,
 // ReLU between layers, no bias, zero "same" padding).
 //
-// One workgroup produces a 16x16 output tile of one image and keeps every
+// One workgroup produces a TW x TH output tile of one image and keeps every
 // intermediate activation of that tile in LDS: the input tile carries a
 // halo of one pixel per layer, layer i is evaluated on the tile grown by
 // (layers - i) pixels per side, and activations that fall outside the image
@@ -24,7 +24,6 @@ namespace nmg {
 
 namespace {
 
-constexpr int kT = 16;        // output tile side
 constexpr int kThreads = 256; // 4 waves
 constexpr int kC = 32;        // hidden channels
 
@@ -32,7 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ inline uint16_t f2bf(float f) {
+inline uint16_t f2bf(float f) {
     // round to nearest even (inputs are finite)
     uint32_t u;
     __builtin_memcpy(&u, &f, 4);
@@ -40,21 +39,15 @@ __host__ __device__ inline uint16_t f2bf(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Byte offset of channel chunk g (8 channels, 16 B) of pixel p in an
-// activation buffer; the XOR spreads consecutive pixels over LDS banks.
-__device__ inline int act_off(int p, int g) { return p * 64 + ((g ^ (p & 3)) << 4); }
+// Activation buffers hold 32 BF16 channels per pixel (64 B) in four chunks of
+// 8 channels; chunk g of pixel (row r, column c) sits at
+//   (r * P + c) * 64 + ((g ^ (c & 3)) << 4)
+// which spreads the 16 consecutive pixels an MFMA operand reads over the LDS
+// banks.  The pitch P is a multiple of 4, so the swizzle depends on the
+// column only and every tap of a lane is its base address plus a constant.
+constexpr int kP = 36;
 
-template <int NL>
-struct Geo {
-    static constexpr int S0 = kT + 2 * NL;                 // input tile side
-    static constexpr int side(int i) { return kT + 2 * (NL - i); }  // output region of layer i (1-based)
-    static constexpr int in_bytes = ((S0 * S0 * 2 + 255) / 256) * 256;
-    static constexpr int bufA = side(1) * side(1) * 64;
-    static constexpr int bufB_act = NL >= 3 ? side(2) * side(2) * 64 : 0;
-    static constexpr int z_bytes = side(NL - 1) * side(NL - 1) * 64;
-    static constexpr int bufB = bufB_act > z_bytes ? bufB_act : z_bytes;
-    static constexpr int lds = in_bytes + bufA + bufB;
-};
+__device__ inline int act_addr(int r, int c, int g) { return (r * kP + c) * 64 + ((g ^ (c & 3)) << 4); }
 
 // Packed weight block (uint16 bf16) per (level, set):
 //   first : [nb 2][lane 64][4]          co = nb*16 + lane%16, tap = 4*(lane/16)+j (0 if >= 9)
@@ -66,7 +59,59 @@ constexpr int kLastElems = 64 * 8;
 
 inline size_t packed_elems(int n_hidden) { return (size_t)kFirstElems + (size_t)n_hidden * kHiddenElems + kLastElems; }
 
+// Tile geometry.  The output tile is TW x TH; layer i (1-based) is evaluated
+// on the tile grown by NL - i pixels per side.  TW makes the hidden layers'
+// output rows whole (or nearly whole) groups of 16 pixels, so one MFMA
+// column group is 16 consecutive pixels of one row.
 template <int NL>
+struct Geo {
+    static constexpr int TW = 32 - 2 * (NL - 2);  // 30 (3 layers), 28 (4 layers)
+    static constexpr int TH = NL == 3 ? 12 : 10;
+    static constexpr int W0 = TW + 2 * NL, H0 = TH + 2 * NL;
+    static constexpr int W(int i) { return TW + 2 * (NL - i); }
+    static constexpr int H(int i) { return TH + 2 * (NL - i); }
+    static constexpr int in_bytes = ((W0 * H0 * 2 + 255) / 256) * 256;
+    static constexpr int bufA = H(1) * kP * 64;
+    static constexpr int bufB = H(2) * kP * 64;
+    static constexpr int lds = in_bytes + bufA + bufB;
+};
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU, round to BF16 (hardware RNE pack) and pack four channels.
+__device__ inline uint2 relu_pack4(floatx4 a) {
+    const float2v lo = {fmaxf(a[0], 0.f), fmaxf(a[1], 0.f)};
+    const float2v hi = {fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)};
+    const bf16x2 pl = __builtin_convertvector(lo, bf16x2);
+    const bf16x2 ph = __builtin_convertvector(hi, bf16x2);
+    uint2 r;
+    __builtin_memcpy(&r.x, &pl, 4);
+    __builtin_memcpy(&r.y, &ph, 4);
+    return r;
+}
+
+__device__ inline uint16_t to_bf16(float v) {
+    const float2v f = {v, 0.f};
+    const bf16x2 p = __builtin_convertvector(f, bf16x2);
+    uint32_t u;
+    __builtin_memcpy(&u, &p, 4);
+    return (uint16_t)(u & 0xFFFFu);
+}
+
+__device__ inline bf16x8 shift_rows(bf16x8 v, bf16x8 fill) {
+    // lane n of each 16-lane row takes lane n+1's operand; lane 15 takes `fill`
+    typedef int int4v __attribute__((ext_vector_type(4)));
+    int4v a, f, r;
+    __builtin_memcpy(&a, &v, 16);
+    __builtin_memcpy(&f, &fill, 16);
+    for (int k = 0; k < 4; ++k) r[k] = __builtin_amdgcn_update_dpp(f[k], a[k], 0x101, 0xF, 0xF, false);
+    bf16x8 out;
+    __builtin_memcpy(&out, &r, 16);
+    return out;
+}
+
+template <int NL, bool DPP>
 __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restrict__ bres,
                                                             const double* __restrict__ nrm2, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
@@ -74,6 +119,7 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                                                             int tiles_x, int tiles_per_img) {
     constexpr int NH = NL - 2;
     using G = Geo<NL>;
+    constexpr int TW = G::TW, TH = G::TH;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     uint16_t* in_t = reinterpret_cast<uint16_t*>(smem);
     char* bufA = smem + G::in_bytes;
@@ -89,16 +135,29 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
     const int set = ws ? ws[img] : 0;
     const uint16_t* wp = wlevel + (size_t)set * set_stride;
 
-    // weights into registers (kept for all tiles of this image)
     short4v w1[2];
     for (int nb = 0; nb < 2; ++nb) w1[nb] = *reinterpret_cast<const short4v*>(wp + (nb * 64 + lane) * 4);
-    bf16x8 wh[NH > 0 ? NH : 1][9][2];
+    bf16x8 wh[NH][9][2];
     for (int h = 0; h < NH; ++h)
         for (int t = 0; t < 9; ++t)
             for (int nb = 0; nb < 2; ++nb)
                 wh[h][t][nb] = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)h * kHiddenElems +
                                                                 ((t * 2 + nb) * 64 + lane) * 8);
     const bf16x8 wl = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)NH * kHiddenElems + lane * 8);
+
+    // per-lane constants: operand chunk offset of pixel ln (its column & 3 == ln & 3 for
+    // 16-aligned groups) and the output chunk offsets of channels nb*16 + 4*lg .. +3
+    const int swz_in = ((lg ^ (ln & 3)) << 4);
+    int out_off[2];
+    for (int nb = 0; nb < 2; ++nb) {
+        const int co = nb * 16 + lg * 4;
+        out_off[nb] = (((co >> 3) ^ (ln & 3)) << 4) + (co & 7) * 2;
+    }
+    int tapoff[4];
+    for (int j = 0; j < 4; ++j) {
+        const int tap = lg * 4 + j;
+        tapoff[j] = tap < 9 ? (tap / 3) * G::W0 + tap % 3 : -1;
+    }
 
     const size_t per = (size_t)n * n;
     const float* src = bres + (size_t)img * per;
@@ -108,111 +167,127 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
     const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
 
     for (int tile = blockIdx.x; tile < tiles_per_img; tile += gridDim.x) {
-        const int ty0 = (tile / tiles_x) * kT, tx0 = (tile % tiles_x) * kT;
+        const int ty0 = (tile / tiles_x) * TH, tx0 = (tile % tiles_x) * TW;
         // ---- input tile (halo NL), scaled by 1/||b||, zero outside the image
-        {
-            constexpr int S0 = G::S0;
-            for (int e = tid; e < S0 * S0; e += kThreads) {
-                const int gy = ty0 - NL + e / S0, gx = tx0 - NL + e % S0;
+        for (int r = wave; r < G::H0; r += 4) {
+            const int gy = ty0 - NL + r;
+            for (int c = lane; c < G::W0; c += 64) {
+                const int gx = tx0 - NL + c;
                 float v = 0.f;
                 if (gy >= 0 && gy < n && gx >= 0 && gx < n) v = src[(size_t)gy * n + gx] * inv;
-                in_t[e] = f2bf(v);
+                in_t[r * G::W0 + c] = to_bf16(v);
             }
         }
         __syncthreads();
-        // ---- first layer 1 -> 32 on region side(1)
+        // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16)
         {
-            constexpr int S = G::side(1), SI = G::S0, H = NL - 1;
-            constexpr int npx = S * S, ngr = (npx + 15) / 16;
+            constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
+            constexpr int npx = S * HH, ngr = (npx + 15) / 16;
             for (int gi = wave; gi < ngr; gi += 4) {
-                const int q = min(gi * 16 + ln, npx - 1);
-                const int ry = q / S, rx = q % S;
+                const int q0 = gi * 16 + ln;
+                const int q = q0 < npx ? q0 : npx - 1;
+                const int ry = q / S, rx = q - (q / S) * S;
+                const int ib = ry * G::W0 + rx;
                 short4v bop;
-                for (int j = 0; j < 4; ++j) {
-                    const int tap = lg * 4 + j;
-                    uint16_t v = 0;
-                    if (tap < 9) v = in_t[(ry + tap / 3) * SI + rx + tap % 3];
-                    bop[j] = (short)v;
-                }
-                const int gy = ty0 - H + ry, gx = tx0 - H + rx;
-                const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n && (gi * 16 + ln) < npx;
+                for (int j = 0; j < 4; ++j) bop[j] = tapoff[j] >= 0 ? (short)in_t[ib + tapoff[j]] : (short)0;
+                const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
                 for (int nb = 0; nb < 2; ++nb) {
                     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc, 0, 0, 0);
-                    if ((gi * 16 + ln) < npx) {
+                    if (q0 < npx) {
                         const int co = nb * 16 + lg * 4;
-                        uint32_t lo = 0, hi = 0;
-                        if (inside) {
-                            lo = (uint32_t)f2bf(fmaxf(acc[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1], 0.f)) << 16);
-                            hi = (uint32_t)f2bf(fmaxf(acc[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3], 0.f)) << 16);
-                        }
-                        uint2* p = reinterpret_cast<uint2*>(bufA + act_off(q, co >> 3) + (co & 7) * 2);
-                        *p = make_uint2(lo, hi);
+                        const uint2 v = inside ? relu_pack4(acc) : make_uint2(0u, 0u);
+                        *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
                     }
                 }
             }
         }
         __syncthreads();
-        // ---- hidden layers 32 -> 32 (ping-pong between bufA and bufB)
+        // ---- hidden layers 32 -> 32: groups are 16 consecutive pixels of a row
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            const int layer = 2 + h;  // 1-based layer index
-            const int S = kT + 2 * (NL - layer), SI = S + 2, H = NL - layer;
-            const int npx = S * S, ngr = (npx + 15) / 16;
+            const int layer = 2 + h;
+            const int S = TW + 2 * (NL - layer), HH = TH + 2 * (NL - layer), HALO = NL - layer;
+            const int ngr = HH * 2;  // S <= 32: two groups per row
             const char* ain = (h & 1) ? bufB : bufA;
             char* aout = (h & 1) ? bufA : bufB;
             for (int gi = wave; gi < ngr; gi += 4) {
-                const int q = min(gi * 16 + ln, npx - 1);
-                const int ry = q / S, rx = q % S;
+                const int ry = gi >> 1, rx0 = (gi & 1) * 16;
+                const int rx = rx0 + ln;
+                const char* a0 = ain + (ry * kP + rx) * 64 + swz_in;       // tap (dy, 0) of pixel rx
                 floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (DPP) {
+                    const char* e0 = ain + (ry * kP + rx0 + 16) * 64 + (lg << 4);        // pixel rx0+16
+                    const char* e1 = ain + (ry * kP + rx0 + 17) * 64 + ((lg ^ 1) << 4);  // pixel rx0+17
 #pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    const int p = (ry + t / 3) * SI + rx + t % 3;
-                    const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + act_off(p, lg));
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][t][0], bop, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][t][1], bop, acc1, 0, 0, 0);
-                }
-                if ((gi * 16 + ln) < npx) {
-                    const int gy = ty0 - H + ry, gx = tx0 - H + rx;
-                    const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
-                    for (int nb = 0; nb < 2; ++nb) {
-                        const floatx4 a = nb ? acc1 : acc0;
-                        const int co = nb * 16 + lg * 4;
-                        uint32_t lo = 0, hi = 0;
-                        if (inside) {
-                            lo = (uint32_t)f2bf(fmaxf(a[0], 0.f)) | ((uint32_t)f2bf(fmaxf(a[1], 0.f)) << 16);
-                            hi = (uint32_t)f2bf(fmaxf(a[2], 0.f)) | ((uint32_t)f2bf(fmaxf(a[3], 0.f)) << 16);
-                        }
-                        uint2* pp = reinterpret_cast<uint2*>(aout + act_off(q, co >> 3) + (co & 7) * 2);
-                        *pp = make_uint2(lo, hi);
+                    for (int dy = 0; dy < 3; ++dy) {
+                        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
+                        const bf16x8 x16 = *reinterpret_cast<const bf16x8*>(e0 + dy * kP * 64);
+                        const bf16x8 x17 = *reinterpret_cast<const bf16x8*>(e1 + dy * kP * 64);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][0], b0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][1], b0, acc1, 0, 0, 0);
+                        const bf16x8 b1 = shift_rows(b0, x16);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][0], b1, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][1], b1, acc1, 0, 0, 0);
+                        const bf16x8 b2 = shift_rows(b1, x17);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][0], b2, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][1], b2, acc1, 0, 0, 0);
                     }
+                } else {
+                    // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
+                    const char* a1 = ain + (ry * kP + rx + 1) * 64 + ((lg ^ ((ln + 1) & 3)) << 4);
+                    const char* a2 = ain + (ry * kP + rx + 2) * 64 + ((lg ^ ((ln + 2) & 3)) << 4);
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) {
+                        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
+                        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(a1 + dy * kP * 64);
+                        const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(a2 + dy * kP * 64);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][0], b0, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][1], b0, acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][0], b1, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][1], b1, acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][0], b2, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][1], b2, acc1, 0, 0, 0);
+                    }
+                }
+                if (rx < S) {
+                    const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                    const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                    char* o = aout + (ry * kP + rx) * 64;
+                    *reinterpret_cast<uint2*>(o + out_off[0]) = inside ? relu_pack4(acc0) : make_uint2(0u, 0u);
+                    *reinterpret_cast<uint2*>(o + out_off[1]) = inside ? relu_pack4(acc1) : make_uint2(0u, 0u);
                 }
             }
             __syncthreads();
         }
-        // ---- last layer 32 -> 1: Z[p][t] on region side(NL-1), then gather
+        // ---- last layer 32 -> 1: Z[p][t] on region W(NL-1) x H(NL-1), then gather
         {
-            constexpr int S = G::side(NL - 1);
-            constexpr int npx = S * S, ngr = (npx + 15) / 16;
+            constexpr int S = G::W(NL - 1), HH = G::H(NL - 1);
+            constexpr int ngr = HH * 2;
+            constexpr int ZP = 32;  // Z pixel pitch
             const char* ain = (NH & 1) ? bufB : bufA;
             float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
             for (int gi = wave; gi < ngr; gi += 4) {
-                const int q = min(gi * 16 + ln, npx - 1);
-                const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + act_off(q, lg));
+                const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
+                const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz_in);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bop, acc, 0, 0, 0);
-                if ((gi * 16 + ln) < npx && lg < 3) *reinterpret_cast<floatx4*>(Z + q * 16 + lg * 4) = acc;
+                if (rx < S && lg < 3) *reinterpret_cast<floatx4*>(Z + (ry * ZP + rx) * 16 + lg * 4) = acc;
             }
             __syncthreads();
-            const int oy = tid / kT, ox = tid % kT;
-            const int gy = ty0 + oy, gx = tx0 + ox;
-            if (gy < n && gx < n) {
-                float v = 0.f;
+            for (int e = tid; e < TH * TW; e += kThreads) {
+                const int oy = e / TW, ox = e - (e / TW) * TW;
+                const int gy = ty0 + oy, gx = tx0 + ox;
+                if (gy < n && gx < n) {
+                    const float* zb = Z + (oy * ZP + ox) * 16;
+                    float v = 0.f;
 #pragma unroll
-                for (int t = 0; t < 9; ++t) v += Z[((oy + t / 3) * S + ox + t % 3) * 16 + t];
-                v *= nbf;
-                float* o = out + (size_t)gy * n + gx;
-                *o = accumulate ? *o + v : v;
+                    for (int t = 0; t < 9; ++t) v += zb[((t / 3) * ZP + t % 3) * 16 + t];
+                    v *= nbf;
+                    float* o = out + (size_t)gy * n + gx;
+                    *o = accumulate ? *o + v : v;
+                }
             }
         }
         __syncthreads();
@@ -296,17 +371,19 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
     if (!mfma_supported(c, &why)) return fail(NMG_ERR_STATE, why);
     if (!c->wbf) return fail(NMG_ERR_STATE, "no weights loaded for the BF16 smoother");
     const int n = c->n[(size_t)l];
-    const int tiles_x = (n + kT - 1) / kT;
-    const int tiles = tiles_x * tiles_x;
-    const int per_img = std::max(1, std::min(tiles, (2048 + batch - 1) / batch));
-    dim3 grid((unsigned)per_img, (unsigned)batch);
     const uint16_t* wl = c->wbf + (size_t)l * c->p.n_weight_sets * c->wbf_stride;
     if (c->p.n_layers == 3) {
-        hipLaunchKernelGGL(k_smoother_mfma<3>, grid, dim3(kThreads), Geo<3>::lds, s, b, nrm2, dst, accumulate, wl,
-                           c->wbf_stride, ws, n, tiles_x, tiles);
+        using G = Geo<3>;
+        const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
+        const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
+        hipLaunchKernelGGL((k_smoother_mfma<3, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, n, tiles_x, tiles);
     } else {
-        hipLaunchKernelGGL(k_smoother_mfma<4>, grid, dim3(kThreads), Geo<4>::lds, s, b, nrm2, dst, accumulate, wl,
-                           c->wbf_stride, ws, n, tiles_x, tiles);
+        using G = Geo<4>;
+        const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
+        const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
+        hipLaunchKernelGGL((k_smoother_mfma<4, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, n, tiles_x, tiles);
     }
     NMG_HIP(hipGetLastError());
     return NMG_OK;

@@ -46,9 +46,23 @@ struct Band {
     }
 };
 
+// A band matrix written as a Toeplitz part (coefficients t[d + r] of the
+// interior rows) plus corrections confined to the top-left and bottom-right
+// rc x rc corners: B = T + D_TL + D_BR.  Zero boundary values make the
+// Gaussian factor K^T K differ from its Toeplitz interior only there, and
+// Galerkin products keep that form.
+struct ToeplitzSplit {
+    bool ok = false;
+    int r = 0, rc = 0;
+    std::vector<double> t;        // 2r+1
+    std::vector<double> dtl, dbr; // rc x rc, row-major (row = first index)
+};
+bool split_toeplitz(const Band& B, ToeplitzSplit& out);
+
 struct HostLevel {
     int n = 0;
     Band M, G;
+    ToeplitzSplit Ms, Gs;
 };
 
 // Builds taps, G_1 = K K, M_1 = I and the Galerkin chain; returns false with
@@ -69,6 +83,15 @@ struct LevelBuffers {
     T* t2 = nullptr;  // axis-pass temporary
 };
 
+// Device form of a level's operator for the tiled residual kernel.
+template <typename T>
+struct TiledOp {
+    bool ok = false;
+    int rg = 0, rgp = 0, rc = 0, rm = 0, rmp = 0, m_ident = 0;
+    T *tg = nullptr, *dtl = nullptr, *dbr = nullptr, *tm = nullptr;  // into one allocation
+    T* base = nullptr;
+};
+
 template <typename T>
 struct Work {
     bool ready = false;
@@ -81,6 +104,7 @@ struct Work {
     T* dct = nullptr;    // per level DCT-II matrices [n][n], concatenated
     std::vector<size_t> dct_off;
     T* wts = nullptr;    // smoother weights in this precision [L-1][sets][count]
+    std::vector<TiledOp<T>> tiled;
 };
 
 struct Ctx {
@@ -104,6 +128,8 @@ struct Ctx {
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     std::vector<int> adam_step;        // per set
+    uint16_t* dctbf = nullptr;         // BF16 DCT-II matrices C and C^T per level (padded)
+    std::vector<size_t> dctbf_off;
     uint16_t* wbf = nullptr;           // BF16 MFMA-packed weights
     size_t wbf_stride = 0;             // per (level, set)
     // coarse solve
@@ -112,12 +138,17 @@ struct Ctx {
     double* Gc = nullptr;
     double* chol = nullptr;            // [max_batch][nc][nc] lower factor, row-major
     double* cholT = nullptr;           // [max_batch][nc][nc] its transpose
+    double* cinv = nullptr;            // [max_batch][nc][nc] A_L^{-1} (FP32 / mixed cycles)
+    double* cwork = nullptr;           // [max_batch][nc][nc] L^{-1} scratch
     int* flags = nullptr;              // [max_batch] non-SPD / non-finite flags
     double* alpha_prepared = nullptr;  // [max_batch] device copy of factored alphas
     // norms and scratch
     double* nrm = nullptr;             // [max_batch] per right-hand-side norms
     double* nrm2 = nullptr;            // [max_batch] second norm slot
+    double* norm_part = nullptr;       // [max_batch][kNormChunksPerRhs] partial sums
     double* x64 = nullptr;             // [max_batch][ny][n] refinement scratch
+    float* xs32 = nullptr;             // [max_batch][ny][n] plain-FP32 iterate
+    float* bs32 = nullptr;             // [max_batch][ny][n] plain-FP32 right-hand side
     double* r64 = nullptr;
     double* hist_dev = nullptr;        // [max_batch] residual snapshot
     int* active = nullptr;             // [max_batch]
@@ -127,7 +158,7 @@ struct Ctx {
     Work<float> w32b;
     bool grad_is_fp64 = false;         // which gradient buffer the last loss_grad filled
     // profiler
-    bool prof_on = false;
+    int prof_mask = 0;  // bit k: time kernel family k
     struct ProfEv { hipEvent_t a, b; int kind, level; };
     std::vector<ProfEv> prof_pending;
     std::vector<hipEvent_t> prof_pool;
@@ -162,8 +193,9 @@ size_t level_elems(const Ctx* c, int l);  // ny_l * n_l
 template <typename T>
 nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y,
                            T* out, int mode, Work<T>& w, hipStream_t s);
+constexpr int kNormChunksPerRhs = 32;
 template <typename T>
-nmg_status launch_sumsq(int batch, size_t elems, const T* v, double* out, hipStream_t s);
+nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s);
 template <typename T>
 nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s);
 template <typename T>
@@ -186,8 +218,14 @@ nmg_status launch_jacobi(const Ctx* c, int l, int batch, const double* alpha, do
 template <typename T>
 nmg_status launch_fprime(const Ctx* c, int l, int batch, const T* h, T* dst, int accumulate, Work<T>& w,
                          hipStream_t s);
+nmg_status prepare_fprime_bf16(Ctx* c);
+nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, float* dst, int accumulate, float* t1,
+                              float* t2, hipStream_t s);
 nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
 nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStream_t s);
+nmg_status launch_coarse_inverse(Ctx* c, int batch, hipStream_t s);
+template <typename T>
+nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);
 template <typename T>
 nmg_status launch_coarse_solve(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);
 template <typename T>

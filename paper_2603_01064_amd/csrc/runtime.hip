@@ -8,6 +8,7 @@
 // the same smoother; the coarsest level is solved exactly by Cholesky.
 // The recursion is unrolled on the host into a fixed launch sequence.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -71,7 +72,7 @@ static hipEvent_t prof_event(Ctx* c) {
 }
 
 ProfScope::ProfScope(const Ctx* cc, hipStream_t ss, int k, int l) : c(const_cast<Ctx*>(cc)), s(ss), kind(k), level(l) {
-    if (!c->prof_on) return;
+    if (!(c->prof_mask & (1 << k))) return;
     a = prof_event(c);
     b = prof_event(c);
     if (a && b) (void)hipEventRecord(a, s);
@@ -167,6 +168,43 @@ nmg_status ensure_work(Ctx* c) {
     NMG_TRY(upload(w.Gd, G));
     NMG_TRY(upload(w.Md, M));
     NMG_TRY(upload(w.dct, D));
+    // tiled-residual tables: Toeplitz taps padded to a multiple of 4, corner blocks
+    w.tiled.assign((size_t)c->L, TiledOp<T>{});
+    for (int l = 0; l < c->L; ++l) {
+        const HostLevel& hl = c->host[(size_t)l];
+        TiledOp<T>& op = w.tiled[(size_t)l];
+        if (c->p.dim != 2 || !hl.Gs.ok || !hl.Ms.ok || hl.Ms.rc != 0) continue;
+        const int rg = hl.Gs.r, rm = hl.Ms.r;
+        const int rgp = ((2 * rg + 1) + 3) / 4 * 4, rmp = ((2 * rm + 1) + 3) / 4 * 4;
+        // LDS bound (TH = 32): staged tile + row-pass buffers must fit in 160 KB
+        const int TW = sizeof(T) == 4 ? 64 : 32;
+        const int TH = 64;
+        const size_t lds = ((size_t)(TH + 2 * rg) * (TW + rgp) + (size_t)(TH + rgp) * TW +
+                            (l == 0 ? 0 : (size_t)(TH + rmp) * TW)) * sizeof(T);
+        if (lds > 160 * 1024 || TW + rgp > 256) continue;
+        std::vector<double> tab;
+        std::vector<double> tgv(hl.Gs.t), tmv(hl.Ms.t);
+        tgv.resize((size_t)rgp, 0.0);
+        tmv.resize((size_t)rmp, 0.0);
+        const size_t o_tg = 0, o_tm = o_tg + rgp, o_dtl = o_tm + rmp, o_dbr = o_dtl + hl.Gs.dtl.size();
+        tab.insert(tab.end(), tgv.begin(), tgv.end());
+        tab.insert(tab.end(), tmv.begin(), tmv.end());
+        tab.insert(tab.end(), hl.Gs.dtl.begin(), hl.Gs.dtl.end());
+        tab.insert(tab.end(), hl.Gs.dbr.begin(), hl.Gs.dbr.end());
+        NMG_TRY(dev_alloc(&op.base, tab.size()));
+        NMG_TRY(upload(op.base, tab));
+        op.tg = op.base + o_tg;
+        op.tm = op.base + o_tm;
+        op.dtl = op.base + o_dtl;
+        op.dbr = op.base + o_dbr;
+        op.rg = rg;
+        op.rgp = rgp;
+        op.rc = hl.Gs.rc;
+        op.rm = rm;
+        op.rmp = rmp;
+        op.m_ident = (l == 0) ? 1 : 0;
+        op.ok = true;
+    }
     if (std::is_same<T, double>::value) {
         const size_t wn = (size_t)std::max(1, c->L - 1) * c->p.n_weight_sets * c->wcount;
         NMG_TRY(dev_alloc(&w.wts, wn));
@@ -199,6 +237,8 @@ void free_work(Ctx* c, Work<T>& w) {
     dev_free(w.Gd);
     dev_free(w.Md);
     dev_free(w.dct);
+    for (auto& op : w.tiled) dev_free(op.base);
+    w.tiled.clear();
     if (std::is_same<T, double>::value) dev_free(w.wts);
     w.wts = nullptr;
     w.ready = false;
@@ -259,7 +299,7 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
     } else {
         {
             ProfScope ps(c, a.s, NMG_K_NORM, l);
-            NMG_TRY(launch_sumsq<T>(a.batch, per, bres, c->nrm, a.s));
+            NMG_TRY(launch_sumsq<T>(c, a.batch, per, bres, c->nrm, a.s));
         }
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
         if (a.o.precision == NMG_MIXED) {
@@ -272,7 +312,15 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
     }
     if (a.o.use_fprime) {
         ProfScope ps(c, a.s, NMG_K_FPRIME, l);
-        NMG_TRY(launch_fprime<T>(c, l, a.batch, w.lv[(size_t)l].h, x, x_zero ? 0 : 1, w, a.s));
+        if (a.o.precision == NMG_MIXED && c->p.dim == 2) {
+            NMG_TRY(prepare_fprime_bf16(c));
+            NMG_TRY(launch_fprime_mfma(c, l, a.batch, reinterpret_cast<const float*>(w.lv[(size_t)l].h),
+                                       reinterpret_cast<float*>(x), x_zero ? 0 : 1,
+                                       reinterpret_cast<float*>(w.lv[(size_t)l].t1),
+                                       reinterpret_cast<float*>(w.lv[(size_t)l].t2), a.s));
+        } else {
+            NMG_TRY(launch_fprime<T>(c, l, a.batch, w.lv[(size_t)l].h, x, x_zero ? 0 : 1, w, a.s));
+        }
     }
     return NMG_OK;
 }
@@ -283,7 +331,8 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
     Work<T>& w = *a.w;
     if (l == c->L - 1) {
         ProfScope ps(c, a.s, NMG_K_COARSE, l);
-        return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
+        if (a.o.precision == NMG_FP64) return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
+        return launch_coarse_apply_inverse<T>(c, a.batch, y, x, a.s);
     }
     const size_t per = level_elems(c, l);
     if (x_zero && a.o.nu1 == 0) {
@@ -394,14 +443,19 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(upload(c->Gc, Gc));
     NMG_TRY(dev_alloc(&c->chol, (size_t)B * c->nc * c->nc));
     NMG_TRY(dev_alloc(&c->cholT, (size_t)B * c->nc * c->nc));
+    NMG_TRY(dev_alloc(&c->cinv, (size_t)B * c->nc * c->nc));
+    NMG_TRY(dev_alloc(&c->cwork, (size_t)B * c->nc * c->nc));
     NMG_TRY(dev_alloc(&c->flags, (size_t)B));
     NMG_TRY(dev_alloc(&c->alpha_prepared, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
+    NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kNormChunksPerRhs));
     NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
     NMG_TRY(dev_alloc(&c->active, (size_t)B));
     NMG_TRY(dev_alloc(&c->x64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->xs32, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->bs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->loss_dev, (size_t)nsm));
     NMG_HIP(hipDeviceSynchronize());
     *out = c.release();
@@ -424,18 +478,24 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->adam_m);
     dev_free(c->adam_v);
     dev_free(c->wbf);
+    dev_free(c->dctbf);
     dev_free(c->Mc);
     dev_free(c->Gc);
     dev_free(c->chol);
     dev_free(c->cholT);
+    dev_free(c->cinv);
+    dev_free(c->cwork);
     dev_free(c->flags);
     dev_free(c->alpha_prepared);
     dev_free(c->nrm);
     dev_free(c->nrm2);
+    dev_free(c->norm_part);
     dev_free(c->hist_dev);
     dev_free(c->active);
     dev_free(c->x64);
     dev_free(c->r64);
+    dev_free(c->xs32);
+    dev_free(c->bs32);
     dev_free(c->loss_dev);
     delete h;
 }
@@ -493,6 +553,7 @@ nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha, void* strea
     hipStream_t s = (hipStream_t)stream;
     NMG_HIP(hipMemcpyAsync(h->alpha_prepared, alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToDevice, s));
     NMG_TRY(launch_coarse_factor(h, batch, h->alpha_prepared, s));
+    NMG_TRY(launch_coarse_inverse(h, batch, s));
     std::vector<int> flags((size_t)batch);
     std::vector<double> al((size_t)batch);
     NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -537,7 +598,7 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
         double* oo = (double*)out;
         if (h->kind[(size_t)level] == 1)
             return launch_jacobi<double>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w64, s);
-        NMG_TRY(launch_sumsq<double>(batch, per, bb, h->nrm, s));
+        NMG_TRY(launch_sumsq<double>(h, batch, per, bb, h->nrm, s));
         return launch_conv_smoother<double>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w64, s);
     }
     NMG_TRY(ensure_work<float>(h));
@@ -545,9 +606,29 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
     float* oo = (float*)out;
     if (h->kind[(size_t)level] == 1)
         return launch_jacobi<float>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w32b, s);
-    NMG_TRY(launch_sumsq<float>(batch, per, bb, h->nrm, s));
+    NMG_TRY(launch_sumsq<float>(h, batch, per, bb, h->nrm, s));
     if (prec == NMG_MIXED) return launch_mfma_smoother(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
     return launch_conv_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
+}
+
+nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, void* out, nmg_precision prec,
+                            void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    if (!in || !out) return fail(NMG_ERR_ARG, "null pointer");
+    if (level < 0 || level >= h->L) return fail(NMG_ERR_ARG, "level out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == NMG_FP64) {
+        NMG_TRY(ensure_work<double>(h));
+        return launch_fprime<double>(h, level, batch, (const double*)in, (double*)out, 0, h->w64, s);
+    }
+    NMG_TRY(ensure_work<float>(h));
+    if (prec == NMG_MIXED && h->p.dim == 2) {
+        NMG_TRY(prepare_fprime_bf16(h));
+        return launch_fprime_mfma(h, level, batch, (const float*)in, (float*)out, 0, h->w32b.lv[(size_t)level].t1,
+                                  h->w32b.lv[(size_t)level].t2, s);
+    }
+    return launch_fprime<float>(h, level, batch, (const float*)in, (float*)out, 0, h->w32b, s);
 }
 
 nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* ws, const void* y, void* x,
@@ -564,7 +645,10 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* w
 
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws, const double* b, double* x,
                      double rtol, int max_cycles, const nmg_cycle_opts* o, int* cycles_host, double* history_host,
-                     void* stream) {
+                     double* done_ms_host, void* stream) {
+    const auto t_entry = std::chrono::steady_clock::now();
+    if (done_ms_host)
+        for (int i = 0; i < batch && i < (h ? h->p.max_batch : 0); ++i) done_ms_host[i] = -1.0;
     NMG_TRY(check_handle(h));
     NMG_TRY(check_batch(h, batch));
     NMG_TRY(check_opts(h, o));
@@ -577,11 +661,9 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     NMG_TRY(ensure_work<double>(h));
     const bool plain32 = o->precision == NMG_FP32;
     if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
-    float* xs = h->w32b.ready ? h->w32b.lv[0].h : nullptr;  // plain FP32 iterate
-    float* bs = h->w32b.ready ? h->w32b.lv[0].b : nullptr;  // plain FP32 right-hand side
-    float* r32 = h->w32b.ready ? h->w32b.lv[0].t1 : nullptr;
-    (void)r32;
-    // plain FP32 keeps its own iterate; the residual buffer of level 0 is reused
+    // plain FP32 keeps its own iterate and right-hand side; its residual lives in r64's storage
+    float* xs = h->xs32;
+    float* bs = h->bs32;
     float* rs = nullptr;
     if (plain32) {
         NMG_TRY(launch_convert<double, float>(b, bs, cnt, s));
@@ -590,7 +672,7 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     } else {
         NMG_TRY(launch_zero<double>(x, cnt, s));
     }
-    NMG_TRY(launch_sumsq<double>(batch, per, b, h->nrm2, s));
+    NMG_TRY(launch_sumsq<double>(h, batch, per, b, h->nrm2, s));
     std::vector<double> bn2((size_t)batch), rn2((size_t)batch);
     NMG_HIP(hipMemcpyAsync(bn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
     double* bn2_dev = h->hist_dev;
@@ -610,15 +692,15 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
             ProfScope ps(h, s, NMG_K_REFINE, 0);
             if (plain32) {
                 NMG_TRY(launch_operator<float>(h, 0, batch, alpha, xs, bs, rs, 0, h->w32b, s));
-                NMG_TRY(launch_sumsq<float>(batch, per, rs, h->nrm2, s));
+                NMG_TRY(launch_sumsq<float>(h, batch, per, rs, h->nrm2, s));
             } else {
                 NMG_TRY(launch_operator<double>(h, 0, batch, alpha, x, b, h->r64, 0, h->w64, s));
-                NMG_TRY(launch_sumsq<double>(batch, per, h->r64, h->nrm2, s));
+                NMG_TRY(launch_sumsq<double>(h, batch, per, h->r64, h->nrm2, s));
             }
         }
         NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
         NMG_HIP(hipStreamSynchronize(s));
-        if (h->prof_on) NMG_TRY(prof_resolve(h));
+        if (h->prof_mask) NMG_TRY(prof_resolve(h));
         bool any = false;
         for (int i = 0; i < batch; ++i) {
             if (done[(size_t)i]) continue;
@@ -631,6 +713,9 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
             if (history_host) history_host[(size_t)i * (max_cycles + 1) + it] = bb > 0 ? std::sqrt(r / bb) : 0.0;
             if (!(r > tol2 * bb)) {
                 done[(size_t)i] = 1;
+                if (done_ms_host)
+                    done_ms_host[i] =
+                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
                 continue;
             }
             if (it == max_cycles) continue;
@@ -697,7 +782,7 @@ nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* id
 nmg_status nmg_profile_enable(nmg_handle h, int on) {
     NMG_TRY(check_handle(h));
     NMG_TRY(prof_resolve(h));
-    h->prof_on = on != 0;
+    h->prof_mask = on;
     for (auto& row : h->prof_ms)
         for (auto& v : row) v = 0.0;
     for (auto& row : h->prof_cnt)

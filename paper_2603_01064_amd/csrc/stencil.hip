@@ -79,14 +79,19 @@ __global__ void __launch_bounds__(kBlock) k_colcombine(const T* __restrict__ tg,
     out[base + e] = (mode == 0) ? (y[base + e] - ax) : ax;
 }
 
-// Per right-hand-side sum of squares in FP64, fixed reduction order.
+// Per right-hand-side sum of squares in FP64 with a fixed reduction order:
+// stage 1 writes one partial per (chunk, rhs), stage 2 adds the chunks.
+constexpr int kNormChunks = kNormChunksPerRhs;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sumsq(const T* __restrict__ v, double* __restrict__ out, size_t per) {
+__global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, double* __restrict__ part, size_t per) {
     __shared__ double red[kBlock];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y, ch = blockIdx.x;
+    const size_t len = (per + kNormChunks - 1) / kNormChunks;
+    const size_t e0 = (size_t)ch * len, e1 = e0 + len < per ? e0 + len : per;
     const T* p = v + (size_t)b * per;
     double acc = 0.0;
-    for (size_t e = threadIdx.x; e < per; e += kBlock) {
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
         const double t = (double)p[e];
         acc += t * t;
     }
@@ -96,7 +101,15 @@ __global__ void __launch_bounds__(kBlock) k_sumsq(const T* __restrict__ v, doubl
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[b] = red[0];
+    if (threadIdx.x == 0) part[(size_t)b * kNormChunks + ch] = red[0];
+}
+
+__global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double acc = 0.0;
+    for (int c = 0; c < kNormChunks; ++c) acc += part[(size_t)b * kNormChunks + c];
+    out[b] = acc;
 }
 
 // Full weighting: coarse node i reads fine nodes 2i, 2i+1, 2i+2 (1/4, 1/2, 1/4).
@@ -229,9 +242,187 @@ __global__ void __launch_bounds__(kBlock) k_convert(const A* __restrict__ src, B
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// ---------------------------------------------------------------------------
+// Tiled residual: one workgroup per TH x TW output tile of one right-hand
+// side.  Each factor is split into a Toeplitz interior (wave-uniform
+// coefficients, zero-padded to a multiple of 4 taps) plus rc x rc corner
+// corrections.  The input tile with a halo of rg rows/columns is staged in
+// LDS, the row pass X G (and X M) is evaluated for the tile columns on every
+// halo row, and the column pass G (X G) forms y - A x.  Each thread keeps
+// four outputs in registers and slides a window of eight inputs over the
+// taps, so every LDS read feeds four FMAs.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ inline Vec4<T> lds_load4(const T* p) {
+    Vec4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+    }
+    return r;
+}
+
+// acc[o] += sum_t c[t] * row[base + o + t], o = 0..3, t < tp (tp % 4 == 0),
+// stride = distance between consecutive elements of `row`.
+template <typename T, bool CONTIG>
+__device__ inline void slide4(const T* __restrict__ row, int stride, const T* __restrict__ c, int tp, T acc[4]) {
+    T w[8];
+    if constexpr (CONTIG) {
+        const Vec4<T> a = lds_load4<T>(row);
+        for (int k = 0; k < 4; ++k) w[k] = a.v[k];
+    } else {
+        for (int k = 0; k < 4; ++k) w[k] = row[k * stride];
+    }
+    for (int t4 = 0; t4 < tp; t4 += 4) {
+        if constexpr (CONTIG) {
+            const Vec4<T> b = lds_load4<T>(row + t4 + 4);
+            for (int k = 0; k < 4; ++k) w[4 + k] = b.v[k];
+        } else {
+            for (int k = 0; k < 4; ++k) w[4 + k] = row[(t4 + 4 + k) * stride];
+        }
+        const T c0 = c[t4], c1 = c[t4 + 1], c2 = c[t4 + 2], c3 = c[t4 + 3];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[o] += c0 * w[o] + c1 * w[o + 1] + c2 * w[o + 2] + c3 * w[o + 3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = w[4 + k];
+    }
+}
+
+template <typename T, int TH, int TW>
+__global__ void __launch_bounds__(kBlock) k_residual_tiled(
+    const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ out, const double* __restrict__ alpha, int n,
+    int mode, const T* __restrict__ tg, int rg, int rgp, const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
+    const T* __restrict__ tm, int rm, int rmp, int m_ident, int tiles_x) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int XW = TW + rgp;           // staged columns: image j0 - rg + c
+    const int XH = TH + 2 * rg;        // staged rows:    image i0 - rg + r
+    const int GH = TH + rgp;           // rows of X G (zero beyond XH)
+    const int MH = TH + rmp;           // rows of X M
+    T* X = sm;
+    T* TGs = X + (size_t)XH * XW;
+    T* TMs = TGs + (size_t)GH * TW;
+    const int b = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int i0 = (tile / tiles_x) * TH, j0 = (tile % tiles_x) * TW;
+    const size_t per = (size_t)n * n;
+    const T* xs = x + (size_t)b * per;
+    const int tid = threadIdx.x;
+    {
+        // staging: 4 rows x 64 columns per pass, UNR passes of loads in flight
+        // before their LDS stores (no integer division)
+        constexpr int UNR = 8, KC = 4;  // XW <= 64 * KC (checked on the host)
+        const int ty = tid >> 6, tx = tid & 63;
+        for (int r0 = ty; r0 < XH; r0 += 4 * UNR) {
+            T v[UNR][KC];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int r = r0 + 4 * u;
+                const int gi = i0 - rg + r;
+                const bool row_in = r < XH && gi >= 0 && gi < n;
+                const T* src = xs + (size_t)(row_in ? gi : 0) * n;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int c = tx + 64 * k;
+                    const int gj = j0 - rg + c;
+                    v[u][k] = (row_in && c < XW && gj >= 0 && gj < n) ? src[gj] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int r = r0 + 4 * u;
+                if (r < XH) {
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (tx + 64 * k < XW) X[r * XW + tx + 64 * k] = v[u][k];
+                }
+            }
+        }
+    }
+    for (int e = tid + XH * TW; e < GH * TW; e += kBlock) TGs[e] = 0;
+    if (!m_ident)
+        for (int e = tid + (TH + 2 * rm) * TW; e < MH * TW; e += kBlock) TMs[e] = 0;
+    __syncthreads();
+    // ---- row passes
+    constexpr int CG = TW / 4;
+    for (int item = tid; item < XH * CG; item += kBlock) {
+        const int r = item / CG, jj = (item % CG) * 4;
+        T acc[4] = {0, 0, 0, 0};
+        slide4<T, true>(X + (size_t)r * XW + jj, 1, tg, rgp, acc);
+        const int j = j0 + jj;
+        if (rc > 0 && (j < rc || j + 3 >= n - rc)) {
+            for (int o = 0; o < 4; ++o) {
+                const int jo = j + o;
+                if (jo < rc) {
+                    T s2 = 0;
+                    for (int q = 0; q < rc; ++q) s2 += dtl[q * rc + jo] * X[(size_t)r * XW + (q - j0 + rg)];
+                    acc[o] += s2;
+                } else if (jo >= n - rc && jo < n) {
+                    T s2 = 0;
+                    const int jb = jo - (n - rc);
+                    for (int q = 0; q < rc; ++q) s2 += dbr[q * rc + jb] * X[(size_t)r * XW + (n - rc + q - j0 + rg)];
+                    acc[o] += s2;
+                }
+            }
+        }
+        for (int o = 0; o < 4; ++o) TGs[(size_t)r * TW + jj + o] = acc[o];
+    }
+    if (!m_ident) {
+        const int RH = TH + 2 * rm;
+        for (int item = tid; item < RH * CG; item += kBlock) {
+            const int r = item / CG, jj = (item % CG) * 4;
+            T acc[4] = {0, 0, 0, 0};
+            slide4<T, false>(X + (size_t)(rg - rm + r) * XW + jj + rg - rm, 1, tm, rmp, acc);
+            for (int o = 0; o < 4; ++o) TMs[(size_t)r * TW + jj + o] = acc[o];
+        }
+    }
+    __syncthreads();
+    // ---- column pass and combination
+    const T a = (T)alpha[b];
+    for (int item = tid; item < (TH / 4) * TW; item += kBlock) {
+        const int ii = (item / TW) * 4, jj = item % TW;
+        const int j = j0 + jj;
+        T g4[4] = {0, 0, 0, 0}, m4[4] = {0, 0, 0, 0};
+        slide4<T, false>(TGs + (size_t)ii * TW + jj, TW, tg, rgp, g4);
+        if (m_ident) {
+            for (int o = 0; o < 4; ++o) m4[o] = X[(size_t)(ii + o + rg) * XW + jj + rg];
+        } else {
+            slide4<T, false>(TMs + (size_t)ii * TW + jj, TW, tm, rmp, m4);
+        }
+        for (int o = 0; o < 4; ++o) {
+            const int i = i0 + ii + o;
+            if (i >= n || j >= n) continue;
+            T corr = 0;
+            if (i < rc) {
+                for (int p = 0; p < rc; ++p) corr += dtl[i * rc + p] * TGs[(size_t)(p - i0 + rg) * TW + jj];
+            } else if (i >= n - rc) {
+                const int ib = i - (n - rc);
+                for (int p = 0; p < rc; ++p) corr += dbr[ib * rc + p] * TGs[(size_t)(n - rc + p - i0 + rg) * TW + jj];
+            }
+            const T ax = a * m4[o] + (g4[o] + corr);
+            const size_t idx = (size_t)b * per + (size_t)i * n + j;
+            out[idx] = mode == 0 ? y[idx] - ax : ax;
+        }
+    }
+}
+
 }  // namespace
 
 size_t level_elems(const Ctx* c, int l) { return (size_t)(c->p.dim == 2 ? c->n[l] : 1) * c->n[l]; }
+
+template <typename T>
+constexpr int tile_w() { return sizeof(T) == 4 ? 64 : 32; }
+template <typename T>
+constexpr int tile_h() { return 64; }
 
 template <typename T>
 nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y, T* out,
@@ -239,6 +430,18 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
     const int n = c->n[l];
     const size_t per = level_elems(c, l);
     const HostLevel& hl = c->host[l];
+    const TiledOp<T>& op = w.tiled[(size_t)l];
+    if (c->p.dim == 2 && op.ok) {
+        constexpr int TH = tile_h<T>(), TW = tile_w<T>();
+        const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
+        const int XW = TW + op.rgp, XH = TH + 2 * op.rg, GH = TH + op.rgp, MH = TH + op.rmp;
+        const size_t lds = ((size_t)XH * XW + (size_t)GH * TW + (op.m_ident ? 0 : (size_t)MH * TW)) * sizeof(T);
+        hipLaunchKernelGGL((k_residual_tiled<T, TH, TW>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, x, y,
+                           out, alpha, n, mode, op.tg, op.rg, op.rgp, op.dtl, op.dbr, op.rc, op.tm, op.rm, op.rmp,
+                           op.m_ident, tiles_x);
+        NMG_HIP(hipGetLastError());
+        return NMG_OK;
+    }
     const T* G = w.Gd + w.g_off[l];
     const T* M = w.Md + w.m_off[l];
     dim3 grid(blocks_for(per), batch);
@@ -251,8 +454,10 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
 }
 
 template <typename T>
-nmg_status launch_sumsq(int batch, size_t elems, const T* v, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sumsq<T>, dim3(batch), dim3(kBlock), 0, s, v, out, elems);
+nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s) {
+    double* part = c->norm_part;
+    hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, part, elems);
+    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -323,7 +528,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
 #define NMG_INST(T)                                                                                              \
     template nmg_status launch_operator<T>(const Ctx*, int, int, const double*, const T*, const T*, T*, int,     \
                                            Work<T>&, hipStream_t);                                               \
-    template nmg_status launch_sumsq<T>(int, size_t, const T*, double*, hipStream_t);                            \
+    template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t);                \
     template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                     \
     template nmg_status launch_prolong_transpose<T>(const Ctx*, int, int, const T*, T*, hipStream_t);            \
     template nmg_status launch_prolong_add<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                  \

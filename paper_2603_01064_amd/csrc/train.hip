@@ -467,7 +467,7 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
     NMG_TRY(launch_operator<T>(c, 0, batch, alpha, e, nullptr, tw.b[0], 1, work, s));
     for (int l = 0; l < nsm; ++l) {
         const size_t per = level_elems(c, l);
-        NMG_TRY(launch_sumsq<T>(batch, per, tw.b[(size_t)l], tw.nrm[(size_t)l], s));
+        NMG_TRY(launch_sumsq<T>(c, batch, per, tw.b[(size_t)l], tw.nrm[(size_t)l], s));
         if (mixed) {
             NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
                                          tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,

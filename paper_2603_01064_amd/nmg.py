@@ -64,8 +64,9 @@ def load_library():
         "nmg_prepare": (S, [P, I, P, P]),
         "nmg_apply_operator": (S, [P, I, I, P, P, P, I, P]),
         "nmg_apply_smoother": (S, [P, I, I, P, P, P, P, I, P]),
+        "nmg_apply_fprime": (S, [P, I, I, P, P, I, P]),
         "nmg_vcycle": (S, [P, I, P, P, P, P, ctypes.POINTER(_CycleOpts), P]),
-        "nmg_solve": (S, [P, I, P, P, P, P, D, I, ctypes.POINTER(_CycleOpts), P, P, P]),
+        "nmg_solve": (S, [P, I, P, P, P, P, D, I, ctypes.POINTER(_CycleOpts), P, P, P, P]),
         "nmg_loss_grad": (S, [P, I, I, P, P, I, I, I, I, P, P]),
         "nmg_get_gradient": (S, [P, I, I, P, Z]),
         "nmg_adam_step": (S, [P, I, D, D, D, D, P]),
@@ -220,6 +221,16 @@ class Handle:
                                        _stream()))
         return out
 
+    def apply_fprime(self, level: int, h, precision: str = "fp64"):
+        """``F'_l(h)`` on level ``level``."""
+        import torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        B = h.shape[0]
+        _require(h, dt, self.level_shape(level, B), "h")
+        out = torch.empty_like(h)
+        _check(_lib.nmg_apply_fprime(self.ptr, level, B, _ptr(h), _ptr(out), PRECISION[precision], _stream()))
+        return out
+
     def vcycle(self, y, x, alpha, weight_set=None, nu1: int = 1, nu2: int = 1, use_fprime: bool = False,
                precision: str = "fp64"):
         """In-place ``x <- MG(x, y)``; call ``prepare(alpha)`` first."""
@@ -239,8 +250,10 @@ class Handle:
         return x
 
     def solve(self, b, alpha, weight_set=None, rtol: float = 1e-6, max_cycles: int = 100, nu1: int = 1,
-              nu2: int = 1, use_fprime: bool = False, precision: str = "mixed", x=None, history: bool = False):
-        """Returns ``(x, cycles, history_or_None, status)``."""
+              nu2: int = 1, use_fprime: bool = False, precision: str = "mixed", x=None, history: bool = False,
+              done_ms=None):
+        """Returns ``(x, cycles, history_or_None, status)``; ``done_ms`` (a float64
+        NumPy array of length B) receives per right-hand-side convergence times."""
         import torch
         B = alpha.numel()
         shape = self.level_shape(0, B)
@@ -259,7 +272,8 @@ class Handle:
         st = _check(_lib.nmg_solve(self.ptr, B, _ptr(alpha), ws, _ptr(b), _ptr(x), float(rtol), int(max_cycles),
                                    ctypes.byref(o), cycles.ctypes.data_as(ctypes.c_void_p),
                                    hist.ctypes.data_as(ctypes.c_void_p) if hist is not None else ctypes.c_void_p(),
-                                   _stream()))
+                                   done_ms.ctypes.data_as(ctypes.c_void_p) if done_ms is not None
+                                   else ctypes.c_void_p(), _stream()))
         return x, cycles, hist, st
 
     # -- training ----------------------------------------------------------
@@ -302,8 +316,12 @@ class Handle:
     KERNELS = {"smoother": 0, "operator": 1, "restrict": 2, "prolong": 3, "coarse": 4, "fprime": 5, "refine": 6,
                "norm": 7}
 
-    def profile_enable(self, on: bool = True) -> None:
-        _check(_lib.nmg_profile_enable(self.ptr, 1 if on else 0))
+    def profile_enable(self, kinds=("smoother",)) -> None:
+        """Times the given kernel families (empty: profiling off)."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << self.KERNELS[k]
+        _check(_lib.nmg_profile_enable(self.ptr, mask))
 
     def profile_query(self, kind: str, level: int = -1):
         """``(total_ms, launches)`` of one kernel family (level -1: all levels)."""

@@ -52,7 +52,7 @@ def load_weights(path: str):
 
 
 def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: torch.Generator,
-            precision: str) -> torch.Tensor:
+            precision: str, use_fprime: bool = False) -> torch.Tensor:
     """DataGeneration of Algorithm 5: each sample is run through k ~ U{0..K}
     cycles of the current smoothers (e <- e - NMG(0, A e)) without gradients;
     samples are rescaled to unit RMS so every batch has the same scale."""
@@ -64,7 +64,7 @@ def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: to
     for j in range(K):
         y = h.apply_operator(0, e, alpha, precision="fp32")
         d = torch.zeros_like(e)
-        h.vcycle(y, d, alpha, nu1=1, nu2=0, precision=precision)
+        h.vcycle(y, d, alpha, nu1=1, nu2=0, use_fprime=use_fprime, precision=precision)
         upd = (ks > j).to(e.dtype).reshape(B, 1, 1)
         e = e - upd * d
     rms = e.reshape(B, -1).norm(dim=1) / (e[0].numel() ** 0.5)
@@ -72,7 +72,7 @@ def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: to
 
 
 def train_set(h: nmg.Handle, alpha_value: float, steps: int, batch: int, lr: float, mask: str, seed: int,
-              rollout_K: int = 0, log_every: int = 100, precision: str = "fp32"):
+              rollout_K: int = 0, log_every: int = 100, precision: str = "fp32", use_fprime: bool = False):
     dev = torch.device("cuda:0")
     n = h.problem.n
     alpha = torch.full((batch,), alpha_value, dtype=torch.float64, device=dev)
@@ -81,14 +81,31 @@ def train_set(h: nmg.Handle, alpha_value: float, steps: int, batch: int, lr: flo
     t0 = time.time()
     for step in range(steps):
         e = torch.randn((batch, n, n), generator=gen, dtype=torch.float32).to(dev)
-        e = rollout(h, e, alpha, rollout_K, gen, "mixed" if precision == "mixed" else "fp32")
+        e = rollout(h, e, alpha, rollout_K, gen, "mixed" if precision == "mixed" else "fp32", use_fprime)
         cur_lr = lr * (0.1 ** (step / max(1, steps)))  # decays by 10x over the run
-        losses = h.train_step(e, alpha, mask=mask, precision=precision, lr=cur_lr)
+        losses = h.train_step(e, alpha, mask=mask, use_fprime=use_fprime, precision=precision, lr=cur_lr)
         hist.append(losses.tolist())
         if log_every and step % log_every == 0:
             print(f"  alpha={alpha_value:g} step {step} losses {np.array2string(losses, precision=3)} "
                   f"({time.time() - t0:.1f}s)", flush=True)
     return hist
+
+
+def evaluate(h: nmg.Handle, alpha_value: float, batch: int, nu1: int, nu2: int, use_fprime: bool,
+             max_cycles: int = 100, seed: int = 2000):
+    """Cycles to 1e-6 of the mixed-precision solve on box images (the 2D
+    deblurring right-hand sides) with the handle's weight set 0."""
+    dev = torch.device("cuda:0")
+    n = h.problem.n
+    alpha = torch.full((batch,), alpha_value, dtype=torch.float64, device=dev)
+    u = torch.tensor(np.stack([inputs.boxes_image(n, seed + i) for i in range(batch)]), device=dev)
+    b = h.apply_operator(0, u, alpha, "fp64")
+    try:
+        _, cyc, hist, st = h.solve(b, alpha, rtol=1e-6, max_cycles=max_cycles, nu1=nu1, nu2=nu2,
+                                   use_fprime=use_fprime, precision="mixed", history=True)
+    except nmg.NMGError as e:
+        return None, str(e)
+    return cyc, st
 
 
 def main(argv=None):
@@ -106,22 +123,40 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--seed", type=int, default=7000)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--init", default=None, help="npz written by this script; its last set initialises training")
+    ap.add_argument("--fprime", action="store_true", help="train with F' in the loss (eq. loss_2_modified)")
+    ap.add_argument("--steps-per-alpha", type=int, nargs="+", default=None)
     a = ap.parse_args(argv)
     nmg.load_library()
     prob = nmg.Problem(n=a.n, s=a.s, levels=a.levels, dim=2, max_batch=a.batch, channels=tuple(a.channels),
                        ksize=3, n_weight_sets=1)
     h = nmg.setup_hierarchy(prob)
     L = a.levels
-    for l in range(L - 1):
-        h.load_smoother_weights(l, 0, inputs.he_normal_weights(tuple(a.channels), 3, 2, a.seed + 10 * l))
+    if a.init:
+        _, init_sets = load_weights(a.init)
+        for l in range(L - 1):
+            h.load_smoother_weights(l, 0, [init_sets[-1][l]])
+    else:
+        for l in range(L - 1):
+            h.load_smoother_weights(l, 0, inputs.he_normal_weights(tuple(a.channels), 3, 2, a.seed + 10 * l))
     sets = []
-    for k, av in enumerate(sorted(a.alphas, reverse=True)):
-        print(f"training alpha={av:g} ({a.steps} steps, batch {a.batch}, mask {a.mask})", flush=True)
-        train_set(h, av, a.steps, a.batch, a.lr, a.mask, a.seed + 1000 * k, a.rollout, precision=a.precision)
+    alphas = sorted(a.alphas, reverse=True)
+    for k, av in enumerate(alphas):
+        steps = a.steps_per_alpha[k] if a.steps_per_alpha else a.steps
+        print(f"training alpha={av:g} ({steps} steps, batch {a.batch}, mask {a.mask}, fprime {a.fprime})", flush=True)
+        train_set(h, av, steps, a.batch, a.lr, a.mask, a.seed + 1000 * k, a.rollout, precision=a.precision,
+                  use_fprime=a.fprime)
         sets.append([h.get_smoother_weights(l) for l in range(L - 1)])
-    meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=sorted(a.alphas, reverse=True),
-                steps=a.steps, batch=a.batch, lr=a.lr, mask=a.mask, rollout=a.rollout, precision=a.precision,
-                seed=a.seed, use_fprime=False)
+        for nu in ((1, 1), (2, 0), (1, 0)):
+            cyc, st = evaluate(h, av, min(16, a.batch), nu[0], nu[1], a.fprime)
+            if cyc is None:
+                print(f"  eval alpha={av:g} V{nu} fprime={a.fprime}: {st}", flush=True)
+            else:
+                print(f"  eval alpha={av:g} V{nu} fprime={a.fprime}: cycles mean {cyc.mean():.1f} max {cyc.max()} "
+                      f"status {st}", flush=True)
+    meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=alphas,
+                steps=a.steps_per_alpha or [a.steps] * len(alphas), batch=a.batch, lr=a.lr, mask=a.mask,
+                rollout=a.rollout, precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init)
     save_weights(a.out, meta, sets)
     print(f"wrote {a.out}", flush=True)
     h.close()

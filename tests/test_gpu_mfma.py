@@ -92,3 +92,55 @@ def test_mixed_vcycle_error_stated():
     print(f"  mixed V(1,1)+F' vs fp64 oracle: {err:.2e}", flush=True)
     assert err < 5e-2
     h.close()
+
+
+@pytest.mark.parametrize("n,L", [(63, 3), (255, 5)])
+def test_fprime_every_precision(n, L):
+    """F'(h) = C^T (m' .* (C h C^T)) C: FP64 / FP32 against the oracle, the BF16
+    MFMA form against a stage-by-stage BF16 emulation and the oracle."""
+    print(f"case fprime n={n}", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=0.02, levels=L, max_batch=2, channels=(1, 32, 32, 1), ksize=3))
+    x = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(60))
+    ref = O.fprime(x, 2)
+    g64 = h.apply_fprime(0, x.to(dev), "fp64").cpu()
+    g32 = h.apply_fprime(0, x.float().to(dev), "fp32").cpu().double()
+    gmx = h.apply_fprime(0, x.float().to(dev), "mixed").cpu().double()
+    C = _bf(O.dct2_matrix(n))
+    m = O.fprime_mask(n, 2)
+    t = (_bf(x.float().double()) @ C.T).transpose(1, 2)
+    u = (_bf(t) @ C.T).transpose(1, 2) * m
+    v = (_bf(u) @ C).transpose(1, 2)
+    emul = (_bf(v) @ C).transpose(1, 2)
+    e64, e32, ee, er = _rel(g64, ref), _rel(g32, ref), _rel(gmx, emul), _rel(gmx, ref)
+    print(f"  fp64 {e64:.1e} fp32 {e32:.1e} mixed-vs-emulation {ee:.1e} mixed-vs-oracle {er:.1e}", flush=True)
+    assert e64 < 1e-12 and e32 < 1e-5 and ee < 1e-3 and er < 3e-2
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_solve_fp32_and_mixed_reach_tolerance(prec):
+    """Damped-Jacobi cycle (no learned weights) on 31x31: the plain FP32 and
+    the mixed refinement solves reach 1e-6 and agree with a dense solve."""
+    print(f"case solve {prec} to 1e-6", flush=True)
+    import numpy as np
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    n, s, L, av = 31, 0.04, 3, 1e-1
+    H = O.build_hierarchy(n, s, L, dim=2)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=2, channels=(1, 4, 4, 1), ksize=3))
+    for l in range(L - 1):
+        A = O.dense_operator(H, l, av)
+        d = torch.diagonal(A)
+        h.set_jacobi_smoother(l, 1.0 / float(torch.linalg.eigvals(A / d[:, None]).abs().max()))
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2100 + i) for i in range(2)]))
+    alpha = torch.full((2,), av, dtype=DT)
+    y = O.apply_operator(H, 0, u, alpha)
+    x, cyc, hist, st = h.solve(y.to(dev), alpha.to(dev), rtol=1e-6, max_cycles=300, precision=prec, history=True)
+    assert st == 0, (cyc, hist[:, -3:])
+    dense = torch.linalg.solve(O.dense_operator(H, 0, av), y.reshape(2, -1).T).T.reshape(y.shape)
+    err = _rel(x.cpu(), dense)
+    print(f"  cycles {list(cyc)} error vs dense {err:.2e}", flush=True)
+    assert err < 1e-4
+    h.close()
