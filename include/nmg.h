@@ -121,11 +121,14 @@ nmg_status nmg_get_smoother_weights(nmg_handle h, int level, int weight_set,
  * level `level` (omega > 0), in place of the neural smoother. */
 nmg_status nmg_set_jacobi_smoother(nmg_handle h, int level, double omega);
 
-/* Per right-hand-side coarse factorisation: for every slot b < batch forms
- * A_L = alpha[b] M_L (x) M_L + G_L (x) G_L and its FP64 Cholesky factor
- * (Algorithm 1, exact coarsest solve).  alpha: device double[batch].
- * Must precede nmg_vcycle for those alphas (nmg_solve calls it itself).
- * Synchronises to report NMG_ERR_NOT_SPD. */
+/* Coarse factorisation for the right-hand sides b < batch: for every
+ * distinct alpha[b] forms A_L = alpha M_L (x) M_L + G_L (x) G_L and its FP64
+ * Cholesky factor (Algorithm 1, exact coarsest solve), plus the FP64 inverse
+ * used by FP32 / mixed cycles.  Factors are cached per alpha value (up to
+ * max_batch of them), so repeated alphas cost nothing.  alpha: device
+ * double[batch].  Must precede nmg_vcycle for these right-hand sides
+ * (nmg_solve calls it itself).  Synchronises; NMG_ERR_ARG for alpha <= 0 or
+ * non-finite, NMG_ERR_NOT_SPD if a pivot is not positive. */
 nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha_dev, void* stream);
 
 /* ---- operators ---------------------------------------------------------- */

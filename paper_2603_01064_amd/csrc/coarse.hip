@@ -17,14 +17,17 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Block k factors cache slot slots[k] for alpha alphas[k]; flags[k] reports
+// a non-positive or non-finite pivot.
 __global__ void __launch_bounds__(kBlock) k_cholesky(const double* __restrict__ Mc, const double* __restrict__ Gc,
-                                                     const double* __restrict__ alpha, double* __restrict__ chol,
-                                                     double* __restrict__ cholT, int* __restrict__ flags, int nl,
-                                                     int two_d) {
-    const int b = blockIdx.x;
+                                                     const double* __restrict__ alphas, const int* __restrict__ slots,
+                                                     double* __restrict__ chol, double* __restrict__ cholT,
+                                                     int* __restrict__ flags, int nl, int two_d) {
+    const int k_ = blockIdx.x;
+    const int b = slots[k_];
     const int N = two_d ? nl * nl : nl;
     double* A = chol + (size_t)b * N * N;
-    const double a = alpha[b];
+    const double a = alphas[k_];
     for (int e = threadIdx.x; e < N * N; e += kBlock) {
         const int r = e / N, c = e % N;
         double v;
@@ -69,17 +72,17 @@ __global__ void __launch_bounds__(kBlock) k_cholesky(const double* __restrict__ 
         const int r = e / N, c = e % N;
         AT[(size_t)c * N + r] = A[e];
     }
-    if (threadIdx.x == 0) flags[b] = bad;
+    if (threadIdx.x == 0) flags[k_] = bad;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restrict__ chol,
-                                                         const double* __restrict__ cholT, const T* __restrict__ y,
-                                                         T* __restrict__ x, int N) {
+                                                         const double* __restrict__ cholT, const int* __restrict__ fidx,
+                                                         const T* __restrict__ y, T* __restrict__ x, int N) {
     extern __shared__ double z[];
     const int b = blockIdx.x;
-    const double* Lr = chol + (size_t)b * N * N;
-    const double* Lt = cholT + (size_t)b * N * N;
+    const double* Lr = chol + (size_t)fidx[b] * N * N;
+    const double* Lt = cholT + (size_t)fidx[b] * N * N;
     for (int i = threadIdx.x; i < N; i += kBlock) z[i] = (double)y[(size_t)b * N + i];
     __syncthreads();
     // forward: L z = y, column-oriented (column j of L is row j of L^T)
@@ -104,8 +107,8 @@ __global__ void __launch_bounds__(kBlock) k_coarse_solve(const double* __restric
 // W = L^{-1} by forward substitution on the identity, one column per thread
 // (column c of W lives in W[.][c], so a row of W is read coalesced).
 __global__ void __launch_bounds__(kBlock) k_lower_inverse(const double* __restrict__ chol, double* __restrict__ W,
-                                                          int N) {
-    const int b = blockIdx.x;
+                                                          const int* __restrict__ slots, int N) {
+    const int b = slots[blockIdx.x];
     const double* Lr = chol + (size_t)b * N * N;
     double* Wb = W + (size_t)b * N * N;
     for (int c = threadIdx.x; c < N; c += kBlock) {
@@ -118,8 +121,9 @@ __global__ void __launch_bounds__(kBlock) k_lower_inverse(const double* __restri
 }
 
 // Ainv = W^T W (symmetric), Ainv[i][j] = sum_{k >= max(i,j)} W[k][i] W[k][j].
-__global__ void __launch_bounds__(kBlock) k_gram(const double* __restrict__ W, double* __restrict__ Ainv, int N) {
-    const int b = blockIdx.y;
+__global__ void __launch_bounds__(kBlock) k_gram(const double* __restrict__ W, double* __restrict__ Ainv,
+                                                 const int* __restrict__ slots, int N) {
+    const int b = slots[blockIdx.y];
     const int e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= N * N) return;
     const int i = e / N, j = e % N;
@@ -132,13 +136,13 @@ __global__ void __launch_bounds__(kBlock) k_gram(const double* __restrict__ W, d
 // x = Ainv y per right-hand side; Ainv is symmetric, so thread i reads column
 // i (contiguous across threads for each k).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restrict__ Ainv, const T* __restrict__ y,
-                                                          T* __restrict__ x, int N) {
+__global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restrict__ Ainv, const int* __restrict__ fidx,
+                                                          const T* __restrict__ y, T* __restrict__ x, int N) {
     extern __shared__ double yv[];
     const int b = blockIdx.x;
     for (int i = threadIdx.x; i < N; i += kBlock) yv[i] = (double)y[(size_t)b * N + i];
     __syncthreads();
-    const double* A = Ainv + (size_t)b * N * N;
+    const double* A = Ainv + (size_t)fidx[b] * N * N;
     for (int i = threadIdx.x; i < N; i += kBlock) {
         double acc = 0.0;
         for (int k = 0; k < N; ++k) acc += A[(size_t)k * N + i] * yv[k];
@@ -148,10 +152,11 @@ __global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restri
 
 }  // namespace
 
-nmg_status launch_coarse_inverse(Ctx* c, int batch, hipStream_t s) {
+nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_t s) {
     const int N = c->nc;
-    hipLaunchKernelGGL(k_lower_inverse, dim3(batch), dim3(kBlock), 0, s, c->chol, c->cwork, N);
-    hipLaunchKernelGGL(k_gram, dim3((N * N + kBlock - 1) / kBlock, batch), dim3(kBlock), 0, s, c->cwork, c->cinv, N);
+    hipLaunchKernelGGL(k_lower_inverse, dim3(count), dim3(kBlock), 0, s, c->chol, c->cwork, slots, N);
+    hipLaunchKernelGGL(k_gram, dim3((N * N + kBlock - 1) / kBlock, count), dim3(kBlock), 0, s, c->cwork, c->cinv,
+                       slots, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -159,17 +164,18 @@ nmg_status launch_coarse_inverse(Ctx* c, int batch, hipStream_t s) {
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
     const int N = c->nc;
-    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv, y, x, N);
+    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv, c->coarse_idx,
+                       y, x, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
 template nmg_status launch_coarse_apply_inverse<float>(const Ctx*, int, const float*, float*, hipStream_t);
 template nmg_status launch_coarse_apply_inverse<double>(const Ctx*, int, const double*, double*, hipStream_t);
 
-nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStream_t s) {
+nmg_status launch_coarse_factor(Ctx* c, int count, const double* alphas, const int* slots, hipStream_t s) {
     const int nl = c->n[c->L - 1];
-    hipLaunchKernelGGL(k_cholesky, dim3(batch), dim3(kBlock), 0, s, c->Mc, c->Gc, alpha, c->chol, c->cholT, c->flags,
-                       nl, c->p.dim == 2 ? 1 : 0);
+    hipLaunchKernelGGL(k_cholesky, dim3(count), dim3(kBlock), 0, s, c->Mc, c->Gc, alphas, slots, c->chol, c->cholT,
+                       c->flags, nl, c->p.dim == 2 ? 1 : 0);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -177,8 +183,8 @@ nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStrea
 template <typename T>
 nmg_status launch_coarse_solve(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
     const int N = c->nc;
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->chol, c->cholT, y, x,
-                       N);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->chol, c->cholT,
+                       c->coarse_idx, y, x, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

@@ -21,10 +21,16 @@ constexpr int kThreads = 256;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ inline uint16_t f2bf_d(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to packed BF16 (hardware round-to-nearest-even).
+__device__ inline uint32_t pack_bf16(float a, float b) {
+    const float2v f = {a, b};
+    const bf16x2 p = __builtin_convertvector(f, bf16x2);
+    uint32_t u;
+    __builtin_memcpy(&u, &p, 4);
+    return u;
 }
 
 inline uint16_t f2bf_h(float f) {
@@ -35,50 +41,68 @@ inline uint16_t f2bf_h(float f) {
 }
 
 // EPI 0: store, 1: store times the ramp mask, 2: add into out.
+// Workgroup tile 64 (i) x 128 (j); wave w computes rows 32*(w/2).. and
+// columns 64*(w%2).. as 2 x 4 MFMA blocks.  Each k-step of 32 stages the
+// A tile (converted to BF16) and the B tile in LDS with the 16-byte chunk of
+// row r stored at chunk ^ (r & 3) to spread the fragment reads over banks.
+constexpr int kTI = 64, kTJ = 128, kKS = 32;
+
+__device__ inline int frag_off(int row, int chunk) { return row * 64 + ((chunk ^ (row & 3)) << 4); }
+
 template <int EPI>
 __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict__ in, float* __restrict__ out,
-                                                        const uint16_t* __restrict__ mat, int n, int npad,
+                                                        const uint16_t* __restrict__ mat,
+                                                        const float* __restrict__ ramp, int n, int npad,
                                                         int tiles_j) {
+    __shared__ __attribute__((aligned(16))) char As[kTI * kKS * 2];
+    __shared__ __attribute__((aligned(16))) char Bs[kTJ * kKS * 2];
     const int b = blockIdx.y;
     const int ti = blockIdx.x / tiles_j, tj = blockIdx.x % tiles_j;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int ln = lane & 15, lg = lane >> 4;
-    const int ib = ti * 64 + (wave >> 1) * 32, jb = tj * 64 + (wave & 1) * 32;
+    const int i0 = ti * kTI, j0 = tj * kTJ;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 64;
     const size_t per = (size_t)n * n;
     const float* src = in + (size_t)b * per;
-    floatx4 acc[2][2];
+    floatx4 acc[2][4];
     for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < npad; k0 += 32) {
-        const int k = k0 + lg * 8;
-        bf16x8 af[2], bfr[2];
-        for (int r = 0; r < 2; ++r) {
-            const int i = ib + r * 16 + ln;
-            uint16_t tmp[8];
-            for (int q = 0; q < 8; ++q) {
-                const float v = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
-                tmp[q] = f2bf_d(v);
+        for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // staging roles: A: row tid/4, chunk tid%4 (8 values); B: rows tid/4 and 64 + tid/4
+    const int sr = tid >> 2, sc = tid & 3;
+    for (int k0 = 0; k0 < npad; k0 += kKS) {
+        {
+            const int i = i0 + sr, k = k0 + sc * 8;
+            float v[8];
+            for (int q = 0; q < 8; ++q) v[q] = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
+            *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) =
+                make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+            for (int h = 0; h < 2; ++h) {
+                const int jr = sr + 64 * h;
+                const int j = j0 + jr;  // < npad by construction
+                *reinterpret_cast<uint4*>(Bs + frag_off(jr, sc)) =
+                    *reinterpret_cast<const uint4*>(mat + (size_t)j * npad + k0 + sc * 8);
             }
-            __builtin_memcpy(&af[r], tmp, 16);
         }
-        for (int c = 0; c < 2; ++c) {
-            const int j = jb + c * 16 + ln;  // < npad by construction of the grid
-            bfr[c] = *reinterpret_cast<const bf16x8*>(mat + (size_t)j * npad + k);
-        }
+        __syncthreads();
+        bf16x8 af[2], bfr[4];
+        for (int r = 0; r < 2; ++r) af[r] = *reinterpret_cast<const bf16x8*>(As + frag_off(wi + r * 16 + ln, lg));
+        for (int c = 0; c < 4; ++c) bfr[c] = *reinterpret_cast<const bf16x8*>(Bs + frag_off(wj + c * 16 + ln, lg));
         for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < 4; ++c)
                 acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
+        __syncthreads();
     }
     float* dst = out + (size_t)b * per;
     for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) {
-            const int j = jb + c * 16 + ln;
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + wj + c * 16 + ln;
             if (j >= n) continue;
             for (int q = 0; q < 4; ++q) {
-                const int i = ib + r * 16 + lg * 4 + q;
+                const int i = i0 + wi + r * 16 + lg * 4 + q;
                 if (i >= n) continue;
                 float v = acc[r][c][q];
-                if (EPI == 1) v *= sqrtf((float)(i > j ? i : j) / (float)n);
+                if (EPI == 1) v *= ramp[i > j ? i : j];
                 float* o = dst + (size_t)j * n + i;
                 if (EPI == 2)
                     *o += v;
@@ -91,12 +115,16 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict_
 }  // namespace
 
 nmg_status prepare_fprime_bf16(Ctx* c) {
-    if (c->dctbf) return NMG_OK;
+    if (c->dctbf && c->ramp) return NMG_OK;
+    if (c->dctbf) (void)hipFree(c->dctbf);
+    if (c->ramp) (void)hipFree(c->ramp);
+    c->dctbf = nullptr;
+    c->ramp = nullptr;
     std::vector<uint16_t> all;
     c->dctbf_off.clear();
     for (int l = 0; l < c->L; ++l) {
         const int n = c->n[(size_t)l];
-        const int npad = (n + 63) / 64 * 64;
+        const int npad = (n + 127) / 128 * 128;
         std::vector<uint16_t> C((size_t)npad * npad, 0), Ct((size_t)npad * npad, 0);
         for (int k = 0; k < n; ++k) {
             const double ck = k == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
@@ -110,6 +138,21 @@ nmg_status prepare_fprime_bf16(Ctx* c) {
         all.insert(all.end(), C.begin(), C.end());
         all.insert(all.end(), Ct.begin(), Ct.end());
     }
+    // ramp sqrt(k / n) per level for the mask epilogue
+    std::vector<float> ramps;
+    c->ramp_off.clear();
+    for (int l = 0; l < c->L; ++l) {
+        const int n = c->n[(size_t)l];
+        c->ramp_off.push_back(ramps.size());
+        for (int k = 0; k < n; ++k) ramps.push_back((float)std::sqrt((double)k / (double)n));
+    }
+    hipError_t er = hipMalloc((void**)&c->ramp, ramps.size() * sizeof(float));
+    if (er != hipSuccess) {
+        (void)hipGetLastError();
+        c->ramp = nullptr;
+        return fail(NMG_ERR_OOM, "hipMalloc failed for the F' ramp tables");
+    }
+    NMG_HIP(hipMemcpy(c->ramp, ramps.data(), ramps.size() * sizeof(float), hipMemcpyHostToDevice));
     hipError_t e = hipMalloc((void**)&c->dctbf, all.size() * sizeof(uint16_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -124,18 +167,19 @@ nmg_status prepare_fprime_bf16(Ctx* c) {
 nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, float* dst, int accumulate,
                               float* t1, float* t2, hipStream_t s) {
     const int n = c->n[(size_t)l];
-    const int npad = (n + 63) / 64 * 64;
-    const int tiles = npad / 64;
+    const int npad = (n + 127) / 128 * 128;
+    const int ti = npad / kTI, tj = npad / kTJ;
     const uint16_t* C = c->dctbf + c->dctbf_off[(size_t)l];
     const uint16_t* Ct = C + (size_t)npad * npad;
-    dim3 grid((unsigned)(tiles * tiles), (unsigned)batch);
-    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, h, t1, C, n, npad, tiles);
-    hipLaunchKernelGGL(k_rowgemm_t<1>, grid, dim3(kThreads), 0, s, t1, t2, C, n, npad, tiles);
-    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t2, t1, Ct, n, npad, tiles);
+    dim3 grid((unsigned)(ti * tj), (unsigned)batch);
+    const float* rp = c->ramp + c->ramp_off[(size_t)l];
+    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, h, t1, C, rp, n, npad, tj);
+    hipLaunchKernelGGL(k_rowgemm_t<1>, grid, dim3(kThreads), 0, s, t1, t2, C, rp, n, npad, tj);
+    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t2, t1, Ct, rp, n, npad, tj);
     if (accumulate)
-        hipLaunchKernelGGL(k_rowgemm_t<2>, grid, dim3(kThreads), 0, s, t1, dst, Ct, n, npad, tiles);
+        hipLaunchKernelGGL(k_rowgemm_t<2>, grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj);
     else
-        hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t1, dst, Ct, n, npad, tiles);
+        hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

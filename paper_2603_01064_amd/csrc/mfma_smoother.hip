@@ -41,16 +41,18 @@ inline uint16_t f2bf(float f) {
 
 // Activation buffers hold 32 BF16 channels per pixel (64 B) in four chunks of
 // 8 channels; chunk g of pixel (row r, column c) sits at
-//   (r * P + c) * 64 + ((g ^ (c & 3)) << 4)
-// which spreads the 16 consecutive pixels an MFMA operand reads over the LDS
-// banks.  The pitch P is a multiple of 4, so the swizzle depends on the
-// column only and every tap of a lane is its base address plus a constant.
-constexpr int kP = 36;
+//   (r * P + c) * 64 + ((g ^ ((c >> 1) & 3)) << 4),
+// so any 8 consecutive pixels put a given chunk in 8 distinct 16-byte bank
+// slots and a 16-lane operand read is conflict-free.  The pitch P is a
+// multiple of 8, so the swizzle depends on the column only and every tap of
+// a lane is its base address plus a constant.
+constexpr int kP = 40;
 
-__device__ inline int act_addr(int r, int c, int g) { return (r * kP + c) * 64 + ((g ^ (c & 3)) << 4); }
+__device__ inline int swz(int c, int g) { return (g ^ ((c >> 1) & 3)) << 4; }
+__device__ inline int act_addr(int r, int c, int g) { return (r * kP + c) * 64 + swz(c, g); }
 
 // Packed weight block (uint16 bf16) per (level, set):
-//   first : [nb 2][lane 64][4]          co = nb*16 + lane%16, tap = 4*(lane/16)+j (0 if >= 9)
+//   first : [nb 2][lane 64][4]          co = nb*16 + lane%16, tap (dy, dx) = (lane/16, j), 0 if dy or dx is 3
 //   hidden: [layer][tap 9][nb 2][lane 64][8]  co = nb*16 + lane%16, ci = 8*(lane/16)+j
 //   last  : [lane 64][8]                t = lane%16 (0 if >= 9), ci = 8*(lane/16)+j
 constexpr int kFirstElems = 2 * 64 * 4;
@@ -145,18 +147,15 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                                                                 ((t * 2 + nb) * 64 + lane) * 8);
     const bf16x8 wl = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)NH * kHiddenElems + lane * 8);
 
-    // per-lane constants: operand chunk offset of pixel ln (its column & 3 == ln & 3 for
-    // 16-aligned groups) and the output chunk offsets of channels nb*16 + 4*lg .. +3
-    const int swz_in = ((lg ^ (ln & 3)) << 4);
+    // per-lane constants for 16-aligned pixel groups (column = 16 k + ln): the
+    // operand chunk offset of pixels ln, ln+1, ln+2, of the halo pixels 16 and
+    // 17, and the output chunk offsets of channels nb*16 + 4*lg .. +3
+    const int swz0 = swz(ln, lg), swz1 = swz(ln + 1, lg), swz2 = swz(ln + 2, lg);
+    const int swz16 = swz(16, lg), swz17 = swz(17, lg);
     int out_off[2];
     for (int nb = 0; nb < 2; ++nb) {
         const int co = nb * 16 + lg * 4;
-        out_off[nb] = (((co >> 3) ^ (ln & 3)) << 4) + (co & 7) * 2;
-    }
-    int tapoff[4];
-    for (int j = 0; j < 4; ++j) {
-        const int tap = lg * 4 + j;
-        tapoff[j] = tap < 9 ? (tap / 3) * G::W0 + tap % 3 : -1;
+        out_off[nb] = swz(ln, co >> 3) + (co & 7) * 2;
     }
 
     const size_t per = (size_t)n * n;
@@ -179,27 +178,41 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
             }
         }
         __syncthreads();
-        // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16)
+        // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16);
+        //      operand K slot (lane/16, j) is tap (dy, dx) = (lane/16, j)
         {
             constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
             constexpr int npx = S * HH, ngr = (npx + 15) / 16;
+            int q0 = wave * 16 + ln;
+            int ry = q0 / S, rx = q0 - (q0 / S) * S;
             for (int gi = wave; gi < ngr; gi += 4) {
-                const int q0 = gi * 16 + ln;
-                const int q = q0 < npx ? q0 : npx - 1;
-                const int ry = q / S, rx = q - (q / S) * S;
-                const int ib = ry * G::W0 + rx;
-                short4v bop;
-                for (int j = 0; j < 4; ++j) bop[j] = tapoff[j] >= 0 ? (short)in_t[ib + tapoff[j]] : (short)0;
-                const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                const bool live = q0 < npx;
+                const int ryc = live ? ry : HH - 1, rxc = live ? rx : S - 1;
+                short4v bop = {0, 0, 0, 0};
+                if (lg < 3) {
+                    const uint16_t* ip = in_t + (ryc + lg) * G::W0 + rxc;
+                    bop[0] = (short)ip[0];
+                    bop[1] = (short)ip[1];
+                    bop[2] = (short)ip[2];
+                }
+                const int gy = ty0 - HALO + ryc, gx = tx0 - HALO + rxc;
                 const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
                 for (int nb = 0; nb < 2; ++nb) {
                     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc, 0, 0, 0);
-                    if (q0 < npx) {
+                    if (live) {
                         const int co = nb * 16 + lg * 4;
                         const uint2 v = inside ? relu_pack4(acc) : make_uint2(0u, 0u);
                         *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
                     }
+                }
+                // advance this lane's pixel by 64 = (64 / S) rows + (64 % S) columns
+                q0 += 64;
+                rx += 64 % S;
+                ry += 64 / S;
+                if (rx >= S) {
+                    rx -= S;
+                    ry += 1;
                 }
             }
         }
@@ -215,11 +228,11 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
             for (int gi = wave; gi < ngr; gi += 4) {
                 const int ry = gi >> 1, rx0 = (gi & 1) * 16;
                 const int rx = rx0 + ln;
-                const char* a0 = ain + (ry * kP + rx) * 64 + swz_in;       // tap (dy, 0) of pixel rx
+                const char* a0 = ain + (ry * kP + rx) * 64 + swz0;         // tap (dy, 0) of pixel rx
                 floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
                 if constexpr (DPP) {
-                    const char* e0 = ain + (ry * kP + rx0 + 16) * 64 + (lg << 4);        // pixel rx0+16
-                    const char* e1 = ain + (ry * kP + rx0 + 17) * 64 + ((lg ^ 1) << 4);  // pixel rx0+17
+                    const char* e0 = ain + (ry * kP + rx0 + 16) * 64 + swz16;  // pixel rx0+16
+                    const char* e1 = ain + (ry * kP + rx0 + 17) * 64 + swz17;  // pixel rx0+17
 #pragma unroll
                     for (int dy = 0; dy < 3; ++dy) {
                         const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
@@ -236,8 +249,8 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                     }
                 } else {
                     // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
-                    const char* a1 = ain + (ry * kP + rx + 1) * 64 + ((lg ^ ((ln + 1) & 3)) << 4);
-                    const char* a2 = ain + (ry * kP + rx + 2) * 64 + ((lg ^ ((ln + 2) & 3)) << 4);
+                    const char* a1 = ain + (ry * kP + rx + 1) * 64 + swz1;
+                    const char* a2 = ain + (ry * kP + rx + 2) * 64 + swz2;
 #pragma unroll
                     for (int dy = 0; dy < 3; ++dy) {
                         const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
@@ -261,29 +274,40 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
             }
             __syncthreads();
         }
-        // ---- last layer 32 -> 1: Z[p][t] on region W(NL-1) x H(NL-1), then gather
+        // ---- last layer 32 -> 1: Z[t][p] on region W(NL-1) x H(NL-1) (tap planes,
+        //      so both the stores and the 9-tap gather are unit-stride), then gather
         {
             constexpr int S = G::W(NL - 1), HH = G::H(NL - 1);
             constexpr int ngr = HH * 2;
-            constexpr int ZP = 32;  // Z pixel pitch
+            constexpr int ZP = 32;          // Z pixel pitch
+            constexpr int ZN = HH * ZP;     // pixels per tap plane
             const char* ain = (NH & 1) ? bufB : bufA;
             float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
             for (int gi = wave; gi < ngr; gi += 4) {
                 const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
-                const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz_in);
+                const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bop, acc, 0, 0, 0);
-                if (rx < S && lg < 3) *reinterpret_cast<floatx4*>(Z + (ry * ZP + rx) * 16 + lg * 4) = acc;
+                if (rx < S && lg < 3) {
+                    // lane group lg holds taps 4 lg .. 4 lg + 3; only taps 0..8 exist
+                    float* zp = Z + (lg * 4) * ZN + ry * ZP + rx;
+                    zp[0] = acc[0];
+                    if (lg < 2) {
+                        zp[ZN] = acc[1];
+                        zp[2 * ZN] = acc[2];
+                        zp[3 * ZN] = acc[3];
+                    }
+                }
             }
             __syncthreads();
             for (int e = tid; e < TH * TW; e += kThreads) {
                 const int oy = e / TW, ox = e - (e / TW) * TW;
                 const int gy = ty0 + oy, gx = tx0 + ox;
                 if (gy < n && gx < n) {
-                    const float* zb = Z + (oy * ZP + ox) * 16;
+                    const float* zb = Z + oy * ZP + ox;
                     float v = 0.f;
 #pragma unroll
-                    for (int t = 0; t < 9; ++t) v += zb[((t / 3) * ZP + t % 3) * 16 + t];
+                    for (int t = 0; t < 9; ++t) v += zb[t * ZN + (t / 3) * ZP + t % 3];
                     v *= nbf;
                     float* o = out + (size_t)gy * n + gx;
                     *o = accumulate ? *o + v : v;
@@ -339,8 +363,8 @@ nmg_status repack_bf16(Ctx* c, int level, int weight_set) {
     for (int nb = 0; nb < 2; ++nb)
         for (int lane = 0; lane < 64; ++lane)
             for (int j = 0; j < 4; ++j) {
-                const int co = nb * 16 + lane % 16, tap = 4 * (lane / 16) + j;
-                pk[(size_t)(nb * 64 + lane) * 4 + j] = tap < 9 ? f2bf(w1[co * 9 + tap]) : 0;
+                const int co = nb * 16 + lane % 16, dy = lane / 16, dx = j;
+                pk[(size_t)(nb * 64 + lane) * 4 + j] = (dy < 3 && dx < 3) ? f2bf(w1[co * 9 + dy * 3 + dx]) : 0;
             }
     for (int h = 0; h < NH; ++h) {
         const float* wh = w.data() + c->layer_off[1 + h];  // [32][32][3][3]

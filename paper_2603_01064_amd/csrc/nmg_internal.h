@@ -130,6 +130,8 @@ struct Ctx {
     std::vector<int> adam_step;        // per set
     uint16_t* dctbf = nullptr;         // BF16 DCT-II matrices C and C^T per level (padded)
     std::vector<size_t> dctbf_off;
+    float* ramp = nullptr;             // sqrt(k / n_l) per level (F' mask)
+    std::vector<size_t> ramp_off;
     uint16_t* wbf = nullptr;           // BF16 MFMA-packed weights
     size_t wbf_stride = 0;             // per (level, set)
     // coarse solve
@@ -140,8 +142,14 @@ struct Ctx {
     double* cholT = nullptr;           // [max_batch][nc][nc] its transpose
     double* cinv = nullptr;            // [max_batch][nc][nc] A_L^{-1} (FP32 / mixed cycles)
     double* cwork = nullptr;           // [max_batch][nc][nc] L^{-1} scratch
-    int* flags = nullptr;              // [max_batch] non-SPD / non-finite flags
-    double* alpha_prepared = nullptr;  // [max_batch] device copy of factored alphas
+    int* flags = nullptr;              // [max_batch] non-SPD / non-finite flags per new factor
+    double* alpha_prepared = nullptr;  // [max_batch] alphas of the factors being computed
+    int* slot_dev = nullptr;           // [max_batch] cache slots of the factors being computed
+    int* coarse_idx = nullptr;         // [max_batch] cache slot of each right-hand side
+    // coarse-factor cache: slot k holds the factors of alpha cache_alpha[k]
+    std::vector<double> cache_alpha;   // NaN = empty
+    std::vector<long long> cache_used; // last use (prepare counter)
+    long long prepare_count = 0;
     // norms and scratch
     double* nrm = nullptr;             // [max_batch] per right-hand-side norms
     double* nrm2 = nullptr;            // [max_batch] second norm slot
@@ -222,8 +230,8 @@ nmg_status prepare_fprime_bf16(Ctx* c);
 nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, float* dst, int accumulate, float* t1,
                               float* t2, hipStream_t s);
 nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
-nmg_status launch_coarse_factor(Ctx* c, int batch, const double* alpha, hipStream_t s);
-nmg_status launch_coarse_inverse(Ctx* c, int batch, hipStream_t s);
+nmg_status launch_coarse_factor(Ctx* c, int count, const double* alphas, const int* slots, hipStream_t s);
+nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_t s);
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);
 template <typename T>

@@ -447,6 +447,10 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->cwork, (size_t)B * c->nc * c->nc));
     NMG_TRY(dev_alloc(&c->flags, (size_t)B));
     NMG_TRY(dev_alloc(&c->alpha_prepared, (size_t)B));
+    NMG_TRY(dev_alloc(&c->slot_dev, (size_t)B));
+    NMG_TRY(dev_alloc(&c->coarse_idx, (size_t)B));
+    c->cache_alpha.assign((size_t)B, std::nan(""));
+    c->cache_used.assign((size_t)B, -1);
     NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
     NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kNormChunksPerRhs));
@@ -479,6 +483,7 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->adam_v);
     dev_free(c->wbf);
     dev_free(c->dctbf);
+    dev_free(c->ramp);
     dev_free(c->Mc);
     dev_free(c->Gc);
     dev_free(c->chol);
@@ -487,6 +492,8 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->cwork);
     dev_free(c->flags);
     dev_free(c->alpha_prepared);
+    dev_free(c->slot_dev);
+    dev_free(c->coarse_idx);
     dev_free(c->nrm);
     dev_free(c->nrm2);
     dev_free(c->norm_part);
@@ -551,18 +558,60 @@ nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha, void* strea
     NMG_TRY(check_batch(h, batch));
     if (!alpha) return fail(NMG_ERR_ARG, "null alpha");
     hipStream_t s = (hipStream_t)stream;
-    NMG_HIP(hipMemcpyAsync(h->alpha_prepared, alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToDevice, s));
-    NMG_TRY(launch_coarse_factor(h, batch, h->alpha_prepared, s));
-    NMG_TRY(launch_coarse_inverse(h, batch, s));
-    std::vector<int> flags((size_t)batch);
+    // Factors are cached per alpha value (exact match): a batch with U distinct
+    // alphas factors at most U matrices, and alphas seen before cost nothing.
     std::vector<double> al((size_t)batch);
-    NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
     NMG_HIP(hipMemcpyAsync(al.data(), alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
     NMG_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < batch; ++b) {
+    for (int b = 0; b < batch; ++b)
         if (!std::isfinite(al[(size_t)b]) || !(al[(size_t)b] > 0.0))
             return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(b) + ")");
-        if (flags[(size_t)b]) return fail(NMG_ERR_NOT_SPD, "coarse Cholesky failed for slot " + std::to_string(b));
+    const long long stamp = ++h->prepare_count;
+    const int slots = (int)h->cache_alpha.size();
+    std::vector<int> idx((size_t)batch, -1), new_slots;
+    std::vector<double> new_alphas;
+    auto find = [&](double a) {
+        for (int k = 0; k < slots; ++k)
+            if (h->cache_alpha[(size_t)k] == a) return k;
+        return -1;
+    };
+    for (int b = 0; b < batch; ++b) {
+        const double a = al[(size_t)b];
+        int k = find(a);
+        if (k < 0) {
+            // least recently used slot not claimed by this batch
+            long long best = stamp;  // slots already claimed by this batch carry `stamp`
+            for (int j = 0; j < slots; ++j)
+                if (h->cache_used[(size_t)j] < best) {
+                    best = h->cache_used[(size_t)j];
+                    k = j;
+                }
+            if (k < 0) return fail(NMG_ERR_STATE, "coarse factor cache exhausted");
+            h->cache_alpha[(size_t)k] = a;
+            new_slots.push_back(k);
+            new_alphas.push_back(a);
+        }
+        h->cache_used[(size_t)k] = stamp;
+        idx[(size_t)b] = k;
+    }
+    NMG_HIP(hipMemcpyAsync(h->coarse_idx, idx.data(), (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
+    const int cnt = (int)new_slots.size();
+    if (cnt > 0) {
+        NMG_HIP(hipMemcpyAsync(h->alpha_prepared, new_alphas.data(), (size_t)cnt * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        NMG_HIP(hipMemcpyAsync(h->slot_dev, new_slots.data(), (size_t)cnt * sizeof(int), hipMemcpyHostToDevice, s));
+        NMG_TRY(launch_coarse_factor(h, cnt, h->alpha_prepared, h->slot_dev, s));
+        NMG_TRY(launch_coarse_inverse(h, cnt, h->slot_dev, s));
+        std::vector<int> flags((size_t)cnt);
+        NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+        NMG_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < cnt; ++k)
+            if (flags[(size_t)k]) {
+                h->cache_alpha[(size_t)new_slots[(size_t)k]] = std::nan("");
+                return fail(NMG_ERR_NOT_SPD, "coarse Cholesky failed for alpha " + std::to_string(new_alphas[(size_t)k]));
+            }
+    } else {
+        NMG_HIP(hipStreamSynchronize(s));
     }
     return NMG_OK;
 }

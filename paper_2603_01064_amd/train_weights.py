@@ -108,7 +108,37 @@ def evaluate(h: nmg.Handle, alpha_value: float, batch: int, nu1: int, nu2: int, 
     return cyc, st
 
 
+def merge(argv):
+    """``merge --out F --nu1 1 --nu2 1 --fprime a.npz:k b.npz:k ...``: one file
+    holding the selected sets in the given order (alphas taken from each
+    source file's metadata) plus the cycle the solver should run."""
+    ap = argparse.ArgumentParser(prog="train_weights merge")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--nu1", type=int, default=1)
+    ap.add_argument("--nu2", type=int, default=1)
+    ap.add_argument("--fprime", action="store_true")
+    ap.add_argument("sources", nargs="+")
+    a = ap.parse_args(argv)
+    sets, alphas, metas = [], [], []
+    for src in a.sources:
+        path, k = src.rsplit(":", 1)
+        meta, ss = load_weights(path)
+        sets.append(ss[int(k)])
+        alphas.append(meta["alphas"][int(k)])
+        metas.append({"file": os.path.basename(path), "set": int(k), **{x: meta.get(x) for x in
+                      ("steps", "batch", "lr", "mask", "rollout", "precision", "seed", "use_fprime", "init")}})
+    base = load_weights(a.sources[0].rsplit(":", 1)[0])[0]
+    meta = dict(n=base["n"], s=base["s"], levels=base["levels"], channels=base["channels"], ksize=3,
+                alphas=alphas, cycle={"nu1": a.nu1, "nu2": a.nu2, "use_fprime": bool(a.fprime)}, sources=metas)
+    save_weights(a.out, meta, sets)
+    print(f"wrote {a.out} with alphas {alphas}")
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "merge":
+        return merge(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--s", type=float, default=0.01)
