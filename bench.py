@@ -28,6 +28,9 @@ N, S, LEVELS, BATCH = 255, 0.01, 5, 64
 CHANNELS = (1, 32, 32, 1)
 ALPHAS = (1e-2, 1e-3, 1e-4)
 FLOP_PER_PX = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)  # 19,584: three 3x3 layers
+# smoother input plane read + output plane written (FP32), plus a read of the
+# output when it accumulates into x (no F')
+PLANE_BYTES = 4 * N * N
 BF16_PEAK_TFLOPS = 2500.0
 WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s0.01.npz")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_mfma_grid255_b64_pmc.txt")
@@ -43,9 +46,10 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on another version of the kernel."""
+def traffic_per_image():
+    """Measured HBM bytes per (image x launch) of the level-1 smoother from the
+    committed rocprofv3 counter summary, or None when it is missing or was
+    taken on another version of the kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     txt = open(PMC_SUMMARY).read()
@@ -53,7 +57,7 @@ def traffic_from_profile():
     if f"kernel_source_sha256_16: {want}" not in txt:
         return None
     for line in txt.splitlines():
-        if line.startswith("hbm_bytes_per_launch:"):
+        if line.startswith("hbm_bytes_per_image:"):
             return float(line.split(":")[1])
     return None
 
@@ -68,38 +72,51 @@ def make_inputs(steps, seed0=20000):
     return out
 
 
-def cpu_baseline(meta, mean_cycles, budget_s=20.0):
-    """The FP64 oracle's V-cycle on one right-hand side of the same workload,
-    timed on the host cores; converted to solves/s with the GPU's mean cycle
-    count (the oracle's per-cycle cost does not depend on the weight values,
-    so seeded He-normal weights are used)."""
+def split_layers(flat, channels=CHANNELS, k=3):
+    """Per-layer [Cout][Cin][k][k] views of one level's flat weight vector."""
+    out, off = [], 0
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        size = cout * cin * k * k
+        out.append(np.asarray(flat[off:off + size], dtype=np.float64).reshape(cout, cin, k, k))
+        off += size
+    return out
+
+
+def cpu_baseline(meta, sets, mean_cycles, budget_s=20.0, max_cycles=2000):
+    """The FP64 oracle's V-cycle on one right-hand side of the same workload
+    (alpha = 1e-3, its trained weight set), timed on the host cores for about
+    `budget_s` seconds and converted to solves/s with the GPU run's mean cycle
+    count."""
     import torch
 
     import oracle as O
     from paper_2603_01064_amd import inputs
     H = O.build_hierarchy(N, S, LEVELS, dim=2)
-    W = [[torch.tensor(w) for w in inputs.he_normal_weights(CHANNELS, 3, 2, 7000 + 10 * l)] for l in range(LEVELS - 1)]
-    Sm = [O.neural_smoother(w, 2) for w in W]
+    k = min(range(len(meta["alphas"])), key=lambda i: abs(math.log(meta["alphas"][i] / 1e-3)))
+    Sm = [O.neural_smoother([torch.tensor(w) for w in split_layers(sets[k][l])], 2) for l in range(LEVELS - 1)]
     u = torch.tensor(inputs.boxes_image(N, 1)).unsqueeze(0)
     alpha = torch.tensor([1e-3], dtype=torch.float64)
     y = O.apply_operator(H, 0, u, alpha)
     x = torch.zeros_like(y)
     nu1, nu2, fp = meta["cycle"]["nu1"], meta["cycle"]["nu2"], meta["cycle"]["use_fprime"]
+    tag = f"V({nu1},{nu2})" + ("+F'" if fp else "")
     t0 = time.perf_counter()
     cycles = 0
     while True:
         x = O.vcycle(H, Sm, x, y, alpha, nu1, nu2, fp)
         cycles += 1
-        if time.perf_counter() - t0 > budget_s or cycles >= 50:
+        if time.perf_counter() - t0 > budget_s or cycles >= max_cycles:
             break
-    dt = (time.perf_counter() - t0) / cycles
+    total = time.perf_counter() - t0
+    dt = total / cycles
     return {
-        "value": 1.0 / (dt * mean_cycles),
+        "value": round(1.0 / (dt * mean_cycles), 4),
         "unit": "solves/s",
         "cores": int(torch.get_num_threads()),
         "kind": "oracle",
-        "sample": f"{cycles} FP64 oracle V({nu1},{nu2}){'+F' if fp else ''} cycles on one 255x255 right-hand side "
-                  f"({dt:.2f} s/cycle) x {mean_cycles:.1f} cycles per solve (the GPU run's mean)",
+        "sample": f"{cycles} FP64 oracle {tag} cycles on one 255x255 right-hand side "
+                  f"(alpha 1e-3, trained weights) in {total:.1f} s ({1e3 * dt:.1f} ms/cycle), scaled by "
+                  f"{mean_cycles:.2f} cycles per solve (the GPU run's mean)",
     }
 
 
@@ -112,6 +129,8 @@ def main(argv=None):
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serial-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 64 MiB device copy before timing (reference kernel for HBM counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); every right-hand side is "
@@ -160,6 +179,12 @@ def main(argv=None):
     for k in range(a.warmup):
         log(f"warmup {k + 1}/{a.warmup}")
         run(batches[k])
+    if a.copy_calibration:
+        src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # ---- timed region
     h.profile_enable(("smoother",))
     torch.cuda.synchronize()
@@ -182,13 +207,21 @@ def main(argv=None):
     value = BATCH * a.steps / elapsed
     by_alpha = {f"{av:g}": float(cycles[np.isclose(alphas_all, av)].mean()) for av in ALPHAS
                 if np.isclose(alphas_all, av).any()}
-    flops_launch = FLOP_PER_PX * N * N * BATCH
+    # Converged right-hand sides leave the batch, so level-1 smoother launches
+    # process between 1 and 64 images; nu1 + nu2 launches per cycle of each
+    # right-hand side give the number of images processed in the timed region.
+    images = (cyc_cfg["nu1"] + cyc_cfg["nu2"]) * int(cycles.sum())
     avg_ms = sm_ms / max(sm_n, 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    mean_images = images / max(sm_n, 1)
+    achieved = FLOP_PER_PX * N * N * images / (sm_ms * 1e-3) / 1e12 if sm_ms > 0 else 0.0
+    tpi = traffic_per_image()
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": traffic_from_profile(),
-            "kernel": "k_smoother_mfma<3> (level-1 BF16 smoother, 255x255 x 64)",
-            "avg_launch_ms": round(avg_ms, 4), "launches": sm_n, "flop_per_launch": flops_launch}
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+            "traffic": round(tpi * mean_images) if tpi is not None else None,
+            "kernel": "k_smoother_mfma<3> on level 1 (255x255, BF16 CNN 1-32-32-1)",
+            "avg_launch_ms": round(avg_ms, 4), "launches": sm_n, "images_per_launch": round(mean_images, 2),
+            "flop_per_launch": round(FLOP_PER_PX * N * N * mean_images),
+            "algorithmic_bytes_per_launch": round((2 if cyc_cfg["use_fprime"] else 3) * PLANE_BYTES * mean_images)}
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(1e3 * elapsed / a.steps, 3), "higher_is_better": True,
@@ -216,7 +249,7 @@ def main(argv=None):
                 res["serial_fp32_gpu"]["p99_ratio"] = round(res["serial_fp32_gpu"]["p99_ms"] / res["config"]["p99_ms"], 2)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
-        res["cpu_baseline"] = cpu_baseline(meta, float(cycles.mean()))
+        res["cpu_baseline"] = cpu_baseline(meta, sets, float(cycles.mean()))
     print(json.dumps(res), flush=True)
     h.close()
     return 0

@@ -164,8 +164,9 @@ nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, 
  * b = y - A x, h = ||b|| N(b/||b||), x += F'(h) of Algorithms 2-4, Galerkin
  * coarse levels, Cholesky coarsest solve).  x, y: device, double for
  * NMG_FP64, float otherwise.  weight_set_dev: device int[batch] choosing the
- * smoother set per right-hand side, or NULL for set 0.  Requires
- * nmg_prepare for the same alphas. */
+ * smoother set per right-hand side, or NULL for set 0 (indices outside
+ * [0, n_weight_sets) are clamped into it).  Requires nmg_prepare for the
+ * same alphas. */
 nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
                       const void* y, void* x, const nmg_cycle_opts* opts, void* stream);
 
@@ -175,7 +176,10 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const in
  * NMG_FP64 / NMG_MIXED iterate in FP64 with d = MG(0, r/||r||) computed in
  * the cycle precision (residual-driven form of the same iteration);
  * NMG_FP32 iterates in plain FP32 and converts at the end.  Converged
- * right-hand sides are frozen.  cycles_host (int[batch], may be NULL)
+ * right-hand sides are frozen: they leave the batch, so every cycle runs on
+ * the active ones only, and each result is the same as when that
+ * right-hand side is solved alone.  weight_set_dev entries must lie in
+ * [0, n_weight_sets) (NMG_ERR_ARG otherwise).  cycles_host (int[batch], may be NULL)
  * receives cycles used; history_host (double[batch][max_cycles+1], may be
  * NULL) receives the relative residual before each cycle (unused entries
  * set to -1); done_ms_host (double[batch], may be NULL) receives the host

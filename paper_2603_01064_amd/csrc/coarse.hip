@@ -164,7 +164,8 @@ nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
     const int N = c->nc;
-    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv, c->coarse_idx,
+    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv,
+                       c->cycle_fidx ? c->cycle_fidx : c->coarse_idx,
                        y, x, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
@@ -184,7 +185,7 @@ template <typename T>
 nmg_status launch_coarse_solve(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
     const int N = c->nc;
     hipLaunchKernelGGL(k_coarse_solve<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->chol, c->cholT,
-                       c->coarse_idx, y, x, N);
+                       c->cycle_fidx ? c->cycle_fidx : c->coarse_idx, y, x, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

@@ -117,8 +117,8 @@ template <int NL, bool DPP>
 __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restrict__ bres,
                                                             const double* __restrict__ nrm2, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
-                                                            size_t set_stride, const int* __restrict__ ws, int n,
-                                                            int tiles_x, int tiles_per_img) {
+                                                            size_t set_stride, const int* __restrict__ ws, int nsets,
+                                                            int n, int tiles_x, int tiles_per_img) {
     constexpr int NH = NL - 2;
     using G = Geo<NL>;
     constexpr int TW = G::TW, TH = G::TH;
@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
     const int ln = lane & 15;   // N index (pixel within group)
     const int lg = lane >> 4;   // K group / output row group
 
-    const int set = ws ? ws[img] : 0;
+    // out-of-range set indices are clamped so that a bad index cannot read past the weights
+    const int set = ws ? min(max(ws[img], 0), nsets - 1) : 0;
     const uint16_t* wp = wlevel + (size_t)set * set_stride;
 
     short4v w1[2];
@@ -401,13 +402,13 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
         hipLaunchKernelGGL((k_smoother_mfma<3, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, n, tiles_x, tiles);
+                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
         hipLaunchKernelGGL((k_smoother_mfma<4, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, n, tiles_x, tiles);
+                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     }
     NMG_HIP(hipGetLastError());
     return NMG_OK;

@@ -146,6 +146,9 @@ struct Ctx {
     double* alpha_prepared = nullptr;  // [max_batch] alphas of the factors being computed
     int* slot_dev = nullptr;           // [max_batch] cache slots of the factors being computed
     int* coarse_idx = nullptr;         // [max_batch] cache slot of each right-hand side
+    const int* cycle_fidx = nullptr;   // factor index per batch slot used by the cycle (null: coarse_idx)
+    std::vector<int> coarse_idx_host;  // host copy of coarse_idx from the last prepare
+    std::vector<double> alpha_host;    // alphas of the last prepare
     // coarse-factor cache: slot k holds the factors of alpha cache_alpha[k]
     std::vector<double> cache_alpha;   // NaN = empty
     std::vector<long long> cache_used; // last use (prepare counter)
@@ -154,7 +157,12 @@ struct Ctx {
     double* nrm = nullptr;             // [max_batch] per right-hand-side norms
     double* nrm2 = nullptr;            // [max_batch] second norm slot
     double* norm_part = nullptr;       // [max_batch][kNormChunksPerRhs] partial sums
-    double* x64 = nullptr;             // [max_batch][ny][n] refinement scratch
+    double* x64 = nullptr;             // [max_batch][ny][n] compacted FP64 iterates (solve)
+    double* b64 = nullptr;             // [max_batch][ny][n] compacted FP64 right-hand sides (solve)
+    double* slot_d = nullptr;          // [3][max_batch] alpha, ||b||^2, ||r||^2 per compacted slot
+    int* slot_i = nullptr;             // [2][max_batch] weight set, factor index; then [2][max_batch] x 2 move lists
+    std::vector<double> slot_d_host;   // staging for slot_d
+    std::vector<int> slot_i_host;      // staging for slot_i
     float* xs32 = nullptr;             // [max_batch][ny][n] plain-FP32 iterate
     float* bs32 = nullptr;             // [max_batch][ny][n] plain-FP32 right-hand side
     double* r64 = nullptr;
@@ -240,6 +248,10 @@ template <typename T>
 nmg_status launch_zero(T* p, size_t count, hipStream_t s);
 template <typename A, typename B>
 nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s);
+template <typename T>
+nmg_status launch_move_slots(int count, size_t per, T* a, T* b, T* c, const int* moves, hipStream_t s);
+template <typename T>
+nmg_status launch_scatter_slots(int count, size_t per, const T* xc, double* x, const int* pairs, hipStream_t s);
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
                                double rtol, int* active, hipStream_t s);

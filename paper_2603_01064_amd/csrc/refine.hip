@@ -35,7 +35,53 @@ __global__ void __launch_bounds__(kBlock) k_refine_update(X* __restrict__ x, con
     const X rho = (X)sqrt(rn2[b]);
     x[(size_t)b * per + e] += rho * (X)d[(size_t)b * per + e];
 }
+
+// Active-set compaction: moves[2m] = destination slot, moves[2m+1] = source
+// slot; up to three arrays of [slots][per] move together.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_move_slots(T* __restrict__ a, T* __restrict__ b, T* __restrict__ c,
+                                                       const int* __restrict__ moves, size_t per) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= per) return;
+    const size_t dst = (size_t)moves[2 * blockIdx.y] * per + e;
+    const size_t src = (size_t)moves[2 * blockIdx.y + 1] * per + e;
+    a[dst] = a[src];
+    if (b) b[dst] = b[src];
+    if (c) c[dst] = c[src];
+}
+
+// Final iterates of finished slots: pairs[2m] = slot, pairs[2m+1] = right-hand side.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scatter_slots(const T* __restrict__ xc, double* __restrict__ x,
+                                                          const int* __restrict__ pairs, size_t per) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= per) return;
+    x[(size_t)pairs[2 * blockIdx.y + 1] * per + e] = (double)xc[(size_t)pairs[2 * blockIdx.y] * per + e];
+}
 }  // namespace
+
+template <typename T>
+nmg_status launch_move_slots(int count, size_t per, T* a, T* b, T* c, const int* moves, hipStream_t s) {
+    if (count <= 0) return NMG_OK;
+    dim3 grid((unsigned)((per + kBlock - 1) / kBlock), count);
+    hipLaunchKernelGGL((k_move_slots<T>), grid, dim3(kBlock), 0, s, a, b, c, moves, per);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+
+template <typename T>
+nmg_status launch_scatter_slots(int count, size_t per, const T* xc, double* x, const int* pairs, hipStream_t s) {
+    if (count <= 0) return NMG_OK;
+    dim3 grid((unsigned)((per + kBlock - 1) / kBlock), count);
+    hipLaunchKernelGGL((k_scatter_slots<T>), grid, dim3(kBlock), 0, s, xc, x, pairs, per);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+
+template nmg_status launch_move_slots<double>(int, size_t, double*, double*, double*, const int*, hipStream_t);
+template nmg_status launch_move_slots<float>(int, size_t, float*, float*, float*, const int*, hipStream_t);
+template nmg_status launch_scatter_slots<double>(int, size_t, const double*, double*, const int*, hipStream_t);
+template nmg_status launch_scatter_slots<float>(int, size_t, const float*, double*, const int*, hipStream_t);
 
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,

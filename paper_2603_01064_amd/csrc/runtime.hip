@@ -457,6 +457,11 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
     NMG_TRY(dev_alloc(&c->active, (size_t)B));
     NMG_TRY(dev_alloc(&c->x64, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->b64, (size_t)B * level_elems(c.get(), 0)));
+    NMG_TRY(dev_alloc(&c->slot_d, (size_t)3 * B));
+    NMG_TRY(dev_alloc(&c->slot_i, (size_t)6 * B));
+    c->slot_d_host.assign((size_t)3 * B, 0.0);
+    c->slot_i_host.assign((size_t)6 * B, 0);
     NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->xs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->bs32, (size_t)B * level_elems(c.get(), 0)));
@@ -500,6 +505,9 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->hist_dev);
     dev_free(c->active);
     dev_free(c->x64);
+    dev_free(c->b64);
+    dev_free(c->slot_d);
+    dev_free(c->slot_i);
     dev_free(c->r64);
     dev_free(c->xs32);
     dev_free(c->bs32);
@@ -594,7 +602,10 @@ nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha, void* strea
         h->cache_used[(size_t)k] = stamp;
         idx[(size_t)b] = k;
     }
-    NMG_HIP(hipMemcpyAsync(h->coarse_idx, idx.data(), (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
+    h->coarse_idx_host = idx;
+    h->alpha_host = al;
+    NMG_HIP(hipMemcpyAsync(h->coarse_idx, h->coarse_idx_host.data(), (size_t)batch * sizeof(int),
+                           hipMemcpyHostToDevice, s));
     const int cnt = (int)new_slots.size();
     if (cnt > 0) {
         NMG_HIP(hipMemcpyAsync(h->alpha_prepared, new_alphas.data(), (size_t)cnt * sizeof(double),
@@ -692,6 +703,21 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* w
     return run_cycle<float>(h, batch, alpha, ws, (const float*)y, (float*)x, false, *o, s);
 }
 
+namespace {
+// Restores the cycle's factor indexing to the prepare order on every exit of a solve.
+struct FidxGuard {
+    nmg::Ctx* c;
+    ~FidxGuard() { c->cycle_fidx = nullptr; }
+};
+}  // namespace
+
+// Outer iteration with active-set compaction: the right-hand sides still
+// iterating occupy batch slots 0..k-1 of the handle's compacted buffers
+// (iterate, right-hand side, residual, per-slot alpha / weight set / factor
+// index), so every cycle runs on exactly the k active problems.  A finished
+// right-hand side has its iterate copied to x and its slot refilled from the
+// end of the active range.  Each problem's arithmetic does not depend on which
+// slot it sits in or on the other problems of the batch.
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws, const double* b, double* x,
                      double rtol, int max_cycles, const nmg_cycle_opts* o, int* cycles_host, double* history_host,
                      double* done_ms_host, void* stream) {
@@ -705,103 +731,177 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     if (!(rtol > 0.0) || max_cycles < 0) return fail(NMG_ERR_ARG, "rtol must be > 0 and max_cycles >= 0");
     hipStream_t s = (hipStream_t)stream;
     NMG_TRY(nmg_prepare(h, batch, alpha, stream));
+    const int B = h->p.max_batch;
+    std::vector<int> wsv((size_t)batch, 0);
+    if (ws) {
+        NMG_HIP(hipMemcpyAsync(wsv.data(), ws, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
+        NMG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < batch; ++i)
+            if (wsv[(size_t)i] < 0 || wsv[(size_t)i] >= h->p.n_weight_sets)
+                return fail(NMG_ERR_ARG, "weight set out of range (right-hand side " + std::to_string(i) + ")");
+    }
     const size_t per = level_elems(h, 0);
     const size_t cnt = (size_t)batch * per;
     NMG_TRY(ensure_work<double>(h));
     const bool plain32 = o->precision == NMG_FP32;
     if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
-    // plain FP32 keeps its own iterate and right-hand side; its residual lives in r64's storage
-    float* xs = h->xs32;
-    float* bs = h->bs32;
-    float* rs = nullptr;
-    if (plain32) {
-        NMG_TRY(launch_convert<double, float>(b, bs, cnt, s));
-        NMG_TRY(launch_zero<float>(xs, cnt, s));
-        rs = reinterpret_cast<float*>(h->r64);  // r64 has room for cnt doubles
-    } else {
-        NMG_TRY(launch_zero<double>(x, cnt, s));
-    }
+    FidxGuard guard{h};
+    // compacted state: FP64 iterate / rhs / residual, or their FP32 versions for the plain FP32 iteration
+    double* X64 = h->x64;
+    double* B64 = h->b64;
+    double* R64 = h->r64;
+    float* X32 = h->xs32;
+    float* B32 = h->bs32;
+    float* R32 = reinterpret_cast<float*>(h->r64);  // r64 has room for cnt doubles
     NMG_TRY(launch_sumsq<double>(h, batch, per, b, h->nrm2, s));
-    std::vector<double> bn2((size_t)batch), rn2((size_t)batch);
+    std::vector<double> bn2((size_t)batch), rn2((size_t)batch), last_r2((size_t)batch, 0.0);
     NMG_HIP(hipMemcpyAsync(bn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
-    double* bn2_dev = h->hist_dev;
-    NMG_HIP(hipMemcpyAsync(bn2_dev, h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (plain32) {
+        NMG_TRY(launch_convert<double, float>(b, B32, cnt, s));
+        NMG_TRY(launch_zero<float>(X32, cnt, s));
+    } else {
+        NMG_HIP(hipMemcpyAsync(B64, b, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+        NMG_TRY(launch_zero<double>(X64, cnt, s));
+    }
     NMG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < batch; ++i)
         if (!std::isfinite(bn2[(size_t)i])) return fail(NMG_ERR_NONFINITE, "non-finite right-hand side");
     if (history_host)
         for (size_t i = 0; i < (size_t)batch * (max_cycles + 1); ++i) history_host[i] = -1.0;
-    std::vector<int> cyc((size_t)batch, 0);
-    std::vector<char> done((size_t)batch, 0);
+    std::vector<int> cyc((size_t)batch, 0), slot_rhs((size_t)batch);
+    for (int i = 0; i < batch; ++i) slot_rhs[(size_t)i] = i;
+    double* d_alpha = h->slot_d;
+    double* d_bn2 = h->slot_d + B;
+    double* d_rn2 = h->slot_d + 2 * B;
+    int* d_ws = h->slot_i;
+    int* d_fidx = h->slot_i + B;
+    int* d_pairs = h->slot_i + 2 * B;  // 2B ints: finished (slot, rhs) pairs
+    int* d_moves = h->slot_i + 4 * B;  // 2B ints: (destination, source) slot moves
+    std::vector<double>& hd = h->slot_d_host;
+    std::vector<int>& hi = h->slot_i_host;
+    // per-slot tables for slots [0, k); the staging vectors are only rewritten after a stream sync
+    auto upload_slots = [&](int k, bool with_rn2) -> nmg_status {
+        for (int i = 0; i < k; ++i) {
+            const int r = slot_rhs[(size_t)i];
+            hd[(size_t)i] = h->alpha_host[(size_t)r];
+            hd[(size_t)B + i] = bn2[(size_t)r];
+            hd[(size_t)2 * B + i] = with_rn2 ? rn2[(size_t)i] : 0.0;
+            hi[(size_t)i] = wsv[(size_t)r];
+            hi[(size_t)B + i] = h->coarse_idx_host[(size_t)r];
+        }
+        NMG_HIP(hipMemcpyAsync(h->slot_d, hd.data(), (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
+        NMG_HIP(hipMemcpyAsync(h->slot_i, hi.data(), (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
+        return NMG_OK;
+    };
+    int k = batch;
+    NMG_TRY(upload_slots(k, false));
+    h->cycle_fidx = d_fidx;
     bool nonfinite = false;
     const double tol2 = rtol * rtol;
     for (int it = 0; it <= max_cycles; ++it) {
-        // residual and its norm in the outer precision
+        // residual of the active slots and its norm in the outer precision
         {
             ProfScope ps(h, s, NMG_K_REFINE, 0);
             if (plain32) {
-                NMG_TRY(launch_operator<float>(h, 0, batch, alpha, xs, bs, rs, 0, h->w32b, s));
-                NMG_TRY(launch_sumsq<float>(h, batch, per, rs, h->nrm2, s));
+                NMG_TRY(launch_operator<float>(h, 0, k, d_alpha, X32, B32, R32, 0, h->w32b, s));
+                NMG_TRY(launch_sumsq<float>(h, k, per, R32, h->nrm2, s));
             } else {
-                NMG_TRY(launch_operator<double>(h, 0, batch, alpha, x, b, h->r64, 0, h->w64, s));
-                NMG_TRY(launch_sumsq<double>(h, batch, per, h->r64, h->nrm2, s));
+                NMG_TRY(launch_operator<double>(h, 0, k, d_alpha, X64, B64, R64, 0, h->w64, s));
+                NMG_TRY(launch_sumsq<double>(h, k, per, R64, h->nrm2, s));
             }
         }
-        NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+        NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
         NMG_HIP(hipStreamSynchronize(s));
         if (h->prof_mask) NMG_TRY(prof_resolve(h));
-        bool any = false;
-        for (int i = 0; i < batch; ++i) {
-            if (done[(size_t)i]) continue;
-            const double r = rn2[(size_t)i], bb = bn2[(size_t)i];
-            if (!std::isfinite(r)) {
+        const double now_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
+        std::vector<char> keep((size_t)k, 0);
+        int npairs = 0, nkeep = 0;
+        for (int i = 0; i < k; ++i) {
+            const int r = slot_rhs[(size_t)i];
+            const double q = rn2[(size_t)i], bb = bn2[(size_t)r];
+            last_r2[(size_t)r] = q;
+            bool finished = true;
+            if (!std::isfinite(q)) {
                 nonfinite = true;
-                done[(size_t)i] = 1;
-                continue;
+            } else {
+                if (history_host) history_host[(size_t)r * (max_cycles + 1) + it] = bb > 0 ? std::sqrt(q / bb) : 0.0;
+                if (!(q > tol2 * bb)) {
+                    if (done_ms_host) done_ms_host[r] = now_ms;
+                } else if (it < max_cycles) {
+                    finished = false;
+                }
             }
-            if (history_host) history_host[(size_t)i * (max_cycles + 1) + it] = bb > 0 ? std::sqrt(r / bb) : 0.0;
-            if (!(r > tol2 * bb)) {
-                done[(size_t)i] = 1;
-                if (done_ms_host)
-                    done_ms_host[i] =
-                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
-                continue;
+            if (finished) {
+                hi[(size_t)2 * B + 2 * npairs] = i;
+                hi[(size_t)2 * B + 2 * npairs + 1] = r;
+                ++npairs;
+            } else {
+                keep[(size_t)i] = 1;
+                ++nkeep;
             }
-            if (it == max_cycles) continue;
-            any = true;
         }
-        if (!any) break;
-        // d = MG(0, r / ||r||) for active right-hand sides; converged ones get a zero input
+        if (npairs > 0) {
+            NMG_HIP(hipMemcpyAsync(d_pairs, hi.data() + 2 * B, (size_t)2 * npairs * sizeof(int),
+                                   hipMemcpyHostToDevice, s));
+            if (plain32)
+                NMG_TRY(launch_scatter_slots<float>(npairs, per, X32, x, d_pairs, s));
+            else
+                NMG_TRY(launch_scatter_slots<double>(npairs, per, X64, x, d_pairs, s));
+        }
+        if (nkeep == 0) break;
+        // refill the finished slots below nkeep from active slots at or above it
+        int nmoves = 0;
+        {
+            int src = k - 1;
+            for (int dst = 0; dst < nkeep; ++dst) {
+                if (keep[(size_t)dst]) continue;
+                while (!keep[(size_t)src]) --src;  // src >= nkeep holds an active slot
+                hi[(size_t)4 * B + 2 * nmoves] = dst;
+                hi[(size_t)4 * B + 2 * nmoves + 1] = src;
+                ++nmoves;
+                slot_rhs[(size_t)dst] = slot_rhs[(size_t)src];
+                rn2[(size_t)dst] = rn2[(size_t)src];
+                keep[(size_t)src] = 0;
+                --src;
+            }
+        }
+        if (nmoves > 0) {
+            NMG_HIP(hipMemcpyAsync(d_moves, hi.data() + 4 * B, (size_t)2 * nmoves * sizeof(int),
+                                   hipMemcpyHostToDevice, s));
+            if (plain32)
+                NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
+            else
+                NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
+        }
+        k = nkeep;
+        NMG_TRY(upload_slots(k, true));
+        const int* wsd = ws ? d_ws : nullptr;
+        // d = MG(0, r / ||r||), x += ||r|| d on the k active slots
         if (plain32) {
             Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<float, float>(batch, per, rs, w.lv[0].y, h->nrm2, bn2_dev, rtol, h->active, s));
-            NMG_TRY(run_cycle<float>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<float, float>(batch, per, xs, w.lv[0].x, h->nrm2, h->active, s));
+            NMG_TRY(launch_refine_scale<float, float>(k, per, R32, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
+            NMG_TRY(run_cycle<float>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<float, float>(k, per, X32, w.lv[0].x, d_rn2, h->active, s));
         } else if (o->precision == NMG_FP64) {
             Work<double>& w = h->w64;
-            NMG_TRY(launch_refine_scale<double, double>(batch, per, h->r64, w.lv[0].y, h->nrm2, bn2_dev, rtol,
-                                                        h->active, s));
-            NMG_TRY(run_cycle<double>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<double, double>(batch, per, x, w.lv[0].x, h->nrm2, h->active, s));
+            NMG_TRY(launch_refine_scale<double, double>(k, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
+            NMG_TRY(run_cycle<double>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<double, double>(k, per, X64, w.lv[0].x, d_rn2, h->active, s));
         } else {
             Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<double, float>(batch, per, h->r64, w.lv[0].y, h->nrm2, bn2_dev, rtol,
-                                                       h->active, s));
-            NMG_TRY(run_cycle<float>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<double, float>(batch, per, x, w.lv[0].x, h->nrm2, h->active, s));
+            NMG_TRY(launch_refine_scale<double, float>(k, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
+            NMG_TRY(run_cycle<float>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_refine_update<double, float>(k, per, X64, w.lv[0].x, d_rn2, h->active, s));
         }
-        for (int i = 0; i < batch; ++i)
-            if (!done[(size_t)i]) cyc[(size_t)i] += 1;
+        for (int i = 0; i < k; ++i) cyc[(size_t)slot_rhs[(size_t)i]] += 1;
     }
-    if (plain32) NMG_TRY(launch_convert<float, double>(xs, x, cnt, s));
     NMG_HIP(hipStreamSynchronize(s));
     if (cycles_host)
         for (int i = 0; i < batch; ++i) cycles_host[i] = cyc[(size_t)i];
     if (nonfinite) return fail(NMG_ERR_NONFINITE, "non-finite residual");
-    for (int i = 0; i < batch; ++i) {
-        const double r = rn2[(size_t)i], bb = bn2[(size_t)i];
-        if (r > tol2 * bb) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
-    }
+    for (int i = 0; i < batch; ++i)
+        if (last_r2[(size_t)i] > tol2 * bn2[(size_t)i]) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
     return NMG_OK;
 }
 

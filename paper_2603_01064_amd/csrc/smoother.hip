@@ -22,7 +22,7 @@ constexpr int kBlock = 256;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_conv(const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ wlevel, const int* __restrict__ ws,
-                                                 int wcount, int layer_off, int cin, int cout, int kh, int kw,
+                                                 int nsets, int wcount, int layer_off, int cin, int cout, int kh, int kw,
                                                  int ny, int n, int relu, int first, int last, int accumulate,
                                                  const double* __restrict__ nrm2) {
     const size_t per = (size_t)ny * n;
@@ -31,7 +31,8 @@ __global__ void __launch_bounds__(kBlock) k_conv(const T* __restrict__ in, T* __
     const int co = blockIdx.y;
     const int b = blockIdx.z;
     const int y = (int)(e / n), x = (int)(e % n);
-    const int set = ws ? ws[b] : 0;
+    // out-of-range set indices are clamped so that a bad index cannot read past the weights
+    const int set = ws ? min(max(ws[b], 0), nsets - 1) : 0;
     const T* w = wlevel + (size_t)set * wcount + layer_off + (size_t)co * cin * kh * kw;
     const double nb = sqrt(nrm2[b]);
     const T inscale = first ? (nb > 0.0 ? (T)(1.0 / nb) : (T)0) : (T)1;
@@ -107,7 +108,8 @@ nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, c
         const int first = i == 0, last = i == nl - 1;
         T* out = last ? dst : bufs[i & 1];
         dim3 grid(blocks_for(per), last ? 1 : cout, batch);
-        hipLaunchKernelGGL(k_conv<T>, grid, dim3(kBlock), 0, s, src, out, wl, ws, c->wcount, c->layer_off[i], cin,
+        hipLaunchKernelGGL(k_conv<T>, grid, dim3(kBlock), 0, s, src, out, wl, ws, c->p.n_weight_sets, c->wcount,
+                           c->layer_off[i], cin,
                            cout, kh, kw, ny, n, last ? 0 : 1, first, last, accumulate, nrm2);
         src = out;
     }

@@ -1,0 +1,157 @@
+"""Batched solve with active-set compaction: right-hand sides that converge
+leave the batch, so later cycles run on fewer problems.  Checked against the
+FP64 oracle's per-right-hand-side stopping rule (Sec. 2.3 outer iteration,
+1e-12 relative per cycle) and for batch invariance: every result of a mixed
+batch is bit-identical to solving that right-hand side alone."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s0.01.npz")
+
+
+def _nmg():
+    from paper_2603_01064_amd import nmg
+    nmg.load_library()
+    return nmg
+
+
+def _rel(a, b):
+    return float((a - b).norm() / max(float(b.norm()), 1e-300))
+
+
+def _jacobi_omegas(H, L, alpha_min):
+    """omega_l = 1 / rho(D_l^-1 A_l) at the smallest alpha of the batch; a
+    larger alpha only lowers rho, so the same omega stays convergent."""
+    out = []
+    for l in range(L - 1):
+        A = O.dense_operator(H, l, alpha_min)
+        d = torch.diagonal(A)
+        out.append(1.0 / float(torch.linalg.eigvals(A / d[:, None]).abs().max()))
+    return out
+
+
+def test_fp64_compaction_matches_oracle_per_rhs():
+    """Four alphas converge after different cycle counts; the compacted solve
+    reproduces the oracle's iterates, histories and counts per right-hand side."""
+    print("case solve fp64 compaction Jacobi 31 B=4", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    n, s, L = 31, 0.04, 3
+    alpha = torch.tensor([0.05, 1.0, 0.1, 0.3], dtype=DT)
+    H = O.build_hierarchy(n, s, L, dim=2)
+    om = _jacobi_omegas(H, L, float(alpha.min()))
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2200 + i) for i in range(4)]))
+    y = O.apply_operator(H, 0, u, alpha)
+    ref = O.solve(H, [O.jacobi_smoother(om)] * (L - 1), y, alpha, tol=1e-10, max_cycles=500)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=4, channels=(1, 4, 4, 1), ksize=3))
+    for l in range(L - 1):
+        h.set_jacobi_smoother(l, om[l])
+    x, cyc, hist, st = h.solve(y.to(dev), alpha.to(dev), rtol=1e-10, max_cycles=500, precision="fp64",
+                               history=True)
+    print(f"  cycles gpu {list(cyc)} oracle {[int(c) for c in ref.cycles]}", flush=True)
+    assert st == 0
+    assert len(set(int(c) for c in cyc)) > 1, "the case must exercise compaction"
+    assert list(cyc) == [int(c) for c in ref.cycles]
+    for b in range(4):
+        assert _rel(x[b].cpu(), ref.x[b]) < 1e-12
+        for k, hr in enumerate(ref.history):
+            if hist[b, k] >= 0:
+                assert abs(hist[b, k] - float(hr[b])) <= 1e-9 * float(hr[b]) + 1e-14
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_zero_rhs_and_compaction(prec):
+    """A zero right-hand side is converged before the first cycle (x = 0, no
+    cycles) and leaves the batch at once; the others are unaffected."""
+    print(f"case solve zero rhs {prec}", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    n, s, L, av = 31, 0.04, 3, 0.1
+    H = O.build_hierarchy(n, s, L, dim=2)
+    om = _jacobi_omegas(H, L, av)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=3, channels=(1, 4, 4, 1), ksize=3))
+    for l in range(L - 1):
+        h.set_jacobi_smoother(l, om[l])
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2300 + i) for i in range(3)]))
+    alpha = torch.full((3,), av, dtype=DT)
+    y = O.apply_operator(H, 0, u, alpha)
+    y[0] = 0.0
+    x, cyc, hist, st = h.solve(y.to(dev), alpha.to(dev), rtol=1e-6, max_cycles=300, precision=prec, history=True)
+    assert st == 0
+    assert int(cyc[0]) == 0 and float(x[0].abs().max()) == 0.0
+    solo, cs, _, _ = h.solve(y[1:2].to(dev), alpha[1:2].to(dev), rtol=1e-6, max_cycles=300, precision=prec)
+    assert int(cs[0]) == int(cyc[1]) and torch.equal(solo[0], x[1])
+    h.close()
+
+
+def _trained():
+    from paper_2603_01064_amd.train_weights import load_weights
+    return load_weights(WEIGHTS)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def test_batch_invariance_trained_255(prec):
+    """The benchmark problem (255x255, s = 0.01, trained BF16 smoothers, mixed
+    alphas): each right-hand side of a batch of 6 gives bit-identically the
+    iterate, cycle count and residual history of a solo solve."""
+    print(f"case batch invariance 255 {prec}", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    meta, sets = _trained()
+    n, s, L = meta["n"], meta["s"], meta["levels"]
+    cyc_cfg = meta["cycle"]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=6, channels=(1, 32, 32, 1), ksize=3,
+                                        n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(L - 1):
+            h.load_smoother_weights(l, k, [ws[l]])
+    al = [1e-2, 1e-4, 1e-3, 1e-2, 1e-3, 1e-4]
+    alpha = torch.tensor(al, dtype=DT, device=dev)
+    wsel = [min(range(len(sets)), key=lambda i: abs(math.log(meta["alphas"][i] / a))) for a in al]
+    ws = torch.tensor(wsel, dtype=torch.int32, device=dev)
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2400 + i) for i in range(6)]), device=dev)
+    b = h.apply_operator(0, u, alpha, "fp64")
+    kw = dict(rtol=1e-6, max_cycles=200, nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"], use_fprime=cyc_cfg["use_fprime"],
+              precision=prec, history=True)
+    x, cyc, hist, st = h.solve(b, alpha, weight_set=ws, **kw)
+    print(f"  cycles {list(cyc)}", flush=True)
+    assert st == 0
+    assert len(set(int(c) for c in cyc)) > 1
+    for i in (0, 1, 4):
+        xs, cs, hs, ss = h.solve(b[i:i + 1], alpha[i:i + 1], weight_set=ws[i:i + 1], **kw)
+        assert ss == 0 and int(cs[0]) == int(cyc[i])
+        assert torch.equal(xs[0], x[i])
+        assert np.array_equal(hs[0], hist[i])
+    # the converged iterate solves the FP64 system to the requested tolerance
+    r = b - h.apply_operator(0, x, alpha, "fp64")
+    rel = (r.flatten(1).norm(dim=1) / b.flatten(1).norm(dim=1)).cpu()
+    assert float(rel.max()) <= 1e-6
+    h.close()
+
+
+def test_out_of_range_weight_set_rejected():
+    print("case solve bad weight set", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    h = nmg.setup_hierarchy(nmg.Problem(n=31, s=0.04, levels=3, max_batch=2, channels=(1, 4, 4, 1), ksize=3,
+                                        n_weight_sets=2))
+    for l in range(2):
+        h.set_jacobi_smoother(l, 0.1)
+    b = torch.ones(2, 31, 31, dtype=DT, device=dev)
+    alpha = torch.full((2,), 0.1, dtype=DT, device=dev)
+    with pytest.raises(nmg.NMGError):
+        h.solve(b, alpha, weight_set=torch.tensor([0, 2], dtype=torch.int32, device=dev), max_cycles=3)
+    with pytest.raises(nmg.NMGError):
+        h.solve(b, alpha, weight_set=torch.tensor([-1, 0], dtype=torch.int32, device=dev), max_cycles=3)
+    h.close()
