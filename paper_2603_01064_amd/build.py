@@ -18,6 +18,8 @@ FLAGS = [
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    # MFMA results in ordinary VGPRs (no accumulation-register copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 SOURCES = ["hierarchy.cpp", "stencil.hip", "smoother.hip", "coarse.hip", "fprime.hip", "fprime_mfma.hip",
            "refine.hip", "mfma_smoother.hip", "train.hip", "runtime.hip"]

@@ -81,15 +81,25 @@ struct Geo {
 typedef float float2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// ReLU, round to BF16 (hardware RNE pack) and pack four channels.
+// Round four channels to BF16 (hardware RNE pack), then ReLU on the packed
+// halves: a BF16 value is negative exactly when its 16-bit pattern is
+// negative as a signed integer, so max(v, 0) per 16-bit lane is the ReLU
+// (and rounding commutes with it: rounding never changes the sign).
+typedef short short2v __attribute__((ext_vector_type(2)));
 __device__ inline uint2 relu_pack4(floatx4 a) {
-    const float2v lo = {fmaxf(a[0], 0.f), fmaxf(a[1], 0.f)};
-    const float2v hi = {fmaxf(a[2], 0.f), fmaxf(a[3], 0.f)};
+    const float2v lo = {a[0], a[1]};
+    const float2v hi = {a[2], a[3]};
     const bf16x2 pl = __builtin_convertvector(lo, bf16x2);
     const bf16x2 ph = __builtin_convertvector(hi, bf16x2);
+    short2v sl, sh;
+    __builtin_memcpy(&sl, &pl, 4);
+    __builtin_memcpy(&sh, &ph, 4);
+    const short2v z = {0, 0};
+    sl = __builtin_elementwise_max(sl, z);
+    sh = __builtin_elementwise_max(sh, z);
     uint2 r;
-    __builtin_memcpy(&r.x, &pl, 4);
-    __builtin_memcpy(&r.y, &ph, 4);
+    __builtin_memcpy(&r.x, &sl, 4);
+    __builtin_memcpy(&r.y, &sh, 4);
     return r;
 }
 
@@ -401,13 +411,13 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
         using G = Geo<3>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
-        hipLaunchKernelGGL((k_smoother_mfma<3, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+        hipLaunchKernelGGL((k_smoother_mfma<3, false>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
-        hipLaunchKernelGGL((k_smoother_mfma<4, true>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+        hipLaunchKernelGGL((k_smoother_mfma<4, false>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     }
     NMG_HIP(hipGetLastError());

@@ -7,6 +7,8 @@
 // each column that also forms y - A x.  Transfers are full weighting
 // (1/4, 1/2, 1/4 per axis) and linear interpolation with zero boundary
 // values (Sec. 2.3).
+#include <type_traits>
+
 #include "nmg_internal.h"
 
 namespace nmg {
@@ -415,6 +417,235 @@ __global__ void __launch_bounds__(kBlock) k_residual_tiled(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled residual with a compile-time tap count TP (the Toeplitz interior of
+// G_l, 2 r_g + 1 taps zero-padded to a multiple of 4).  The staged tile has
+// TH + TP rows and TW + TP columns, so every loop has fixed trip counts and
+// unrolls fully; the row pass X G overwrites the staged tile in place (its
+// results are held in registers across a barrier), which keeps the LDS
+// footprint at one tile and allows three or more workgroups per CU.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void lds_load4v(const T* p, T* w) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        w[0] = a.x; w[1] = a.y; w[2] = b.x; w[3] = b.y;
+    }
+}
+
+template <typename T, int TH, int TW, int TP, int OC, int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) k_residual_fixed(
+    const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ out, const double* __restrict__ alpha, int n,
+    int mode, const T* __restrict__ tg, int rg, const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
+    const T* __restrict__ tm, int m_ident, int tiles_x) {
+    constexpr int XH = TH + TP, XW = TW + TP;     // staged rows / columns (image i0 - rg + r, j0 - rg + c)
+    constexpr int CG = TW / 4;                     // row-pass items per row (4 outputs each)
+    constexpr int RITEMS = (XH * CG + NT - 1) / NT;
+    constexpr int CITEMS = (TH / OC) * TW;         // column-pass items (OC outputs each)
+    constexpr int CPT = (CITEMS + NT - 1) / NT;
+    constexpr int MH = TH + 4;                     // rows of X M (radius 1, 4 padded taps)
+    constexpr int WAVES = NT / 64;
+    constexpr int KC = (XW + 63) / 64;             // 64-column chunks per staged row
+    constexpr int SU = (XH + WAVES - 1) / WAVES;   // staged rows per wave
+    static_assert(TH % OC == 0 && TW % 4 == 0 && TP % 4 == 0, "tile shape");
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+    T* TMs = X + XH * XW;
+    const int b = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int i0 = (tile / tiles_x) * TH, j0 = (tile % tiles_x) * TW;
+    const size_t per = (size_t)n * n;
+    const T* xs = x + (size_t)b * per;
+    const int tid = threadIdx.x;
+    const T* taps = tg;
+    // ---- stage the tile with its halo (zero outside the grid); every load of
+    // a thread is issued before the first LDS store
+    {
+        // batches of SB rows per wave keep the in-flight values within the register budget
+        constexpr int SB = sizeof(T) == 4 ? SU : (SU + 1) / 2;
+        const int tx = tid & 63, ty = tid / 64;
+#pragma unroll
+        for (int u0 = 0; u0 < SU; u0 += SB) {
+            T v[SB][KC];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int r = ty + WAVES * (u0 + u);
+                const int gi = i0 - rg + r;
+                const bool row_in = u0 + u < SU && r < XH && gi >= 0 && gi < n;
+                const T* src = xs + (size_t)(row_in ? gi : 0) * n;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int c = tx + 64 * k;
+                    const int gj = j0 - rg + c;
+                    v[u][k] = (row_in && c < XW && gj >= 0 && gj < n) ? src[gj] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int r = ty + WAVES * (u0 + u);
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (u0 + u < SU && r < XH && tx + 64 * k < XW) X[r * XW + tx + 64 * k] = v[u][k];
+            }
+        }
+    }
+    // right-hand side of this thread's outputs, in flight during the passes
+    T yv[CPT][OC];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int item = tid + q * NT;
+        const int ii = (item / TW) * OC, jj = item % TW;
+#pragma unroll
+        for (int o = 0; o < OC; ++o) {
+            const int i = i0 + ii + o, j = j0 + jj;
+            yv[q][o] = (mode == 0 && item < CITEMS && i < n && j < n) ? y[(size_t)b * per + (size_t)i * n + j] : (T)0;
+        }
+    }
+    __syncthreads();
+    // ---- values the column pass needs from X before it is overwritten
+    T xc[CPT][OC];
+    if (m_ident) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int item = tid + q * NT;
+            const int ii = (item / TW) * OC, jj = item % TW;
+#pragma unroll
+            for (int o = 0; o < OC; ++o) xc[q][o] = item < CITEMS ? X[(ii + o + rg) * XW + jj + rg] : (T)0;
+        }
+    } else {
+        // X M on rows i0 - 1 .. i0 + TH (M has radius 1 and an exact Toeplitz form)
+        const T m0 = tm[0], m1 = tm[1], m2 = tm[2];
+        for (int e = tid; e < MH * TW; e += NT) {
+            const int r = e / TW, jj = e % TW;
+            T v = 0;
+            if (r < TH + 2) {
+                const T* row = X + (r + rg - 1) * XW + jj + rg - 1;
+                v = m0 * row[0] + m1 * row[1] + m2 * row[2];
+            }
+            TMs[e] = v;
+        }
+    }
+    // ---- row pass into registers
+    T racc[RITEMS][4];
+#pragma unroll
+    for (int q = 0; q < RITEMS; ++q) {
+        const int item = tid + q * NT;
+        const int r = item / CG, jj = (item % CG) * 4;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) racc[q][o] = 0;
+        if (item < XH * CG) {
+            const T* row = X + r * XW + jj;
+            // sliding window of 8 values, refilled 4 at a time
+            T w[8];
+            lds_load4v<T>(row, w);
+#pragma unroll
+            for (int t4 = 0; t4 < TP; t4 += 4) {
+                lds_load4v<T>(row + t4 + 4, w + 4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const T ct = taps[t4 + t];
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) racc[q][o] = fma(ct, w[o + t], racc[q][o]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[k] = w[4 + k];
+            }
+            const int j = j0 + jj;
+            if (rc > 0 && (j < rc || j + 3 >= n - rc)) {
+                for (int o = 0; o < 4; ++o) {
+                    const int jo = j + o;
+                    if (jo < rc) {
+                        T s2 = 0;
+                        for (int p = 0; p < rc; ++p) s2 += dtl[p * rc + jo] * X[r * XW + (p - j0 + rg)];
+                        racc[q][o] += s2;
+                    } else if (jo >= n - rc && jo < n) {
+                        T s2 = 0;
+                        const int jb = jo - (n - rc);
+                        for (int p = 0; p < rc; ++p) s2 += dbr[p * rc + jb] * X[r * XW + (n - rc + p - j0 + rg)];
+                        racc[q][o] += s2;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // X G replaces the staged tile: row r keeps its TW row-pass values in columns 0..TW-1
+#pragma unroll
+    for (int q = 0; q < RITEMS; ++q) {
+        const int item = tid + q * NT;
+        if (item < XH * CG) {
+            const int r = item / CG, jj = (item % CG) * 4;
+            T* dst = X + r * XW + jj;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) dst[o] = racc[q][o];
+        }
+    }
+    __syncthreads();
+    // ---- column pass and combination
+    const T a = (T)alpha[b];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int item = tid + q * NT;
+        if (item >= CITEMS) continue;
+        const int ii = (item / TW) * OC, jj = item % TW;
+        const int j = j0 + jj;
+        T g[OC];
+#pragma unroll
+        for (int o = 0; o < OC; ++o) g[o] = 0;
+        {
+            // sliding window of OC + 4 values down the column, refilled 4 at a time
+            const T* col = X + ii * XW + jj;
+            T w[OC + 4];
+#pragma unroll
+            for (int k = 0; k < OC; ++k) w[k] = col[k * XW];
+#pragma unroll
+            for (int t4 = 0; t4 < TP; t4 += 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[OC + k] = col[(t4 + OC + k) * XW];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const T ct = taps[t4 + t];
+#pragma unroll
+                    for (int o = 0; o < OC; ++o) g[o] = fma(ct, w[o + t], g[o]);
+                }
+#pragma unroll
+                for (int k = 0; k < OC; ++k) w[k] = w[4 + k];
+            }
+        }
+        T mv[OC];
+        if (m_ident) {
+#pragma unroll
+            for (int o = 0; o < OC; ++o) mv[o] = xc[q][o];
+        } else {
+            const T m0 = tm[0], m1 = tm[1], m2 = tm[2];
+#pragma unroll
+            for (int o = 0; o < OC; ++o) {
+                const T* col = TMs + (ii + o) * TW + jj;
+                mv[o] = m0 * col[0] + m1 * col[TW] + m2 * col[2 * TW];
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < OC; ++o) {
+            const int i = i0 + ii + o;
+            if (i >= n || j >= n) continue;
+            T corr = 0;
+            if (i < rc) {
+                for (int p = 0; p < rc; ++p) corr += dtl[i * rc + p] * X[(p - i0 + rg) * XW + jj];
+            } else if (i >= n - rc) {
+                const int ib = i - (n - rc);
+                for (int p = 0; p < rc; ++p) corr += dbr[ib * rc + p] * X[(n - rc + p - i0 + rg) * XW + jj];
+            }
+            const T ax = a * mv[o] + (g[o] + corr);
+            const size_t idx = (size_t)b * per + (size_t)i * n + j;
+            out[idx] = mode == 0 ? yv[q][o] - ax : ax;
+        }
+    }
+}
+
 }  // namespace
 
 size_t level_elems(const Ctx* c, int l) { return (size_t)(c->p.dim == 2 ? c->n[l] : 1) * c->n[l]; }
@@ -431,6 +662,41 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
     const size_t per = level_elems(c, l);
     const HostLevel& hl = c->host[l];
     const TiledOp<T>& op = w.tiled[(size_t)l];
+    if (c->p.dim == 2 && op.ok && op.rgp <= 48 && (op.m_ident || op.rm == 1)) {
+        // fixed-tap kernel: TP = padded Toeplitz taps of G_l
+        bool launched = false;
+        nmg_status st = NMG_OK;
+        auto go = [&](auto tp_tag) {
+            constexpr int TP = decltype(tp_tag)::value;
+            if (launched || op.rgp != TP) return;
+            launched = true;
+            // FP32: 128 x 64 tiles, 512 threads, 4 waves per SIMD; FP64: 32 x 32 tiles, 256 threads
+            constexpr bool F = sizeof(T) == 4;
+            constexpr int TH = F ? 128 : 32, TW = F ? 64 : 32, OC = F ? 8 : 4, NT = F ? 512 : 256, WPE = F ? 4 : 1;
+            const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
+            const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW)) * sizeof(T);
+            hipLaunchKernelGGL((k_residual_fixed<T, TH, TW, TP, OC, NT, WPE>), dim3(tiles_x * tiles_y, batch), dim3(NT),
+                               lds, s, x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
+                               op.m_ident, tiles_x);
+            st = NMG_OK;
+        };
+        go(std::integral_constant<int, 4>{});
+        go(std::integral_constant<int, 8>{});
+        go(std::integral_constant<int, 12>{});
+        go(std::integral_constant<int, 16>{});
+        go(std::integral_constant<int, 20>{});
+        go(std::integral_constant<int, 24>{});
+        go(std::integral_constant<int, 28>{});
+        go(std::integral_constant<int, 32>{});
+        go(std::integral_constant<int, 36>{});
+        go(std::integral_constant<int, 40>{});
+        go(std::integral_constant<int, 44>{});
+        go(std::integral_constant<int, 48>{});
+        if (launched) {
+            NMG_HIP(hipGetLastError());
+            return st;
+        }
+    }
     if (c->p.dim == 2 && op.ok) {
         constexpr int TH = tile_h<T>(), TW = tile_w<T>();
         const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
