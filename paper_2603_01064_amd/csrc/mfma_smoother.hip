@@ -16,6 +16,7 @@
 //                           then out[p] = sum_t Z[p + off(t)][t]
 // Weights are packed once per weight set into the per-lane operand order and
 // kept in registers while a workgroup walks the tiles of its image.
+#include <type_traits>
 #include <vector>
 
 #include "nmg_internal.h"
@@ -72,10 +73,15 @@ struct Geo {
     static constexpr int W0 = TW + 2 * NL, H0 = TH + 2 * NL;
     static constexpr int W(int i) { return TW + 2 * (NL - i); }
     static constexpr int H(int i) { return TH + 2 * (NL - i); }
-    static constexpr int in_bytes = ((W0 * H0 * 2 + 255) / 256) * 256;
+    // first-layer operand records: pixel (r, c) of the input tile holds the
+    // BF16 values of columns c, c+1, c+2 (and a zero), one 8-byte record
+    static constexpr int RW = W0 - 2;  // = W(1)
+    static constexpr int NREC = H0 * RW;
+    static constexpr int in_bytes = ((NREC * 8 + 255) / 256) * 256;
     static constexpr int bufA = H(1) * kP * 64;
     static constexpr int bufB = H(2) * kP * 64;
     static constexpr int lds = in_bytes + bufA + bufB;
+    static constexpr int RPT = (NREC + 255) / 256;  // records per thread
 };
 
 typedef float float2v __attribute__((ext_vector_type(2)));
@@ -103,27 +109,15 @@ __device__ inline uint2 relu_pack4(floatx4 a) {
     return r;
 }
 
-__device__ inline uint16_t to_bf16(float v) {
-    const float2v f = {v, 0.f};
+__device__ inline uint32_t pack2_bf16(float a, float b) {
+    const float2v f = {a, b};
     const bf16x2 p = __builtin_convertvector(f, bf16x2);
     uint32_t u;
     __builtin_memcpy(&u, &p, 4);
-    return (uint16_t)(u & 0xFFFFu);
+    return u;
 }
 
-__device__ inline bf16x8 shift_rows(bf16x8 v, bf16x8 fill) {
-    // lane n of each 16-lane row takes lane n+1's operand; lane 15 takes `fill`
-    typedef int int4v __attribute__((ext_vector_type(4)));
-    int4v a, f, r;
-    __builtin_memcpy(&a, &v, 16);
-    __builtin_memcpy(&f, &fill, 16);
-    for (int k = 0; k < 4; ++k) r[k] = __builtin_amdgcn_update_dpp(f[k], a[k], 0x101, 0xF, 0xF, false);
-    bf16x8 out;
-    __builtin_memcpy(&out, &r, 16);
-    return out;
-}
-
-template <int NL, bool DPP>
+template <int NL>
 __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restrict__ bres,
                                                             const double* __restrict__ nrm2, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
@@ -131,9 +125,9 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                                                             int n, int tiles_x, int tiles_per_img) {
     constexpr int NH = NL - 2;
     using G = Geo<NL>;
-    constexpr int TW = G::TW, TH = G::TH;
+    constexpr int TW = G::TW, TH = G::TH, RW = G::RW;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    uint16_t* in_t = reinterpret_cast<uint16_t*>(smem);
+    char* recs = smem;
     char* bufA = smem + G::in_bytes;
     char* bufB = bufA + G::bufA;
 
@@ -159,10 +153,9 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
     const bf16x8 wl = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)NH * kHiddenElems + lane * 8);
 
     // per-lane constants for 16-aligned pixel groups (column = 16 k + ln): the
-    // operand chunk offset of pixels ln, ln+1, ln+2, of the halo pixels 16 and
-    // 17, and the output chunk offsets of channels nb*16 + 4*lg .. +3
+    // operand chunk offsets of pixels ln, ln+1, ln+2 and the output chunk
+    // offsets of channels nb*16 + 4*lg .. +3
     const int swz0 = swz(ln, lg), swz1 = swz(ln + 1, lg), swz2 = swz(ln + 2, lg);
-    const int swz16 = swz(16, lg), swz17 = swz(17, lg);
     int out_off[2];
     for (int nb = 0; nb < 2; ++nb) {
         const int co = nb * 16 + lg * 4;
@@ -176,92 +169,94 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
     const float nbf = (float)sqrt(nb2);
     const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
 
+    // input values of this thread's first-layer records (three per record),
+    // loaded one tile ahead so the global latency overlaps the layers
+    float pv[G::RPT][3];
+    auto load_records = [&](int tile) {
+        const int ty0 = (tile / tiles_x) * TH, tx0 = (tile % tiles_x) * TW;
+#pragma unroll
+        for (int k = 0; k < G::RPT; ++k) {
+            const int e = tid + k * kThreads;
+            const int r = e / RW, c = e - (e / RW) * RW;
+            const int gy = ty0 - NL + r, gx = tx0 - NL + c;
+            const bool row_ok = e < G::NREC && gy >= 0 && gy < n;
+            const float* rp = src + (size_t)(row_ok ? gy : 0) * n;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                pv[k][d] = (tile < tiles_per_img && row_ok && gx + d >= 0 && gx + d < n) ? rp[gx + d] : 0.f;
+        }
+    };
+    load_records(blockIdx.x);
+
     for (int tile = blockIdx.x; tile < tiles_per_img; tile += gridDim.x) {
         const int ty0 = (tile / tiles_x) * TH, tx0 = (tile % tiles_x) * TW;
-        // ---- input tile (halo NL), scaled by 1/||b||, zero outside the image
-        for (int r = wave; r < G::H0; r += 4) {
-            const int gy = ty0 - NL + r;
-            for (int c = lane; c < G::W0; c += 64) {
-                const int gx = tx0 - NL + c;
-                float v = 0.f;
-                if (gy >= 0 && gy < n && gx >= 0 && gx < n) v = src[(size_t)gy * n + gx] * inv;
-                in_t[r * G::W0 + c] = to_bf16(v);
-            }
+        // ---- records of this tile (scaled by 1/||b||, zero outside the image)
+#pragma unroll
+        for (int k = 0; k < G::RPT; ++k) {
+            const int e = tid + k * kThreads;
+            if (e < G::NREC)
+                *reinterpret_cast<uint2*>(recs + e * 8) =
+                    make_uint2(pack2_bf16(pv[k][0] * inv, pv[k][1] * inv), pack2_bf16(pv[k][2] * inv, 0.f));
         }
+        load_records(tile + gridDim.x);
         __syncthreads();
-        // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16);
-        //      operand K slot (lane/16, j) is tap (dy, dx) = (lane/16, j)
-        {
-            constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
-            constexpr int npx = S * HH, ngr = (npx + 15) / 16;
-            int q0 = wave * 16 + ln;
-            int ry = q0 / S, rx = q0 - (q0 / S) * S;
-            for (int gi = wave; gi < ngr; gi += 4) {
-                const bool live = q0 < npx;
-                const int ryc = live ? ry : HH - 1, rxc = live ? rx : S - 1;
-                short4v bop = {0, 0, 0, 0};
-                if (lg < 3) {
-                    const uint16_t* ip = in_t + (ryc + lg) * G::W0 + rxc;
-                    bop[0] = (short)ip[0];
-                    bop[1] = (short)ip[1];
-                    bop[2] = (short)ip[2];
-                }
-                const int gy = ty0 - HALO + ryc, gx = tx0 - HALO + rxc;
-                const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
-                for (int nb = 0; nb < 2; ++nb) {
-                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc, 0, 0, 0);
-                    if (live) {
-                        const int co = nb * 16 + lg * 4;
-                        const uint2 v = inside ? relu_pack4(acc) : make_uint2(0u, 0u);
-                        *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
+        // tiles whose input region lies inside the image need no zero masking
+        const bool interior = ty0 >= NL && tx0 >= NL && ty0 + TH + NL <= n && tx0 + TW + NL <= n;
+        auto layers = [&](auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16);
+            //      operand K slot (lane/16, j) is tap (dy, dx) = (lane/16, j)
+            {
+                constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
+                constexpr int npx = S * HH, ngr = (npx + 15) / 16;
+                int q0 = wave * 16 + ln;
+                int ry = q0 / S, rx = q0 - (q0 / S) * S;
+                for (int gi = wave; gi < ngr; gi += 4) {
+                    const bool live = q0 < npx;
+                    const int ryc = live ? ry : HH - 1, rxc = live ? rx : S - 1;
+                    short4v bop = {0, 0, 0, 0};
+                    if (lg < 3) bop = *reinterpret_cast<const short4v*>(recs + ((ryc + lg) * RW + rxc) * 8);
+                    bool inside = true;
+                    if constexpr (EDGE) {
+                        const int gy = ty0 - HALO + ryc, gx = tx0 - HALO + rxc;
+                        inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                    }
+                    for (int nb = 0; nb < 2; ++nb) {
+                        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc, 0, 0, 0);
+                        if (live) {
+                            const int co = nb * 16 + lg * 4;
+                            const uint2 v = inside ? relu_pack4(acc) : make_uint2(0u, 0u);
+                            *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
+                        }
+                    }
+                    // advance this lane's pixel by 64 = (64 / S) rows + (64 % S) columns
+                    q0 += 64;
+                    rx += 64 % S;
+                    ry += 64 / S;
+                    if (rx >= S) {
+                        rx -= S;
+                        ry += 1;
                     }
                 }
-                // advance this lane's pixel by 64 = (64 / S) rows + (64 % S) columns
-                q0 += 64;
-                rx += 64 % S;
-                ry += 64 / S;
-                if (rx >= S) {
-                    rx -= S;
-                    ry += 1;
-                }
             }
-        }
-        __syncthreads();
-        // ---- hidden layers 32 -> 32: groups are 16 consecutive pixels of a row
+            __syncthreads();
+            // ---- hidden layers 32 -> 32: groups are 16 consecutive pixels of a row
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            const int layer = 2 + h;
-            const int S = TW + 2 * (NL - layer), HH = TH + 2 * (NL - layer), HALO = NL - layer;
-            const int ngr = HH * 2;  // S <= 32: two groups per row
-            const char* ain = (h & 1) ? bufB : bufA;
-            char* aout = (h & 1) ? bufA : bufB;
-            for (int gi = wave; gi < ngr; gi += 4) {
-                const int ry = gi >> 1, rx0 = (gi & 1) * 16;
-                const int rx = rx0 + ln;
-                const char* a0 = ain + (ry * kP + rx) * 64 + swz0;         // tap (dy, 0) of pixel rx
-                floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-                if constexpr (DPP) {
-                    const char* e0 = ain + (ry * kP + rx0 + 16) * 64 + swz16;  // pixel rx0+16
-                    const char* e1 = ain + (ry * kP + rx0 + 17) * 64 + swz17;  // pixel rx0+17
-#pragma unroll
-                    for (int dy = 0; dy < 3; ++dy) {
-                        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
-                        const bf16x8 x16 = *reinterpret_cast<const bf16x8*>(e0 + dy * kP * 64);
-                        const bf16x8 x17 = *reinterpret_cast<const bf16x8*>(e1 + dy * kP * 64);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][0], b0, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][1], b0, acc1, 0, 0, 0);
-                        const bf16x8 b1 = shift_rows(b0, x16);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][0], b1, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][1], b1, acc1, 0, 0, 0);
-                        const bf16x8 b2 = shift_rows(b1, x17);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][0], b2, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][1], b2, acc1, 0, 0, 0);
-                    }
-                } else {
+            for (int h = 0; h < NH; ++h) {
+                const int layer = 2 + h;
+                const int S = TW + 2 * (NL - layer), HH = TH + 2 * (NL - layer), HALO = NL - layer;
+                const int ngr = HH * 2;  // S <= 32: two groups per row
+                const char* ain = (h & 1) ? bufB : bufA;
+                char* aout = (h & 1) ? bufA : bufB;
+                for (int gi = wave; gi < ngr; gi += 4) {
+                    const int ry = gi >> 1, rx0 = (gi & 1) * 16;
+                    const int rx = rx0 + ln;
                     // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
+                    const char* a0 = ain + (ry * kP + rx) * 64 + swz0;
                     const char* a1 = ain + (ry * kP + rx + 1) * 64 + swz1;
                     const char* a2 = ain + (ry * kP + rx + 2) * 64 + swz2;
+                    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int dy = 0; dy < 3; ++dy) {
                         const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
@@ -274,57 +269,64 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][0], b2, acc0, 0, 0, 0);
                         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][1], b2, acc1, 0, 0, 0);
                     }
+                    if (rx < S) {
+                        bool inside = true;
+                        if constexpr (EDGE) {
+                            const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                            inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                        }
+                        char* o = aout + (ry * kP + rx) * 64;
+                        *reinterpret_cast<uint2*>(o + out_off[0]) = inside ? relu_pack4(acc0) : make_uint2(0u, 0u);
+                        *reinterpret_cast<uint2*>(o + out_off[1]) = inside ? relu_pack4(acc1) : make_uint2(0u, 0u);
+                    }
                 }
-                if (rx < S) {
-                    const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
-                    const bool inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
-                    char* o = aout + (ry * kP + rx) * 64;
-                    *reinterpret_cast<uint2*>(o + out_off[0]) = inside ? relu_pack4(acc0) : make_uint2(0u, 0u);
-                    *reinterpret_cast<uint2*>(o + out_off[1]) = inside ? relu_pack4(acc1) : make_uint2(0u, 0u);
-                }
+                __syncthreads();
             }
-            __syncthreads();
-        }
-        // ---- last layer 32 -> 1: Z[t][p] on region W(NL-1) x H(NL-1) (tap planes,
-        //      so both the stores and the 9-tap gather are unit-stride), then gather
-        {
-            constexpr int S = G::W(NL - 1), HH = G::H(NL - 1);
-            constexpr int ngr = HH * 2;
-            constexpr int ZP = 32;          // Z pixel pitch
-            constexpr int ZN = HH * ZP;     // pixels per tap plane
-            const char* ain = (NH & 1) ? bufB : bufA;
-            float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
-            for (int gi = wave; gi < ngr; gi += 4) {
-                const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
-                const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bop, acc, 0, 0, 0);
-                if (rx < S && lg < 3) {
-                    // lane group lg holds taps 4 lg .. 4 lg + 3; only taps 0..8 exist
-                    float* zp = Z + (lg * 4) * ZN + ry * ZP + rx;
-                    zp[0] = acc[0];
-                    if (lg < 2) {
-                        zp[ZN] = acc[1];
-                        zp[2 * ZN] = acc[2];
-                        zp[3 * ZN] = acc[3];
+            // ---- last layer 32 -> 1: Z[t][p] on region W(NL-1) x H(NL-1) (tap planes,
+            //      so both the stores and the 9-tap gather are unit-stride), then gather
+            {
+                constexpr int S = G::W(NL - 1), HH = G::H(NL - 1);
+                constexpr int ngr = HH * 2;
+                constexpr int ZP = 32;          // Z pixel pitch
+                constexpr int ZN = HH * ZP;     // pixels per tap plane
+                const char* ain = (NH & 1) ? bufB : bufA;
+                float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
+                for (int gi = wave; gi < ngr; gi += 4) {
+                    const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
+                    const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bop, acc, 0, 0, 0);
+                    if (rx < S && lg < 3) {
+                        // lane group lg holds taps 4 lg .. 4 lg + 3; only taps 0..8 exist
+                        float* zp = Z + (lg * 4) * ZN + ry * ZP + rx;
+                        zp[0] = acc[0];
+                        if (lg < 2) {
+                            zp[ZN] = acc[1];
+                            zp[2 * ZN] = acc[2];
+                            zp[3 * ZN] = acc[3];
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < TH * TW; e += kThreads) {
+                    const int oy = e / TW, ox = e - (e / TW) * TW;
+                    const int gy = ty0 + oy, gx = tx0 + ox;
+                    if (!EDGE || (gy < n && gx < n)) {
+                        const float* zb = Z + oy * ZP + ox;
+                        float v = 0.f;
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) v += zb[t * ZN + (t / 3) * ZP + t % 3];
+                        v *= nbf;
+                        float* o = out + (size_t)gy * n + gx;
+                        *o = accumulate ? *o + v : v;
                     }
                 }
             }
-            __syncthreads();
-            for (int e = tid; e < TH * TW; e += kThreads) {
-                const int oy = e / TW, ox = e - (e / TW) * TW;
-                const int gy = ty0 + oy, gx = tx0 + ox;
-                if (gy < n && gx < n) {
-                    const float* zb = Z + oy * ZP + ox;
-                    float v = 0.f;
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) v += zb[t * ZN + (t / 3) * ZP + t % 3];
-                    v *= nbf;
-                    float* o = out + (size_t)gy * n + gx;
-                    *o = accumulate ? *o + v : v;
-                }
-            }
-        }
+        };
+        if (interior)
+            layers(std::false_type{});
+        else
+            layers(std::true_type{});
         __syncthreads();
     }
 }
@@ -411,13 +413,13 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
         using G = Geo<3>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
-        hipLaunchKernelGGL((k_smoother_mfma<3, false>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+        hipLaunchKernelGGL((k_smoother_mfma<3>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
-        hipLaunchKernelGGL((k_smoother_mfma<4, false>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
+        hipLaunchKernelGGL((k_smoother_mfma<4>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     }
     NMG_HIP(hipGetLastError());
