@@ -223,6 +223,15 @@ nmg_status nmg_train_step(nmg_handle h, int weight_set, int batch, const double*
                           const void* e_dev, nmg_mask_kind mask, int use_fprime,
                           nmg_precision precision, double lr, double* losses_host, void* stream);
 
+/* ---- execution ------------------------------------------------------------ */
+
+/* nmg_solve replays each outer iteration (refinement scaling, cycle, update,
+ * next residual) as a captured HIP graph, one graph per launch size, cached
+ * in the handle (default on).  enable = 0 frees the graphs and launches every
+ * kernel directly; the results are the same either way.  Synchronises the
+ * device when turning graphs off. */
+nmg_status nmg_set_graphs(nmg_handle h, int enable);
+
 /* ---- profiling ------------------------------------------------------------ */
 
 /* Kernel families timed by the built-in profiler. */
@@ -233,7 +242,8 @@ typedef enum {
 
 /* Turns HIP-event timing on for the kernel families in kind_mask (bit k =
  * nmg_kernel_kind k; 0 turns it off) and clears the accumulated times.
- * Events are recorded on the caller's stream around each timed launch. */
+ * Events are recorded on the caller's stream around each timed launch (as
+ * event nodes inside captured solve iterations). */
 nmg_status nmg_profile_enable(nmg_handle h, int kind_mask);
 
 /* Accumulated device time (ms) and launch count of one kernel family on one

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/nmg.h"
@@ -180,19 +181,40 @@ struct Ctx {
     std::vector<hipEvent_t> prof_pool;
     double prof_ms[8][16] = {};
     int prof_cnt[8][16] = {};
+    // captured solve iterations (refine scale, cycle, update, next residual)
+    // inside graphs the profiler brackets a launch with two tiny kernels that
+    // store the device wall clock into stamp slots (first, first + 1)
+    struct StampEv { int first, kind, level; };
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        std::vector<StampEv> stamps;
+    };
+    std::map<std::vector<long long>, GraphEntry> graphs;
+    bool use_graphs = true;
+    bool capturing = false;
+    std::vector<StampEv> capture_stamps;
+    std::vector<StampEv> stamp_pending;
+    long long* stamps = nullptr;       // [kStampSlots] device wall-clock stamps
+    int stamp_next = 0;
+    double wall_khz = 0.0;
+    hipStream_t cap_stream = nullptr;
 };
 
 // Records a start event on construction and a stop event on destruction
 // when profiling is on.
+constexpr int kStampSlots = 8192;
 struct ProfScope {
     Ctx* c;
     hipStream_t s;
     int kind, level;
     hipEvent_t a = nullptr, b = nullptr;
+    int stamp = -1;
     ProfScope(const Ctx* cc, hipStream_t ss, int k, int l);
     ~ProfScope();
 };
 nmg_status prof_resolve(Ctx* c);
+void release_graphs(Ctx* c);
+void launch_stamp(long long* slot, hipStream_t s);
 
 template <typename T>
 Work<T>& work_of(Ctx* c);

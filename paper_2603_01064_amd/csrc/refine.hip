@@ -58,7 +58,14 @@ __global__ void __launch_bounds__(kBlock) k_scatter_slots(const T* __restrict__ 
     if (e >= per) return;
     x[(size_t)pairs[2 * blockIdx.y + 1] * per + e] = (double)xc[(size_t)pairs[2 * blockIdx.y] * per + e];
 }
+
+// Device wall clock (constant rate) into one slot: a profiler stamp inside graphs.
+__global__ void k_stamp(long long* slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
 }  // namespace
+
+void launch_stamp(long long* slot, hipStream_t s) { hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, slot); }
 
 template <typename T>
 nmg_status launch_move_slots(int count, size_t per, T* a, T* b, T* c, const int* moves, hipStream_t s) {

@@ -73,12 +73,25 @@ static hipEvent_t prof_event(Ctx* c) {
 
 ProfScope::ProfScope(const Ctx* cc, hipStream_t ss, int k, int l) : c(const_cast<Ctx*>(cc)), s(ss), kind(k), level(l) {
     if (!(c->prof_mask & (1 << k))) return;
+    if (c->capturing) {
+        // graph node timing: wall-clock stamps (events cannot be timed inside graphs)
+        if (!c->stamps || c->stamp_next + 2 > kStampSlots) return;
+        stamp = c->stamp_next;
+        c->stamp_next += 2;
+        launch_stamp(c->stamps + stamp, s);
+        return;
+    }
     a = prof_event(c);
     b = prof_event(c);
     if (a && b) (void)hipEventRecord(a, s);
 }
 
 ProfScope::~ProfScope() {
+    if (stamp >= 0) {
+        launch_stamp(c->stamps + stamp + 1, s);
+        c->capture_stamps.push_back({stamp, kind, level});
+        return;
+    }
     if (!a || !b) return;
     (void)hipEventRecord(b, s);
     c->prof_pending.push_back({a, b, kind, level});
@@ -96,7 +109,27 @@ nmg_status prof_resolve(Ctx* c) {
         c->prof_pool.push_back(ev.b);
     }
     c->prof_pending.clear();
+    if (!c->stamp_pending.empty()) {
+        std::vector<long long> st((size_t)c->stamp_next);
+        NMG_HIP(hipDeviceSynchronize());
+        NMG_HIP(hipMemcpy(st.data(), c->stamps, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
+        for (auto& e : c->stamp_pending) {
+            const double ms = (double)(st[(size_t)e.first + 1] - st[(size_t)e.first]) / c->wall_khz;
+            const int k = e.kind & 7, l = e.level < 0 ? 0 : (e.level > 15 ? 15 : e.level);
+            c->prof_ms[k][l] += ms;
+            c->prof_cnt[k][l] += 1;
+        }
+        c->stamp_pending.clear();
+    }
     return NMG_OK;
+}
+
+void release_graphs(Ctx* c) {
+    for (auto& kv : c->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    c->graphs.clear();
+    c->stamp_pending.clear();
+    c->stamp_next = 0;
 }
 
 namespace {
@@ -375,6 +408,59 @@ nmg_status run_cycle(Ctx* c, int batch, const double* alpha, const int* ws, cons
 using namespace nmg;
 
 
+namespace nmg {
+namespace {
+// Launch sizes for captured iterations: exact up to 4, then multiples of 4 up
+// to 32 and of 8 beyond (at most 15 graphs for a batch of 64).
+int graph_batch(int k, int B) {
+    int kb = k <= 4 ? k : (k <= 32 ? (k + 3) / 4 * 4 : (k + 7) / 8 * 8);
+    return std::min(kb, B);
+}
+
+// Captures the work `body` enqueues on the handle's capture stream into an
+// executable graph; profiler events recorded during the capture belong to it.
+template <typename F>
+nmg_status capture_graph(Ctx* h, F&& body, Ctx::GraphEntry& ge) {
+    if (!h->cap_stream) NMG_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = h->cap_stream;
+    if (h->prof_mask && !h->stamps) {
+        int khz = 0;
+        NMG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0));
+        h->wall_khz = khz > 0 ? (double)khz : 1.0e5;
+        NMG_HIP(hipMalloc((void**)&h->stamps, (size_t)kStampSlots * sizeof(long long)));
+    }
+    h->capture_stamps.clear();
+    NMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    h->capturing = true;
+    const nmg_status st = body(cs);
+    h->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    auto drop_events = [&]() { h->capture_stamps.clear(); };
+    if (st != NMG_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        drop_events();
+        (void)hipGetLastError();
+        return st != NMG_OK ? st : hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        drop_events();
+        (void)hipGetLastError();
+        return hip_fail(ei, "hipGraphInstantiate", __FILE__, __LINE__);
+    }
+    ge.exec = ex;
+    ge.stamps = h->capture_stamps;
+    h->capture_stamps.clear();
+    return NMG_OK;
+}
+
+}  // namespace
+
+}  // namespace nmg
+
 extern "C" {
 
 const char* nmg_last_error(void) { return nmg::g_last_error.c_str(); }
@@ -478,6 +564,11 @@ void nmg_destroy(nmg_handle h) {
     (void)prof_resolve(c);
     for (auto e : c->prof_pool) (void)hipEventDestroy(e);
     c->prof_pool.clear();
+    release_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+    if (c->stamps) (void)hipFree(c->stamps);
+    c->stamps = nullptr;
     release_training(c);
     free_work(c, c->w64);
     free_work(c, c->w32b);
@@ -780,12 +871,13 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     std::vector<double>& hd = h->slot_d_host;
     std::vector<int>& hi = h->slot_i_host;
     // per-slot tables for slots [0, k); the staging vectors are only rewritten after a stream sync
-    auto upload_slots = [&](int k, bool with_rn2) -> nmg_status {
-        for (int i = 0; i < k; ++i) {
-            const int r = slot_rhs[(size_t)i];
+    auto upload_slots = [&](int k, int kb) -> nmg_status {
+        for (int i = 0; i < kb; ++i) {
+            const int src = i < k ? i : 0;
+            const int r = slot_rhs[(size_t)src];
             hd[(size_t)i] = h->alpha_host[(size_t)r];
             hd[(size_t)B + i] = bn2[(size_t)r];
-            hd[(size_t)2 * B + i] = with_rn2 ? rn2[(size_t)i] : 0.0;
+            hd[(size_t)2 * B + i] = i < k ? rn2[(size_t)i] : 0.0;
             hi[(size_t)i] = wsv[(size_t)r];
             hi[(size_t)B + i] = h->coarse_idx_host[(size_t)r];
         }
@@ -794,22 +886,48 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
         return NMG_OK;
     };
     int k = batch;
-    NMG_TRY(upload_slots(k, false));
+    for (int i = 0; i < batch; ++i) rn2[(size_t)i] = 0.0;
+    NMG_TRY(upload_slots(k, k));
     h->cycle_fidx = d_fidx;
     bool nonfinite = false;
     const double tol2 = rtol * rtol;
-    for (int it = 0; it <= max_cycles; ++it) {
-        // residual of the active slots and its norm in the outer precision
-        {
-            ProfScope ps(h, s, NMG_K_REFINE, 0);
-            if (plain32) {
-                NMG_TRY(launch_operator<float>(h, 0, k, d_alpha, X32, B32, R32, 0, h->w32b, s));
-                NMG_TRY(launch_sumsq<float>(h, k, per, R32, h->nrm2, s));
-            } else {
-                NMG_TRY(launch_operator<double>(h, 0, k, d_alpha, X64, B64, R64, 0, h->w64, s));
-                NMG_TRY(launch_sumsq<double>(h, k, per, R64, h->nrm2, s));
-            }
+    // residual of slots [0, kk) and its norm in the outer precision
+    auto residual = [&](int kk, hipStream_t st) -> nmg_status {
+        ProfScope ps(h, st, NMG_K_REFINE, 0);
+        if (plain32) {
+            NMG_TRY(launch_operator<float>(h, 0, kk, d_alpha, X32, B32, R32, 0, h->w32b, st));
+            NMG_TRY(launch_sumsq<float>(h, kk, per, R32, h->nrm2, st));
+        } else {
+            NMG_TRY(launch_operator<double>(h, 0, kk, d_alpha, X64, B64, R64, 0, h->w64, st));
+            NMG_TRY(launch_sumsq<double>(h, kk, per, R64, h->nrm2, st));
         }
+        return NMG_OK;
+    };
+    // one outer iteration on slots [0, kk): d = MG(0, r / ||r||), x += ||r|| d,
+    // then the residual for the next convergence check
+    const int* wsd = ws ? d_ws : nullptr;
+    auto iterate = [&](int kk, hipStream_t st) -> nmg_status {
+        if (plain32) {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<float, float>(kk, per, R32, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<float, float>(kk, per, X32, w.lv[0].x, d_rn2, h->active, st));
+        } else if (o->precision == NMG_FP64) {
+            Work<double>& w = h->w64;
+            NMG_TRY(launch_refine_scale<double, double>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<double>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<double, double>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
+        } else {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<double, float>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
+        }
+        return residual(kk, st);
+    };
+    if (o->precision == NMG_MIXED && h->p.dim == 2 && o->use_fprime) NMG_TRY(prepare_fprime_bf16(h));
+    NMG_TRY(residual(k, s));
+    for (int it = 0; it <= max_cycles; ++it) {
         NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
         NMG_HIP(hipStreamSynchronize(s));
         if (h->prof_mask) NMG_TRY(prof_resolve(h));
@@ -875,24 +993,29 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
                 NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
         }
         k = nkeep;
-        NMG_TRY(upload_slots(k, true));
-        const int* wsd = ws ? d_ws : nullptr;
-        // d = MG(0, r / ||r||), x += ||r|| d on the k active slots
-        if (plain32) {
-            Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<float, float>(k, per, R32, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
-            NMG_TRY(run_cycle<float>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<float, float>(k, per, X32, w.lv[0].x, d_rn2, h->active, s));
-        } else if (o->precision == NMG_FP64) {
-            Work<double>& w = h->w64;
-            NMG_TRY(launch_refine_scale<double, double>(k, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
-            NMG_TRY(run_cycle<double>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<double, double>(k, per, X64, w.lv[0].x, d_rn2, h->active, s));
+        // the iteration runs on kb >= k slots (a fixed set of launch sizes, so
+        // a few captured graphs serve every active count); slots k..kb-1 carry
+        // slot 0's parameters with a zero residual norm, which the cycle treats
+        // as converged (zero input, no update)
+        const int kb = h->use_graphs ? graph_batch(k, B) : k;
+        NMG_TRY(upload_slots(k, kb));
+        if (h->use_graphs) {
+            std::vector<long long> key = {kb, (long long)o->precision, o->nu1, o->nu2, o->use_fprime, ws ? 1 : 0,
+                                          (long long)h->prof_mask};
+            long long rbits;
+            __builtin_memcpy(&rbits, &rtol, sizeof(rbits));
+            key.push_back(rbits);
+            auto found = h->graphs.find(key);
+            if (found == h->graphs.end()) {
+                Ctx::GraphEntry ge;
+                NMG_TRY(capture_graph(h, [&](hipStream_t cs) { return iterate(kb, cs); }, ge));
+                found = h->graphs.emplace(key, std::move(ge)).first;
+            }
+            if (h->prof_mask)
+                for (auto& e : found->second.stamps) h->stamp_pending.push_back(e);
+            NMG_HIP(hipGraphLaunch(found->second.exec, s));
         } else {
-            Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<double, float>(k, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, s));
-            NMG_TRY(run_cycle<float>(h, k, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, s));
-            NMG_TRY(launch_refine_update<double, float>(k, per, X64, w.lv[0].x, d_rn2, h->active, s));
+            NMG_TRY(iterate(kb, s));
         }
         for (int i = 0; i < k; ++i) cyc[(size_t)slot_rhs[(size_t)i]] += 1;
     }
@@ -926,6 +1049,16 @@ nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* id
     dev_free(di);
     dev_free(dw);
     return st;
+}
+
+nmg_status nmg_set_graphs(nmg_handle h, int enable) {
+    NMG_TRY(check_handle(h));
+    h->use_graphs = enable != 0;
+    if (!h->use_graphs) {
+        NMG_HIP(hipDeviceSynchronize());
+        release_graphs(h);
+    }
+    return NMG_OK;
 }
 
 nmg_status nmg_profile_enable(nmg_handle h, int on) {

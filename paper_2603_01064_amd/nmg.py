@@ -73,6 +73,7 @@ def load_library():
         "nmg_train_step": (S, [P, I, I, P, P, I, I, I, D, P, P]),
         "nmg_level_size": (I, [P, I]),
         "nmg_profile_enable": (S, [P, I]),
+        "nmg_set_graphs": (S, [P, I]),
         "nmg_profile_query": (S, [P, I, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "nmg_debug_transfer_map": (S, [P, I, I, P, P]),
         "nmg_debug_factor": (S, [P, I, I, P, P]),
@@ -315,6 +316,10 @@ class Handle:
     # -- profiling ---------------------------------------------------------
     KERNELS = {"smoother": 0, "operator": 1, "restrict": 2, "prolong": 3, "coarse": 4, "fprime": 5, "refine": 6,
                "norm": 7}
+
+    def set_graphs(self, enable: bool) -> None:
+        """Replay solve iterations as captured HIP graphs (default) or launch eagerly."""
+        _check(_lib.nmg_set_graphs(self.ptr, 1 if enable else 0))
 
     def profile_enable(self, kinds=("smoother",)) -> None:
         """Times the given kernel families (empty: profiling off)."""

@@ -155,3 +155,45 @@ def test_out_of_range_weight_set_rejected():
     with pytest.raises(nmg.NMGError):
         h.solve(b, alpha, weight_set=torch.tensor([-1, 0], dtype=torch.int32, device=dev), max_cycles=3)
     h.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replay_equals_eager(prec):
+    """Captured iterations (one graph per launch size, replayed many times with
+    host synchronisation and compaction between replays) give bit-identically
+    the eagerly launched solve, on two solves in a row."""
+    print(f"case graph replay vs eager {prec}", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    meta, sets = _trained()
+    n, s, L = meta["n"], meta["s"], meta["levels"]
+    cyc_cfg = meta["cycle"]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=7, channels=(1, 32, 32, 1), ksize=3,
+                                        n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(L - 1):
+            h.load_smoother_weights(l, k, [ws[l]])
+    al = [1e-2, 1e-4, 1e-3, 1e-2, 1e-3, 1e-4, 1e-3]
+    alpha = torch.tensor(al, dtype=DT, device=dev)
+    ws = torch.tensor([min(range(len(sets)), key=lambda i: abs(math.log(meta["alphas"][i] / a))) for a in al],
+                      dtype=torch.int32, device=dev)
+    u = torch.tensor(np.stack([inputs.boxes_image(n, 2500 + i) for i in range(7)]), device=dev)
+    b = h.apply_operator(0, u, alpha, "fp64")
+    max_cycles = 200 if prec == "mixed" else 12
+    kw = dict(rtol=1e-6, max_cycles=max_cycles, nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"],
+              use_fprime=cyc_cfg["use_fprime"], precision=prec, history=True)
+    res = []
+    for graphs in (True, True, False):
+        h.set_graphs(graphs)
+        h.profile_enable(("smoother",))
+        x, cyc, hist, st = h.solve(b, alpha, weight_set=ws, **kw)
+        ms, cnt = h.profile_query("smoother", 0)
+        h.profile_enable(())
+        assert cnt == 2 * int(np.max(cyc)) and ms > 0  # level-1 smoother timed in graph and eager runs
+        res.append((x.clone(), cyc.copy(), hist.copy(), st))
+    print(f"  cycles {list(res[0][1])}", flush=True)
+    for x, cyc, hist, st in res[1:]:
+        assert st == res[0][3]
+        assert np.array_equal(cyc, res[0][1]) and np.array_equal(hist, res[0][2])
+        assert torch.equal(x, res[0][0])
+    h.close()
