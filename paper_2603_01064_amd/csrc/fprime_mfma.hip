@@ -112,6 +112,72 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict_
         }
 }
 
+// The same four products for a level with NP = n rounded up to 32 <= 64:
+// one workgroup per image keeps the whole (BF16) intermediate in LDS, so the
+// filter is one launch.  Every pass computes out[j][i] = sum_k Mat[j][k]
+// in[i][k] tile by tile with the K steps of the four-launch kernel in the
+// same order, and rounds its result to BF16 exactly where that kernel
+// stages its operand, so both give the same values.
+template <int NP>
+__global__ void __launch_bounds__(kThreads) k_fprime_small(const float* __restrict__ in, float* __restrict__ dst,
+                                                           const uint16_t* __restrict__ C,
+                                                           const uint16_t* __restrict__ Ct,
+                                                           const float* __restrict__ ramp, int n, int mstride,
+                                                           int accumulate) {
+    constexpr int NT = NP / 16;             // 16 x 16 output tiles per side
+    constexpr int KS = NP / 32;             // K steps
+    constexpr int RB = NP * 2;              // bytes per BF16 row
+    __shared__ __attribute__((aligned(16))) char buf[2][NP * RB];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ln = lane & 15, lg = lane >> 4;
+    const float* src = in + (size_t)b * n * n;
+    // stage H (rows i, columns k) as BF16, zero beyond n
+    for (int e = tid; e < NP * NP / 2; e += kThreads) {
+        const int i = e / (NP / 2), k = (e % (NP / 2)) * 2;
+        const float v0 = (i < n && k < n) ? src[(size_t)i * n + k] : 0.f;
+        const float v1 = (i < n && k + 1 < n) ? src[(size_t)i * n + k + 1] : 0.f;
+        *reinterpret_cast<uint32_t*>(buf[0] + i * RB + k * 2) = pack_bf16(v0, v1);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int pass = 0; pass < 4; ++pass) {
+        const uint16_t* M = pass < 2 ? C : Ct;
+        const char* cur = buf[pass & 1];
+        char* nxt = buf[(pass + 1) & 1];
+        for (int t = wave; t < NT * NT; t += 4) {
+            const int tj = t / NT, ti = t % NT;  // output rows j (M), columns i (N)
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k0 = ks * 32 + lg * 8;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(M + (size_t)(tj * 16 + ln) * mstride + k0);
+                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(cur + (ti * 16 + ln) * RB + k0 * 2);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+            }
+            const int i = ti * 16 + ln;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = tj * 16 + lg * 4 + q;
+                float v = acc[q];
+                if (pass == 1) v = (i < n && j < n) ? v * ramp[i > j ? i : j] : 0.f;
+                if (pass < 3) {
+                    // next pass reads row j, column i
+                    const float2v f = {v, 0.f};
+                    const bf16x2 p = __builtin_convertvector(f, bf16x2);
+                    uint16_t u;
+                    __builtin_memcpy(&u, &p, 2);
+                    *reinterpret_cast<uint16_t*>(nxt + j * RB + i * 2) = u;
+                } else if (i < n && j < n) {
+                    float* o = dst + (size_t)b * n * n + (size_t)j * n + i;
+                    *o = accumulate ? *o + v : v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 nmg_status prepare_fprime_bf16(Ctx* c) {
@@ -171,6 +237,17 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, fl
     const int ti = npad / kTI, tj = npad / kTJ;
     const uint16_t* C = c->dctbf + c->dctbf_off[(size_t)l];
     const uint16_t* Ct = C + (size_t)npad * npad;
+    if (n <= 64) {
+        const float* rp = c->ramp + c->ramp_off[(size_t)l];
+        if (n <= 32)
+            hipLaunchKernelGGL(k_fprime_small<32>, dim3(batch), dim3(kThreads), 0, s, h, dst, C, Ct, rp, n, npad,
+                               accumulate);
+        else
+            hipLaunchKernelGGL(k_fprime_small<64>, dim3(batch), dim3(kThreads), 0, s, h, dst, C, Ct, rp, n, npad,
+                               accumulate);
+        NMG_HIP(hipGetLastError());
+        return NMG_OK;
+    }
     dim3 grid((unsigned)(ti * tj), (unsigned)batch);
     const float* rp = c->ramp + c->ramp_off[(size_t)l];
     hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, h, t1, C, rp, n, npad, tj);

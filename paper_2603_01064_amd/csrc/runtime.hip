@@ -540,6 +540,7 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
     NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kNormChunksPerRhs));
+
     NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
     NMG_TRY(dev_alloc(&c->active, (size_t)B));
     NMG_TRY(dev_alloc(&c->x64, (size_t)B * level_elems(c.get(), 0)));

@@ -665,20 +665,32 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
     if (c->p.dim == 2 && op.ok && op.rgp <= 48 && (op.m_ident || op.rm == 1)) {
         // fixed-tap kernel: TP = padded Toeplitz taps of G_l
         bool launched = false;
-        nmg_status st = NMG_OK;
-        auto go = [&](auto tp_tag) {
+        // FP32: 128 x 64 tiles (512 threads, 4 waves per SIMD) when they give at
+        // least 512 workgroups, else 32 x 32 tiles (256 threads) for more
+        // parallelism at small batches and on coarse levels; FP64: 32 x 32 tiles
+        const bool big = sizeof(T) == 4 && (long)((n + 63) / 64) * ((n + 127) / 128) * batch >= 512;
+        auto launch = [&](auto cfg_tag, auto tp_tag) {
             constexpr int TP = decltype(tp_tag)::value;
-            if (launched || op.rgp != TP) return;
-            launched = true;
-            // FP32: 128 x 64 tiles, 512 threads, 4 waves per SIMD; FP64: 32 x 32 tiles, 256 threads
-            constexpr bool F = sizeof(T) == 4;
-            constexpr int TH = F ? 128 : 32, TW = F ? 64 : 32, OC = F ? 8 : 4, NT = F ? 512 : 256, WPE = F ? 4 : 1;
+            constexpr bool BIG = decltype(cfg_tag)::value;
+            constexpr int TH = BIG ? 128 : 32, TW = BIG ? 64 : 32, OC = BIG ? 8 : 4, NT = BIG ? 512 : 256;
+            constexpr int WPE = BIG ? 4 : 1;
             const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
             const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW)) * sizeof(T);
             hipLaunchKernelGGL((k_residual_fixed<T, TH, TW, TP, OC, NT, WPE>), dim3(tiles_x * tiles_y, batch), dim3(NT),
                                lds, s, x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
                                op.m_ident, tiles_x);
-            st = NMG_OK;
+        };
+        auto go = [&](auto tp_tag) {
+            constexpr int TP = decltype(tp_tag)::value;
+            if (launched || op.rgp != TP) return;
+            launched = true;
+            if constexpr (sizeof(T) == 4) {
+                if (big) {
+                    launch(std::true_type{}, tp_tag);
+                    return;
+                }
+            }
+            launch(std::false_type{}, tp_tag);
         };
         go(std::integral_constant<int, 4>{});
         go(std::integral_constant<int, 8>{});
@@ -694,7 +706,7 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
         go(std::integral_constant<int, 48>{});
         if (launched) {
             NMG_HIP(hipGetLastError());
-            return st;
+            return NMG_OK;
         }
     }
     if (c->p.dim == 2 && op.ok) {
