@@ -186,11 +186,53 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const in
  * time in ms from entry to the residual check that found each right-hand
  * side converged (-1 if it never did).  Synchronises once per cycle.
  * Returns NMG_NOT_CONVERGED if any right-hand side missed rtol,
- * NMG_ERR_NONFINITE on NaN/Inf residuals. */
+ * NMG_ERR_NONFINITE on NaN/Inf residuals, NMG_ERR_STATE while serving
+ * requests are queued or active (it runs on the same engine). */
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
                      const double* b_dev, double* x_dev, double rtol, int max_cycles,
                      const nmg_cycle_opts* opts, int* cycles_host, double* history_host,
                      double* done_ms_host, void* stream);
+
+/* ---- serving: continuous batching ----------------------------------------
+ *
+ * Every right-hand side is an independent solve (Sec. 2.3 outer iteration,
+ * Sec. 4 stopping rule), so requests can join and leave the batch between
+ * outer iterations: the handle keeps up to max_batch requests in flight,
+ * runs one iteration on all of them per step, retires the ones that reached
+ * rtol (or max_cycles, or a non-finite residual) and admits queued requests
+ * into the freed slots.  A request's result does not depend on which other
+ * requests share its iterations.  nmg_solve runs on the same engine. */
+
+typedef struct {
+    long long id;         /* the caller's request id */
+    int status;           /* NMG_OK, NMG_NOT_CONVERGED or NMG_ERR_NONFINITE */
+    int cycles;           /* outer iterations applied */
+    double rel_residual;  /* ||b - A x||_2 / ||b||_2 when it left (0 for b = 0) */
+    double latency_ms;    /* host time from submission to the check that finished it */
+} nmg_request_result;
+
+/* Queues one request (host side only, no device work): b_dev is the
+ * right-hand side, x_dev receives the solution when the request finishes
+ * (device double[ny][n] each, caller-owned; both must stay valid until
+ * then).  alpha > 0 finite; weight_set in [0, n_weight_sets). */
+nmg_status nmg_serve_submit(nmg_handle h, long long id, double alpha, int weight_set,
+                            const double* b_dev, double* x_dev);
+
+/* One engine step on `stream`: admits queued requests into free slots
+ * (copies b, factors new alphas), checks every active request against
+ * rtol / max_cycles, writes the iterates of finished requests to their x_dev
+ * and reports them in done (host array of at least max_batch entries;
+ * *n_done = count), then runs one outer iteration on the remaining ones.
+ * opts->precision must stay the same while requests are active.
+ * Synchronises the stream. */
+nmg_status nmg_serve_step(nmg_handle h, double rtol, int max_cycles, const nmg_cycle_opts* opts,
+                          nmg_request_result* done, int* n_done, void* stream);
+
+/* Queued and active request counts. */
+nmg_status nmg_serve_pending(nmg_handle h, int* queued, int* active);
+
+/* Drops every queued and active request (their x_dev are left as they are). */
+nmg_status nmg_serve_reset(nmg_handle h);
 
 /* ---- training (Sec. 3.2 eq. loss_2_modified / Sec. 3.3 eq. loss_3,
  *      Algorithm 5) ----------------------------------------------------- */

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <string>
+#include <deque>
+#include <chrono>
 #include <map>
 #include <vector>
 
@@ -108,6 +110,39 @@ struct Work {
     std::vector<TiledOp<T>> tiled;
 };
 
+// Serving engine: requests wait in a host queue and are admitted into free
+// batch slots between outer iterations; slots [0, k) are the active ones.
+struct EngineRequest {
+    long long id;
+    double alpha;
+    int ws;
+    const double* b;
+    double* x;
+    double* hist;  // host row of residual history or null
+    int hist_len;
+    double t_submit;
+};
+struct EngineSlot {
+    long long id = 0;
+    double* x = nullptr;
+    double* hist = nullptr;
+    int hist_len = 0;
+    int cycles = 0;
+    double alpha = 0.0, bn2 = 0.0, rn2 = 0.0;
+    int ws = 0, fidx = 0;
+    double t_submit = 0.0;
+};
+struct Engine {
+    std::deque<EngineRequest> queue;
+    std::vector<EngineSlot> slot;
+    int precision = -1;  // cycle precision of the active slots
+    bool any_ws = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
 struct Ctx {
     nmg_problem p{};
     int L = 0;
@@ -164,6 +199,9 @@ struct Ctx {
     int* slot_i = nullptr;             // [2][max_batch] weight set, factor index; then [2][max_batch] x 2 move lists
     std::vector<double> slot_d_host;   // staging for slot_d
     std::vector<int> slot_i_host;      // staging for slot_i
+    double** xptr_dev = nullptr;       // [max_batch] destinations of finished iterates
+    std::vector<double*> xptr_host;
+    Engine eng;
     float* xs32 = nullptr;             // [max_batch][ny][n] plain-FP32 iterate
     float* bs32 = nullptr;             // [max_batch][ny][n] plain-FP32 right-hand side
     double* r64 = nullptr;
@@ -274,6 +312,10 @@ template <typename T>
 nmg_status launch_move_slots(int count, size_t per, T* a, T* b, T* c, const int* moves, hipStream_t s);
 template <typename T>
 nmg_status launch_scatter_slots(int count, size_t per, const T* xc, double* x, const int* pairs, hipStream_t s);
+template <typename T>
+nmg_status launch_scatter_ptrs(int count, size_t per, const T* xc, double* const* dst, const int* slots,
+                               hipStream_t s);
+nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>& idx, hipStream_t s);
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
                                double rtol, int* active, hipStream_t s);

@@ -59,6 +59,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter_slots(const T* __restrict__ 
     x[(size_t)pairs[2 * blockIdx.y + 1] * per + e] = (double)xc[(size_t)pairs[2 * blockIdx.y] * per + e];
 }
 
+// Finished iterates to their owners: dst[m] receives slot slots[m].
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scatter_ptrs(const T* __restrict__ xc, double* const* __restrict__ dst,
+                                                         const int* __restrict__ slots, size_t per) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= per) return;
+    dst[blockIdx.y][e] = (double)xc[(size_t)slots[blockIdx.y] * per + e];
+}
+
 // Device wall clock (constant rate) into one slot: a profiler stamp inside graphs.
 __global__ void k_stamp(long long* slot) {
     if (threadIdx.x == 0) *slot = wall_clock64();
@@ -84,6 +93,18 @@ nmg_status launch_scatter_slots(int count, size_t per, const T* xc, double* x, c
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
+
+template <typename T>
+nmg_status launch_scatter_ptrs(int count, size_t per, const T* xc, double* const* dst, const int* slots,
+                               hipStream_t s) {
+    if (count <= 0) return NMG_OK;
+    dim3 grid((unsigned)((per + kBlock - 1) / kBlock), count);
+    hipLaunchKernelGGL((k_scatter_ptrs<T>), grid, dim3(kBlock), 0, s, xc, dst, slots, per);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_scatter_ptrs<double>(int, size_t, const double*, double* const*, const int*, hipStream_t);
+template nmg_status launch_scatter_ptrs<float>(int, size_t, const float*, double* const*, const int*, hipStream_t);
 
 template nmg_status launch_move_slots<double>(int, size_t, double*, double*, double*, const int*, hipStream_t);
 template nmg_status launch_move_slots<float>(int, size_t, float*, float*, float*, const int*, hipStream_t);

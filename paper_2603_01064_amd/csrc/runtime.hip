@@ -409,6 +409,65 @@ using namespace nmg;
 
 
 namespace nmg {
+
+// Coarse factors are cached per alpha value (exact match): U distinct alphas
+// need at most U factorizations, and alphas seen before cost nothing.  idx
+// receives the cache slot of every alpha.  Slots used by requests the
+// serving engine holds are never evicted.
+nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>& idx, hipStream_t s) {
+    const int n = (int)al.size();
+    for (int b = 0; b < n; ++b)
+        if (!std::isfinite(al[(size_t)b]) || !(al[(size_t)b] > 0.0))
+            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(b) + ")");
+    const long long stamp = ++h->prepare_count;
+    const int slots = (int)h->cache_alpha.size();
+    for (const auto& sl : h->eng.slot) h->cache_used[(size_t)sl.fidx] = stamp;
+    idx.assign((size_t)n, -1);
+    std::vector<int> new_slots;
+    std::vector<double> new_alphas;
+    auto find = [&](double a) {
+        for (int k = 0; k < slots; ++k)
+            if (h->cache_alpha[(size_t)k] == a) return k;
+        return -1;
+    };
+    for (int b = 0; b < n; ++b) {
+        const double a = al[(size_t)b];
+        int k = find(a);
+        if (k < 0) {
+            // least recently used slot not claimed by this call (claimed slots carry `stamp`)
+            long long best = stamp;
+            for (int j = 0; j < slots; ++j)
+                if (h->cache_used[(size_t)j] < best) {
+                    best = h->cache_used[(size_t)j];
+                    k = j;
+                }
+            if (k < 0) return fail(NMG_ERR_STATE, "coarse factor cache exhausted");
+            h->cache_alpha[(size_t)k] = a;
+            new_slots.push_back(k);
+            new_alphas.push_back(a);
+        }
+        h->cache_used[(size_t)k] = stamp;
+        idx[(size_t)b] = k;
+    }
+    const int cnt = (int)new_slots.size();
+    if (cnt > 0) {
+        NMG_HIP(hipMemcpyAsync(h->alpha_prepared, new_alphas.data(), (size_t)cnt * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        NMG_HIP(hipMemcpyAsync(h->slot_dev, new_slots.data(), (size_t)cnt * sizeof(int), hipMemcpyHostToDevice, s));
+        NMG_TRY(launch_coarse_factor(h, cnt, h->alpha_prepared, h->slot_dev, s));
+        NMG_TRY(launch_coarse_inverse(h, cnt, h->slot_dev, s));
+        std::vector<int> flags((size_t)cnt);
+        NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+        NMG_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < cnt; ++k)
+            if (flags[(size_t)k]) {
+                h->cache_alpha[(size_t)new_slots[(size_t)k]] = std::nan("");
+                return fail(NMG_ERR_NOT_SPD, "coarse Cholesky failed for alpha " + std::to_string(new_alphas[(size_t)k]));
+            }
+    }
+    return NMG_OK;
+}
+
 namespace {
 // Launch sizes for captured iterations: exact up to 4, then multiples of 4 up
 // to 32 and of 8 beyond (at most 15 graphs for a batch of 64).
@@ -458,6 +517,246 @@ nmg_status capture_graph(Ctx* h, F&& body, Ctx::GraphEntry& ge) {
 }
 
 }  // namespace
+
+namespace {
+// Points the cycle's coarse solve at the engine's per-slot factor indices
+// for one step and restores the prepare order on every exit.
+struct FidxGuard {
+    Ctx* c;
+    ~FidxGuard() { c->cycle_fidx = nullptr; }
+};
+}  // namespace
+
+// One step of the serving engine (see nmg_serve_step).
+nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts* o,
+                       std::vector<nmg_request_result>& done, hipStream_t s) {
+    Engine& E = h->eng;
+    const int B = h->p.max_batch;
+    const size_t per = level_elems(h, 0);
+    const bool plain32 = o->precision == NMG_FP32;
+    int k = (int)E.slot.size();
+    if (k > 0 && E.precision != (int)o->precision)
+        return fail(NMG_ERR_STATE, "cycle precision changed while requests are active");
+    NMG_TRY(ensure_work<double>(h));
+    if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
+    if (o->precision == NMG_MIXED && h->p.dim == 2 && o->use_fprime) NMG_TRY(prepare_fprime_bf16(h));
+    FidxGuard guard{h};
+    double* X64 = h->x64;
+    double* B64 = h->b64;
+    double* R64 = h->r64;
+    float* X32 = h->xs32;
+    float* B32 = h->bs32;
+    float* R32 = reinterpret_cast<float*>(h->r64);  // r64 has room for max_batch doubles per point
+    double* d_alpha = h->slot_d;
+    double* d_bn2 = h->slot_d + B;
+    double* d_rn2 = h->slot_d + 2 * B;
+    int* d_ws = h->slot_i;
+    int* d_fidx = h->slot_i + B;
+    int* d_pairs = h->slot_i + 2 * B;  // 2B ints: slots of finished requests
+    int* d_moves = h->slot_i + 4 * B;  // 2B ints: (destination, source) slot moves
+    std::vector<double>& hd = h->slot_d_host;
+    std::vector<int>& hi = h->slot_i_host;
+    // ---- admission: queued requests fill slots [k, k + m)
+    const int m = std::min(B - k, (int)E.queue.size());
+    if (m > 0) {
+        std::vector<double> al((size_t)m);
+        for (int i = 0; i < m; ++i) al[(size_t)i] = E.queue[(size_t)i].alpha;
+        std::vector<int> fidx;
+        NMG_TRY(factor_alphas(h, al, fidx, s));
+        // copy runs of contiguous right-hand sides with one transfer each
+        for (int i = 0; i < m;) {
+            int j = i + 1;
+            while (j < m && E.queue[(size_t)j].b == E.queue[(size_t)i].b + (size_t)(j - i) * per) ++j;
+            NMG_HIP(hipMemcpyAsync(B64 + (size_t)(k + i) * per, E.queue[(size_t)i].b, (size_t)(j - i) * per *
+                                   sizeof(double), hipMemcpyDeviceToDevice, s));
+            i = j;
+        }
+        const size_t off = (size_t)k * per, cnt = (size_t)m * per;
+        // x0 = 0, so the first residual is b itself
+        if (plain32) {
+            NMG_TRY(launch_sumsq<double>(h, m, per, B64 + off, h->nrm + k, s));  // ||b||^2 in FP64
+            NMG_TRY(launch_convert<double, float>(B64 + off, B32 + off, cnt, s));
+            NMG_HIP(hipMemcpyAsync(R32 + off, B32 + off, cnt * sizeof(float), hipMemcpyDeviceToDevice, s));
+            NMG_TRY(launch_zero<float>(X32 + off, cnt, s));
+            NMG_TRY(launch_sumsq<float>(h, m, per, R32 + off, h->nrm2 + k, s));
+        } else {
+            NMG_TRY(launch_sumsq<double>(h, m, per, B64 + off, h->nrm2 + k, s));
+            NMG_HIP(hipMemcpyAsync(R64 + off, B64 + off, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+            NMG_TRY(launch_zero<double>(X64 + off, cnt, s));
+        }
+        for (int i = 0; i < m; ++i) {
+            const EngineRequest& r = E.queue[(size_t)i];
+            EngineSlot sl;
+            sl.id = r.id;
+            sl.x = r.x;
+            sl.hist = r.hist;
+            sl.hist_len = r.hist_len;
+            sl.alpha = r.alpha;
+            sl.ws = r.ws;
+            sl.fidx = fidx[(size_t)i];
+            sl.t_submit = r.t_submit;
+            E.slot.push_back(sl);
+            E.any_ws = E.any_ws || r.ws != 0;
+        }
+        E.queue.erase(E.queue.begin(), E.queue.begin() + m);
+        E.precision = (int)o->precision;
+    }
+    k = (int)E.slot.size();
+    if (k == 0) return NMG_OK;
+    // ---- residual norms of every active slot (new ones: ||b||^2)
+    std::vector<double> rn2((size_t)k), bn2n((size_t)std::max(m, 1));
+    NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (m > 0)
+        NMG_HIP(hipMemcpyAsync(bn2n.data(), (plain32 ? h->nrm : h->nrm2) + (k - m), (size_t)m * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    if (h->prof_mask) NMG_TRY(prof_resolve(h));
+    for (int i = 0; i < m; ++i) E.slot[(size_t)(k - m + i)].bn2 = bn2n[(size_t)i];
+    const double now = E.now_ms();
+    const double tol2 = rtol * rtol;
+    // ---- retire finished requests
+    std::vector<char> keep((size_t)k, 0);
+    int nfin = 0, nkeep = 0;
+    h->xptr_host.resize((size_t)B);
+    for (int i = 0; i < k; ++i) {
+        EngineSlot& sl = E.slot[(size_t)i];
+        const double q = rn2[(size_t)i], bb = sl.bn2;
+        sl.rn2 = q;
+        int status = -100;  // still running
+        if (!std::isfinite(q) || !std::isfinite(bb)) {
+            status = NMG_ERR_NONFINITE;
+        } else {
+            if (sl.hist && sl.cycles < sl.hist_len) sl.hist[sl.cycles] = bb > 0 ? std::sqrt(q / bb) : 0.0;
+            if (!(q > tol2 * bb))
+                status = NMG_OK;
+            else if (sl.cycles >= max_cycles)
+                status = NMG_NOT_CONVERGED;
+        }
+        if (status == -100) {
+            keep[(size_t)i] = 1;
+            ++nkeep;
+            continue;
+        }
+        nmg_request_result res;
+        res.id = sl.id;
+        res.status = status;
+        res.cycles = sl.cycles;
+        res.rel_residual = (std::isfinite(q) && bb > 0) ? std::sqrt(q / bb) : (bb > 0 ? q : 0.0);
+        res.latency_ms = now - sl.t_submit;
+        done.push_back(res);
+        hi[(size_t)2 * B + nfin] = i;
+        h->xptr_host[(size_t)nfin] = sl.x;
+        ++nfin;
+    }
+    if (nfin > 0) {
+        NMG_HIP(hipMemcpyAsync(d_pairs, hi.data() + 2 * B, (size_t)nfin * sizeof(int), hipMemcpyHostToDevice, s));
+        NMG_HIP(hipMemcpyAsync(h->xptr_dev, h->xptr_host.data(), (size_t)nfin * sizeof(double*),
+                               hipMemcpyHostToDevice, s));
+        if (plain32)
+            NMG_TRY(launch_scatter_ptrs<float>(nfin, per, X32, h->xptr_dev, d_pairs, s));
+        else
+            NMG_TRY(launch_scatter_ptrs<double>(nfin, per, X64, h->xptr_dev, d_pairs, s));
+    }
+    // ---- refill the finished slots below nkeep from active slots at or above it
+    int nmoves = 0;
+    {
+        int src = k - 1;
+        for (int dst = 0; dst < nkeep; ++dst) {
+            if (keep[(size_t)dst]) continue;
+            while (!keep[(size_t)src]) --src;  // src >= nkeep holds an active slot
+            hi[(size_t)4 * B + 2 * nmoves] = dst;
+            hi[(size_t)4 * B + 2 * nmoves + 1] = src;
+            ++nmoves;
+            E.slot[(size_t)dst] = E.slot[(size_t)src];
+            keep[(size_t)src] = 0;
+            --src;
+        }
+    }
+    if (nmoves > 0) {
+        NMG_HIP(hipMemcpyAsync(d_moves, hi.data() + 4 * B, (size_t)2 * nmoves * sizeof(int), hipMemcpyHostToDevice,
+                               s));
+        if (plain32)
+            NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
+        else
+            NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
+    }
+    E.slot.resize((size_t)nkeep);
+    k = nkeep;
+    if (k == 0) {
+        E.precision = -1;
+        E.any_ws = false;
+        NMG_HIP(hipStreamSynchronize(s));
+        return NMG_OK;
+    }
+    // ---- one outer iteration on kb >= k slots (a fixed set of launch sizes,
+    // so a few captured graphs serve every active count); slots k..kb-1 carry
+    // slot 0's parameters with a zero residual norm, which the cycle treats as
+    // converged (zero input, no update)
+    const int kb = h->use_graphs ? graph_batch(k, B) : k;
+    for (int i = 0; i < kb; ++i) {
+        const EngineSlot& sl = E.slot[(size_t)(i < k ? i : 0)];
+        hd[(size_t)i] = sl.alpha;
+        hd[(size_t)B + i] = sl.bn2;
+        hd[(size_t)2 * B + i] = i < k ? sl.rn2 : 0.0;
+        hi[(size_t)i] = sl.ws;
+        hi[(size_t)B + i] = sl.fidx;
+    }
+    NMG_HIP(hipMemcpyAsync(h->slot_d, hd.data(), (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
+    NMG_HIP(hipMemcpyAsync(h->slot_i, hi.data(), (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
+    h->cycle_fidx = d_fidx;
+    const int* wsd = E.any_ws ? d_ws : nullptr;
+    auto residual = [&](int kk, hipStream_t st) -> nmg_status {
+        ProfScope ps(h, st, NMG_K_REFINE, 0);
+        if (plain32) {
+            NMG_TRY(launch_operator<float>(h, 0, kk, d_alpha, X32, B32, R32, 0, h->w32b, st));
+            NMG_TRY(launch_sumsq<float>(h, kk, per, R32, h->nrm2, st));
+        } else {
+            NMG_TRY(launch_operator<double>(h, 0, kk, d_alpha, X64, B64, R64, 0, h->w64, st));
+            NMG_TRY(launch_sumsq<double>(h, kk, per, R64, h->nrm2, st));
+        }
+        return NMG_OK;
+    };
+    // d = MG(0, r / ||r||), x += ||r|| d, then the residual for the next check
+    auto iterate = [&](int kk, hipStream_t st) -> nmg_status {
+        if (plain32) {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<float, float>(kk, per, R32, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<float, float>(kk, per, X32, w.lv[0].x, d_rn2, h->active, st));
+        } else if (o->precision == NMG_FP64) {
+            Work<double>& w = h->w64;
+            NMG_TRY(launch_refine_scale<double, double>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<double>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<double, double>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
+        } else {
+            Work<float>& w = h->w32b;
+            NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            NMG_TRY(launch_refine_update<double, float>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
+        }
+        return residual(kk, st);
+    };
+    if (h->use_graphs) {
+        std::vector<long long> key = {kb, (long long)o->precision, o->nu1, o->nu2, o->use_fprime, wsd ? 1 : 0,
+                                      (long long)h->prof_mask};
+        long long rbits;
+        __builtin_memcpy(&rbits, &rtol, sizeof(rbits));
+        key.push_back(rbits);
+        auto found = h->graphs.find(key);
+        if (found == h->graphs.end()) {
+            Ctx::GraphEntry ge;
+            NMG_TRY(capture_graph(h, [&](hipStream_t cs) { return iterate(kb, cs); }, ge));
+            found = h->graphs.emplace(key, std::move(ge)).first;
+        }
+        if (h->prof_mask)
+            for (auto& e : found->second.stamps) h->stamp_pending.push_back(e);
+        NMG_HIP(hipGraphLaunch(found->second.exec, s));
+    } else {
+        NMG_TRY(iterate(kb, s));
+    }
+    for (int i = 0; i < k; ++i) E.slot[(size_t)i].cycles += 1;
+    return NMG_OK;
+}
 
 }  // namespace nmg
 
@@ -547,6 +846,7 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->b64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->slot_d, (size_t)3 * B));
     NMG_TRY(dev_alloc(&c->slot_i, (size_t)6 * B));
+    NMG_HIP(hipMalloc((void**)&c->xptr_dev, (size_t)B * sizeof(double*)));
     c->slot_d_host.assign((size_t)3 * B, 0.0);
     c->slot_i_host.assign((size_t)6 * B, 0);
     NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
@@ -600,6 +900,7 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->b64);
     dev_free(c->slot_d);
     dev_free(c->slot_i);
+    dev_free(c->xptr_dev);
     dev_free(c->r64);
     dev_free(c->xs32);
     dev_free(c->bs32);
@@ -658,64 +959,16 @@ nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha, void* strea
     NMG_TRY(check_batch(h, batch));
     if (!alpha) return fail(NMG_ERR_ARG, "null alpha");
     hipStream_t s = (hipStream_t)stream;
-    // Factors are cached per alpha value (exact match): a batch with U distinct
-    // alphas factors at most U matrices, and alphas seen before cost nothing.
     std::vector<double> al((size_t)batch);
     NMG_HIP(hipMemcpyAsync(al.data(), alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
     NMG_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < batch; ++b)
-        if (!std::isfinite(al[(size_t)b]) || !(al[(size_t)b] > 0.0))
-            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(b) + ")");
-    const long long stamp = ++h->prepare_count;
-    const int slots = (int)h->cache_alpha.size();
-    std::vector<int> idx((size_t)batch, -1), new_slots;
-    std::vector<double> new_alphas;
-    auto find = [&](double a) {
-        for (int k = 0; k < slots; ++k)
-            if (h->cache_alpha[(size_t)k] == a) return k;
-        return -1;
-    };
-    for (int b = 0; b < batch; ++b) {
-        const double a = al[(size_t)b];
-        int k = find(a);
-        if (k < 0) {
-            // least recently used slot not claimed by this batch
-            long long best = stamp;  // slots already claimed by this batch carry `stamp`
-            for (int j = 0; j < slots; ++j)
-                if (h->cache_used[(size_t)j] < best) {
-                    best = h->cache_used[(size_t)j];
-                    k = j;
-                }
-            if (k < 0) return fail(NMG_ERR_STATE, "coarse factor cache exhausted");
-            h->cache_alpha[(size_t)k] = a;
-            new_slots.push_back(k);
-            new_alphas.push_back(a);
-        }
-        h->cache_used[(size_t)k] = stamp;
-        idx[(size_t)b] = k;
-    }
+    std::vector<int> idx;
+    NMG_TRY(factor_alphas(h, al, idx, s));
     h->coarse_idx_host = idx;
     h->alpha_host = al;
     NMG_HIP(hipMemcpyAsync(h->coarse_idx, h->coarse_idx_host.data(), (size_t)batch * sizeof(int),
                            hipMemcpyHostToDevice, s));
-    const int cnt = (int)new_slots.size();
-    if (cnt > 0) {
-        NMG_HIP(hipMemcpyAsync(h->alpha_prepared, new_alphas.data(), (size_t)cnt * sizeof(double),
-                               hipMemcpyHostToDevice, s));
-        NMG_HIP(hipMemcpyAsync(h->slot_dev, new_slots.data(), (size_t)cnt * sizeof(int), hipMemcpyHostToDevice, s));
-        NMG_TRY(launch_coarse_factor(h, cnt, h->alpha_prepared, h->slot_dev, s));
-        NMG_TRY(launch_coarse_inverse(h, cnt, h->slot_dev, s));
-        std::vector<int> flags((size_t)cnt);
-        NMG_HIP(hipMemcpyAsync(flags.data(), h->flags, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, s));
-        NMG_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < cnt; ++k)
-            if (flags[(size_t)k]) {
-                h->cache_alpha[(size_t)new_slots[(size_t)k]] = std::nan("");
-                return fail(NMG_ERR_NOT_SPD, "coarse Cholesky failed for alpha " + std::to_string(new_alphas[(size_t)k]));
-            }
-    } else {
-        NMG_HIP(hipStreamSynchronize(s));
-    }
+    NMG_HIP(hipStreamSynchronize(s));
     return NMG_OK;
 }
 
@@ -795,25 +1048,10 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* w
     return run_cycle<float>(h, batch, alpha, ws, (const float*)y, (float*)x, false, *o, s);
 }
 
-namespace {
-// Restores the cycle's factor indexing to the prepare order on every exit of a solve.
-struct FidxGuard {
-    nmg::Ctx* c;
-    ~FidxGuard() { c->cycle_fidx = nullptr; }
-};
-}  // namespace
-
-// Outer iteration with active-set compaction: the right-hand sides still
-// iterating occupy batch slots 0..k-1 of the handle's compacted buffers
-// (iterate, right-hand side, residual, per-slot alpha / weight set / factor
-// index), so every cycle runs on exactly the k active problems.  A finished
-// right-hand side has its iterate copied to x and its slot refilled from the
-// end of the active range.  Each problem's arithmetic does not depend on which
-// slot it sits in or on the other problems of the batch.
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws, const double* b, double* x,
                      double rtol, int max_cycles, const nmg_cycle_opts* o, int* cycles_host, double* history_host,
                      double* done_ms_host, void* stream) {
-    const auto t_entry = std::chrono::steady_clock::now();
+    const double t_entry = h ? h->eng.now_ms() : 0.0;
     if (done_ms_host)
         for (int i = 0; i < batch && i < (h ? h->p.max_batch : 0); ++i) done_ms_host[i] = -1.0;
     NMG_TRY(check_handle(h));
@@ -821,211 +1059,89 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     NMG_TRY(check_opts(h, o));
     if (!alpha || !b || !x) return fail(NMG_ERR_ARG, "null pointer");
     if (!(rtol > 0.0) || max_cycles < 0) return fail(NMG_ERR_ARG, "rtol must be > 0 and max_cycles >= 0");
+    if (!h->eng.queue.empty() || !h->eng.slot.empty())
+        return fail(NMG_ERR_STATE, "serving requests are queued or active on this handle");
     hipStream_t s = (hipStream_t)stream;
-    NMG_TRY(nmg_prepare(h, batch, alpha, stream));
-    const int B = h->p.max_batch;
+    std::vector<double> al((size_t)batch);
     std::vector<int> wsv((size_t)batch, 0);
-    if (ws) {
-        NMG_HIP(hipMemcpyAsync(wsv.data(), ws, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
-        NMG_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i < batch; ++i)
-            if (wsv[(size_t)i] < 0 || wsv[(size_t)i] >= h->p.n_weight_sets)
-                return fail(NMG_ERR_ARG, "weight set out of range (right-hand side " + std::to_string(i) + ")");
-    }
-    const size_t per = level_elems(h, 0);
-    const size_t cnt = (size_t)batch * per;
-    NMG_TRY(ensure_work<double>(h));
-    const bool plain32 = o->precision == NMG_FP32;
-    if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
-    FidxGuard guard{h};
-    // compacted state: FP64 iterate / rhs / residual, or their FP32 versions for the plain FP32 iteration
-    double* X64 = h->x64;
-    double* B64 = h->b64;
-    double* R64 = h->r64;
-    float* X32 = h->xs32;
-    float* B32 = h->bs32;
-    float* R32 = reinterpret_cast<float*>(h->r64);  // r64 has room for cnt doubles
-    NMG_TRY(launch_sumsq<double>(h, batch, per, b, h->nrm2, s));
-    std::vector<double> bn2((size_t)batch), rn2((size_t)batch), last_r2((size_t)batch, 0.0);
-    NMG_HIP(hipMemcpyAsync(bn2.data(), h->nrm2, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (plain32) {
-        NMG_TRY(launch_convert<double, float>(b, B32, cnt, s));
-        NMG_TRY(launch_zero<float>(X32, cnt, s));
-    } else {
-        NMG_HIP(hipMemcpyAsync(B64, b, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
-        NMG_TRY(launch_zero<double>(X64, cnt, s));
-    }
+    NMG_HIP(hipMemcpyAsync(al.data(), alpha, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (ws) NMG_HIP(hipMemcpyAsync(wsv.data(), ws, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
     NMG_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < batch; ++i)
-        if (!std::isfinite(bn2[(size_t)i])) return fail(NMG_ERR_NONFINITE, "non-finite right-hand side");
+    for (int i = 0; i < batch; ++i) {
+        if (!std::isfinite(al[(size_t)i]) || !(al[(size_t)i] > 0.0))
+            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(i) + ")");
+        if (wsv[(size_t)i] < 0 || wsv[(size_t)i] >= h->p.n_weight_sets)
+            return fail(NMG_ERR_ARG, "weight set out of range (right-hand side " + std::to_string(i) + ")");
+    }
     if (history_host)
         for (size_t i = 0; i < (size_t)batch * (max_cycles + 1); ++i) history_host[i] = -1.0;
-    std::vector<int> cyc((size_t)batch, 0), slot_rhs((size_t)batch);
-    for (int i = 0; i < batch; ++i) slot_rhs[(size_t)i] = i;
-    double* d_alpha = h->slot_d;
-    double* d_bn2 = h->slot_d + B;
-    double* d_rn2 = h->slot_d + 2 * B;
-    int* d_ws = h->slot_i;
-    int* d_fidx = h->slot_i + B;
-    int* d_pairs = h->slot_i + 2 * B;  // 2B ints: finished (slot, rhs) pairs
-    int* d_moves = h->slot_i + 4 * B;  // 2B ints: (destination, source) slot moves
-    std::vector<double>& hd = h->slot_d_host;
-    std::vector<int>& hi = h->slot_i_host;
-    // per-slot tables for slots [0, k); the staging vectors are only rewritten after a stream sync
-    auto upload_slots = [&](int k, int kb) -> nmg_status {
-        for (int i = 0; i < kb; ++i) {
-            const int src = i < k ? i : 0;
-            const int r = slot_rhs[(size_t)src];
-            hd[(size_t)i] = h->alpha_host[(size_t)r];
-            hd[(size_t)B + i] = bn2[(size_t)r];
-            hd[(size_t)2 * B + i] = i < k ? rn2[(size_t)i] : 0.0;
-            hi[(size_t)i] = wsv[(size_t)r];
-            hi[(size_t)B + i] = h->coarse_idx_host[(size_t)r];
-        }
-        NMG_HIP(hipMemcpyAsync(h->slot_d, hd.data(), (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
-        NMG_HIP(hipMemcpyAsync(h->slot_i, hi.data(), (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
-        return NMG_OK;
-    };
-    int k = batch;
-    for (int i = 0; i < batch; ++i) rn2[(size_t)i] = 0.0;
-    NMG_TRY(upload_slots(k, k));
-    h->cycle_fidx = d_fidx;
-    bool nonfinite = false;
-    const double tol2 = rtol * rtol;
-    // residual of slots [0, kk) and its norm in the outer precision
-    auto residual = [&](int kk, hipStream_t st) -> nmg_status {
-        ProfScope ps(h, st, NMG_K_REFINE, 0);
-        if (plain32) {
-            NMG_TRY(launch_operator<float>(h, 0, kk, d_alpha, X32, B32, R32, 0, h->w32b, st));
-            NMG_TRY(launch_sumsq<float>(h, kk, per, R32, h->nrm2, st));
-        } else {
-            NMG_TRY(launch_operator<double>(h, 0, kk, d_alpha, X64, B64, R64, 0, h->w64, st));
-            NMG_TRY(launch_sumsq<double>(h, kk, per, R64, h->nrm2, st));
-        }
-        return NMG_OK;
-    };
-    // one outer iteration on slots [0, kk): d = MG(0, r / ||r||), x += ||r|| d,
-    // then the residual for the next convergence check
-    const int* wsd = ws ? d_ws : nullptr;
-    auto iterate = [&](int kk, hipStream_t st) -> nmg_status {
-        if (plain32) {
-            Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<float, float>(kk, per, R32, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
-            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
-            NMG_TRY(launch_refine_update<float, float>(kk, per, X32, w.lv[0].x, d_rn2, h->active, st));
-        } else if (o->precision == NMG_FP64) {
-            Work<double>& w = h->w64;
-            NMG_TRY(launch_refine_scale<double, double>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
-            NMG_TRY(run_cycle<double>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
-            NMG_TRY(launch_refine_update<double, double>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
-        } else {
-            Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
-            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
-            NMG_TRY(launch_refine_update<double, float>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
-        }
-        return residual(kk, st);
-    };
-    if (o->precision == NMG_MIXED && h->p.dim == 2 && o->use_fprime) NMG_TRY(prepare_fprime_bf16(h));
-    NMG_TRY(residual(k, s));
-    for (int it = 0; it <= max_cycles; ++it) {
-        NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
-        NMG_HIP(hipStreamSynchronize(s));
-        if (h->prof_mask) NMG_TRY(prof_resolve(h));
-        const double now_ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
-        std::vector<char> keep((size_t)k, 0);
-        int npairs = 0, nkeep = 0;
-        for (int i = 0; i < k; ++i) {
-            const int r = slot_rhs[(size_t)i];
-            const double q = rn2[(size_t)i], bb = bn2[(size_t)r];
-            last_r2[(size_t)r] = q;
-            bool finished = true;
-            if (!std::isfinite(q)) {
-                nonfinite = true;
-            } else {
-                if (history_host) history_host[(size_t)r * (max_cycles + 1) + it] = bb > 0 ? std::sqrt(q / bb) : 0.0;
-                if (!(q > tol2 * bb)) {
-                    if (done_ms_host) done_ms_host[r] = now_ms;
-                } else if (it < max_cycles) {
-                    finished = false;
-                }
-            }
-            if (finished) {
-                hi[(size_t)2 * B + 2 * npairs] = i;
-                hi[(size_t)2 * B + 2 * npairs + 1] = r;
-                ++npairs;
-            } else {
-                keep[(size_t)i] = 1;
-                ++nkeep;
-            }
-        }
-        if (npairs > 0) {
-            NMG_HIP(hipMemcpyAsync(d_pairs, hi.data() + 2 * B, (size_t)2 * npairs * sizeof(int),
-                                   hipMemcpyHostToDevice, s));
-            if (plain32)
-                NMG_TRY(launch_scatter_slots<float>(npairs, per, X32, x, d_pairs, s));
-            else
-                NMG_TRY(launch_scatter_slots<double>(npairs, per, X64, x, d_pairs, s));
-        }
-        if (nkeep == 0) break;
-        // refill the finished slots below nkeep from active slots at or above it
-        int nmoves = 0;
-        {
-            int src = k - 1;
-            for (int dst = 0; dst < nkeep; ++dst) {
-                if (keep[(size_t)dst]) continue;
-                while (!keep[(size_t)src]) --src;  // src >= nkeep holds an active slot
-                hi[(size_t)4 * B + 2 * nmoves] = dst;
-                hi[(size_t)4 * B + 2 * nmoves + 1] = src;
-                ++nmoves;
-                slot_rhs[(size_t)dst] = slot_rhs[(size_t)src];
-                rn2[(size_t)dst] = rn2[(size_t)src];
-                keep[(size_t)src] = 0;
-                --src;
-            }
-        }
-        if (nmoves > 0) {
-            NMG_HIP(hipMemcpyAsync(d_moves, hi.data() + 4 * B, (size_t)2 * nmoves * sizeof(int),
-                                   hipMemcpyHostToDevice, s));
-            if (plain32)
-                NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
-            else
-                NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
-        }
-        k = nkeep;
-        // the iteration runs on kb >= k slots (a fixed set of launch sizes, so
-        // a few captured graphs serve every active count); slots k..kb-1 carry
-        // slot 0's parameters with a zero residual norm, which the cycle treats
-        // as converged (zero input, no update)
-        const int kb = h->use_graphs ? graph_batch(k, B) : k;
-        NMG_TRY(upload_slots(k, kb));
-        if (h->use_graphs) {
-            std::vector<long long> key = {kb, (long long)o->precision, o->nu1, o->nu2, o->use_fprime, ws ? 1 : 0,
-                                          (long long)h->prof_mask};
-            long long rbits;
-            __builtin_memcpy(&rbits, &rtol, sizeof(rbits));
-            key.push_back(rbits);
-            auto found = h->graphs.find(key);
-            if (found == h->graphs.end()) {
-                Ctx::GraphEntry ge;
-                NMG_TRY(capture_graph(h, [&](hipStream_t cs) { return iterate(kb, cs); }, ge));
-                found = h->graphs.emplace(key, std::move(ge)).first;
-            }
-            if (h->prof_mask)
-                for (auto& e : found->second.stamps) h->stamp_pending.push_back(e);
-            NMG_HIP(hipGraphLaunch(found->second.exec, s));
-        } else {
-            NMG_TRY(iterate(kb, s));
-        }
-        for (int i = 0; i < k; ++i) cyc[(size_t)slot_rhs[(size_t)i]] += 1;
-    }
-    NMG_HIP(hipStreamSynchronize(s));
-    if (cycles_host)
-        for (int i = 0; i < batch; ++i) cycles_host[i] = cyc[(size_t)i];
-    if (nonfinite) return fail(NMG_ERR_NONFINITE, "non-finite residual");
+    const size_t per = level_elems(h, 0);
     for (int i = 0; i < batch; ++i)
-        if (last_r2[(size_t)i] > tol2 * bn2[(size_t)i]) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
+        h->eng.queue.push_back({(long long)i, al[(size_t)i], wsv[(size_t)i], b + (size_t)i * per,
+                                x + (size_t)i * per,
+                                history_host ? history_host + (size_t)i * (max_cycles + 1) : nullptr, max_cycles + 1,
+                                t_entry});
+    std::vector<nmg_request_result> done;
+    nmg_status st = NMG_OK;
+    while (st == NMG_OK && (!h->eng.queue.empty() || !h->eng.slot.empty()))
+        st = engine_step(h, rtol, max_cycles, o, done, s);
+    if (st != NMG_OK) {
+        h->eng.queue.clear();
+        h->eng.slot.clear();
+        h->eng.precision = -1;
+        h->eng.any_ws = false;
+        return st;
+    }
+    bool nonfinite = false, missed = false;
+    for (const auto& r : done) {
+        const int i = (int)r.id;
+        if (cycles_host) cycles_host[i] = r.cycles;
+        if (done_ms_host && r.status == NMG_OK) done_ms_host[i] = r.latency_ms;
+        nonfinite = nonfinite || r.status == NMG_ERR_NONFINITE;
+        missed = missed || r.status == NMG_NOT_CONVERGED;
+    }
+    if (nonfinite) return fail(NMG_ERR_NONFINITE, "non-finite residual");
+    if (missed) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
+    return NMG_OK;
+}
+
+nmg_status nmg_serve_submit(nmg_handle h, long long id, double alpha, int weight_set, const double* b_dev,
+                            double* x_dev) {
+    NMG_TRY(check_handle(h));
+    if (!b_dev || !x_dev) return fail(NMG_ERR_ARG, "null pointer");
+    if (!std::isfinite(alpha) || !(alpha > 0.0)) return fail(NMG_ERR_ARG, "alpha must be positive and finite");
+    if (weight_set < 0 || weight_set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight set out of range");
+    h->eng.queue.push_back({id, alpha, weight_set, b_dev, x_dev, nullptr, 0, h->eng.now_ms()});
+    return NMG_OK;
+}
+
+nmg_status nmg_serve_step(nmg_handle h, double rtol, int max_cycles, const nmg_cycle_opts* o,
+                          nmg_request_result* done, int* n_done, void* stream) {
+    if (n_done) *n_done = 0;
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_opts(h, o));
+    if (!done || !n_done) return fail(NMG_ERR_ARG, "null result array");
+    if (!(rtol > 0.0) || max_cycles < 0) return fail(NMG_ERR_ARG, "rtol must be > 0 and max_cycles >= 0");
+    std::vector<nmg_request_result> out;
+    NMG_TRY(engine_step(h, rtol, max_cycles, o, out, (hipStream_t)stream));
+    for (size_t i = 0; i < out.size(); ++i) done[i] = out[i];
+    *n_done = (int)out.size();
+    return NMG_OK;
+}
+
+nmg_status nmg_serve_pending(nmg_handle h, int* queued, int* active) {
+    NMG_TRY(check_handle(h));
+    if (queued) *queued = (int)h->eng.queue.size();
+    if (active) *active = (int)h->eng.slot.size();
+    return NMG_OK;
+}
+
+nmg_status nmg_serve_reset(nmg_handle h) {
+    NMG_TRY(check_handle(h));
+    h->eng.queue.clear();
+    h->eng.slot.clear();
+    h->eng.precision = -1;
+    h->eng.any_ws = false;
     return NMG_OK;
 }
 

@@ -37,6 +37,12 @@ class _Problem(ctypes.Structure):
     ]
 
 
+class RequestResult(ctypes.Structure):
+    """``nmg_request_result``: one finished serving request."""
+    _fields_ = [("id", ctypes.c_longlong), ("status", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
 class _CycleOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("use_fprime", ctypes.c_int),
                 ("precision", ctypes.c_int)]
@@ -74,6 +80,10 @@ def load_library():
         "nmg_level_size": (I, [P, I]),
         "nmg_profile_enable": (S, [P, I]),
         "nmg_set_graphs": (S, [P, I]),
+        "nmg_serve_submit": (S, [P, ctypes.c_longlong, D, I, P, P]),
+        "nmg_serve_step": (S, [P, D, I, ctypes.POINTER(_CycleOpts), P, ctypes.POINTER(ctypes.c_int), P]),
+        "nmg_serve_pending": (S, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "nmg_serve_reset": (S, [P]),
         "nmg_profile_query": (S, [P, I, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "nmg_debug_transfer_map": (S, [P, I, I, P, P]),
         "nmg_debug_factor": (S, [P, I, I, P, P]),
@@ -149,6 +159,8 @@ class Handle:
     """An ``nmg_handle`` plus the problem it was built for."""
     problem: Problem
     ptr: ctypes.c_void_p = field(default_factory=ctypes.c_void_p)
+    _serve_refs: dict = field(default_factory=dict)
+    _next_id: int = 0
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -276,6 +288,44 @@ class Handle:
                                    done_ms.ctypes.data_as(ctypes.c_void_p) if done_ms is not None
                                    else ctypes.c_void_p(), _stream()))
         return x, cycles, hist, st
+
+    # -- serving (continuous batching) --------------------------------------
+    def serve_submit(self, b, x, alpha: float, weight_set: int = 0, rid: int | None = None) -> int:
+        """Queues one request: ``b`` (float64 [ny, n] device tensor) is solved into
+        ``x`` (same shape) when the request finishes.  Both tensors are kept
+        alive by the handle until then.  Returns the request id."""
+        import torch
+        _require(b, torch.float64, self.level_shape(0, 1)[1:], "b")
+        _require(x, torch.float64, self.level_shape(0, 1)[1:], "x")
+        if rid is None:
+            rid = self._next_id
+        self._next_id = max(self._next_id, rid) + 1
+        _check(_lib.nmg_serve_submit(self.ptr, int(rid), float(alpha), int(weight_set), _ptr(b), _ptr(x)))
+        self._serve_refs[int(rid)] = (b, x)
+        return int(rid)
+
+    def serve_step(self, rtol: float = 1e-6, max_cycles: int = 100, nu1: int = 1, nu2: int = 1,
+                   use_fprime: bool = False, precision: str = "mixed"):
+        """One engine step; returns the list of finished :class:`RequestResult`."""
+        done = (RequestResult * self.problem.max_batch)()
+        nd = ctypes.c_int(0)
+        o = _CycleOpts(nu1, nu2, 1 if use_fprime else 0, PRECISION[precision])
+        _check(_lib.nmg_serve_step(self.ptr, float(rtol), int(max_cycles), ctypes.byref(o), done, ctypes.byref(nd),
+                                   _stream()))
+        out = [done[i] for i in range(nd.value)]
+        for r in out:
+            self._serve_refs.pop(int(r.id), None)
+        return out
+
+    def serve_pending(self):
+        """``(queued, active)`` request counts."""
+        q, a = ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib.nmg_serve_pending(self.ptr, ctypes.byref(q), ctypes.byref(a)))
+        return q.value, a.value
+
+    def serve_reset(self) -> None:
+        _check(_lib.nmg_serve_reset(self.ptr))
+        self._serve_refs.clear()
 
     # -- training ----------------------------------------------------------
     def loss_grad(self, e, alpha, weight_set: int = 0, mask: str = "ramp", use_fprime: bool = False,
