@@ -129,6 +129,7 @@ def main(argv=None):
     ap.add_argument("--max-cycles", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serial-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 64 MiB device copy before timing (reference kernel for HBM counters)")
     a = ap.parse_args(argv)
@@ -247,6 +248,10 @@ def main(argv=None):
             res["serial_fp32_gpu"]["speedup_solves_per_s"] = round(value / res["serial_fp32_gpu"]["value"], 1)
             if res["config"]["p99_ms"] and res["serial_fp32_gpu"]["p99_ms"]:
                 res["serial_fp32_gpu"]["p99_ratio"] = round(res["serial_fp32_gpu"]["p99_ms"] / res["config"]["p99_ms"], 2)
+    if not a.no_serving:
+        log("serving: continuous batching on Poisson arrivals")
+        res["serving"] = serving(nmg, h, sets, set_alphas, cyc_cfg, batches[a.warmup:], a.max_cycles,
+                                 serial=not a.no_serial_baseline)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(meta, sets, float(cycles.mean()))
@@ -255,16 +260,22 @@ def main(argv=None):
     return 0
 
 
-def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8):
-    """Plain FP32 V-cycle solving one right-hand side at a time (no batching,
-    no BF16, no refinement) on the first `count` problems of a batch."""
-    import torch
-    dev = torch.device("cuda:0")
+def _serial_handle(nmg, sets):
     h1 = nmg.setup_hierarchy(nmg.Problem(n=N, s=S, levels=LEVELS, max_batch=1, channels=CHANNELS, ksize=3,
                                          n_weight_sets=len(sets)))
     for k, ws in enumerate(sets):
         for l in range(LEVELS - 1):
             h1.load_smoother_weights(l, k, [ws[l]])
+    h1.set_graphs(False)
+    return h1
+
+
+def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8):
+    """Plain FP32 V-cycle solving one right-hand side at a time (no batching,
+    no BF16, no refinement, no graphs) on the first `count` problems of a batch."""
+    import torch
+    dev = torch.device("cuda:0")
+    h1 = _serial_handle(nmg, sets)
     probs = []
     for i in range(count):
         alpha = torch.tensor([alpha_np[i]], dtype=torch.float64, device=dev)
@@ -290,7 +301,53 @@ def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8
     h1.close()
     return {"value": round(count / elapsed, 3), "unit": "solves/s", "p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2), "converged": ok, "solves": count, "cycles": cyc_all,
-            "note": "one request at a time, plain FP32 cycle and FP32 direct-convolution smoother"}
+            "note": "one request at a time, plain FP32 cycle and FP32 direct-convolution smoother, no graphs"}
+
+
+def serving(nmg, h, sets, set_alphas, cyc_cfg, batches, max_cycles, rates=(20.0, 1000.0), low_count=48,
+            serial=True):
+    """Continuous batching through the handle's 64 slots on Poisson arrival
+    traces of the same synthetic requests (latency = arrival to completion,
+    queueing included), and the serial plain-FP32 solver on the low-rate
+    trace; plus the saturated rate with every request queued at once."""
+    import torch
+
+    from paper_2603_01064_amd import inputs
+    from paper_2603_01064_amd.serve import serve_requests, serve_serially
+    b = torch.cat([bt[2] for bt in batches])
+    alpha = torch.cat([bt[0] for bt in batches]).cpu().numpy()
+    ws = torch.cat([bt[1] for bt in batches]).cpu().numpy()
+    x = torch.empty_like(b)
+    kw = dict(rtol=1e-6, max_cycles=max_cycles, nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"],
+              use_fprime=cyc_cfg["use_fprime"], precision="mixed")
+    out = {}
+    total = b.shape[0]
+    rep = serve_requests(h, b, x, alpha, ws, np.zeros(total), **kw)
+    out["saturated"] = rep.summary()
+    for rate in rates:
+        cnt = low_count if rate < 100 else total
+        arr = inputs.poisson_arrivals(rate, cnt, seed=31000 + int(rate))
+        arr = arr - arr[0]
+        rep = serve_requests(h, b[:cnt], x[:cnt], alpha[:cnt], ws[:cnt], arr, **kw)
+        out[f"poisson_{int(rate)}_per_s"] = rep.summary()
+        if serial and rate < 100:
+            h1 = _serial_handle(nmg, sets)
+            dev = b.device
+
+            def solve_one(i):
+                try:
+                    _, cyc, _, st = h1.solve(b[i:i + 1], torch.tensor([alpha[i]], dtype=torch.float64, device=dev),
+                                             weight_set=torch.tensor([int(ws[i])], dtype=torch.int32, device=dev),
+                                             rtol=1e-6, max_cycles=max_cycles, nu1=cyc_cfg["nu1"],
+                                             nu2=cyc_cfg["nu2"], use_fprime=cyc_cfg["use_fprime"], precision="fp32")
+                    return int(cyc[0]), int(st)
+                except nmg.NMGError:
+                    return -1, -1
+
+            srep = serve_serially(solve_one, arr)
+            h1.close()
+            out[f"poisson_{int(rate)}_per_s"]["serial_fp32"] = srep.summary()
+    return out
 
 
 if __name__ == "__main__":
