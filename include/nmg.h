@@ -288,6 +288,10 @@ typedef enum {
  * event nodes inside captured solve iterations). */
 nmg_status nmg_profile_enable(nmg_handle h, int kind_mask);
 
+/* Restricts timing to the levels in level_mask (bit l = level l; default
+ * all levels).  Fewer timed launches mean less timing overhead. */
+nmg_status nmg_profile_levels(nmg_handle h, int level_mask);
+
 /* Accumulated device time (ms) and launch count of one kernel family on one
  * level (level -1 sums all levels).  Synchronises the recorded events. */
 nmg_status nmg_profile_query(nmg_handle h, int kind, int level, double* total_ms, int* launches);

@@ -213,7 +213,8 @@ struct Ctx {
     Work<float> w32b;
     bool grad_is_fp64 = false;         // which gradient buffer the last loss_grad filled
     // profiler
-    int prof_mask = 0;  // bit k: time kernel family k
+    int prof_mask = 0;         // bit k: time kernel family k
+    int prof_levels = 0xFFFF;  // bit l: time launches on level l
     struct ProfEv { hipEvent_t a, b; int kind, level; };
     std::vector<ProfEv> prof_pending;
     std::vector<hipEvent_t> prof_pool;

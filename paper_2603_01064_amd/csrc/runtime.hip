@@ -72,7 +72,7 @@ static hipEvent_t prof_event(Ctx* c) {
 }
 
 ProfScope::ProfScope(const Ctx* cc, hipStream_t ss, int k, int l) : c(const_cast<Ctx*>(cc)), s(ss), kind(k), level(l) {
-    if (!(c->prof_mask & (1 << k))) return;
+    if (!(c->prof_mask & (1 << k)) || !(c->prof_levels & (1 << (l < 0 ? 0 : (l > 15 ? 15 : l))))) return;
     if (c->capturing) {
         // graph node timing: wall-clock stamps (events cannot be timed inside graphs)
         if (!c->stamps || c->stamp_next + 2 > kStampSlots) return;
@@ -738,7 +738,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     };
     if (h->use_graphs) {
         std::vector<long long> key = {kb, (long long)o->precision, o->nu1, o->nu2, o->use_fprime, wsd ? 1 : 0,
-                                      (long long)h->prof_mask};
+                                      (long long)h->prof_mask, (long long)h->prof_levels};
         long long rbits;
         __builtin_memcpy(&rbits, &rtol, sizeof(rbits));
         key.push_back(rbits);
@@ -1186,6 +1186,13 @@ nmg_status nmg_profile_enable(nmg_handle h, int on) {
         for (auto& v : row) v = 0.0;
     for (auto& row : h->prof_cnt)
         for (auto& v : row) v = 0;
+    return NMG_OK;
+}
+
+nmg_status nmg_profile_levels(nmg_handle h, int level_mask) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(prof_resolve(h));
+    h->prof_levels = level_mask;
     return NMG_OK;
 }
 

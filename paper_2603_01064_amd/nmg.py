@@ -80,6 +80,7 @@ def load_library():
         "nmg_level_size": (I, [P, I]),
         "nmg_profile_enable": (S, [P, I]),
         "nmg_set_graphs": (S, [P, I]),
+        "nmg_profile_levels": (S, [P, I]),
         "nmg_serve_submit": (S, [P, ctypes.c_longlong, D, I, P, P]),
         "nmg_serve_step": (S, [P, D, I, ctypes.POINTER(_CycleOpts), P, ctypes.POINTER(ctypes.c_int), P]),
         "nmg_serve_pending": (S, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -377,6 +378,11 @@ class Handle:
         for k in kinds:
             mask |= 1 << self.KERNELS[k]
         _check(_lib.nmg_profile_enable(self.ptr, mask))
+
+    def profile_levels(self, levels=None) -> None:
+        """Time only the given levels (None: all levels)."""
+        mask = 0xFFFF if levels is None else sum(1 << int(l) for l in levels)
+        _check(_lib.nmg_profile_levels(self.ptr, mask))
 
     def profile_query(self, kind: str, level: int = -1):
         """``(total_ms, launches)`` of one kernel family (level -1: all levels)."""
