@@ -40,20 +40,26 @@ inline uint16_t f2bf_h(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// EPI 0: store, 1: store times the ramp mask, 2: add into out.
-// Workgroup tile 64 (i) x 128 (j); wave w computes rows 32*(w/2).. and
-// columns 64*(w%2).. as 2 x 4 MFMA blocks.  Each k-step of 32 stages the
-// A tile (converted to BF16) and the B tile in LDS with the 16-byte chunk of
-// row r stored at chunk ^ (r & 3) to spread the fragment reads over banks.
+// One pass out[b][j][i] = sum_k in[b][i][k] Mat[j][k] on a workgroup tile of
+// 64 (i) x 128 (j); wave w computes rows 32*(w/2).. and columns 64*(w%2).. as
+// 2 x 4 MFMA blocks.  Each k-step of 32 stages the A tile (in) and the B
+// tile (Mat) in LDS with the 16-byte chunk of row r stored at chunk ^ (r & 3)
+// to spread the fragment reads over banks.
+//   IN  0: in is the FP32 n x n level array (rounded to BF16 while staging)
+//       1: in is a BF16 npad x npad intermediate (zero padded)
+//   OUT 0: BF16 npad x npad intermediate; 1: the same times the ramp mask;
+//       2: FP32 n x n result, stored or added (accumulate) into out
+// BF16 intermediates are exactly the values the next pass would have rounded
+// an FP32 intermediate to, and they halve the traffic between passes.
 constexpr int kTI = 64, kTJ = 128, kKS = 32;
 
 __device__ inline int frag_off(int row, int chunk) { return row * 64 + ((chunk ^ (row & 3)) << 4); }
 
-template <int EPI>
-__global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict__ in, float* __restrict__ out,
+template <int IN, int OUT>
+__global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__ in_v, void* __restrict__ out_v,
                                                         const uint16_t* __restrict__ mat,
                                                         const float* __restrict__ ramp, int n, int npad,
-                                                        int tiles_j) {
+                                                        int tiles_j, int accumulate) {
     __shared__ __attribute__((aligned(16))) char As[kTI * kKS * 2];
     __shared__ __attribute__((aligned(16))) char Bs[kTJ * kKS * 2];
     const int b = blockIdx.y;
@@ -63,8 +69,6 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict_
     const int ln = lane & 15, lg = lane >> 4;
     const int i0 = ti * kTI, j0 = tj * kTJ;
     const int wi = (wave >> 1) * 32, wj = (wave & 1) * 64;
-    const size_t per = (size_t)n * n;
-    const float* src = in + (size_t)b * per;
     floatx4 acc[2][4];
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -73,10 +77,17 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict_
     for (int k0 = 0; k0 < npad; k0 += kKS) {
         {
             const int i = i0 + sr, k = k0 + sc * 8;
-            float v[8];
-            for (int q = 0; q < 8; ++q) v[q] = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
-            *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) =
-                make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+            if constexpr (IN == 0) {
+                const float* src = reinterpret_cast<const float*>(in_v) + (size_t)b * n * n;
+                float v[8];
+                for (int q = 0; q < 8; ++q) v[q] = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
+                *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) = make_uint4(
+                    pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+            } else {
+                const uint16_t* src = reinterpret_cast<const uint16_t*>(in_v) + (size_t)b * npad * npad;
+                *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) =
+                    *reinterpret_cast<const uint4*>(src + (size_t)i * npad + k);
+            }
             for (int h = 0; h < 2; ++h) {
                 const int jr = sr + 64 * h;
                 const int j = j0 + jr;  // < npad by construction
@@ -93,21 +104,29 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const float* __restrict_
                 acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
         __syncthreads();
     }
-    float* dst = out + (size_t)b * per;
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 4; ++c) {
             const int j = j0 + wj + c * 16 + ln;
-            if (j >= n) continue;
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + wi + r * 16 + lg * 4 + q;
-                if (i >= n) continue;
-                float v = acc[r][c][q];
-                if (EPI == 1) v *= ramp[i > j ? i : j];
-                float* o = dst + (size_t)j * n + i;
-                if (EPI == 2)
-                    *o += v;
-                else
-                    *o = v;
+            const int ib = i0 + wi + r * 16 + lg * 4;  // four consecutive i
+            if constexpr (OUT == 2) {
+                if (j >= n) continue;
+                float* dst = reinterpret_cast<float*>(out_v) + (size_t)b * n * n + (size_t)j * n;
+                for (int q = 0; q < 4; ++q) {
+                    const int i = ib + q;
+                    if (i >= n) continue;
+                    dst[i] = accumulate ? dst[i] + acc[r][c][q] : acc[r][c][q];
+                }
+            } else {
+                float v[4];
+                for (int q = 0; q < 4; ++q) {
+                    v[q] = acc[r][c][q];
+                    if constexpr (OUT == 1) {
+                        const int i = ib + q;
+                        v[q] = (i < n && j < n) ? v[q] * ramp[i > j ? i : j] : 0.f;
+                    }
+                }
+                uint16_t* dst = reinterpret_cast<uint16_t*>(out_v) + (size_t)b * npad * npad + (size_t)j * npad;
+                *reinterpret_cast<uint2*>(dst + ib) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
             }
         }
 }
@@ -248,15 +267,15 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, fl
         NMG_HIP(hipGetLastError());
         return NMG_OK;
     }
+    if ((size_t)npad * npad * 2 > (size_t)n * n * 4)
+        return fail(NMG_ERR_SHAPE, "F' scratch too small for this level size");
     dim3 grid((unsigned)(ti * tj), (unsigned)batch);
     const float* rp = c->ramp + c->ramp_off[(size_t)l];
-    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, h, t1, C, rp, n, npad, tj);
-    hipLaunchKernelGGL(k_rowgemm_t<1>, grid, dim3(kThreads), 0, s, t1, t2, C, rp, n, npad, tj);
-    hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t2, t1, Ct, rp, n, npad, tj);
-    if (accumulate)
-        hipLaunchKernelGGL(k_rowgemm_t<2>, grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj);
-    else
-        hipLaunchKernelGGL(k_rowgemm_t<0>, grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj);
+    // BF16 intermediates (npad x npad per image) live in the level scratch buffers
+    hipLaunchKernelGGL((k_rowgemm_t<0, 0>), grid, dim3(kThreads), 0, s, h, t1, C, rp, n, npad, tj, 0);
+    hipLaunchKernelGGL((k_rowgemm_t<1, 1>), grid, dim3(kThreads), 0, s, t1, t2, C, rp, n, npad, tj, 0);
+    hipLaunchKernelGGL((k_rowgemm_t<1, 0>), grid, dim3(kThreads), 0, s, t2, t1, Ct, rp, n, npad, tj, 0);
+    hipLaunchKernelGGL((k_rowgemm_t<1, 2>), grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj, accumulate);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
