@@ -197,10 +197,13 @@ struct Ctx {
     double* b64 = nullptr;             // [max_batch][ny][n] compacted FP64 right-hand sides (solve)
     double* slot_d = nullptr;          // [3][max_batch] alpha, ||b||^2, ||r||^2 per compacted slot
     int* slot_i = nullptr;             // [2][max_batch] weight set, factor index; then [2][max_batch] x 2 move lists
-    std::vector<double> slot_d_host;   // staging for slot_d
-    std::vector<int> slot_i_host;      // staging for slot_i
+    // pinned host staging of the engine (rewritten only after a stream sync):
+    // pin_d [3B] slot tables, [B] residual norms, [B] right-hand-side norms;
+    // pin_i [6B] slot tables and move lists; pin_ptr [B] destinations
+    double* pin_d = nullptr;
+    int* pin_i = nullptr;
+    double** pin_ptr = nullptr;
     double** xptr_dev = nullptr;       // [max_batch] destinations of finished iterates
-    std::vector<double*> xptr_host;
     Engine eng;
     float* xs32 = nullptr;             // [max_batch][ny][n] plain-FP32 iterate
     float* bs32 = nullptr;             // [max_batch][ny][n] plain-FP32 right-hand side

@@ -554,8 +554,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     int* d_fidx = h->slot_i + B;
     int* d_pairs = h->slot_i + 2 * B;  // 2B ints: slots of finished requests
     int* d_moves = h->slot_i + 4 * B;  // 2B ints: (destination, source) slot moves
-    std::vector<double>& hd = h->slot_d_host;
-    std::vector<int>& hi = h->slot_i_host;
+    double* hd = h->pin_d;
+    int* hi = h->pin_i;
     // ---- admission: queued requests fill slots [k, k + m)
     const int m = std::min(B - k, (int)E.queue.size());
     if (m > 0) {
@@ -604,10 +604,11 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     k = (int)E.slot.size();
     if (k == 0) return NMG_OK;
     // ---- residual norms of every active slot (new ones: ||b||^2)
-    std::vector<double> rn2((size_t)k), bn2n((size_t)std::max(m, 1));
-    NMG_HIP(hipMemcpyAsync(rn2.data(), h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
+    double* rn2 = h->pin_d + 3 * B;
+    double* bn2n = h->pin_d + 4 * B;
+    NMG_HIP(hipMemcpyAsync(rn2, h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
     if (m > 0)
-        NMG_HIP(hipMemcpyAsync(bn2n.data(), (plain32 ? h->nrm : h->nrm2) + (k - m), (size_t)m * sizeof(double),
+        NMG_HIP(hipMemcpyAsync(bn2n, (plain32 ? h->nrm : h->nrm2) + (k - m), (size_t)m * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     NMG_HIP(hipStreamSynchronize(s));
     if (h->prof_mask) NMG_TRY(prof_resolve(h));
@@ -617,7 +618,6 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     // ---- retire finished requests
     std::vector<char> keep((size_t)k, 0);
     int nfin = 0, nkeep = 0;
-    h->xptr_host.resize((size_t)B);
     for (int i = 0; i < k; ++i) {
         EngineSlot& sl = E.slot[(size_t)i];
         const double q = rn2[(size_t)i], bb = sl.bn2;
@@ -645,12 +645,12 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         res.latency_ms = now - sl.t_submit;
         done.push_back(res);
         hi[(size_t)2 * B + nfin] = i;
-        h->xptr_host[(size_t)nfin] = sl.x;
+        h->pin_ptr[nfin] = sl.x;
         ++nfin;
     }
     if (nfin > 0) {
-        NMG_HIP(hipMemcpyAsync(d_pairs, hi.data() + 2 * B, (size_t)nfin * sizeof(int), hipMemcpyHostToDevice, s));
-        NMG_HIP(hipMemcpyAsync(h->xptr_dev, h->xptr_host.data(), (size_t)nfin * sizeof(double*),
+        NMG_HIP(hipMemcpyAsync(d_pairs, hi + 2 * B, (size_t)nfin * sizeof(int), hipMemcpyHostToDevice, s));
+        NMG_HIP(hipMemcpyAsync(h->xptr_dev, h->pin_ptr, (size_t)nfin * sizeof(double*),
                                hipMemcpyHostToDevice, s));
         if (plain32)
             NMG_TRY(launch_scatter_ptrs<float>(nfin, per, X32, h->xptr_dev, d_pairs, s));
@@ -673,7 +673,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         }
     }
     if (nmoves > 0) {
-        NMG_HIP(hipMemcpyAsync(d_moves, hi.data() + 4 * B, (size_t)2 * nmoves * sizeof(int), hipMemcpyHostToDevice,
+        NMG_HIP(hipMemcpyAsync(d_moves, hi + 4 * B, (size_t)2 * nmoves * sizeof(int), hipMemcpyHostToDevice,
                                s));
         if (plain32)
             NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
@@ -701,8 +701,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         hi[(size_t)i] = sl.ws;
         hi[(size_t)B + i] = sl.fidx;
     }
-    NMG_HIP(hipMemcpyAsync(h->slot_d, hd.data(), (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
-    NMG_HIP(hipMemcpyAsync(h->slot_i, hi.data(), (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
+    NMG_HIP(hipMemcpyAsync(h->slot_d, hd, (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
+    NMG_HIP(hipMemcpyAsync(h->slot_i, hi, (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
     h->cycle_fidx = d_fidx;
     const int* wsd = E.any_ws ? d_ws : nullptr;
     auto residual = [&](int kk, hipStream_t st) -> nmg_status {
@@ -847,8 +847,9 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->slot_d, (size_t)3 * B));
     NMG_TRY(dev_alloc(&c->slot_i, (size_t)6 * B));
     NMG_HIP(hipMalloc((void**)&c->xptr_dev, (size_t)B * sizeof(double*)));
-    c->slot_d_host.assign((size_t)3 * B, 0.0);
-    c->slot_i_host.assign((size_t)6 * B, 0);
+    NMG_HIP(hipHostMalloc((void**)&c->pin_d, (size_t)5 * B * sizeof(double), hipHostMallocDefault));
+    NMG_HIP(hipHostMalloc((void**)&c->pin_i, (size_t)6 * B * sizeof(int), hipHostMallocDefault));
+    NMG_HIP(hipHostMalloc((void**)&c->pin_ptr, (size_t)B * sizeof(double*), hipHostMallocDefault));
     NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->xs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->bs32, (size_t)B * level_elems(c.get(), 0)));
@@ -901,6 +902,9 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->slot_d);
     dev_free(c->slot_i);
     dev_free(c->xptr_dev);
+    if (c->pin_d) (void)hipHostFree(c->pin_d);
+    if (c->pin_i) (void)hipHostFree(c->pin_i);
+    if (c->pin_ptr) (void)hipHostFree(c->pin_ptr);
     dev_free(c->r64);
     dev_free(c->xs32);
     dev_free(c->bs32);
