@@ -117,8 +117,9 @@ __device__ inline uint32_t pack2_bf16(float a, float b) {
     return u;
 }
 
+// LDS allows two workgroups (8 waves) per CU, so up to 256 VGPRs cost no occupancy.
 template <int NL>
-__global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restrict__ bres,
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NL == 3 ? 1 : 2, 2))) k_smoother_mfma(const float* __restrict__ bres,
                                                             const double* __restrict__ nrm2, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
                                                             size_t set_stride, const int* __restrict__ ws, int nsets,
@@ -209,34 +210,45 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
             {
                 constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
                 constexpr int npx = S * HH, ngr = (npx + 15) / 16;
-                int q0 = wave * 16 + ln;
-                int ry = q0 / S, rx = q0 - (q0 / S) * S;
-                for (int gi = wave; gi < ngr; gi += 4) {
-                    const bool live = q0 < npx;
-                    const int ryc = live ? ry : HH - 1, rxc = live ? rx : S - 1;
-                    short4v bop = {0, 0, 0, 0};
-                    if (lg < 3) bop = *reinterpret_cast<const short4v*>(recs + ((ryc + lg) * RW + rxc) * 8);
-                    bool inside = true;
-                    if constexpr (EDGE) {
-                        const int gy = ty0 - HALO + ryc, gx = tx0 - HALO + rxc;
-                        inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
-                    }
+                constexpr int GPW = (ngr + 3) / 4;  // groups per wave
+                // all of a wave's groups are independent: operands first, then the
+                // MFMAs, then the stores, fully unrolled so their latencies overlap
+                short4v bop[GPW];
+                int pry[GPW], prx[GPW];
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    const int q = (wave + 4 * k) * 16 + ln;
+                    const bool live = q < npx;
+                    const int qc = live ? q : npx - 1;
+                    pry[k] = live ? q / S : -1;
+                    prx[k] = qc - (qc / S) * S;
+                    const int ryc = qc / S;
+                    bop[k] = short4v{0, 0, 0, 0};
+                    if (lg < 3 && wave + 4 * k < ngr)
+                        bop[k] = *reinterpret_cast<const short4v*>(recs + ((ryc + lg) * RW + prx[k]) * 8);
+                }
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    if (wave + 4 * k >= ngr) break;
+                    floatx4 acc[2];
+#pragma unroll
                     for (int nb = 0; nb < 2; ++nb) {
-                        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc, 0, 0, 0);
-                        if (live) {
+                        acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop[k], acc[nb], 0, 0, 0);
+                    }
+                    if (pry[k] >= 0) {
+                        const int ry = pry[k], rx = prx[k];
+                        bool inside = true;
+                        if constexpr (EDGE) {
+                            const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                            inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                        }
+#pragma unroll
+                        for (int nb = 0; nb < 2; ++nb) {
                             const int co = nb * 16 + lg * 4;
-                            const uint2 v = inside ? relu_pack4(acc) : make_uint2(0u, 0u);
+                            const uint2 v = inside ? relu_pack4(acc[nb]) : make_uint2(0u, 0u);
                             *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
                         }
-                    }
-                    // advance this lane's pixel by 64 = (64 / S) rows + (64 % S) columns
-                    q0 += 64;
-                    rx += 64 % S;
-                    ry += 64 / S;
-                    if (rx >= S) {
-                        rx -= S;
-                        ry += 1;
                     }
                 }
             }
@@ -291,11 +303,21 @@ __global__ void __launch_bounds__(kThreads) k_smoother_mfma(const float* __restr
                 constexpr int ZN = HH * ZP;     // pixels per tap plane
                 const char* ain = (NH & 1) ? bufB : bufA;
                 float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
-                for (int gi = wave; gi < ngr; gi += 4) {
+                constexpr int GPW = (ngr + 3) / 4;
+                bf16x8 bl[GPW];
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    const int gi = wave + 4 * k;
                     const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
-                    const bf16x8 bop = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
+                    if (gi < ngr) bl[k] = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
+                }
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    const int gi = wave + 4 * k;
+                    if (gi >= ngr) break;
+                    const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
                     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bop, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bl[k], acc, 0, 0, 0);
                     if (rx < S && lg < 3) {
                         // lane group lg holds taps 4 lg .. 4 lg + 3; only taps 0..8 exist
                         float* zp = Z + (lg * 4) * ZN + ry * ZP + rx;
