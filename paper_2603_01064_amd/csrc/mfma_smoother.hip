@@ -261,7 +261,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                 const int ngr = HH * 2;  // S <= 32: two groups per row
                 const char* ain = (h & 1) ? bufB : bufA;
                 char* aout = (h & 1) ? bufA : bufB;
-                for (int gi = wave; gi < ngr; gi += 4) {
+                constexpr int GPWH = (2 * G::H(2) + 3) / 4;  // groups per wave, largest hidden region
+#pragma unroll
+                for (int k = 0; k < GPWH; ++k) {
+                    const int gi = wave + 4 * k;
+                    if (gi >= ngr) break;
                     const int ry = gi >> 1, rx0 = (gi & 1) * 16;
                     const int rx = rx0 + ln;
                     // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
@@ -330,7 +334,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                     }
                 }
                 __syncthreads();
-                for (int e = tid; e < TH * TW; e += kThreads) {
+#pragma unroll
+                for (int k = 0; k < (TH * TW + kThreads - 1) / kThreads; ++k) {
+                    const int e = tid + k * kThreads;
+                    if (e >= TH * TW) break;
                     const int oy = e / TW, ox = e - (e / TW) * TW;
                     const int gy = ty0 + oy, gx = tx0 + ox;
                     if (!EDGE || (gy < n && gx < n)) {
