@@ -89,7 +89,8 @@ struct LevelBuffers {
 // Device form of a level's operator for the tiled residual kernel.
 template <typename T>
 struct TiledOp {
-    bool ok = false;
+    bool ok = false;        // Toeplitz + corner tables exist (2D, exact split)
+    bool fused_ok = false;  // the generic one-launch tile kernel fits in LDS
     int rg = 0, rgp = 0, rc = 0, rm = 0, rmp = 0, m_ident = 0;
     T *tg = nullptr, *dtl = nullptr, *dbr = nullptr, *tm = nullptr;  // into one allocation
     T* base = nullptr;

@@ -214,7 +214,7 @@ nmg_status ensure_work(Ctx* c) {
         const int TH = 64;
         const size_t lds = ((size_t)(TH + 2 * rg) * (TW + rgp) + (size_t)(TH + rgp) * TW +
                             (l == 0 ? 0 : (size_t)(TH + rmp) * TW)) * sizeof(T);
-        if (lds > 160 * 1024 || TW + rgp > 256) continue;
+        op.fused_ok = !(lds > 160 * 1024 || TW + rgp > 256);
         std::vector<double> tab;
         std::vector<double> tgv(hl.Gs.t), tmv(hl.Ms.t);
         tgv.resize((size_t)rgp, 0.0);

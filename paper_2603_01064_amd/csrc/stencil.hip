@@ -646,6 +646,188 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-launch operator for long bands and for FP64: the row pass writes X G
+// (and X M) for whole rows of an image to the level scratch, then a column
+// pass stages 64-column strips of it (with the band's halo rows) in LDS and
+// forms y - A x.  Unlike the one-launch tile kernel, no row-pass output is
+// computed twice, at the price of one extra round trip of X G through
+// L2 / HBM.
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerBlock = 4;
+
+template <typename T, int TP>
+__global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, T* __restrict__ tg,
+                                                       T* __restrict__ tm, const T* __restrict__ taps, int rg,
+                                                       const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
+                                                       const T* __restrict__ mt, int m_ident, int n) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* rows = reinterpret_cast<T*>(smem_raw);
+    const int LW = (n + TP + 4 + 3) & ~3;  // staged column c <-> image column c - rg
+    const int b = blockIdx.y, r0 = blockIdx.x * kRowsPerBlock;
+    const size_t per = (size_t)n * n;
+    const T* xs = x + (size_t)b * per;
+    // staging in batches of 8 loads per thread in flight
+    for (int e0 = threadIdx.x; e0 < kRowsPerBlock * LW; e0 += 8 * kBlock) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBlock;
+            const int r = e / LW, c = e - r * LW;
+            const int gi = r0 + r, gj = c - rg;
+            v[u] = (e < kRowsPerBlock * LW && gi < n && gj >= 0 && gj < n) ? xs[(size_t)gi * n + gj] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + u * kBlock < kRowsPerBlock * LW) rows[e0 + u * kBlock] = v[u];
+    }
+    __syncthreads();
+    const int ngrp = (n + 3) / 4;
+    for (int item = threadIdx.x; item < kRowsPerBlock * ngrp; item += kBlock) {
+        const int r = item / ngrp, j = (item - r * ngrp) * 4;
+        const int gi = r0 + r;
+        if (gi >= n) continue;
+        const T* row = rows + r * LW + j;
+        T acc[4] = {0, 0, 0, 0};
+        T w[8];
+        lds_load4v<T>(row, w);
+#pragma unroll
+        for (int t4 = 0; t4 < TP; t4 += 4) {
+            lds_load4v<T>(row + t4 + 4, w + 4);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T ct = taps[t4 + t];
+#pragma unroll
+                for (int o = 0; o < 4; ++o) acc[o] = fma(ct, w[o + t], acc[o]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = w[4 + k];
+        }
+        if (rc > 0 && (j < rc || j + 3 >= n - rc)) {
+            for (int o = 0; o < 4; ++o) {
+                const int jo = j + o;
+                if (jo < rc) {
+                    T s2 = 0;
+                    for (int p = 0; p < rc; ++p) s2 += dtl[p * rc + jo] * rows[r * LW + p + rg];
+                    acc[o] += s2;
+                } else if (jo >= n - rc && jo < n) {
+                    T s2 = 0;
+                    const int jb = jo - (n - rc);
+                    for (int p = 0; p < rc; ++p) s2 += dbr[p * rc + jb] * rows[r * LW + n - rc + p + rg];
+                    acc[o] += s2;
+                }
+            }
+        }
+        T* trow = tg + (size_t)b * per + (size_t)gi * n;
+        for (int o = 0; o < 4; ++o)
+            if (j + o < n) trow[j + o] = acc[o];
+        if (!m_ident) {
+            T* mrow = tm + (size_t)b * per + (size_t)gi * n;
+            for (int o = 0; o < 4; ++o)
+                if (j + o < n) mrow[j + o] = mt[0] * row[rg - 1 + o] + mt[1] * row[rg + o] + mt[2] * row[rg + 1 + o];
+        }
+    }
+}
+
+template <typename T, int TP>
+__global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg, const T* __restrict__ tm,
+                                                       const T* __restrict__ x, const T* __restrict__ y,
+                                                       T* __restrict__ out, const double* __restrict__ alpha, int n,
+                                                       int mode, const T* __restrict__ taps, int rg,
+                                                       const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
+                                                       const T* __restrict__ mt, int m_ident, int tiles_x) {
+    constexpr int TH = 64, TW = 64, OC = 16;  // 4 x 64 threads, 16 rows each
+    constexpr int XH = TH + TP;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* G = reinterpret_cast<T*>(smem_raw);    // [XH][TW]: row r <-> image row i0 - rg + r
+    T* Ms = G + XH * TW;                      // [TH + 4][TW]: row r <-> image row i0 - 1 + r
+    const int b = blockIdx.y;
+    const int i0 = (blockIdx.x / tiles_x) * TH, j0 = (blockIdx.x % tiles_x) * TW;
+    const size_t per = (size_t)n * n;
+    const T* tgs = tg + (size_t)b * per;
+    const int tid = threadIdx.x;
+    // staging in batches of 8 loads per thread in flight
+    for (int e0 = tid; e0 < XH * TW; e0 += 8 * kBlock) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBlock;
+            const int r = e / TW, c = e - r * TW;
+            const int gi = i0 - rg + r, gj = j0 + c;
+            v[u] = (e < XH * TW && gi >= 0 && gi < n && gj < n) ? tgs[(size_t)gi * n + gj] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + u * kBlock < XH * TW) G[e0 + u * kBlock] = v[u];
+    }
+    if (!m_ident) {
+        const T* tms = tm + (size_t)b * per;
+        for (int e = tid; e < (TH + 4) * TW; e += kBlock) {
+            const int r = e / TW, c = e - r * TW;
+            const int gi = i0 - 1 + r, gj = j0 + c;
+            Ms[e] = (r < TH + 2 && gi >= 0 && gi < n && gj < n) ? tms[(size_t)gi * n + gj] : (T)0;
+        }
+    }
+    __syncthreads();
+    const int jj = tid % TW, ii = (tid / TW) * OC;
+    const int j = j0 + jj;
+    if (j >= n) return;
+    // the right-hand side (and x for M = I) of this thread's outputs, loaded before the pass
+    T yv[OC], xv[OC];
+#pragma unroll
+    for (int o = 0; o < OC; ++o) {
+        const int i = i0 + ii + o;
+        const size_t idx = (size_t)b * per + (size_t)i * n + j;
+        yv[o] = (mode == 0 && i < n) ? y[idx] : (T)0;
+        xv[o] = (m_ident && i < n) ? x[idx] : (T)0;
+    }
+    T g[OC];
+#pragma unroll
+    for (int o = 0; o < OC; ++o) g[o] = 0;
+    {
+        const T* col = G + ii * TW + jj;
+        T w[OC + 4];
+#pragma unroll
+        for (int k = 0; k < OC; ++k) w[k] = col[k * TW];
+#pragma unroll
+        for (int t4 = 0; t4 < TP; t4 += 4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[OC + k] = col[(t4 + OC + k) * TW];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T ct = taps[t4 + t];
+#pragma unroll
+                for (int o = 0; o < OC; ++o) g[o] = fma(ct, w[o + t], g[o]);
+            }
+#pragma unroll
+            for (int k = 0; k < OC; ++k) w[k] = w[4 + k];
+        }
+    }
+    const T a = (T)alpha[b];
+#pragma unroll
+    for (int o = 0; o < OC; ++o) {
+        const int i = i0 + ii + o;
+        if (i >= n) break;
+        T corr = 0;
+        if (i < rc) {
+            for (int p = 0; p < rc; ++p) corr += dtl[i * rc + p] * G[(p - i0 + rg) * TW + jj];
+        } else if (i >= n - rc) {
+            const int ib = i - (n - rc);
+            for (int p = 0; p < rc; ++p) corr += dbr[ib * rc + p] * G[(n - rc + p - i0 + rg) * TW + jj];
+        }
+        const size_t idx = (size_t)b * per + (size_t)i * n + j;
+        T mv;
+        if (m_ident) {
+            mv = xv[o];
+        } else {
+            const T* c = Ms + (ii + o) * TW + jj;
+            mv = mt[0] * c[0] + mt[1] * c[TW] + mt[2] * c[2 * TW];
+        }
+        const T ax = a * mv + (g[o] + corr);
+        out[idx] = mode == 0 ? yv[o] - ax : ax;
+    }
+}
+
 }  // namespace
 
 size_t level_elems(const Ctx* c, int l) { return (size_t)(c->p.dim == 2 ? c->n[l] : 1) * c->n[l]; }
@@ -662,6 +844,44 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
     const size_t per = level_elems(c, l);
     const HostLevel& hl = c->host[l];
     const TiledOp<T>& op = w.tiled[(size_t)l];
+    // FP64 (the refinement residual) and bands longer than 48 taps: two launches
+    // (row pass through the level scratch, then the column pass)
+    if (c->p.dim == 2 && op.ok && (op.m_ident || op.rm == 1) && (sizeof(T) == 8 || op.rgp > 48)) {
+        bool launched = false;
+        auto go2 = [&](auto tp_tag) {
+            constexpr int TP = decltype(tp_tag)::value;
+            if (launched || op.rgp != TP) return;
+            launched = true;
+            T* tg = w.lv[l].t1;
+            T* tm = w.lv[l].t2;
+            const int LW = (n + TP + 4 + 3) & ~3;
+            hipLaunchKernelGGL((k_rows_fixed<T, TP>), dim3((n + kRowsPerBlock - 1) / kRowsPerBlock, batch),
+                               dim3(kBlock), (size_t)kRowsPerBlock * LW * sizeof(T), s, x, tg, tm, op.tg, op.rg,
+                               op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n);
+            const int tiles_x = (n + 63) / 64, tiles_y = (n + 63) / 64;
+            const size_t lds = ((size_t)(64 + TP) * 64 + (op.m_ident ? 0 : (size_t)68 * 64)) * sizeof(T);
+            hipLaunchKernelGGL((k_cols_fixed<T, TP>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, tg, tm,
+                               x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident,
+                               tiles_x);
+        };
+        go2(std::integral_constant<int, 8>{});
+        go2(std::integral_constant<int, 12>{});
+        go2(std::integral_constant<int, 16>{});
+        go2(std::integral_constant<int, 20>{});
+        go2(std::integral_constant<int, 24>{});
+        go2(std::integral_constant<int, 28>{});
+        go2(std::integral_constant<int, 32>{});
+        go2(std::integral_constant<int, 36>{});
+        go2(std::integral_constant<int, 40>{});
+        go2(std::integral_constant<int, 44>{});
+        go2(std::integral_constant<int, 48>{});
+        go2(std::integral_constant<int, 84>{});
+        go2(std::integral_constant<int, 164>{});
+        if (launched) {
+            NMG_HIP(hipGetLastError());
+            return NMG_OK;
+        }
+    }
     if (c->p.dim == 2 && op.ok && op.rgp <= 48 && (op.m_ident || op.rm == 1)) {
         // fixed-tap kernel: TP = padded Toeplitz taps of G_l
         bool launched = false;
@@ -709,7 +929,7 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             return NMG_OK;
         }
     }
-    if (c->p.dim == 2 && op.ok) {
+    if (c->p.dim == 2 && op.ok && op.fused_ok) {
         constexpr int TH = tile_h<T>(), TW = tile_w<T>();
         const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
         const int XW = TW + op.rgp, XH = TH + 2 * op.rg, GH = TH + op.rgp, MH = TH + op.rmp;
