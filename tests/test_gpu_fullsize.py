@@ -53,6 +53,24 @@ def setup():
     h.close()
 
 
+def test_fullsize_operator_every_rhs(setup):
+    """y - A x for all 64 right-hand sides in the benchmark's launch configuration
+    (FP32 128 x 64 tiles, FP64 two-launch kernel) against the oracle."""
+    print("case full-size operator 255x255 x 64", flush=True)
+    S = setup
+    dev = S["dev"]
+    g = torch.Generator().manual_seed(77)
+    xr = torch.randn(S["B"], S["n"], S["n"], dtype=DT, generator=g)
+    ref = S["b"] - O.apply_operator(S["H"], 0, xr, S["alpha"])
+    ad = S["alpha"].to(dev)
+    bd = S["b"].to(dev)
+    r64 = (bd - S["h"].apply_operator(0, xr.to(dev), ad, "fp64")).cpu()
+    assert float((r64 - ref).norm() / ref.norm()) < 1e-12
+    ref32 = O.apply_operator(S["H"], 0, xr.float().double(), S["alpha"])
+    a32 = S["h"].apply_operator(0, xr.float().to(dev), ad, "fp32").cpu().double()
+    assert float((a32 - ref32).norm() / ref32.norm()) < 1e-5
+
+
 @pytest.mark.parametrize("prec,tol", [("mixed", 3e-2), ("fp32", 1e-5)])
 def test_fullsize_vcycle_sampled_against_oracle(setup, prec, tol):
     """One V(1,1)+F' cycle from zero on all 64 right-hand sides (mixed: BF16

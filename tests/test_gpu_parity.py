@@ -90,7 +90,8 @@ def test_transfer_index_maps_bit_exact(n, L):
     h.close()
 
 
-@pytest.mark.parametrize("dim,n,s,L", [(2, 255, 0.01, 5), (2, 63, 0.04, 4), (1, 255, 0.02, 4)])
+# (2, 511, 0.02, 6): s/h = 10.24, band radii 80 / 41 / 21 / 11 / 6 / 4 (the long-band two-launch kernels)
+@pytest.mark.parametrize("dim,n,s,L", [(2, 255, 0.01, 5), (2, 63, 0.04, 4), (1, 255, 0.02, 4), (2, 511, 0.02, 6)])
 def test_operator_every_level(dim, n, s, L):
     print(f"case operator dim={dim} n={n} L={L}", flush=True)
     dev = _dev()
