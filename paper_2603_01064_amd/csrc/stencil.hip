@@ -437,6 +437,37 @@ __device__ inline void lds_load4v(const T* p, T* w) {
     }
 }
 
+// Corner corrections of the band factor (rc x rc blocks where G_l differs from
+// its Toeplitz interior) for the row pass, in outer-product order: one pass
+// over the rc coupled values with independent accumulators per output, so
+// the loads pipeline instead of forming one dependent chain per output (every
+// wave of a row pass holds corner columns).  Outputs j .. j+3 of a staged
+// row; row[c + off] is image column c.
+template <typename T>
+__device__ inline void row_corners(const T* row, int off, const T* cs, int rc, int n, int j, T acc[4]) {
+    const int rc2 = rc * rc;
+    const bool left = j < rc, right = j + 3 >= n - rc;
+    T cl[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0};
+    for (int p = 0; p < rc; ++p) {
+        if (left) {
+            const T xv = row[p + off];
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                if (j + o < rc) cl[o] += cs[p * rc + j + o] * xv;
+        }
+        if (right) {
+            const T xv = row[n - rc + p + off];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int jo = j + o;
+                if (jo >= rc && jo >= n - rc && jo < n) cr[o] += cs[rc2 + p * rc + (jo - (n - rc))] * xv;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) acc[o] += (j + o < rc) ? cl[o] : cr[o];
+}
+
 template <typename T, int TH, int TW, int TP, int OC, int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) k_residual_fixed(
     const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ out, const double* __restrict__ alpha, int n,
@@ -455,6 +486,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     T* TMs = X + XH * XW;
+    // corner corrections staged next to the tile (rc x rc each)
+    T* cs = TMs + (m_ident ? 0 : MH * TW);
+    const int rc2 = rc * rc;
     const int b = blockIdx.y;
     const int tile = blockIdx.x;
     const int i0 = (tile / tiles_x) * TH, j0 = (tile % tiles_x) * TW;
@@ -462,6 +496,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     const T* xs = x + (size_t)b * per;
     const int tid = threadIdx.x;
     const T* taps = tg;
+    for (int e = threadIdx.x; e < rc2; e += NT) {
+        cs[e] = dtl[e];
+        cs[rc2 + e] = dbr[e];
+    }
     // ---- stage the tile with its halo (zero outside the grid); every load of
     // a thread is issued before the first LDS store
     {
@@ -555,21 +593,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
                 for (int k = 0; k < 4; ++k) w[k] = w[4 + k];
             }
             const int j = j0 + jj;
-            if (rc > 0 && (j < rc || j + 3 >= n - rc)) {
-                for (int o = 0; o < 4; ++o) {
-                    const int jo = j + o;
-                    if (jo < rc) {
-                        T s2 = 0;
-                        for (int p = 0; p < rc; ++p) s2 += dtl[p * rc + jo] * X[r * XW + (p - j0 + rg)];
-                        racc[q][o] += s2;
-                    } else if (jo >= n - rc && jo < n) {
-                        T s2 = 0;
-                        const int jb = jo - (n - rc);
-                        for (int p = 0; p < rc; ++p) s2 += dbr[p * rc + jb] * X[r * XW + (n - rc + p - j0 + rg)];
-                        racc[q][o] += s2;
-                    }
-                }
-            }
+            if (rc > 0 && (j < rc || j + 3 >= n - rc))
+                row_corners<T>(X + r * XW, rg - j0, cs, rc, n, j, racc[q]);
         }
     }
     __syncthreads();
@@ -632,12 +657,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
         for (int o = 0; o < OC; ++o) {
             const int i = i0 + ii + o;
             if (i >= n || j >= n) continue;
+            // corner rows: first and last tile rows only, computed in place
             T corr = 0;
             if (i < rc) {
-                for (int p = 0; p < rc; ++p) corr += dtl[i * rc + p] * X[(p - i0 + rg) * XW + jj];
+                for (int p = 0; p < rc; ++p) corr += cs[i * rc + p] * X[(p - i0 + rg) * XW + jj];
             } else if (i >= n - rc) {
                 const int ib = i - (n - rc);
-                for (int p = 0; p < rc; ++p) corr += dbr[ib * rc + p] * X[(n - rc + p - i0 + rg) * XW + jj];
+                for (int p = 0; p < rc; ++p) corr += cs[rc2 + ib * rc + p] * X[(n - rc + p - i0 + rg) * XW + jj];
             }
             const T ax = a * mv[o] + (g[o] + corr);
             const size_t idx = (size_t)b * per + (size_t)i * n + j;
@@ -664,22 +690,34 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, 
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* rows = reinterpret_cast<T*>(smem_raw);
     const int LW = (n + TP + 4 + 3) & ~3;  // staged column c <-> image column c - rg
+    T* cs = rows + kRowsPerBlock * LW;     // corner corrections (rc x rc each)
+    const int rc2 = rc * rc;
+    for (int e = threadIdx.x; e < rc2; e += kBlock) {
+        cs[e] = dtl[e];
+        cs[rc2 + e] = dbr[e];
+    }
     const int b = blockIdx.y, r0 = blockIdx.x * kRowsPerBlock;
     const size_t per = (size_t)n * n;
     const T* xs = x + (size_t)b * per;
-    // staging in batches of 8 loads per thread in flight
-    for (int e0 = threadIdx.x; e0 < kRowsPerBlock * LW; e0 += 8 * kBlock) {
-        T v[8];
+    // staging: wave w loads row r0 + w, lane-contiguous, eight loads per lane in flight
+    {
+        const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int gi = r0 + r;
+        const T* src = xs + (size_t)(gi < n ? gi : 0) * n;
+        static_assert(kRowsPerBlock * 64 == kBlock, "one wave per staged row");
+        for (int q0 = 0; q0 * 64 < LW; q0 += 8) {
+            T v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kBlock;
-            const int r = e / LW, c = e - r * LW;
-            const int gi = r0 + r, gj = c - rg;
-            v[u] = (e < kRowsPerBlock * LW && gi < n && gj >= 0 && gj < n) ? xs[(size_t)gi * n + gj] : (T)0;
+            for (int u = 0; u < 8; ++u) {
+                const int c = lane + 64 * (q0 + u), gj = c - rg;
+                v[u] = (c < LW && gi < n && gj >= 0 && gj < n) ? src[gj] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = lane + 64 * (q0 + u);
+                if (c < LW) rows[r * LW + c] = v[u];
+            }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (e0 + u * kBlock < kRowsPerBlock * LW) rows[e0 + u * kBlock] = v[u];
     }
     __syncthreads();
     const int ngrp = (n + 3) / 4;
@@ -703,24 +741,10 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[k] = w[4 + k];
         }
-        if (rc > 0 && (j < rc || j + 3 >= n - rc)) {
-            for (int o = 0; o < 4; ++o) {
-                const int jo = j + o;
-                if (jo < rc) {
-                    T s2 = 0;
-                    for (int p = 0; p < rc; ++p) s2 += dtl[p * rc + jo] * rows[r * LW + p + rg];
-                    acc[o] += s2;
-                } else if (jo >= n - rc && jo < n) {
-                    T s2 = 0;
-                    const int jb = jo - (n - rc);
-                    for (int p = 0; p < rc; ++p) s2 += dbr[p * rc + jb] * rows[r * LW + n - rc + p + rg];
-                    acc[o] += s2;
-                }
-            }
-        }
+        if (rc > 0 && (j < rc || j + 3 >= n - rc)) row_corners<T>(rows + r * LW, rg, cs, rc, n, j, acc);
         T* trow = tg + (size_t)b * per + (size_t)gi * n;
         for (int o = 0; o < 4; ++o)
-            if (j + o < n) trow[j + o] = acc[o];
+            if (j + o < n) trow[j + o] = acc[o];  // lanes write consecutive 4-value runs
         if (!m_ident) {
             T* mrow = tm + (size_t)b * per + (size_t)gi * n;
             for (int o = 0; o < 4; ++o)
@@ -741,11 +765,17 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* G = reinterpret_cast<T*>(smem_raw);    // [XH][TW]: row r <-> image row i0 - rg + r
     T* Ms = G + XH * TW;                      // [TH + 4][TW]: row r <-> image row i0 - 1 + r
+    T* cs = Ms + (m_ident ? 0 : (TH + 4) * TW);  // corner corrections (rc x rc each)
+    const int rc2 = rc * rc;
     const int b = blockIdx.y;
     const int i0 = (blockIdx.x / tiles_x) * TH, j0 = (blockIdx.x % tiles_x) * TW;
     const size_t per = (size_t)n * n;
     const T* tgs = tg + (size_t)b * per;
     const int tid = threadIdx.x;
+    for (int e = tid; e < rc2; e += kBlock) {
+        cs[e] = dtl[e];
+        cs[rc2 + e] = dbr[e];
+    }
     // staging in batches of 8 loads per thread in flight
     for (int e0 = tid; e0 < XH * TW; e0 += 8 * kBlock) {
         T v[8];
@@ -808,12 +838,14 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     for (int o = 0; o < OC; ++o) {
         const int i = i0 + ii + o;
         if (i >= n) break;
+        // corner rows occur only in the first and last tile rows, for a quarter of
+        // the threads; computed in place they cost no registers elsewhere
         T corr = 0;
         if (i < rc) {
-            for (int p = 0; p < rc; ++p) corr += dtl[i * rc + p] * G[(p - i0 + rg) * TW + jj];
+            for (int p = 0; p < rc; ++p) corr += cs[i * rc + p] * G[(p - i0 + rg) * TW + jj];
         } else if (i >= n - rc) {
             const int ib = i - (n - rc);
-            for (int p = 0; p < rc; ++p) corr += dbr[ib * rc + p] * G[(n - rc + p - i0 + rg) * TW + jj];
+            for (int p = 0; p < rc; ++p) corr += cs[rc2 + ib * rc + p] * G[(n - rc + p - i0 + rg) * TW + jj];
         }
         const size_t idx = (size_t)b * per + (size_t)i * n + j;
         T mv;
@@ -856,10 +888,12 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             T* tm = w.lv[l].t2;
             const int LW = (n + TP + 4 + 3) & ~3;
             hipLaunchKernelGGL((k_rows_fixed<T, TP>), dim3((n + kRowsPerBlock - 1) / kRowsPerBlock, batch),
-                               dim3(kBlock), (size_t)kRowsPerBlock * LW * sizeof(T), s, x, tg, tm, op.tg, op.rg,
+                               dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(T), s,
+                               x, tg, tm, op.tg, op.rg,
                                op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n);
             const int tiles_x = (n + 63) / 64, tiles_y = (n + 63) / 64;
-            const size_t lds = ((size_t)(64 + TP) * 64 + (op.m_ident ? 0 : (size_t)68 * 64)) * sizeof(T);
+            const size_t lds = ((size_t)(64 + TP) * 64 + (op.m_ident ? 0 : (size_t)68 * 64) +
+                                2 * (size_t)op.rc * op.rc) * sizeof(T);
             hipLaunchKernelGGL((k_cols_fixed<T, TP>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, tg, tm,
                                x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident,
                                tiles_x);
@@ -895,7 +929,8 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             constexpr int TH = BIG ? 128 : 32, TW = BIG ? 64 : 32, OC = BIG ? 8 : 4, NT = BIG ? 512 : 256;
             constexpr int WPE = BIG ? 4 : 1;
             const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
-            const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW)) * sizeof(T);
+            const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW) +
+                                2 * (size_t)op.rc * op.rc) * sizeof(T);
             hipLaunchKernelGGL((k_residual_fixed<T, TH, TW, TP, OC, NT, WPE>), dim3(tiles_x * tiles_y, batch), dim3(NT),
                                lds, s, x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
                                op.m_ident, tiles_x);
