@@ -130,6 +130,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serial-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching measurements")
+    ap.add_argument("--no-training", action="store_true", help="skip the training-step measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 64 MiB device copy before timing (reference kernel for HBM counters)")
     a = ap.parse_args(argv)
@@ -249,6 +250,9 @@ def main(argv=None):
             res["serial_fp32_gpu"]["speedup_solves_per_s"] = round(value / res["serial_fp32_gpu"]["value"], 1)
             if res["config"]["p99_ms"] and res["serial_fp32_gpu"]["p99_ms"]:
                 res["serial_fp32_gpu"]["p99_ratio"] = round(res["serial_fp32_gpu"]["p99_ms"] / res["config"]["p99_ms"], 2)
+    if not a.no_training:
+        log("training step (127x127, batch 256)")
+        res["training"] = training(nmg)
     if not a.no_serving:
         log("serving: continuous batching on Poisson arrivals")
         res["serving"] = serving(nmg, h, sets, set_alphas, cyc_cfg, batches[a.warmup:], a.max_cycles,
@@ -259,6 +263,38 @@ def main(argv=None):
     print(json.dumps(res), flush=True)
     h.close()
     return 0
+
+
+def training(nmg, steps=10, warmup=2):
+    """Level-wise training step (loss, hand-written adjoint, Adam) at the
+    training workload's shape: 127x127, s = 0.01, five levels, CNN 1-32-32-1,
+    batch 256 of i.i.d. N(0, 1) error vectors, alpha 1e-3, band mask, FP32 with
+    BF16 MFMA forward, lr 1e-3."""
+    import torch
+
+    from paper_2603_01064_amd import inputs
+    dev = torch.device("cuda:0")
+    n, s, L, B = 127, 0.01, 5, 256
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=CHANNELS, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, inputs.he_normal_weights(CHANNELS, 3, 2, 7000 + 10 * l))
+    alpha = torch.full((B,), 1e-3, dtype=torch.float64, device=dev)
+    es = [torch.tensor(inputs.iid_normal((B, n, n), 40000 + k), dtype=torch.float32, device=dev)
+          for k in range(warmup + steps)]
+    for k in range(warmup):
+        h.train_step(es[k], alpha, mask="band", precision="mixed", lr=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = last = None
+    for k in range(steps):
+        losses = h.train_step(es[warmup + k], alpha, mask="band", precision="mixed", lr=1e-3)
+        first = float(losses.sum()) if first is None else first
+        last = float(losses.sum())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.close()
+    return {"ms_per_step": round(1e3 * dt / steps, 2), "samples_per_s": round(B * steps / dt, 1), "steps": steps,
+            "batch": B, "grid": n, "levels": L, "mask": "band", "loss_sum_first": first, "loss_sum_last": last}
 
 
 def _serial_handle(nmg, sets):
