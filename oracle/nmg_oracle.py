@@ -18,6 +18,10 @@ What the paper fixes and how each piece is pinned (tests marked ``not gpu``):
   the regularised system ``(K^T K + alpha I) u = b`` with a truncated Gaussian
   convolution matrix ``K``; 2D uses ``K2 = K (x) K``.  Pinned by brute force
   (dense Toeplitz / Kronecker matrices), symmetry and positive definiteness.
+* Operator variants: ``alpha I + K`` (2D ``alpha I (x) I + K (x) K``) as the
+  paper writes it, and the 1D anisotropic ``alpha D + K`` (Sec. 4.1).  Pinned
+  by dense definitions, the spectrum from the eigenvalues of ``K``, the
+  discrete energy identity of ``D`` and its constant-coefficient closed form.
 * Grids and transfers (Sec. 2.3, Algorithm 1): linear interpolation ``P`` and
   full weighting ``R = P^T / 2^d``; Galerkin coarse operators
   ``A_{l+1} = R A_l P``.  Pinned by adjointness, exact interpolation of
@@ -101,6 +105,30 @@ def conv_matrix(n: int, s: float, trunc: float = 4.0) -> torch.Tensor:
     return K
 
 
+def anisotropic_regulariser(n: int, a: Optional[Callable[[float], float]] = None) -> torch.Tensor:
+    """Tridiagonal ``D`` of the 1D regulariser ``-(a u')'`` (Sec. 4.1,
+    anisotropic case, ``a(z) = 1 + 0.5 sin(2 pi z)``), zero boundary values.
+
+    Conservative three-point differences with ``a`` taken at the cell
+    midpoints ``(i + 1/2) h``: ``(D v)_i = a_{i-1/2} (v_i - v_{i-1}) -
+    a_{i+1/2} (v_{i+1} - v_i)``.  The factor ``1/h^2`` is left out (reading:
+    the paper's alphas for this case match those of the ``alpha I`` case, so
+    ``D`` carries the same O(1) scale as ``I``).
+    """
+    if a is None:
+        a = lambda z: 1.0 + 0.5 * math.sin(2.0 * math.pi * z)
+    h = mesh_width(n)
+    D = torch.zeros(n, n, dtype=DT)
+    for i in range(n):
+        left, right = a((i + 0.5) * h), a((i + 1.5) * h)
+        D[i, i] = left + right
+        if i > 0:
+            D[i, i - 1] = -left
+        if i + 1 < n:
+            D[i, i + 1] = -right
+    return D
+
+
 # ---------------------------------------------------------------------------
 # Grid hierarchy and transfers (Sec. 2.3, Algorithm 1)
 # ---------------------------------------------------------------------------
@@ -155,13 +183,25 @@ class Hierarchy:
         return len(self.levels)
 
 
-def build_hierarchy(n: int, s: float, levels: int, dim: int = 2, trunc: float = 4.0) -> Hierarchy:
-    """Hierarchy of Algorithm 1: ``n_{l+1} = (n_l - 1)/2`` and Galerkin RAP."""
+def build_hierarchy(n: int, s: float, levels: int, dim: int = 2, trunc: float = 4.0,
+                    form: str = "normal") -> Hierarchy:
+    """Hierarchy of Algorithm 1: ``n_{l+1} = (n_l - 1)/2`` and Galerkin RAP.
+
+    ``form`` picks the fine operator: ``"normal"`` is ``alpha I + K^T K`` (2D:
+    ``alpha I + (K (x) K)^T (K (x) K)``), ``"kernel"`` is the paper's own
+    ``alpha I + K`` (Sec. 2.1; 2D ``alpha I (x) I + K (x) K`` of Sec. 4.2) and
+    ``"aniso"`` is ``alpha D + K`` with the anisotropic regulariser (1D only,
+    Sec. 4.1).
+    """
     if dim not in (1, 2):
         raise ValueError("dim must be 1 or 2")
+    if form not in ("normal", "kernel", "aniso"):
+        raise ValueError("form must be 'normal', 'kernel' or 'aniso'")
+    if form == "aniso" and dim != 1:
+        raise ValueError("the anisotropic regulariser is one-dimensional")
     K = conv_matrix(n, s, trunc)
-    G = K.T @ K
-    M = torch.eye(n, dtype=DT)
+    G = K.T @ K if form == "normal" else K
+    M = anisotropic_regulariser(n) if form == "aniso" else torch.eye(n, dtype=DT)
     H = Hierarchy(dim=dim, n=n, s=s)
     H.levels.append(Level(n=n, M=M, G=G))
     for _ in range(1, levels):

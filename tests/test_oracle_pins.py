@@ -74,6 +74,78 @@ def test_operator_equals_dense_definition(dim):
     assert torch.allclose(Ax, ref, rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_kernel_form_operator_equals_dense_definition(dim):
+    """The paper's own form alpha I + K (2D alpha I (x) I + K (x) K, Sec. 2.1 and
+    Sec. 4.2): dense matrix, matrix-vector product, and the spectrum
+    {alpha + lambda_i} (1D) / {alpha + lambda_i lambda_j} (2D) from the
+    eigenvalues of K alone."""
+    n, s, alpha = 15, 0.08, 3e-3
+    H = O.build_hierarchy(n, s, 2, dim=dim, form="kernel")
+    K = O.conv_matrix(n, s)
+    K2 = K if dim == 1 else torch.kron(K, K)
+    A = K2 + alpha * torch.eye(K2.shape[0], dtype=DT)
+    assert torch.allclose(O.dense_operator(H, 0, alpha), A, rtol=0, atol=1e-15)
+    x = torch.randn((2,) + (n,) * dim, dtype=DT, generator=torch.Generator().manual_seed(2))
+    Ax = O.apply_operator(H, 0, x, torch.tensor([alpha, alpha], dtype=DT))
+    assert torch.allclose(Ax, (A @ x.reshape(2, -1).T).T.reshape(x.shape), rtol=0, atol=1e-14)
+    lam = torch.linalg.eigvalsh(K)
+    spec = alpha + (lam if dim == 1 else torch.outer(lam, lam).flatten())
+    assert torch.allclose(torch.linalg.eigvalsh(O.dense_operator(H, 0, alpha)), torch.sort(spec).values,
+                          rtol=0, atol=1e-13)
+
+
+def test_truncated_gaussian_is_slightly_indefinite():
+    """The truncated Gaussian K has a small negative eigenvalue at s/h = 2.56,
+    so alpha I + K (x) K loses definiteness for alpha below
+    -lambda_min(K) lambda_max(K), about 2.4e-5 at n = 63, s = 0.04."""
+    n, s = 63, 0.04
+    lam = torch.linalg.eigvalsh(O.conv_matrix(n, s))
+    floor = -float(lam.min() * lam.max())
+    assert 2.0e-5 < floor < 2.8e-5
+    H = O.build_hierarchy(n, s, 1, dim=2, form="kernel")
+    assert float(torch.linalg.eigvalsh(O.dense_operator(H, 0, 0.5 * floor)).min()) < 0
+    assert float(torch.linalg.eigvalsh(O.dense_operator(H, 0, 1.1 * floor)).min()) > 0
+
+
+def test_anisotropic_regulariser_energy_identity():
+    """v^T D v equals the discrete Dirichlet energy sum_k a(z_{k+1/2}) (v_{k+1} - v_k)^2
+    over all n + 1 cells, with zero boundary values (Sec. 4.1 anisotropic case,
+    a(z) = 1 + 0.5 sin 2 pi z): checks every index shift, sign and midpoint."""
+    n = 31
+    h = 1.0 / (n + 1)
+    D = O.anisotropic_regulariser(n)
+    assert torch.equal(D, D.T)
+    assert int((D != 0).sum()) == 3 * n - 2
+    g = torch.Generator().manual_seed(5)
+    for _ in range(3):
+        v = torch.randn(n, dtype=DT, generator=g)
+        ext = np.concatenate([[0.0], v.numpy(), [0.0]])  # boundary nodes z = 0 and z = 1
+        energy = sum((1.0 + 0.5 * math.sin(2.0 * math.pi * (k + 0.5) * h)) * (ext[k + 1] - ext[k]) ** 2
+                     for k in range(n + 1))
+        assert abs(float(v @ D @ v) - energy) <= 1e-13 * energy
+    assert float(torch.linalg.eigvalsh(D).min()) > 0
+
+
+def test_anisotropic_regulariser_constant_coefficient_closed_form():
+    """a = 1 gives tridiag(-1, 2, -1), with eigenvalues 2 - 2 cos(k pi / (n + 1))."""
+    n = 15
+    D = O.anisotropic_regulariser(n, a=lambda z: 1.0)
+    ev = torch.linalg.eigvalsh(D)
+    k = torch.arange(1, n + 1, dtype=DT)
+    assert torch.allclose(ev, torch.sort(2.0 - 2.0 * torch.cos(k * math.pi / (n + 1))).values, rtol=0, atol=1e-13)
+
+
+def test_anisotropic_operator_equals_dense_definition():
+    """alpha D + K (Sec. 4.1), the one-dimensional anisotropic system."""
+    n, s, alpha = 31, 1.5 / 32, 1e-4
+    H = O.build_hierarchy(n, s, 3, dim=1, form="aniso")
+    A = alpha * O.anisotropic_regulariser(n) + O.conv_matrix(n, s)
+    assert torch.allclose(O.dense_operator(H, 0, alpha), A, rtol=0, atol=1e-16)
+    with pytest.raises(ValueError):
+        O.build_hierarchy(n, s, 3, dim=2, form="aniso")
+
+
 @pytest.mark.parametrize("alpha", [1e-2, 1e-4])
 def test_operator_spd_bounds(alpha):
     n, s = 15, 0.06
@@ -125,10 +197,10 @@ def test_transfer_index_maps_brute_force():
         assert pmap[p] == exp
 
 
-@pytest.mark.parametrize("dim", [1, 2])
-def test_galerkin_factors_equal_dense_rap(dim):
+@pytest.mark.parametrize("dim,form", [(1, "normal"), (2, "normal"), (1, "kernel"), (2, "kernel"), (1, "aniso")])
+def test_galerkin_factors_equal_dense_rap(dim, form):
     n, s, alpha = 31, 0.05, 1e-3
-    H = O.build_hierarchy(n, s, 4, dim=dim)
+    H = O.build_hierarchy(n, s, 4, dim=dim, form=form)
     for l in range(H.L - 1):
         P = H.levels[l].P
         P2 = P if dim == 1 else torch.kron(P, P)
