@@ -45,7 +45,7 @@ typedef enum {
     NMG_ERR_ARG = -1,        /* bad argument value or NULL pointer        */
     NMG_ERR_SHAPE = -2,      /* n, levels, batch or layer shapes invalid  */
     NMG_ERR_OOM = -3,        /* device allocation failed                  */
-    NMG_ERR_NOT_SPD = -4,    /* coarse Cholesky met a non-positive pivot  */
+    NMG_ERR_NOT_SPD = -4,    /* alpha leaves an operator indefinite       */
     NMG_ERR_NONFINITE = -5,  /* NaN/Inf in an input or a residual         */
     NMG_ERR_HIP = -6,        /* HIP runtime error                         */
     NMG_ERR_BUDGET = -7,     /* request exceeds the handle's HBM budget   */
@@ -65,6 +65,24 @@ typedef enum { NMG_MASK_BAND = 0, NMG_MASK_RAMP = 1 } nmg_mask_kind;
 #define NMG_MAX_LAYERS 7
 
 /* Problem and smoother architecture fixed for the lifetime of a handle. */
+/* Fine-grid operator (Sec. 2.1; 2D Kronecker form of Sec. 4.2).  K is the
+ * truncated Gaussian convolution (Toeplitz, zero boundary values).
+ *  NMG_OP_NORMAL : A = alpha I + K^T K (2D: alpha I + (K(x)K)^T (K(x)K)),
+ *                  the Tikhonov normal equations; SPD for every alpha > 0.
+ *  NMG_OP_KERNEL : A = alpha I + K (2D: alpha I(x)I + K(x)K), the form the
+ *                  paper writes.
+ *  NMG_OP_ANISO  : A = alpha D + K, 1D only (Sec. 4.1, anisotropic case): D
+ *                  is the three-point -(a u')' with a(z) = 1 + 0.5 sin 2 pi z
+ *                  at cell midpoints, without the 1/h^2 factor.
+ * The truncated Gaussian K can be slightly indefinite (lowest eigenvalue
+ * about -3e-5 at s/h = 2.56), so the last two forms are SPD only for alpha
+ * above a floor, which setup computes to about 1e-16 (host band Cholesky,
+ * bisection on alpha in 1D and on the ends of the spectrum of K in 2D).
+ * Every entry point that takes alphas for a solve (nmg_prepare, nmg_solve,
+ * nmg_serve_submit) rejects one at or below the floor with NMG_ERR_NOT_SPD.
+ * The Galerkin levels below the finest inherit definiteness. */
+typedef enum { NMG_OP_NORMAL = 0, NMG_OP_KERNEL = 1, NMG_OP_ANISO = 2 } nmg_operator_form;
+
 typedef struct {
     int dim;                         /* 1 or 2                                   */
     int n;                           /* interior points per axis, 2^k - 1        */
@@ -76,6 +94,7 @@ typedef struct {
     int channels[NMG_MAX_LAYERS + 1];/* channels[0] = channels[n_layers] = 1     */
     int ksize;                       /* odd convolution kernel size              */
     int n_weight_sets;               /* independent smoother sets per level      */
+    int operator_form;               /* nmg_operator_form (0: the default below) */
 } nmg_problem;
 
 /* Options of one V(nu1, nu2) cycle (Algorithm 1 with the neural smoothing
@@ -128,7 +147,8 @@ nmg_status nmg_set_jacobi_smoother(nmg_handle h, int level, double omega);
  * max_batch of them), so repeated alphas cost nothing.  alpha: device
  * double[batch].  Must precede nmg_vcycle for these right-hand sides
  * (nmg_solve calls it itself).  Synchronises; NMG_ERR_ARG for alpha <= 0 or
- * non-finite, NMG_ERR_NOT_SPD if a pivot is not positive. */
+ * non-finite, NMG_ERR_NOT_SPD if a pivot is not positive or alpha is at
+ * or below the floor of NMG_OP_KERNEL. */
 nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha_dev, void* stream);
 
 /* ---- operators ---------------------------------------------------------- */
@@ -300,6 +320,11 @@ nmg_status nmg_profile_query(nmg_handle h, int kind, int level, double* total_ms
 
 /* Grid size of level `level` (0-based). */
 int nmg_level_size(nmg_handle h, int level);
+
+/* The alpha floor of the handle's operator form (see nmg_operator_form):
+ * alphas at or below it are rejected with NMG_ERR_NOT_SPD; 0 for
+ * NMG_OP_NORMAL and for kernels with no negative eigenvalue. */
+nmg_status nmg_alpha_floor(nmg_handle h, double* floor_out);
 
 /* Integer index maps of the 1D transfers between level and level+1 as the
  * kernels use them.  kind 0 = restriction: idx int32[n_{l+1}][3], w float

@@ -3,7 +3,8 @@
 // Level 1 carries A_1 = alpha I + K^T K with the truncated Gaussian
 // convolution K of the integral equation (Sec. 2.1); in 2D the operator is
 // the Kronecker form alpha I (x) I + (K (x) K)^T (K (x) K) (Sec. 4.2 with the
-// Tikhonov normal equations).  Coarser levels are Galerkin products
+// Tikhonov normal equations).  The paper's own form alpha I + K (2D
+// alpha I (x) I + K (x) K) uses G_1 = K instead of K^T K.  Coarser levels are Galerkin products
 // A_{l+1} = I_l^{l+1} A_l I_{l+1}^l (Algorithm 1), which keep the form
 // alpha M_l (x) M_l + G_l (x) G_l with M_{l+1} = R1 M_l P1 and
 // G_{l+1} = R1 G_l P1 for the 1D transfers R1 = P1^T / 2 (full weighting)
@@ -36,6 +37,18 @@ Band gaussian_normal_band(int n, const std::vector<double>& taps, int R) {
             g.a[(size_t)i * w + (j - i + g.r)] = acc;
         }
     }
+    return g;
+}
+
+// K itself: the radius-R Toeplitz band.
+Band gaussian_band(int n, const std::vector<double>& taps, int R) {
+    Band g;
+    g.n = n;
+    g.r = R;
+    const int w = 2 * R + 1;
+    g.a.assign((size_t)n * w, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(0, i - R); j <= std::min(n - 1, i + R); ++j) g.a[(size_t)i * w + (j - i + R)] = taps[(size_t)(j - i + R)];
     return g;
 }
 
@@ -95,8 +108,106 @@ bool split_toeplitz(const Band& B, ToeplitzSplit& out) {
     return true;
 }
 
-bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector<HostLevel>& out,
-                          int* taps_radius, std::string& err) {
+// D of the 1D regulariser -(a u')' with a(z) = 1 + 0.5 sin(2 pi z) taken at
+// the cell midpoints (i + 1/2) h; the 1/h^2 factor is left out so that D has
+// the O(1) scale of the identity it replaces (Sec. 4.1, anisotropic case).
+Band anisotropic_band(int n) {
+    Band d;
+    d.n = n;
+    d.r = 1;
+    d.a.assign((size_t)n * 3, 0.0);
+    const double h = 1.0 / (n + 1);
+    auto a = [&](int k) { return 1.0 + 0.5 * std::sin(2.0 * M_PI * (k + 0.5) * h); };
+    for (int i = 0; i < n; ++i) {
+        if (i > 0) d.a[(size_t)i * 3 + 0] = -a(i);
+        d.a[(size_t)i * 3 + 1] = a(i) + a(i + 1);
+        if (i + 1 < n) d.a[(size_t)i * 3 + 2] = -a(i + 1);
+    }
+    return d;
+}
+
+// Cholesky of the symmetric band matrix cx X + cy Y + shift I in O(n r^2);
+// true when every pivot is positive (the matrix is positive definite).
+bool band_pd(const Band& X, double cx, const Band& Y, double cy, double shift) {
+    const int n = X.n, r = std::max(X.r, Y.r), w = r + 1;
+    std::vector<double> L((size_t)n * w, 0.0);  // L[i*w + (i - j)], j in [i - r, i]
+    for (int i = 0; i < n; ++i) {
+        for (int j = std::max(0, i - r); j <= i; ++j) {
+            double v = cx * X.get(i, j) + cy * Y.get(i, j) + (i == j ? shift : 0.0);
+            for (int m = std::max(0, i - r); m < j; ++m) v -= L[(size_t)i * w + (i - m)] * L[(size_t)j * w + (j - m)];
+            if (j == i) {
+                if (!(v > 0.0) || !std::isfinite(v)) return false;
+                L[(size_t)i * w] = std::sqrt(v);
+            } else {
+                L[(size_t)i * w + (i - j)] = v / L[(size_t)j * w];
+            }
+        }
+    }
+    return true;
+}
+
+// Smallest alpha (to bisection accuracy, rounded up) at or below which the
+// finest operator is not positive definite; 0 when it is for every alpha > 0.
+//  1D: alpha M + G with M = I or D, by bisection on alpha.
+//  2D: alpha I + G (x) G has eigenvalues alpha + g_i g_j, so the floor is
+//      -g_min g_max when g_min < 0; both ends of the spectrum of G by
+//      bisection on a shift.
+double alpha_floor_of(const Band& M, const Band& G, int dim) {
+    const int n = G.n;
+    Band zero;
+    zero.n = n;
+    zero.r = 0;
+    zero.a.assign((size_t)n, 0.0);
+    if (dim == 1) {
+        if (band_pd(G, 1.0, M, 0.0, 0.0)) return 0.0;
+        double hi = 1e-12;
+        while (!band_pd(M, hi, G, 1.0, 0.0)) {
+            hi *= 2.0;
+            if (hi > 1e12) return INFINITY;
+        }
+        double lo = 0.0;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            (band_pd(M, mid, G, 1.0, 0.0) ? hi : lo) = mid;
+        }
+        return hi;
+    }
+    if (band_pd(G, 1.0, zero, 0.0, 0.0)) return 0.0;
+    double gersh = 0.0, dmin = INFINITY, dmax = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        double off = 0.0;
+        for (int j = std::max(0, i - G.r); j <= std::min(n - 1, i + G.r); ++j)
+            if (j != i) off += std::fabs(G.get(i, j));
+        gersh = std::max(gersh, std::fabs(G.get(i, i)) + off);
+        dmin = std::min(dmin, G.get(i, i));
+        dmax = std::max(dmax, G.get(i, i));
+    }
+    // lambda_min: G - t I is positive definite exactly for t < lambda_min
+    double ok = -gersh, bad = dmin;
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (ok + bad);
+        (band_pd(G, 1.0, zero, 0.0, -mid) ? ok : bad) = mid;
+    }
+    const double gmin = ok;  // at or below lambda_min
+    // lambda_max: t I - G is positive definite exactly for t > lambda_max
+    double okm = gersh, badm = dmax;
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (okm + badm);
+        (band_pd(G, -1.0, zero, 0.0, mid) ? okm : badm) = mid;
+    }
+    return -gmin * okm;  // okm at or above lambda_max
+}
+
+bool build_host_hierarchy(int n, double s, double trunc, int levels, int dim, int form, std::vector<HostLevel>& out,
+                          int* taps_radius, double* alpha_floor, std::string& err) {
+    if (form != NMG_OP_NORMAL && form != NMG_OP_KERNEL && form != NMG_OP_ANISO) {
+        err = "unknown operator form";
+        return false;
+    }
+    if (form == NMG_OP_ANISO && dim != 1) {
+        err = "the anisotropic regulariser is one-dimensional";
+        return false;
+    }
     if (n < 1) {
         err = "n must be positive";
         return false;
@@ -129,10 +240,16 @@ bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector
     out.clear();
     HostLevel l0;
     l0.n = n;
-    l0.G = gaussian_normal_band(n, taps, R);
-    l0.M.n = n;
-    l0.M.r = 0;
-    l0.M.a.assign((size_t)n, 1.0);
+    l0.G = form == NMG_OP_NORMAL ? gaussian_normal_band(n, taps, R) : gaussian_band(n, taps, R);
+    if (form == NMG_OP_ANISO) {
+        l0.M = anisotropic_band(n);
+    } else {
+        l0.M.n = n;
+        l0.M.r = 0;
+        l0.M.a.assign((size_t)n, 1.0);
+    }
+    // K^T K is positive semi-definite, so the normal equations need only alpha > 0
+    *alpha_floor = form == NMG_OP_NORMAL ? 0.0 : alpha_floor_of(l0.M, l0.G, dim);
     out.push_back(std::move(l0));
     for (int l = 1; l < levels; ++l) {
         HostLevel c;

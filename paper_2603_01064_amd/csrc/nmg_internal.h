@@ -70,8 +70,8 @@ struct HostLevel {
 
 // Builds taps, G_1 = K K, M_1 = I and the Galerkin chain; returns false with
 // a message on invalid input.
-bool build_host_hierarchy(int n, double s, double trunc, int levels, std::vector<HostLevel>& out,
-                          int* taps_radius, std::string& err);
+bool build_host_hierarchy(int n, double s, double trunc, int levels, int dim, int form, std::vector<HostLevel>& out,
+                          int* taps_radius, double* alpha_floor, std::string& err);
 
 // ---------------------------------------------------------------------------
 // Device-side state
@@ -151,6 +151,7 @@ struct Ctx {
     std::vector<int> n;                // points per axis per level
     std::vector<HostLevel> host;
     int taps_radius = 0;
+    double alpha_floor = 0.0;  // alphas at or below it leave the fine operator indefinite
     // smoother description
     int wcount = 0;                    // weights per (level, set)
     std::vector<int> layer_off;        // offset of each layer in a weight block

@@ -414,11 +414,18 @@ namespace nmg {
 // need at most U factorizations, and alphas seen before cost nothing.  idx
 // receives the cache slot of every alpha.  Slots used by requests the
 // serving engine holds are never evicted.
+nmg_status check_alpha(const Ctx* h, double a, int slot) {
+    if (!std::isfinite(a) || !(a > 0.0))
+        return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(slot) + ")");
+    if (!(a > h->alpha_floor))
+        return fail(NMG_ERR_NOT_SPD, "alpha " + std::to_string(a) + " leaves alpha I + K indefinite (needs > " +
+                                         std::to_string(h->alpha_floor) + ", slot " + std::to_string(slot) + ")");
+    return NMG_OK;
+}
+
 nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>& idx, hipStream_t s) {
     const int n = (int)al.size();
-    for (int b = 0; b < n; ++b)
-        if (!std::isfinite(al[(size_t)b]) || !(al[(size_t)b] > 0.0))
-            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(b) + ")");
+    for (int b = 0; b < n; ++b) NMG_TRY(check_alpha(h, al[(size_t)b], b));
     const long long stamp = ++h->prepare_count;
     const int slots = (int)h->cache_alpha.size();
     for (const auto& sl : h->eng.slot) h->cache_used[(size_t)sl.fidx] = stamp;
@@ -780,7 +787,8 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     std::unique_ptr<nmg_ctx> c(new nmg_ctx());
     c->p = *p;
     std::string err;
-    if (!build_host_hierarchy(p->n, p->s, p->trunc, p->levels, c->host, &c->taps_radius, err))
+    if (!build_host_hierarchy(p->n, p->s, p->trunc, p->levels, p->dim, p->operator_form, c->host, &c->taps_radius,
+                              &c->alpha_floor, err))
         return fail(NMG_ERR_SHAPE, err);
     c->L = p->levels;
     for (auto& hl : c->host) c->n.push_back(hl.n);
@@ -915,6 +923,13 @@ void nmg_destroy(nmg_handle h) {
 int nmg_level_size(nmg_handle h, int level) {
     if (!h || level < 0 || level >= h->L) return -1;
     return h->n[(size_t)level];
+}
+
+nmg_status nmg_alpha_floor(nmg_handle h, double* floor_out) {
+    NMG_TRY(check_handle(h));
+    if (!floor_out) return fail(NMG_ERR_ARG, "null pointer");
+    *floor_out = h->alpha_floor;
+    return NMG_OK;
 }
 
 nmg_status nmg_load_smoother_weights(nmg_handle h, int level, int weight_set, const float* w, size_t count) {
@@ -1072,8 +1087,7 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
     if (ws) NMG_HIP(hipMemcpyAsync(wsv.data(), ws, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
     NMG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < batch; ++i) {
-        if (!std::isfinite(al[(size_t)i]) || !(al[(size_t)i] > 0.0))
-            return fail(NMG_ERR_ARG, "alpha must be positive and finite (slot " + std::to_string(i) + ")");
+        NMG_TRY(check_alpha(h, al[(size_t)i], i));
         if (wsv[(size_t)i] < 0 || wsv[(size_t)i] >= h->p.n_weight_sets)
             return fail(NMG_ERR_ARG, "weight set out of range (right-hand side " + std::to_string(i) + ")");
     }
@@ -1113,7 +1127,7 @@ nmg_status nmg_serve_submit(nmg_handle h, long long id, double alpha, int weight
                             double* x_dev) {
     NMG_TRY(check_handle(h));
     if (!b_dev || !x_dev) return fail(NMG_ERR_ARG, "null pointer");
-    if (!std::isfinite(alpha) || !(alpha > 0.0)) return fail(NMG_ERR_ARG, "alpha must be positive and finite");
+    NMG_TRY(check_alpha(h, alpha, 0));
     if (weight_set < 0 || weight_set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight set out of range");
     h->eng.queue.push_back({id, alpha, weight_set, b_dev, x_dev, nullptr, 0, h->eng.now_ms()});
     return NMG_OK;

@@ -34,6 +34,7 @@ class _Problem(ctypes.Structure):
         ("dim", ctypes.c_int), ("n", ctypes.c_int), ("s", ctypes.c_double), ("trunc", ctypes.c_double),
         ("levels", ctypes.c_int), ("max_batch", ctypes.c_int), ("n_layers", ctypes.c_int),
         ("channels", ctypes.c_int * (MAX_LAYERS + 1)), ("ksize", ctypes.c_int), ("n_weight_sets", ctypes.c_int),
+        ("operator_form", ctypes.c_int),
     ]
 
 
@@ -78,6 +79,7 @@ def load_library():
         "nmg_adam_step": (S, [P, I, D, D, D, D, P]),
         "nmg_train_step": (S, [P, I, I, P, P, I, I, I, D, P, P]),
         "nmg_level_size": (I, [P, I]),
+        "nmg_alpha_floor": (S, [P, ctypes.POINTER(ctypes.c_double)]),
         "nmg_profile_enable": (S, [P, I]),
         "nmg_set_graphs": (S, [P, I]),
         "nmg_profile_levels": (S, [P, I]),
@@ -139,6 +141,7 @@ class Problem:
     channels: Sequence[int] = (1, 32, 32, 1)
     ksize: int = 3
     n_weight_sets: int = 1
+    operator: str = "normal"   # "normal": alpha I + K^T K; "kernel": alpha I + K; "aniso": alpha D + K (1D)
 
     def to_c(self) -> _Problem:
         p = _Problem()
@@ -148,6 +151,10 @@ class Problem:
         for i, c in enumerate(self.channels):
             p.channels[i] = int(c)
         p.ksize, p.n_weight_sets = self.ksize, self.n_weight_sets
+        forms = {"normal": 0, "kernel": 1, "aniso": 2}
+        if self.operator not in forms:
+            raise ValueError(f"operator must be one of {sorted(forms)}, not {self.operator!r}")
+        p.operator_form = forms[self.operator]
         return p
 
     def weight_count(self) -> int:
@@ -178,6 +185,12 @@ class Handle:
     # -- geometry --------------------------------------------------------
     def level_size(self, level: int) -> int:
         return int(_lib.nmg_level_size(self.ptr, level))
+
+    def alpha_floor(self) -> float:
+        """Alphas at or below this value leave the operator indefinite and are rejected."""
+        out = ctypes.c_double()
+        _check(_lib.nmg_alpha_floor(self.ptr, ctypes.byref(out)))
+        return float(out.value)
 
     def level_shape(self, level: int, batch: int):
         n = self.level_size(level)

@@ -156,10 +156,12 @@ def main(argv=None):
     ap.add_argument("--init", default=None, help="npz written by this script; its last set initialises training")
     ap.add_argument("--fprime", action="store_true", help="train with F' in the loss (eq. loss_2_modified)")
     ap.add_argument("--steps-per-alpha", type=int, nargs="+", default=None)
+    ap.add_argument("--operator", default="normal", choices=["normal", "kernel"],
+                    help="fine operator: alpha I + K^T K (normal) or alpha I (x) I + K (x) K (kernel)")
     a = ap.parse_args(argv)
     nmg.load_library()
     prob = nmg.Problem(n=a.n, s=a.s, levels=a.levels, dim=2, max_batch=a.batch, channels=tuple(a.channels),
-                       ksize=3, n_weight_sets=1)
+                       ksize=3, n_weight_sets=1, operator=a.operator)
     h = nmg.setup_hierarchy(prob)
     L = a.levels
     if a.init:
@@ -186,7 +188,8 @@ def main(argv=None):
                       f"status {st}", flush=True)
     meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=alphas,
                 steps=a.steps_per_alpha or [a.steps] * len(alphas), batch=a.batch, lr=a.lr, mask=a.mask,
-                rollout=a.rollout, precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init)
+                rollout=a.rollout, precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init,
+                operator=a.operator)
     save_weights(a.out, meta, sets)
     print(f"wrote {a.out}", flush=True)
     h.close()
