@@ -41,6 +41,9 @@ What the paper fixes and how each piece is pinned (tests marked ``not gpu``):
 * Level-wise loss (Sec. 3.2 eq. "loss_2_modified", 2D eq. "loss_3"): pinned
   by the Parseval identity of Sec. 3.2 and central finite differences of the
   gradient.
+* Combined loss (Sec. 3.2 eq. "loss_1"): pinned by the two-grid error
+  propagation identity built from dense matrices and by central finite
+  differences of the joint gradient over all levels.
 
 Parity unpinned: iteration counts of trained or seeded neural cycles (the
 paper prints no worked values for them); they are compared GPU-vs-oracle only.
@@ -549,6 +552,28 @@ def level_loss_grads(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e:
     total.backward()
     grads = [[w.grad.detach().clone() for w in lw] for lw in ws]
     return torch.stack([x.detach() for x in losses]), grads
+
+
+def cycle_loss(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e: torch.Tensor, alpha: torch.Tensor,
+               use_fprime: bool = False) -> torch.Tensor:
+    """Combined loss of Sec. 3.2 eq. loss_1: the mean over samples of
+    ``||e - NMG(0, A e)||^2`` for one cycle from zero with pre-smoothing only
+    (the cycle of Algorithms 2 and 4), the exact coarsest solve included.
+    Every level's weights receive gradient, through the residuals that the
+    corrections of finer levels leave for coarser ones."""
+    S = [neural_smoother(w, H.dim) for w in weights]
+    y = apply_operator(H, 0, e, alpha)
+    x = vcycle(H, S, torch.zeros_like(e), y, alpha, nu1=1, nu2=0, use_fprime=use_fprime)
+    return ((e - x) ** 2).sum() / e.shape[0]
+
+
+def cycle_loss_grads(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e: torch.Tensor,
+                     alpha: torch.Tensor, use_fprime: bool = False):
+    """``(loss, grads)`` of eq. loss_1 with ``grads[l][i] = dL / d weights[l][i]``."""
+    ws = [[w.detach().clone().requires_grad_(True) for w in lw] for lw in weights]
+    loss = cycle_loss(H, ws, e, alpha, use_fprime)
+    loss.backward()
+    return loss.detach(), [[w.grad.detach().clone() for w in lw] for lw in ws]
 
 
 def adam_update(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,

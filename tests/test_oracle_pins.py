@@ -547,6 +547,50 @@ def test_level_loss_gradient_ignores_later_levels():
     assert all(w.grad is None or float(w.grad.abs().max()) == 0.0 for w in ws[1])
 
 
+def test_cycle_loss_two_grid_identity():
+    """eq. loss_1 at L = 2: one cycle from zero gives e - x = T (e - S(A e)) with
+    the coarse-grid correction T = I - P (R A P)^{-1} R A, formed here from dense
+    Kronecker matrices instead of the recursive cycle."""
+    H, W, _ = _setup(n=15, L=2, ch=(1, 4, 4, 1))
+    e = torch.randn(3, 15, 15, dtype=DT, generator=torch.Generator().manual_seed(23))
+    a = torch.tensor([1e-2, 1e-3, 1e-4], dtype=DT)
+    loss = float(O.cycle_loss(H, W, e, a))
+    P = torch.kron(H.levels[0].P, H.levels[0].P)
+    R = P.T / 4.0
+    y = O.apply_operator(H, 0, e, a)
+    h = O.neural_smoother(W[0], 2)(H, 0, y, a)
+    tot = 0.0
+    for i in range(3):
+        A = O.dense_operator(H, 0, float(a[i]))
+        T = torch.eye(225, dtype=DT) - P @ torch.linalg.solve(R @ A @ P, R @ A)
+        tot += float(((T @ (e[i] - h[i]).reshape(-1)) ** 2).sum())
+    assert abs(loss - tot / 3) <= 1e-12 * tot
+
+
+@pytest.mark.parametrize("use_fp", [False, True])
+def test_cycle_loss_gradient_matches_central_differences(use_fp):
+    """The joint gradient of eq. loss_1: every level's weights, including the
+    effect of a finer level's correction on the residuals of coarser ones."""
+    H, W, _ = _setup(n=15, L=3, ch=(1, 4, 4, 1))
+    e = torch.randn(2, 15, 15, dtype=DT, generator=torch.Generator().manual_seed(24))
+    a = torch.tensor([1e-2, 1e-3], dtype=DT)
+    loss, grads = O.cycle_loss_grads(H, W, e, a, use_fp)
+    rng = np.random.default_rng(1)
+    eps = 1e-6
+    for l in range(2):
+        for li in range(3):
+            for _ in range(3):
+                idx = tuple(int(rng.integers(0, d)) for d in W[l][li].shape)
+                Wp = [[w.clone() for w in lw] for lw in W]
+                Wm = [[w.clone() for w in lw] for lw in W]
+                Wp[l][li][idx] += eps
+                Wm[l][li][idx] -= eps
+                fd = (float(O.cycle_loss(H, Wp, e, a, use_fp)) - float(O.cycle_loss(H, Wm, e, a, use_fp))) / (2 * eps)
+                g = float(grads[l][li][idx])
+                assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (l, li, idx, fd, g)
+    assert float(grads[0][0].abs().max()) > 0 and float(grads[1][0].abs().max()) > 0
+
+
 def test_adam_matches_library():
     g = torch.Generator().manual_seed(20)
     p = torch.randn(10, dtype=DT, generator=g)
