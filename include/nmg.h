@@ -60,7 +60,7 @@ typedef enum {
  *              iterative refinement. */
 typedef enum { NMG_FP64 = 0, NMG_FP32 = 1, NMG_MIXED = 2 } nmg_precision;
 
-typedef enum { NMG_MASK_BAND = 0, NMG_MASK_RAMP = 1 } nmg_mask_kind;
+typedef enum { NMG_MASK_BAND = 0, NMG_MASK_RAMP = 1, NMG_LOSS_CYCLE = 2 } nmg_mask_kind;
 
 #define NMG_MAX_LAYERS 7
 
@@ -265,7 +265,15 @@ nmg_status nmg_serve_reset(nmg_handle h);
  * losses_host: double[L-1] (may be NULL).  The gradients are accumulated
  * into the handle's gradient buffers of `weight_set` (zeroed first when
  * zero_grad != 0).  Precision NMG_FP64 computes everything in FP64;
- * otherwise FP32 arithmetic with BF16 MFMA smoother forward.  Synchronises. */
+ * otherwise FP32 arithmetic with BF16 MFMA smoother forward.  Synchronises.
+ *
+ * mask = NMG_LOSS_CYCLE selects the combined loss of Sec. 3.2 eq. loss_1
+ * instead: L = (1/B) sum_i || e_i - NMG(0, A e_i) ||^2 for the whole
+ * pre-smoothing-only cycle with its exact coarsest solve, and dL/dtheta_l
+ * for every level jointly (finer corrections change coarser residuals).
+ * It factors the batch's alphas itself (as nmg_prepare does, so the coarse
+ * indices of a following nmg_vcycle refer to these alphas).  losses_host[0]
+ * receives L, the other entries 0. */
 nmg_status nmg_loss_grad(nmg_handle h, int weight_set, int batch, const double* alpha_dev,
                          const void* e_dev, nmg_mask_kind mask, int use_fprime,
                          nmg_precision precision, int zero_grad, double* losses_host, void* stream);

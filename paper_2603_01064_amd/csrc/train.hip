@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(kBlock) k_conv_train(const T* __restrict__ in,
     out[((size_t)b * cout + co) * per + e] = acc;
 }
 
-// Data gradient: din[b][ci][p] = [a_in > 0] * sum_co sum_t W[co][ci][t] dout[b][co][p - off(t)].
+// Data gradient: din[b][ci][p] = [a_in > 0] * sum_co sum_t W[co][ci][t] dout[b][co][p - off(t)]
+// (no ReLU mask when a_in is null: the network input).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const T* __restrict__ dout, const T* __restrict__ a_in,
                                                           T* __restrict__ din, const T* __restrict__ W, int cin,
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const T* __restrict__ 
     if (e >= per) return;
     const int ci = blockIdx.y, b = blockIdx.z;
     const size_t idx = ((size_t)b * cin + ci) * per + e;
-    if (!(a_in[idx] > (T)0)) {
+    if (a_in && !(a_in[idx] > (T)0)) {
         din[idx] = 0;
         return;
     }
@@ -214,6 +215,68 @@ __global__ void __launch_bounds__(kBlock) k_scale_by_norm(const T* __restrict__ 
     out[(size_t)b * per + e] = scale * (T)sqrt(nrm2[b]) * in[(size_t)b * per + e];
 }
 
+// out = a x + c y (elementwise; out may alias x or y)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axpby(const T* x, const T* y, T* out, T a, T c, size_t total) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < total) out[e] = a * x[e] + c * y[e];
+}
+
+// Per right-hand side b: d1[b] = <u_b, v_b>, d2[b] = <w_b, z_b> in FP64, one
+// block per right-hand side with a fixed reduction order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot2(const T* __restrict__ u, const T* __restrict__ v,
+                                                 const T* __restrict__ w, const T* __restrict__ z,
+                                                 double* __restrict__ d1, double* __restrict__ d2, size_t per) {
+    __shared__ double s1[kBlock], s2[kBlock];
+    const int b = blockIdx.x;
+    const size_t o = (size_t)b * per;
+    double a1 = 0.0, a2 = 0.0;
+    for (size_t e = threadIdx.x; e < per; e += kBlock) {
+        a1 += (double)u[o + e] * (double)v[o + e];
+        a2 += (double)w[o + e] * (double)z[o + e];
+    }
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+            s2[threadIdx.x] += s2[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d1[b] = s1[0];
+        d2[b] = s2[0];
+    }
+}
+
+// Gradient of the loss with respect to the smoother input b of one level,
+// plus the restriction adjoint of the coarser level's gradient:
+//   h = ||b|| N(b/||b||), gh = dL/dh, dU = J_N^T (||b|| gh) (network input),
+//   dL/db = b (<gh,h>/||b||^2 - <b,dU>/||b||^3) + dU/||b||   (0 when b = 0),
+//   out = dL/db + rscale * pg   with pg = P gy_{l+1}, rscale = 2^-d (R^T = P / 2^d).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_input_grad(const T* __restrict__ bv, const T* __restrict__ dU,
+                                                       const T* __restrict__ pg, const double* __restrict__ gh_h,
+                                                       const double* __restrict__ b_dU,
+                                                       const double* __restrict__ nrm2, T* __restrict__ out,
+                                                       T rscale, size_t per) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int b = blockIdx.y;
+    if (e >= per) return;
+    const size_t i = (size_t)b * per + e;
+    const double q = nrm2[b];
+    T g = 0;
+    if (q > 0.0) {
+        const double nb = sqrt(q);
+        const T cb = (T)(gh_h[b] / q - b_dU[b] / (q * nb));
+        g = cb * bv[i] + (T)(1.0 / nb) * dU[i];
+    }
+    out[i] = g + rscale * pg[i];
+}
+
 template <typename G>
 __global__ void __launch_bounds__(kBlock) k_adam(float* __restrict__ w, const G* __restrict__ g, float* __restrict__ m,
                                                  float* __restrict__ v, int count, float lr, float b1, float b2,
@@ -242,6 +305,7 @@ struct TrainWork {
     T* part = nullptr;          // weight-gradient partials
     size_t part_count = 0;
     double* lossb = nullptr;    // [B]
+    double* dots = nullptr;     // [2B] per-RHS dot products of the cycle-loss adjoint
 };
 
 template <typename T>
@@ -298,6 +362,7 @@ static void free_train_work(TrainWork<T>& w) {
     f(w.d1);
     f(w.part);
     f(w.lossb);
+    f(w.dots);
     w.ready = false;
 }
 
@@ -358,6 +423,7 @@ static nmg_status ensure_train(const Ctx* c, TrainWork<T>& w) {
     w.part_count = chunks * maxlayer;
     NMG_TRY(talloc(&w.part, w.part_count));
     NMG_TRY(talloc(&w.lossb, (size_t)B));
+    NMG_TRY(talloc(&w.dots, (size_t)2 * B));
     w.ready = true;
     return NMG_OK;
 }
@@ -404,7 +470,7 @@ float* grad_ptr<float>(Ctx* c, int l, int set) {
 
 template <typename T>
 static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int l, int set, int batch,
-                                    const T* upstream, T sign, int accumulate, hipStream_t s) {
+                                    const T* upstream, T sign, int accumulate, hipStream_t s, T* din0 = nullptr) {
     const int n = c->n[(size_t)l];
     const int ny = c->p.dim == 2 ? n : 1;
     const int kh = c->p.dim == 2 ? c->p.ksize : 1, kw = c->p.ksize;
@@ -442,6 +508,9 @@ static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int
                                tw.acts[(size_t)i - 1], dnext, Wbase + c->layer_off[(size_t)i], cin, cout, kh, kw, ny,
                                n);
             std::swap(dcur, dnext);
+        } else if (din0) {  // gradient at the network input u = b / ||b||
+            hipLaunchKernelGGL(k_conv_bwd_data<T>, dim3(blocks_for(per), cin, batch), dim3(kBlock), 0, s, dcur,
+                               (const T*)nullptr, din0, Wbase + c->layer_off[0], cin, cout, kh, kw, ny, n);
         }
     }
     NMG_HIP(hipGetLastError());
@@ -528,6 +597,114 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
     return NMG_OK;
 }
 
+// Combined loss of the whole cycle (Sec. 3.2 eq. loss_1) and its joint
+// gradient over every level.  Forward (levels 0-based, L-1 the coarsest):
+//   y_0 = A e;  h_l = S_l(y_l), hc_l = F'_l(h_l) or h_l;
+//   y_{l+1} = R(y_l - A_l hc_l);  x_c = A_{L-1}^{-1} y_{L-1};
+//   x = sum_l I_l^0 hc_l + I_{L-1}^0 x_c;  L = (1/B) sum_i ||e_i - x_i||^2.
+// Adjoint: g_0 = -(2/B)(e - x), g_{l+1} = P^T g_l (gradient of each level's
+// output), gy_{L-1} = A_{L-1}^{-1} g_{L-1}, then for l = L-2 .. 0:
+//   dL/dhc_l = g_l - A_l R^T gy_{l+1}       (hc_l also feeds y_{l+1})
+//   dL/dh_l  = F'_l(dL/dhc_l) or the same    (F'_l is symmetric)
+//   theta_l gradient from dL/dh_l (network backward)
+//   gy_l     = J_{S_l}^T dL/dh_l + R^T gy_{l+1}   (y_l feeds h_l and y_{l+1})
+// with R^T = P / 2^d.  A_l and A_{L-1}^{-1} are symmetric.
+template <typename T>
+nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const double* alpha, const T* e,
+                           int use_fprime, bool mixed, int zero_grad, double* losses_host, hipStream_t s) {
+    TrainState& ts = train_state(c);
+    TrainWork<T>& tw = tw_of<T>(ts);
+    NMG_TRY(ensure_train<T>(c, tw));
+    NMG_TRY(nmg_prepare(static_cast<nmg_handle>(c), batch, alpha, s));  // coarse factors of these alphas
+    const int L = c->L;
+    const int nsm = L - 1;
+    const int two_d = c->p.dim == 2 ? 1 : 0;
+    const T rscale = (T)(two_d ? 0.25 : 0.5);
+    const size_t per0 = level_elems(c, 0);
+    const size_t fine = (size_t)batch * per0;
+    std::vector<int> wsv((size_t)batch, set);
+    int* ws_dev = c->active;
+    NMG_HIP(hipMemcpyAsync(ws_dev, wsv.data(), (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
+    LevelBuffers<T>& coarse = work.lv[(size_t)nsm];
+    auto coarse_solve = [&](const T* y, T* x) -> nmg_status {
+        if (std::is_same<T, double>::value) return launch_coarse_solve<T>(c, batch, y, x, s);
+        return launch_coarse_apply_inverse<T>(c, batch, y, x, s);
+    };
+    // ---- forward
+    NMG_TRY(launch_operator<T>(c, 0, batch, alpha, e, nullptr, tw.b[0], 1, work, s));
+    for (int l = 0; l < nsm; ++l) {
+        const size_t per = level_elems(c, l);
+        NMG_TRY(launch_sumsq<T>(c, batch, per, tw.b[(size_t)l], tw.nrm[(size_t)l], s));
+        if (mixed) {
+            NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
+                                         tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
+                                         *reinterpret_cast<Work<float>*>(&work), s));
+        } else {
+            NMG_TRY(launch_conv_smoother<T>(c, l, batch, ws_dev, tw.b[(size_t)l], tw.nrm[(size_t)l], tw.h[(size_t)l],
+                                            0, work, s));
+        }
+        T* hc = tw.h[(size_t)l];
+        if (use_fprime) {
+            NMG_TRY(launch_fprime<T>(c, l, batch, tw.h[(size_t)l], tw.hc[(size_t)l], 0, work, s));
+            hc = tw.hc[(size_t)l];
+        }
+        T* ynext = l + 1 < nsm ? tw.b[(size_t)l + 1] : coarse.y;
+        NMG_TRY(launch_operator<T>(c, l, batch, alpha, hc, tw.b[(size_t)l], work.lv[(size_t)l].b, 0, work, s));
+        NMG_TRY(launch_restrict<T>(c, l, batch, work.lv[(size_t)l].b, ynext, s));
+    }
+    NMG_TRY(coarse_solve(coarse.y, coarse.x));
+    NMG_TRY(launch_zero<T>(tw.acc, fine, s));
+    for (int l = 0; l < nsm; ++l) {
+        NMG_TRY(prolong_chain<T>(c, work, l, batch, use_fprime ? tw.hc[(size_t)l] : tw.h[(size_t)l], tw.F1, s));
+        NMG_TRY(launch_axpy<T>(batch, per0, tw.F1, tw.acc, 1, s));
+    }
+    NMG_TRY(prolong_chain<T>(c, work, nsm, batch, coarse.x, tw.F1, s));
+    hipLaunchKernelGGL(k_error<T>, dim3(blocks_for(fine)), dim3(kBlock), 0, s, e, tw.acc, tw.F1, tw.E, fine);
+    NMG_TRY(launch_sumsq<T>(c, batch, per0, tw.E, tw.lossb, s));
+    // ---- adjoint
+    auto gbuf = [&](int l) -> T* { return l == 0 ? tw.E : (l < nsm ? tw.hc[(size_t)l] : coarse.y); };
+    hipLaunchKernelGGL(k_axpby<T>, dim3(blocks_for(fine)), dim3(kBlock), 0, s, tw.E, tw.E, tw.E,
+                       (T)(-2.0 / batch), (T)0, fine);
+    for (int l = 0; l < nsm; ++l) NMG_TRY(launch_prolong_transpose<T>(c, l, batch, gbuf(l), gbuf(l + 1), s));
+    NMG_TRY(coarse_solve(coarse.y, coarse.x));  // gy_{L-1}
+    for (int l = nsm - 1; l >= 0; --l) {
+        const size_t per = level_elems(c, l);
+        const size_t tot = (size_t)batch * per;
+        LevelBuffers<T>& lb = work.lv[(size_t)l];
+        const T* gy_next = work.lv[(size_t)l + 1].x;
+        NMG_TRY(launch_zero<T>(lb.b, tot, s));
+        NMG_TRY(launch_prolong_add<T>(c, l, batch, gy_next, lb.b, s));                  // pg = P gy_{l+1}
+        NMG_TRY(launch_operator<T>(c, l, batch, alpha, lb.b, nullptr, lb.h, 1, work, s));  // A_l pg
+        T* ghc = gbuf(l);
+        hipLaunchKernelGGL(k_axpby<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, ghc, lb.h, ghc, (T)1, -rscale,
+                           tot);
+        const T* gh = ghc;
+        if (use_fprime) {
+            NMG_TRY(launch_fprime<T>(c, l, batch, ghc, lb.h, 0, work, s));
+            gh = lb.h;
+        }
+        NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)1, zero_grad ? 0 : 1, s,
+                                     l > 0 ? tw.F1 : nullptr));
+        if (l > 0) {
+            hipLaunchKernelGGL(k_dot2<T>, dim3(batch), dim3(kBlock), 0, s, gh, tw.h[(size_t)l], tw.b[(size_t)l],
+                               tw.F1, tw.dots, tw.dots + batch, per);
+            hipLaunchKernelGGL(k_input_grad<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, tw.b[(size_t)l],
+                               tw.F1, lb.b, tw.dots, tw.dots + batch, tw.nrm[(size_t)l], lb.x, rscale, per);
+        }
+    }
+    NMG_HIP(hipGetLastError());
+    std::vector<double> lossb((size_t)batch);
+    NMG_HIP(hipMemcpyAsync(lossb.data(), tw.lossb, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    if (losses_host) {
+        double total = 0.0;
+        for (int b = 0; b < batch; ++b) total += lossb[(size_t)b];
+        losses_host[0] = total / batch;
+        for (int l = 1; l < nsm; ++l) losses_host[l] = 0.0;
+    }
+    return NMG_OK;
+}
+
 }  // namespace nmg
 
 using namespace nmg;
@@ -539,7 +716,8 @@ nmg_status check_training(nmg_handle h, int set, int batch, nmg_mask_kind mask, 
     if (h->L < 2) return fail(NMG_ERR_SHAPE, "training needs at least two levels");
     if (batch < 1 || batch > h->p.max_batch) return fail(NMG_ERR_SHAPE, "batch must be in [1, max_batch]");
     if (set < 0 || set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight_set out of range");
-    if (mask != NMG_MASK_BAND && mask != NMG_MASK_RAMP) return fail(NMG_ERR_ARG, "unknown mask kind");
+    if (mask != NMG_MASK_BAND && mask != NMG_MASK_RAMP && mask != NMG_LOSS_CYCLE)
+        return fail(NMG_ERR_ARG, "unknown loss kind");
     if (prec != NMG_FP64 && prec != NMG_FP32 && prec != NMG_MIXED) return fail(NMG_ERR_ARG, "unknown precision");
     const int kk = h->p.dim == 2 ? h->p.ksize * h->p.ksize : h->p.ksize;
     if (kk > kMaxTaps) return fail(NMG_ERR_SHAPE, "training supports at most 25 taps per kernel");
@@ -560,14 +738,22 @@ nmg_status nmg_loss_grad(nmg_handle h, int set, int batch, const double* alpha, 
     hipStream_t s = (hipStream_t)stream;
     if (prec == NMG_FP64) {
         NMG_TRY(ensure_work<double>(h));
-        NMG_TRY(loss_grad_impl<double>(h, h->w64, set, batch, alpha, (const double*)e, mask, use_fprime, false,
-                                       zero_grad, losses_host, s));
+        if (mask == NMG_LOSS_CYCLE)
+            NMG_TRY(cycle_loss_impl<double>(h, h->w64, set, batch, alpha, (const double*)e, use_fprime, false,
+                                            zero_grad, losses_host, s));
+        else
+            NMG_TRY(loss_grad_impl<double>(h, h->w64, set, batch, alpha, (const double*)e, mask, use_fprime, false,
+                                           zero_grad, losses_host, s));
         h->grad_is_fp64 = true;
         return NMG_OK;
     }
     NMG_TRY(ensure_work<float>(h));
-    NMG_TRY(loss_grad_impl<float>(h, h->w32b, set, batch, alpha, (const float*)e, mask, use_fprime,
-                                  prec == NMG_MIXED, zero_grad, losses_host, s));
+    if (mask == NMG_LOSS_CYCLE)
+        NMG_TRY(cycle_loss_impl<float>(h, h->w32b, set, batch, alpha, (const float*)e, use_fprime,
+                                       prec == NMG_MIXED, zero_grad, losses_host, s));
+    else
+        NMG_TRY(loss_grad_impl<float>(h, h->w32b, set, batch, alpha, (const float*)e, mask, use_fprime,
+                                      prec == NMG_MIXED, zero_grad, losses_host, s));
     h->grad_is_fp64 = false;
     return NMG_OK;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnmg.so")
 NMG_OK = 0
 NMG_NOT_CONVERGED = 1
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
-MASK = {"band": 0, "ramp": 1}
+MASK = {"band": 0, "ramp": 1, "cycle": 2}  # "cycle": the combined loss eq. loss_1
 MAX_LAYERS = 7
 
 

@@ -2,14 +2,15 @@
 
 Each weight set belongs to one operator (grid, kernel width, alpha): the
 paper trains smoothers for a fixed coefficient matrix and retrains when it
-changes.  Training uses the library's own ``train_step`` (level-wise loss,
-hand-written adjoint, Adam) on batches of i.i.d. N(0,1) error vectors, an
+changes.  Training uses the library's own ``train_step`` (level-wise loss or
+the combined cycle loss, hand-written adjoint, Adam) on batches of i.i.d. N(0,1) error vectors, an
 optional rollout of k in 1..K cycles of the current smoothers before each
 batch (Algorithm 5, DataGeneration) and a curriculum over alpha (weights of
 a larger alpha initialise the next smaller one, Sec. 4.1).
 
 Usage: python -m paper_2603_01064_amd.train_weights --n 255 --s 0.01 --levels 5 \
            --alphas 1e-2 1e-3 1e-4 --steps 1500 --out paper_2603_01064_amd/weights/grid255_s0.01.npz
+       python -m paper_2603_01064_amd.train_weights levels --weights F.npz --set 1   (coarsest-level sweep)
 """
 from __future__ import annotations
 
@@ -134,11 +135,53 @@ def merge(argv):
     print(f"wrote {a.out} with alphas {alphas}")
 
 
+def coarsest_level_sweep(argv):
+    """``levels --weights F [--set k] [--levels 2 3 4 5] [--batch 16]``: the
+    coarsest-level change of Sec. 4 (loss ablation): smoothers trained with L
+    levels solve with L' <= L levels (the first L'-1 smoothers, exact solve on
+    level L'); prints the cycles to 1e-6 per L'.  A coarser L' needs a
+    coarsest grid small enough for the dense factor."""
+    ap = argparse.ArgumentParser(prog="train_weights levels")
+    ap.add_argument("--weights", required=True)
+    ap.add_argument("--set", type=int, default=0)
+    ap.add_argument("--levels", type=int, nargs="+", default=None)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--max-cycles", type=int, default=200)
+    a = ap.parse_args(argv)
+    nmg.load_library()
+    meta, sets = load_weights(a.weights)
+    cyc_cfg = meta.get("cycle", {"nu1": 1, "nu2": 1, "use_fprime": False})
+    alpha = meta["alphas"][a.set]
+    out = {}
+    for Lp in a.levels or list(range(2, meta["levels"] + 1)):
+        if Lp > meta["levels"]:
+            raise SystemExit(f"the weights have {meta['levels']} levels; L' = {Lp} is not available")
+        prob = nmg.Problem(n=meta["n"], s=meta["s"], levels=Lp, max_batch=a.batch, channels=tuple(meta["channels"]),
+                           ksize=meta.get("ksize", 3), operator=meta.get("operator", "normal"))
+        try:
+            h = nmg.setup_hierarchy(prob)
+        except nmg.NMGError as e:
+            print(f"L' = {Lp}: {e}", flush=True)
+            continue
+        for l in range(Lp - 1):
+            h.load_smoother_weights(l, 0, [sets[a.set][l]])
+        cyc, st = evaluate(h, alpha, a.batch, cyc_cfg["nu1"], cyc_cfg["nu2"], cyc_cfg["use_fprime"], a.max_cycles)
+        h.close()
+        if cyc is None:
+            print(f"L' = {Lp}: {st}", flush=True)
+            continue
+        out[Lp] = (float(cyc.mean()), int(cyc.max()), int(st))
+        print(f"L' = {Lp}: alpha {alpha:g} cycles mean {cyc.mean():.2f} max {cyc.max()} status {st}", flush=True)
+    return out
+
+
 def main(argv=None):
     import sys
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "merge":
         return merge(argv[1:])
+    if argv and argv[0] == "levels":
+        return coarsest_level_sweep(argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--s", type=float, default=0.01)
@@ -148,7 +191,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--mask", default="ramp", choices=["ramp", "band"])
+    ap.add_argument("--mask", default="ramp", choices=["ramp", "band", "cycle"],
+                    help="level-wise spectral loss with the ramp or band mask, or the combined loss of the whole "
+                         "cycle (eq. loss_1, all levels trained jointly)")
     ap.add_argument("--rollout", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--seed", type=int, default=7000)
