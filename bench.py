@@ -131,6 +131,9 @@ def main(argv=None):
     ap.add_argument("--no-serial-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching measurements")
     ap.add_argument("--no-training", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--no-mixed-sizes", action="store_true",
+                    help="skip the serving stream over grid sides 64..1024 (needs the s = 2.5h weights)")
+    ap.add_argument("--mixed-requests", type=int, default=300, help="requests per arrival rate, mixed sizes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 64 MiB device copy before timing (reference kernel for HBM counters)")
     a = ap.parse_args(argv)
@@ -257,6 +260,9 @@ def main(argv=None):
         log("serving: continuous batching on Poisson arrivals")
         res["serving"] = serving(nmg, h, sets, set_alphas, cyc_cfg, batches[a.warmup:], a.max_cycles,
                                  serial=not a.no_serial_baseline)
+    if not a.no_mixed_sizes and os.path.exists(MIXED_WEIGHTS):
+        log("serving: grid sides 64..1024 through one pool")
+        res["serving_mixed_sizes"] = mixed_sizes_serving(nmg, count=a.mixed_requests, max_cycles=a.max_cycles)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(meta, sets, float(cycles.mean()))
@@ -384,6 +390,119 @@ def serving(nmg, h, sets, set_alphas, cyc_cfg, batches, max_cycles, rates=(20.0,
             srep = serve_serially(solve_one, arr)
             h1.close()
             out[f"poisson_{int(rate)}_per_s"]["serial_fp32"] = srep.summary()
+    return out
+
+
+MIXED_WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s2.5h.npz")
+MIXED_SIDES = (64, 128, 256, 512, 1024)
+MIXED_SLOTS = {64: 64, 128: 64, 256: 64, 512: 32, 1024: 16}
+
+
+def _mixed_handle(nmg, side, meta, sets, max_batch):
+    """Grid side N (N - 1 interior points per axis), s = 2.5 / N, levels down
+    to 15^2.  Level l uses trained level min(l, deepest): the kernel width in
+    grid units (s/h = 2.5) and so every level's operator matches the training
+    grid's level l up to boundary rows; deeper levels reuse the deepest set."""
+    n = side - 1
+    L = int(round(math.log2(side / 16))) + 1
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=2.5 / side, levels=L, max_batch=max_batch,
+                                        channels=tuple(meta["channels"]), ksize=3, n_weight_sets=len(sets)))
+    deepest = meta["levels"] - 2
+    for k, ws in enumerate(sets):
+        for l in range(L - 1):
+            h.load_smoother_weights(l, k, [ws[min(l, deepest)]])
+    return h
+
+
+def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, serial_count=40, max_cycles=200,
+                        budget=2 << 30):
+    """Serving stream of 2D solves with grid side uniform over 64..1024,
+    s = 2.5 grid spacings, alpha log-uniform in [1e-5, 1e-2], box-image
+    right-hand sides and Poisson arrivals, through one pool (one handle per
+    side, 2 GiB budget) with the BF16/FP32/FP64 cycle to 1e-6; the serial
+    plain-FP32 one-request-at-a-time solver runs the first requests of the
+    lowest-rate trace."""
+    import torch
+
+    from paper_2603_01064_amd import inputs
+    from paper_2603_01064_amd.serve import serve_pool_requests, serve_serially
+    from paper_2603_01064_amd.train_weights import load_weights
+    dev = torch.device("cuda:0")
+    meta, sets = load_weights(MIXED_WEIGHTS)
+    set_alphas = list(meta["alphas"])
+    cyc_cfg = meta["cycle"]
+    kw = dict(rtol=1e-6, max_cycles=max_cycles, nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"],
+              use_fprime=cyc_cfg["use_fprime"])
+    handles = [_mixed_handle(nmg, sd, meta, sets, MIXED_SLOTS[sd]) for sd in MIXED_SIDES]
+    pool = nmg.Pool(budget)
+    for h in handles:
+        pool.add(h)
+    rng = np.random.default_rng(41000)
+    member = rng.integers(0, len(MIXED_SIDES), size=count)
+    alpha = inputs.log_uniform(1e-5, 1e-2, count, seed=41001)
+    ws = np.array([set_alphas.index(min(set_alphas, key=lambda v: abs(math.log(v / a)))) for a in alpha])
+    b, x = [], []
+    for i in range(count):
+        h, side = handles[member[i]], MIXED_SIDES[member[i]]
+        u = torch.tensor(inputs.boxes_image(side - 1, 42000 + i)[None], device=dev)
+        bi = h.apply_operator(0, u, torch.tensor([alpha[i]], dtype=torch.float64, device=dev), "fp64")[0]
+        b.append(bi.contiguous())
+        x.append(torch.empty_like(bi))
+    torch.cuda.synchronize()
+    # warm-up: one request per side (graph capture, coarse factors)
+    for m in range(len(MIXED_SIDES)):
+        i = int(np.nonzero(member == m)[0][0])
+        serve_pool_requests(pool, [m], [b[i]], [x[i]], [alpha[i]], [ws[i]], np.zeros(1), precision="mixed", **kw)
+    out = {"workload": f"grid side uniform over {list(MIXED_SIDES)} (n = side - 1, s = 2.5/side, levels to 15^2), "
+                       f"alpha log-uniform [1e-5, 1e-2], box-image right-hand sides, Poisson arrivals, "
+                       f"{count} requests per rate, budget {budget >> 20} MiB, rtol 1e-6",
+           "slots": {str(sd): MIXED_SLOTS[sd] for sd in MIXED_SIDES},
+           "request_mib": {str(sd): round(h.request_bytes("mixed") / 2 ** 20, 1)
+                           for sd, h in zip(MIXED_SIDES, handles)}}
+    for rate in rates:
+        arr = inputs.poisson_arrivals(rate, count, seed=43000 + int(rate))
+        arr = arr - arr[0]
+        rep = serve_pool_requests(pool, member, b, x, alpha, ws, arr, precision="mixed", **kw)
+        summ = rep.summary()
+        ok = rep.status == 0
+        summ["p99_ms_by_side"] = {str(sd): round(float(np.percentile(rep.latency_ms[(member == m) & ok], 99)), 2)
+                                  for m, sd in enumerate(MIXED_SIDES) if ((member == m) & ok).any()}
+        summ["mean_cycles_by_side"] = {str(sd): round(float(rep.cycles[member == m].mean()), 2)
+                                       for m, sd in enumerate(MIXED_SIDES) if (member == m).any()}
+        out[f"poisson_{int(rate)}_per_s"] = summ
+        log(f"mixed-size serving at {rate:g}/s: {summ['solves_per_s']} solves/s, p50 {summ['p50_ms']} ms, "
+            f"p99 {summ['p99_ms']} ms, converged {summ['converged']}/{summ['requests']}")
+    pool.close()
+    # the serial plain-FP32 solver on the first requests of the lowest rate
+    rate = min(rates)
+    arr = inputs.poisson_arrivals(rate, count, seed=43000 + int(rate))[:serial_count]
+    arr = arr - arr[0]
+    serial = [_mixed_handle(nmg, sd, meta, sets, 1) for sd in MIXED_SIDES]
+    for h1 in serial:
+        h1.set_graphs(False)
+
+    def solve_one(i):
+        h1 = serial[member[i]]
+        try:
+            _, cyc, _, st = h1.solve(b[i][None], torch.tensor([alpha[i]], dtype=torch.float64, device=dev),
+                                     weight_set=torch.tensor([int(ws[i])], dtype=torch.int32, device=dev),
+                                     precision="fp32", **kw)
+            return int(cyc[0]), int(st)
+        except nmg.NMGError:
+            return -1, -1
+
+    solve_one(0)
+    srep = serve_serially(solve_one, arr)
+    for h1 in serial:
+        h1.close()
+    s_sum = srep.summary()
+    s_sum["requests_of_trace"] = serial_count
+    out[f"poisson_{int(rate)}_per_s"]["serial_fp32_first_requests"] = s_sum
+    pool_first = out[f"poisson_{int(rate)}_per_s"]
+    for h in handles:
+        h.close()
+    log(f"serial FP32 on the first {serial_count} requests at {rate:g}/s: p50 {s_sum['p50_ms']} ms, "
+        f"p99 {s_sum['p99_ms']} ms (pool p99 {pool_first['p99_ms']} ms over {count})")
     return out
 
 

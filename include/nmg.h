@@ -254,6 +254,47 @@ nmg_status nmg_serve_pending(nmg_handle h, int* queued, int* active);
 /* Drops every queued and active request (their x_dev are left as they are). */
 nmg_status nmg_serve_reset(nmg_handle h);
 
+/* ---- serving pool: several handles, one budget ------------------------ */
+
+/* Device bytes one request slot occupies in a solve of `precision` on this
+ * handle: the engine's FP64/FP32 planes plus the cycle's level buffers (and
+ * the direct-convolution activations for FP32 / FP64 cycles). */
+nmg_status nmg_request_bytes(nmg_handle h, nmg_precision precision, size_t* bytes);
+
+/* A pool serves requests of several problems at once (Sec. 2.3: every
+ * right-hand side is an independent solve), typically one handle per grid
+ * size.  Each member handle keeps its hierarchy, weights and iterates on the
+ * device and runs its continuous-batching engine (nmg_serve_*) on a stream
+ * the pool creates for it (default priority); one pool step advances every
+ * member with work by one outer iteration, and a member waits only for its
+ * own previous iteration, so different members' iterations overlap on the
+ * device.  Requests wait in one FIFO and are admitted while the bytes of
+ * the admitted requests (nmg_request_bytes at the step's precision) stay
+ * within hbm_budget_bytes; the head request is always admitted when nothing
+ * is in flight.  The pool does not own its handles: they must outlive it and
+ * receive no other solve or serving calls while it holds work.  Not
+ * thread-safe. */
+typedef struct nmg_pool_ctx* nmg_pool;
+nmg_status nmg_pool_create(size_t hbm_budget_bytes, nmg_pool* out);
+void nmg_pool_destroy(nmg_pool p);  /* waits for the members' streams */
+/* Adds a handle (with no serving work of its own); *member_out = its index. */
+nmg_status nmg_pool_add(nmg_pool p, nmg_handle h, int* member_out);
+/* Queues request `id` (unique among the pool's queued and running requests)
+ * for member `member`: b_dev / x_dev as in nmg_serve_submit, ready on the
+ * device before the next nmg_pool_step (the pool's streams do not wait on
+ * the caller's).  NMG_ERR_ARG if one request of this size exceeds the budget
+ * in mixed precision, NMG_ERR_NOT_SPD / NMG_ERR_ARG for a bad alpha. */
+nmg_status nmg_pool_submit(nmg_pool p, int member, long long id, double alpha, int weight_set,
+                           const double* b_dev, double* x_dev);
+/* Admission, then one outer iteration of every member with work.  Finished
+ * requests are written to done[0..*n_done) with their member index in
+ * done_member; latency_ms counts from nmg_pool_submit.  Their solutions are
+ * complete in x when the call returns.  capacity must be at least the
+ * number of requests in flight (nmg_pool_pending). */
+nmg_status nmg_pool_step(nmg_pool p, double rtol, int max_cycles, const nmg_cycle_opts* opts,
+                         nmg_request_result* done, int* done_member, int capacity, int* n_done);
+nmg_status nmg_pool_pending(nmg_pool p, int* queued, int* active, size_t* bytes_in_flight);
+
 /* ---- training (Sec. 3.2 eq. loss_2_modified / Sec. 3.3 eq. loss_3,
  *      Algorithm 5) ----------------------------------------------------- */
 

@@ -264,6 +264,8 @@ template <typename T>
 Work<T>& work_of(Ctx* c);
 template <typename T>
 nmg_status ensure_work(Ctx* c);
+template <typename T>
+nmg_status ensure_acts(Ctx* c);
 void release_training(const Ctx* c);
 
 size_t level_elems(const Ctx* c, int l);  // ny_l * n_l
@@ -322,6 +324,16 @@ template <typename T>
 nmg_status launch_scatter_ptrs(int count, size_t per, const T* xc, double* const* dst, const int* slots,
                                hipStream_t s);
 nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>& idx, hipStream_t s);
+nmg_status check_opts(const Ctx* c, const nmg_cycle_opts* o);
+nmg_status check_alpha(const Ctx* h, double a, int slot);
+// One continuous-batching step on stream s; `retired`, when given, is
+// recorded on s once the solutions of the requests returned in `done` have
+// been written (before the next iteration is launched).
+nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts* o,
+                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired = nullptr);
+// Device bytes one request slot of the handle occupies in a solve of the
+// given precision (engine planes plus the cycle's level buffers).
+size_t request_bytes(const Ctx* c, nmg_precision prec);
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
                                double rtol, int* active, hipStream_t s);

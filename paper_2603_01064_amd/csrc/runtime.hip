@@ -178,9 +178,6 @@ nmg_status ensure_work(Ctx* c) {
         NMG_TRY(dev_alloc(&lb.t1, cnt));
         NMG_TRY(dev_alloc(&lb.t2, cnt));
     }
-    const size_t act = (size_t)B * c->cmax * level_elems(c, 0);
-    NMG_TRY(dev_alloc(&w.act0, act));
-    NMG_TRY(dev_alloc(&w.act1, act));
     // band tables and DCT matrices
     std::vector<double> G, M, D;
     w.g_off.clear();
@@ -253,6 +250,38 @@ nmg_status ensure_work(Ctx* c) {
 template nmg_status ensure_work<float>(Ctx*);
 template nmg_status ensure_work<double>(Ctx*);
 
+// Activation buffers of the direct-convolution smoother (FP32 and FP64
+// cycles, training): cmax channels of the finest level per slot, allocated
+// on first use only, since the BF16 MFMA smoother of mixed-precision cycles
+// keeps its activations in LDS.  Never called inside a graph capture.
+template <typename T>
+nmg_status ensure_acts(Ctx* c) {
+    NMG_TRY(ensure_work<T>(c));
+    Work<T>& w = work_of<T>(c);
+    if (w.act0) return NMG_OK;
+    if (c->capturing) return fail(NMG_ERR_STATE, "smoother buffers must exist before graph capture");
+    const size_t act = (size_t)c->p.max_batch * c->cmax * level_elems(c, 0);
+    NMG_TRY(dev_alloc(&w.act0, act));
+    NMG_TRY(dev_alloc(&w.act1, act));
+    return NMG_OK;
+}
+template nmg_status ensure_acts<float>(Ctx*);
+template nmg_status ensure_acts<double>(Ctx*);
+
+size_t request_bytes(const Ctx* c, nmg_precision prec) {
+    size_t levels = 0;
+    for (int l = 0; l < c->L; ++l) levels += level_elems(c, l);
+    const size_t fine = level_elems(c, 0);
+    // engine: x, b, r in FP64 and x, b in FP32; FP64 level buffers (6 planes)
+    // always (refinement residual), FP32 ones for FP32 / mixed cycles, and the
+    // direct-convolution activations for FP32 / FP64 cycles
+    size_t bytes = fine * (3 * 8 + 2 * 4) + levels * 6 * 8;
+    if (prec != NMG_FP64) bytes += levels * 6 * 4;
+    if (prec == NMG_FP64) bytes += fine * 2 * (size_t)c->cmax * 8;
+    if (prec == NMG_FP32) bytes += fine * 2 * (size_t)c->cmax * 4;
+    return bytes;
+}
+
 namespace {
 
 template <typename T>
@@ -288,6 +317,8 @@ nmg_status check_batch(const Ctx* c, int batch) {
     return NMG_OK;
 }
 
+}  // namespace
+
 nmg_status check_opts(const Ctx* c, const nmg_cycle_opts* o) {
     if (!o) return fail(NMG_ERR_ARG, "null cycle options");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 16) return fail(NMG_ERR_ARG, "nu1/nu2 out of range");
@@ -298,6 +329,8 @@ nmg_status check_opts(const Ctx* c, const nmg_cycle_opts* o) {
     }
     return NMG_OK;
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // The cycle
@@ -397,6 +430,7 @@ template <typename T>
 nmg_status run_cycle(Ctx* c, int batch, const double* alpha, const int* ws, const T* y, T* x, bool x_zero,
                      const nmg_cycle_opts& o, hipStream_t s) {
     NMG_TRY(ensure_work<T>(c));
+    if (o.precision != NMG_MIXED) NMG_TRY(ensure_acts<T>(c));
     CycleArgs<T> a{c, &work_of<T>(c), batch, alpha, ws, o, s};
     return cycle<T>(a, 0, x, y, x_zero);
 }
@@ -536,7 +570,7 @@ struct FidxGuard {
 
 // One step of the serving engine (see nmg_serve_step).
 nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts* o,
-                       std::vector<nmg_request_result>& done, hipStream_t s) {
+                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired) {
     Engine& E = h->eng;
     const int B = h->p.max_batch;
     const size_t per = level_elems(h, 0);
@@ -546,6 +580,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         return fail(NMG_ERR_STATE, "cycle precision changed while requests are active");
     NMG_TRY(ensure_work<double>(h));
     if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
+    if (o->precision == NMG_FP64) NMG_TRY(ensure_acts<double>(h));
+    if (o->precision == NMG_FP32) NMG_TRY(ensure_acts<float>(h));
     if (o->precision == NMG_MIXED && h->p.dim == 2 && o->use_fprime) NMG_TRY(prepare_fprime_bf16(h));
     FidxGuard guard{h};
     double* X64 = h->x64;
@@ -663,6 +699,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             NMG_TRY(launch_scatter_ptrs<float>(nfin, per, X32, h->xptr_dev, d_pairs, s));
         else
             NMG_TRY(launch_scatter_ptrs<double>(nfin, per, X64, h->xptr_dev, d_pairs, s));
+        if (retired) NMG_HIP(hipEventRecord(retired, s));
     }
     // ---- refill the finished slots below nkeep from active slots at or above it
     int nmoves = 0;
@@ -1023,6 +1060,7 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
         if (h->kind[(size_t)level] == 1)
             return launch_jacobi<double>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w64, s);
         NMG_TRY(launch_sumsq<double>(h, batch, per, bb, h->nrm, s));
+        NMG_TRY(ensure_acts<double>(h));
         return launch_conv_smoother<double>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w64, s);
     }
     NMG_TRY(ensure_work<float>(h));
@@ -1032,6 +1070,7 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
         return launch_jacobi<float>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w32b, s);
     NMG_TRY(launch_sumsq<float>(h, batch, per, bb, h->nrm, s));
     if (prec == NMG_MIXED) return launch_mfma_smoother(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
+    NMG_TRY(ensure_acts<float>(h));
     return launch_conv_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
 }
 

@@ -102,6 +102,7 @@ nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, c
     const T* wl = w.wts + (size_t)l * c->p.n_weight_sets * c->wcount;
     const int nl = c->p.n_layers;
     const T* src = b;
+    if (!w.act0 || !w.act1) return fail(NMG_ERR_STATE, "convolution smoother buffers not allocated");
     T* bufs[2] = {w.act0, w.act1};
     for (int i = 0; i < nl; ++i) {
         const int cin = c->p.channels[i], cout = c->p.channels[i + 1];

@@ -523,6 +523,7 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
+    if (!mixed) NMG_TRY(ensure_acts<T>(c));
     const int L = c->L;
     const int nsm = L - 1;
     const int N = c->n[0];
@@ -615,6 +616,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
+    if (!mixed) NMG_TRY(ensure_acts<T>(c));
     NMG_TRY(nmg_prepare(static_cast<nmg_handle>(c), batch, alpha, s));  // coarse factors of these alphas
     const int L = c->L;
     const int nsm = L - 1;

@@ -87,6 +87,14 @@ def load_library():
         "nmg_serve_step": (S, [P, D, I, ctypes.POINTER(_CycleOpts), P, ctypes.POINTER(ctypes.c_int), P]),
         "nmg_serve_pending": (S, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "nmg_serve_reset": (S, [P]),
+        "nmg_request_bytes": (S, [P, I, ctypes.POINTER(ctypes.c_size_t)]),
+        "nmg_pool_create": (S, [ctypes.c_size_t, ctypes.POINTER(P)]),
+        "nmg_pool_destroy": (None, [P]),
+        "nmg_pool_add": (S, [P, P, ctypes.POINTER(ctypes.c_int)]),
+        "nmg_pool_submit": (S, [P, I, ctypes.c_longlong, D, I, P, P]),
+        "nmg_pool_step": (S, [P, D, I, ctypes.POINTER(_CycleOpts), P, P, I, ctypes.POINTER(ctypes.c_int)]),
+        "nmg_pool_pending": (S, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_size_t)]),
         "nmg_profile_query": (S, [P, I, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "nmg_debug_transfer_map": (S, [P, I, I, P, P]),
         "nmg_debug_factor": (S, [P, I, I, P, P]),
@@ -185,6 +193,12 @@ class Handle:
     # -- geometry --------------------------------------------------------
     def level_size(self, level: int) -> int:
         return int(_lib.nmg_level_size(self.ptr, level))
+
+    def request_bytes(self, precision: str = "mixed") -> int:
+        """Device bytes one request slot occupies in a solve of ``precision``."""
+        out = ctypes.c_size_t(0)
+        _check(_lib.nmg_request_bytes(self.ptr, PRECISION[precision], ctypes.byref(out)))
+        return int(out.value)
 
     def alpha_floor(self) -> float:
         """Alphas at or below this value leave the operator indefinite and are rejected."""
@@ -446,3 +460,76 @@ def solve(h: Handle, *args, **kw):
 
 def train_step(h: Handle, *args, **kw):
     return h.train_step(*args, **kw)
+
+
+class Pool:
+    """``nmg_pool``: continuous batching over several handles (one per grid
+    size, say) with admission by a device-memory budget.  Handles stay owned
+    by the caller and must outlive the pool."""
+
+    def __init__(self, hbm_budget_bytes: int):
+        load_library()
+        self.ptr = ctypes.c_void_p()
+        _check(_lib.nmg_pool_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(self.ptr)))
+        self.members = []
+        self._refs = {}
+        self._next_id = 0
+
+    def add(self, handle: Handle) -> int:
+        m = ctypes.c_int(-1)
+        _check(_lib.nmg_pool_add(self.ptr, handle.ptr, ctypes.byref(m)))
+        self.members.append(handle)
+        return m.value
+
+    def submit(self, member: int, b, x, alpha: float, weight_set: int = 0, rid: int | None = None) -> int:
+        """Queues a request for ``member``; ``b``/``x`` are float64 device
+        tensors of that member's grid, kept alive until the request finishes.
+        Synchronises the current stream first, so ``b`` is ready for the
+        pool's own streams."""
+        import torch
+        h = self.members[member]
+        _require(b, torch.float64, h.level_shape(0, 1)[1:], "b")
+        _require(x, torch.float64, h.level_shape(0, 1)[1:], "x")
+        if rid is None:
+            rid = self._next_id
+        self._next_id = max(self._next_id, rid) + 1
+        torch.cuda.current_stream().synchronize()
+        _check(_lib.nmg_pool_submit(self.ptr, int(member), int(rid), float(alpha), int(weight_set), _ptr(b),
+                                    _ptr(x)))
+        self._refs[int(rid)] = (b, x)
+        return int(rid)
+
+    def step(self, rtol: float = 1e-6, max_cycles: int = 100, nu1: int = 1, nu2: int = 1, use_fprime: bool = False,
+             precision: str = "mixed"):
+        """Admission plus one outer iteration of every member with work;
+        returns ``[(member, RequestResult), ...]`` of finished requests."""
+        q, a = self.pending()[:2]
+        cap = max(1, a + q)
+        done = (RequestResult * cap)()
+        dm = (ctypes.c_int * cap)()
+        nd = ctypes.c_int(0)
+        o = _CycleOpts(nu1, nu2, 1 if use_fprime else 0, PRECISION[precision])
+        _check(_lib.nmg_pool_step(self.ptr, float(rtol), int(max_cycles), ctypes.byref(o), done, dm, cap,
+                                  ctypes.byref(nd)))
+        out = [(int(dm[i]), done[i]) for i in range(nd.value)]
+        for _, r in out:
+            self._refs.pop(int(r.id), None)
+        return out
+
+    def pending(self):
+        """``(queued, active, bytes_in_flight)``."""
+        q, a, by = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_size_t(0)
+        _check(_lib.nmg_pool_pending(self.ptr, ctypes.byref(q), ctypes.byref(a), ctypes.byref(by)))
+        return q.value, a.value, by.value
+
+    def close(self) -> None:
+        if self.ptr:
+            _lib.nmg_pool_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+            self._refs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,8 +7,9 @@ while any request is queued or active.  A request's latency is the wall time
 from its arrival to the end of the step that retired it, so it includes the
 time it waited for a free batch slot.
 
-Only scheduling lives here: admission, the iteration and retirement run in
-the HIP library (``nmg_serve_step``).
+Only the arrival clock lives here: admission, the iteration and retirement
+run in the HIP library (``nmg_serve_step`` for one handle, ``nmg_pool_step``
+for a pool of handles of different grid sizes under one memory budget).
 """
 from __future__ import annotations
 
@@ -90,3 +91,38 @@ def serve_serially(solve_one, arrivals, clock=time.perf_counter, sleep=time.slee
         status[i] = st
     wall = (clock() - t0) - float(arrivals[0]) if count else 0.0
     return ServeReport(latency_ms=lat, cycles=cyc, status=status, wall_s=wall, steps=count)
+
+
+def serve_pool_requests(pool, member, b, x, alpha, weight_set, arrivals, *, rtol=1e-6, max_cycles=200, nu1=1,
+                        nu2=1, use_fprime=False, precision="mixed", clock=time.perf_counter,
+                        sleep=time.sleep) -> ServeReport:
+    """As :func:`serve_requests` over a :class:`nmg.Pool`: request ``i`` goes
+    to pool member ``member[i]`` (its grid size) with ``b[i]``/``x[i]`` of
+    that member's shape.  Latency counts from the arrival time."""
+    count = len(arrivals)
+    lat = np.full(count, np.nan)
+    cyc = np.zeros(count, dtype=np.int64)
+    status = np.full(count, -1, dtype=np.int64)
+    finished = nxt = steps = 0
+    t0 = clock()
+    while finished < count:
+        now = clock() - t0
+        while nxt < count and arrivals[nxt] <= now:
+            pool.submit(int(member[nxt]), b[nxt], x[nxt], float(alpha[nxt]), int(weight_set[nxt]), rid=nxt)
+            nxt += 1
+        queued, active, _ = pool.pending()
+        if queued + active == 0:
+            sleep(max(0.0, float(arrivals[nxt]) - (clock() - t0)))
+            continue
+        done = pool.step(rtol=rtol, max_cycles=max_cycles, nu1=nu1, nu2=nu2, use_fprime=use_fprime,
+                         precision=precision)
+        steps += 1
+        t_done = clock() - t0
+        for _, r in done:
+            i = int(r.id)
+            lat[i] = 1e3 * (t_done - float(arrivals[i]))
+            cyc[i] = int(r.cycles)
+            status[i] = int(r.status)
+            finished += 1
+    wall = (clock() - t0) - float(arrivals[0]) if count else 0.0
+    return ServeReport(latency_ms=lat, cycles=cyc, status=status, wall_s=wall, steps=steps)

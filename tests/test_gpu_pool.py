@@ -1,0 +1,129 @@
+"""Serving pool: requests of several grid sizes and alphas in flight
+together, one handle per size, admission by a device-memory budget.  Each
+result is bit-identical to solving that right-hand side alone on its
+handle, and the admitted bytes never exceed the budget."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s0.01.npz")
+
+
+def _nmg():
+    from paper_2603_01064_amd import nmg
+    nmg.load_library()
+    return nmg
+
+
+def _jacobi_handle(nmg, n, s, L, B, alpha_min):
+    H = O.build_hierarchy(n, s, L, dim=2)
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=(1, 4, 4, 1), ksize=3))
+    for l in range(L - 1):
+        A = O.dense_operator(H, l, alpha_min)
+        h.set_jacobi_smoother(l, 1.0 / float(torch.linalg.eigvals(A / torch.diagonal(A)[:, None]).abs().max()))
+    return h
+
+
+def _trained_handle(nmg, B):
+    from paper_2603_01064_amd.train_weights import load_weights
+    meta, sets = load_weights(WEIGHTS)
+    h = nmg.setup_hierarchy(nmg.Problem(n=meta["n"], s=meta["s"], levels=meta["levels"], max_batch=B,
+                                        channels=(1, 32, 32, 1), ksize=3, n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(meta["levels"] - 1):
+            h.load_smoother_weights(l, k, [ws[l]])
+    return h, meta
+
+
+def _rhs(h, n, alpha, seed, dev):
+    u = torch.tensor(inputs.boxes_image(n, seed)[None], device=dev)
+    return h.apply_operator(0, u, torch.tensor([alpha], dtype=DT, device=dev), "fp64")[0].contiguous()
+
+
+def test_pool_mixed_sizes_bit_identical_to_solo():
+    """Twelve requests over three sizes (31 and 63 with damped Jacobi, 255
+    with the trained BF16 smoothers) and mixed alphas, served through a pool
+    with fewer slots than requests: every solution, cycle count and status
+    equals the solo solve on the same handle."""
+    print("case pool 31/63/255 mixed alphas", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    h31 = _jacobi_handle(nmg, 31, 0.04, 3, 3, 0.1)
+    h63 = _jacobi_handle(nmg, 63, 0.04, 4, 3, 0.1)
+    h255, meta = _trained_handle(nmg, 3)
+    handles = [(h31, 31), (h63, 63), (h255, 255)]
+    pool = nmg.Pool(64 << 30)
+    for h, _ in handles:
+        pool.add(h)
+    al_j = [0.1, 0.3, 1.0]
+    al_t = [1e-2, 1e-3, 1e-4]
+    reqs = []
+    for i in range(12):
+        m = i % 3
+        a = (al_t if m == 2 else al_j)[(i // 3) % 3]
+        ws = min(range(3), key=lambda k: abs(math.log(meta["alphas"][k] / a))) if m == 2 else 0
+        b = _rhs(handles[m][0], handles[m][1], a, 2700 + i, dev)
+        reqs.append((m, a, ws, b, torch.zeros_like(b)))
+    for i, (m, a, ws, b, x) in enumerate(reqs):
+        pool.submit(m, b, x, a, ws, rid=i)
+    got = {}
+    kw = dict(rtol=1e-6, max_cycles=300, nu1=1, nu2=1, use_fprime=True, precision="mixed")
+    while len(got) < len(reqs):
+        for m, r in pool.step(**kw):
+            got[int(r.id)] = (m, int(r.status), int(r.cycles))
+    pool.close()
+    for i, (m, a, ws, b, x) in enumerate(reqs):
+        h = handles[m][0]
+        xs, cs, _, st = h.solve(b[None], torch.tensor([a], dtype=DT, device=dev),
+                                weight_set=torch.tensor([ws], dtype=torch.int32, device=dev), **kw)
+        assert got[i][0] == m
+        assert got[i][1] == st and got[i][2] == int(cs[0]), (i, got[i], st, int(cs[0]))
+        assert torch.equal(xs[0], x), i
+    print(f"  cycles {[got[i][2] for i in range(len(reqs))]}", flush=True)
+    for h, _ in handles:
+        h.close()
+
+
+def test_pool_budget_bounds_bytes_in_flight():
+    """A budget of two requests of 63^2 keeps at most two in flight; all
+    eight finish, and a request larger than the budget is refused."""
+    print("case pool budget", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    h63 = _jacobi_handle(nmg, 63, 0.04, 4, 8, 0.1)
+    per = h63.request_bytes("fp32")
+    assert per > 0 and h63.request_bytes("mixed") > 0
+    pool = nmg.Pool(2 * per)
+    pool.add(h63)
+    xs = []
+    for i in range(8):
+        b = _rhs(h63, 63, 0.3, 2800 + i, dev)
+        x = torch.zeros_like(b)
+        xs.append(x)
+        pool.submit(0, b, x, 0.3, rid=i)
+    finished, worst, peak_active = 0, 0, 0
+    while finished < 8:
+        done = pool.step(rtol=1e-6, max_cycles=300, precision="fp32")
+        q, a, by = pool.pending()
+        worst = max(worst, by)
+        peak_active = max(peak_active, a + len(done))
+        finished += len(done)
+        assert all(r.status == 0 for _, r in done)
+    assert worst <= 2 * per and peak_active == 2
+    h255, _ = _trained_handle(nmg, 1)
+    pool.add(h255)
+    b = torch.zeros(255, 255, dtype=DT, device=dev)
+    with pytest.raises(nmg.NMGError):
+        pool.submit(1, b, torch.zeros_like(b), 1e-3, rid=100)
+    pool.close()
+    h63.close()
+    h255.close()
