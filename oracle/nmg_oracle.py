@@ -28,6 +28,9 @@ What the paper fixes and how each piece is pinned (tests marked ``not gpu``):
   linear functions and a dense RAP product.
 * Coarse solve (Algorithm 1, coarsest level): Cholesky of the dense coarse
   matrix.  Pinned against a dense LU solve.
+* Exact fine-level solve for large grids: eigendecomposition of ``G_1``
+  (the Kronecker operator is diagonal in the tensor eigenbasis).  Pinned
+  against a dense solve on small grids.
 * Neural smoother (Algorithm 2 / Algorithm 4 pre-smoothing step):
   ``h = ||b|| N(b / ||b||)`` with a bias-free ReLU CNN.  Pinned by an explicit
   dense convolution matrix and positive homogeneity.
@@ -295,6 +298,29 @@ def coarse_solve(H: Hierarchy, y: torch.Tensor, alpha: torch.Tensor) -> torch.Te
         z = torch.linalg.solve_triangular(Lf, v, upper=False)
         w = torch.linalg.solve_triangular(Lf.T, z, upper=True)
         out[b] = w.reshape(y[b].shape)
+    return out
+
+
+def direct_solve(H: Hierarchy, y: torch.Tensor, alpha: torch.Tensor) -> torch.Tensor:
+    """Exact solution of the finest system ``A_1 x = y`` when ``M_1 = I``.
+
+    ``A_1 = alpha I + G (x) G`` (2D) is diagonalised by ``Q (x) Q`` with
+    ``G = Q diag(lam) Q^T``: ``x = Q [(Q^T Y Q) / (alpha + lam_i lam_j)] Q^T``;
+    in 1D ``x = Q diag(1 / (alpha + lam)) Q^T y``.  One symmetric
+    eigendecomposition of ``n x n`` serves every right-hand side, so this
+    reaches grids far beyond a dense factorisation of ``A_1``.
+    """
+    lv = H.levels[0]
+    if not torch.equal(lv.M, torch.eye(lv.n, dtype=DT)):
+        raise ValueError("direct_solve needs M_1 = I")
+    lam, Q = torch.linalg.eigh(lv.G)
+    out = torch.empty_like(y)
+    for b in range(y.shape[0]):
+        a = float(alpha[b])
+        if H.dim == 1:
+            out[b] = Q @ ((Q.T @ y[b]) / (a + lam))
+        else:
+            out[b] = Q @ ((Q.T @ y[b] @ Q) / (a + lam[:, None] * lam[None, :])) @ Q.T
     return out
 
 

@@ -228,6 +228,21 @@ def test_coarse_mass_factor_is_toeplitz_tridiagonal():
 # --------------------------------------------------------------------------
 
 
+@pytest.mark.parametrize("dim,form", [(1, "normal"), (2, "normal"), (2, "kernel")])
+def test_direct_solve_matches_dense_solve(dim, form):
+    """The eigenbasis solve of the finest system against a dense LU solve."""
+    n, s = 15, 0.06
+    H = O.build_hierarchy(n, s, 2, dim=dim, form=form)
+    alpha = torch.tensor([1e-2, 1e-4], dtype=DT)
+    y = torch.randn((2,) + (n,) * dim, dtype=DT, generator=torch.Generator().manual_seed(25))
+    x = O.direct_solve(H, y, alpha)
+    for b in range(2):
+        ref = torch.linalg.solve(O.dense_operator(H, 0, float(alpha[b])), y[b].reshape(-1))
+        assert float((x[b].reshape(-1) - ref).norm() / ref.norm()) < 1e-11
+    with pytest.raises(ValueError):
+        O.direct_solve(O.build_hierarchy(15, 0.06, 2, dim=1, form="aniso"), y[:, 0], alpha)
+
+
 @pytest.mark.parametrize("alpha", [1e-2, 1e-4])
 def test_coarse_solve_matches_lu(alpha):
     H = O.build_hierarchy(63, 0.04, 3, dim=2)
