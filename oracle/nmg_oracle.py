@@ -37,6 +37,12 @@ What the paper fixes and how each piece is pinned (tests marked ``not gpu``):
 * Filter ``F'_l`` (Sec. 3.2, Algorithm 3; 2D Sec. 3.3, Algorithm 4): ramp mask
   in an orthonormal DCT-II basis on the level grid.  Pinned by orthogonality
   and the closed-form response on single basis vectors.
+* FNO smoother (Sec. 3.1 neural operators; appendix network description):
+  lift, Fourier layers (truncated real DFT, complex mode mixing, "same"
+  convolution, bias, GELU), projection.  Pinned by an explicit DFT-matrix
+  evaluation of the spectral layer, a dense convolution matrix, the
+  closed-form response of a single retained mode, and the erf definition
+  of GELU.
 * Cycle (Algorithms 1, 2, 4): pinned by the residual-driven identity, the
   cycle decomposition identity of Sec. 3.2, the exact-smoother and one-level
   cases, and reduction to a textbook damped-Jacobi V-cycle.
@@ -342,6 +348,76 @@ def cnn_forward(weights: Sequence[torch.Tensor], x: torch.Tensor, dim: int) -> t
         if i + 1 < len(weights):
             z = torch.relu(z)
     return z.squeeze(1)
+
+
+def fno_modes(n: int, k: int) -> int:
+    """Retained Fourier modes per axis on an ``n``-point grid: ``min(k, n // 2)``
+    (in 2D the two retained row blocks ``[0, k)`` and ``[n - k, n)`` stay
+    disjoint)."""
+    return min(k, n // 2)
+
+
+def gelu(x: torch.Tensor) -> torch.Tensor:
+    """GELU with the exact error function, ``x Phi(x)``."""
+    return 0.5 * x * (1.0 + torch.erf(x / math.sqrt(2.0)))
+
+
+def spectral_conv(z: torch.Tensor, R: torch.Tensor, k: int, dim: int) -> torch.Tensor:
+    """``DFT^-1 (R . DFT(z))`` keeping the ``k`` lowest modes per axis (the
+    Fourier layer of the appendix's network description).
+
+    ``z``: ``[B, C, n]`` or ``[B, C, n, n]`` real; the DFT is the real FFT over
+    the grid values.  1D: ``R`` is complex ``[C, C, k]`` and mode ``m < k``
+    maps as ``out[co, m] = sum_ci in[ci, m] R[ci, co, m]``.  2D: ``R`` is
+    complex ``[2, C, C, k, k]`` for the row blocks ``[0, k)`` and
+    ``[n - k, n)`` times columns ``[0, k)`` of the half spectrum.  All other
+    modes are zero."""
+    n = z.shape[-1]
+    if dim == 1:
+        zf = torch.fft.rfft(z, dim=-1)
+        out = torch.zeros_like(zf)
+        out[..., :k] = torch.einsum("bim,iom->bom", zf[..., :k], R)
+        return torch.fft.irfft(out, n=n, dim=-1)
+    zf = torch.fft.rfft2(z, dim=(-2, -1))
+    out = torch.zeros_like(zf)
+    out[..., :k, :k] = torch.einsum("bixy,ioxy->boxy", zf[..., :k, :k], R[0])
+    out[..., n - k:, :k] = torch.einsum("bixy,ioxy->boxy", zf[..., n - k:, :k], R[1])
+    return torch.fft.irfft2(out, s=(n, n), dim=(-2, -1))
+
+
+def fno_forward(params: dict, x: torch.Tensor, dim: int, modes: int) -> torch.Tensor:
+    """Fourier neural operator of the appendix: a pointwise fully connected
+    lift ``1 -> C`` (weight and bias), Fourier layers
+    ``z <- sigma(DFT^-1 R DFT z + W z + B)`` with ``W`` a "same"-padded
+    convolution and ``sigma`` = GELU, then a pointwise projection ``C -> 1``.
+
+    ``params``: ``lift_w [C]``, ``lift_b [C]``, ``layers`` = list of dicts
+    with ``R`` (complex, see :func:`spectral_conv`), ``W [C, C, ks(, ks)]``,
+    ``B [C]``; ``proj_w [C]``, ``proj_b`` (scalar tensor)."""
+    n = x.shape[-1]
+    k = fno_modes(n, modes)
+    shape = (1, -1) + (1,) * dim
+    z = params["lift_w"].reshape(shape) * x.unsqueeze(1) + params["lift_b"].reshape(shape)
+    conv = F.conv1d if dim == 1 else F.conv2d
+    for layer in params["layers"]:
+        R = layer["R"][..., :k] if dim == 1 else layer["R"][..., :k, :k]
+        s = spectral_conv(z, R, k, dim)
+        w = conv(z, layer["W"], bias=layer["B"], padding=layer["W"].shape[-1] // 2)
+        z = gelu(s + w)
+    return (params["proj_w"].reshape(shape) * z).sum(dim=1) + params["proj_b"]
+
+
+def fno_smoother(params: dict, dim: int, modes: int) -> Callable:
+    """``h = ||b|| N(b / ||b||)`` with the FNO as ``N``; zero for ``b = 0``."""
+
+    def apply(H, l, b, alpha):
+        nrm = batch_norm2(b)
+        safe = torch.where(nrm > 0, nrm, torch.ones_like(nrm))
+        shape = (-1,) + (1,) * (b.dim() - 1)
+        out = fno_forward(params, b / safe.reshape(shape), dim, modes) * nrm.reshape(shape)
+        return torch.where(nrm.reshape(shape) > 0, out, torch.zeros_like(out))
+
+    return apply
 
 
 def batch_norm2(b: torch.Tensor) -> torch.Tensor:

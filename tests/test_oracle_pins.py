@@ -619,3 +619,115 @@ def test_adam_matches_library():
         opt.step()
         p, m, v = O.adam_update(p, grad, m, v, step, 1e-3)
         assert torch.allclose(p, q.detach(), rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# FNO smoother (Sec. 3.1; appendix network description)
+# --------------------------------------------------------------------------
+
+
+def test_gelu_matches_erf_definition():
+    x = torch.linspace(-6, 6, 101, dtype=DT)
+    ref = torch.tensor([0.5 * v * (1.0 + math.erf(v / math.sqrt(2.0))) for v in x.tolist()], dtype=DT)
+    assert torch.allclose(O.gelu(x), ref, rtol=0, atol=1e-15)
+
+
+def _rand_complex(shape, seed):
+    g = torch.Generator().manual_seed(seed)
+    return torch.complex(torch.randn(shape, dtype=DT, generator=g), torch.randn(shape, dtype=DT, generator=g))
+
+
+def test_spectral_conv_1d_brute_force():
+    """Explicit DFT sums: X[m] = sum_x z[x] e^{-2 pi i m x / n} for m < k, mode
+    mixing, and the real inverse (1/n)(Re Y[0] + 2 sum_{m>0} Re Y[m] e^{2 pi i m x / n})."""
+    n, C, k = 15, 3, 5
+    z = torch.randn(2, C, n, dtype=DT, generator=torch.Generator().manual_seed(30))
+    R = _rand_complex((C, C, k), 31)
+    got = O.spectral_conv(z, R, k, 1)
+    for b in range(2):
+        X = [[sum(float(z[b, c, x]) * complex(math.cos(-2 * math.pi * m * x / n), math.sin(-2 * math.pi * m * x / n))
+                  for x in range(n)) for m in range(k)] for c in range(C)]
+        for co in range(C):
+            Y = [sum(X[ci][m] * complex(R[ci, co, m]) for ci in range(C)) for m in range(k)]
+            for x in range(n):
+                v = Y[0].real + 2 * sum((Y[m] * complex(math.cos(2 * math.pi * m * x / n),
+                                                        math.sin(2 * math.pi * m * x / n))).real for m in range(1, k))
+                assert abs(float(got[b, co, x]) - v / n) < 1e-12
+
+
+def test_spectral_conv_2d_brute_force():
+    """2D: retained modes rows [0, k) and [n-k, n) x columns [0, k) of the
+    explicit 2D DFT, mixed per mode, inverted along rows (complex) and then
+    along columns as a real half spectrum."""
+    n, C, k = 9, 2, 3
+    z = torch.randn(1, C, n, n, dtype=DT, generator=torch.Generator().manual_seed(32))
+    R = _rand_complex((2, C, C, k, k), 33)
+    got = O.spectral_conv(z, R, k, 2)
+    e = lambda a: complex(math.cos(a), math.sin(a))
+    rows = list(range(k)) + list(range(n - k, n))
+    X = {}
+    for c in range(C):
+        for u in rows:
+            for v in range(k):
+                X[c, u, v] = sum(float(z[0, c, x, y]) * e(-2 * math.pi * (u * x + v * y) / n)
+                                 for x in range(n) for y in range(n))
+    for co in range(C):
+        Y = {(u, v): sum(X[ci, u, v] * complex(R[0 if u < k else 1, ci, co, u if u < k else u - (n - k), v])
+                         for ci in range(C)) for u in rows for v in range(k)}
+        for x in range(n):
+            cv = [sum(Y[u, v] * e(2 * math.pi * u * x / n) for u in rows) / n for v in range(k)]
+            for y in range(n):
+                val = (cv[0].real + 2 * sum((cv[v] * e(2 * math.pi * v * y / n)).real for v in range(1, k))) / n
+                assert abs(float(got[0, co, x, y]) - val) < 1e-12
+
+
+def test_spectral_conv_single_mode_closed_form():
+    """A cosine of frequency m0 < k through mode weight r comes out as
+    Re(r) cos - Im(r) sin at the same frequency; m0 >= k is removed."""
+    n, k = 31, 6
+    x = torch.arange(n, dtype=DT)
+    R = torch.zeros(1, 1, k, dtype=torch.complex128)
+    r = complex(0.7, -1.3)
+    for m0 in (2, 5):
+        R.zero_()
+        R[0, 0, m0] = r
+        z = torch.cos(2 * math.pi * m0 * x / n).reshape(1, 1, n)
+        ref = r.real * torch.cos(2 * math.pi * m0 * x / n) - r.imag * torch.sin(2 * math.pi * m0 * x / n)
+        assert torch.allclose(O.spectral_conv(z, R, k, 1)[0, 0], ref, atol=1e-13)
+    z = torch.cos(2 * math.pi * 9 * x / n).reshape(1, 1, n)
+    R[0, 0, :] = r
+    assert float(O.spectral_conv(z, R, k, 1).abs().max()) < 1e-13
+
+
+def test_fno_forward_1d_brute_force():
+    """Whole FNO on a 7-point grid from pure-Python loops: lift, Fourier
+    layers (DFT sums, mode mixing, real inverse, convolution with bias, GELU)
+    and projection."""
+    n, C, k, ks, nl = 7, 2, 3, 3, 2
+    g = torch.Generator().manual_seed(34)
+    p = {"lift_w": torch.randn(C, dtype=DT, generator=g), "lift_b": torch.randn(C, dtype=DT, generator=g),
+         "proj_w": torch.randn(C, dtype=DT, generator=g), "proj_b": torch.randn((), dtype=DT, generator=g),
+         "layers": [{"R": _rand_complex((C, C, k), 35 + i), "W": torch.randn(C, C, ks, dtype=DT, generator=g),
+                     "B": torch.randn(C, dtype=DT, generator=g)} for i in range(nl)]}
+    xin = torch.randn(1, n, dtype=DT, generator=g)
+    got = O.fno_forward(p, xin, 1, k)
+    gel = lambda v: 0.5 * v * (1.0 + math.erf(v / math.sqrt(2.0)))
+    z = [[float(p["lift_w"][c]) * float(xin[0, x]) + float(p["lift_b"][c]) for x in range(n)] for c in range(C)]
+    for L in p["layers"]:
+        X = [[sum(z[c][x] * complex(math.cos(-2 * math.pi * m * x / n), math.sin(-2 * math.pi * m * x / n))
+                  for x in range(n)) for m in range(k)] for c in range(C)]
+        new = []
+        for co in range(C):
+            Y = [sum(X[ci][m] * complex(L["R"][ci, co, m]) for ci in range(C)) for m in range(k)]
+            row = []
+            for x in range(n):
+                sp = (Y[0].real + 2 * sum((Y[m] * complex(math.cos(2 * math.pi * m * x / n),
+                                                          math.sin(2 * math.pi * m * x / n))).real
+                                          for m in range(1, k))) / n
+                cv = float(L["B"][co]) + sum(float(L["W"][co, ci, t]) * z[ci][x + t - ks // 2]
+                                             for ci in range(C) for t in range(ks) if 0 <= x + t - ks // 2 < n)
+                row.append(gel(sp + cv))
+            new.append(row)
+        z = new
+    ref = [sum(float(p["proj_w"][c]) * z[c][x] for c in range(C)) + float(p["proj_b"]) for x in range(n)]
+    assert torch.allclose(got[0], torch.tensor(ref, dtype=DT), rtol=0, atol=1e-12)
