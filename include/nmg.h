@@ -95,7 +95,37 @@ typedef struct {
     int ksize;                       /* odd convolution kernel size              */
     int n_weight_sets;               /* independent smoother sets per level      */
     int operator_form;               /* nmg_operator_form (0: the default below) */
+    int smoother_arch;               /* nmg_smoother_arch (0: the CNN above)     */
+    int fno_width;                   /* FNO: channels C                          */
+    int fno_layers;                  /* FNO: Fourier layers                      */
+    int fno_modes;                   /* FNO: retained modes per axis, k          */
+    int fno_ksize;                   /* FNO: odd size of the convolution W       */
 } nmg_problem;
+
+/* Smoother network N of h = ||b|| N(b / ||b||).
+ *  NMG_ARCH_CNN : bias-free ReLU CNN of n_layers convolutions (channels,
+ *                 ksize); BF16 MFMA kernels in mixed precision.
+ *  NMG_ARCH_FNO : Fourier neural operator (Sec. 3.1; network description
+ *                 of the appendix): pointwise lift 1 -> C with bias, then
+ *                 fno_layers Fourier layers
+ *                   z <- GELU(DFT^-1 R DFT z + W z + B)
+ *                 with the real DFT of the level's grid values, R complex on
+ *                 the k_l = min(fno_modes, n_l / 2) lowest modes per axis
+ *                 (2D: rows [0, k_l) and [n_l - k_l, n_l) of the half
+ *                 spectrum times columns [0, k_l)), W a same-padded
+ *                 fno_ksize convolution C -> C and B a bias, then a pointwise
+ *                 projection C -> 1 with bias (C <= 256, k <= 128).  Runs in FP32 (also inside
+ *                 mixed-precision cycles) or FP64; not trainable here.
+ *                 Weight block per (level, set), float, in this order:
+ *                   lift_w[C], lift_b[C],
+ *                   per layer: R_re[RM], R_im[RM], W[C][C][ks(][ks)], B[C]
+ *                     with RM = 2*C*C*k*k in 2D ([corner][ci][co][u][v],
+ *                     corner 1 = rows n - k + u) and C*C*k in 1D ([ci][co][v]),
+ *                     k = fno_modes (a level uses the leading k_l x k_l),
+ *                   proj_w[C], proj_b.
+ *                 The CNN fields must still describe a valid CNN (they are
+ *                 ignored). */
+typedef enum { NMG_ARCH_CNN = 0, NMG_ARCH_FNO = 1 } nmg_smoother_arch;
 
 /* Options of one V(nu1, nu2) cycle (Algorithm 1 with the neural smoothing
  * step of Algorithms 2-4; use_fprime enables the filter F'_l of Algorithms 3

@@ -1,0 +1,387 @@
+// Fourier-neural-operator smoother h = ||b|| N(b / ||b||) (Sec. 3.1; the
+// appendix's network description): pointwise lift 1 -> C with bias, Fourier
+// layers z <- GELU(DFT^-1 R DFT z + W z + B), pointwise projection C -> 1.
+//
+// Only the k lowest modes per axis are kept, so the transforms are evaluated
+// as truncated DFT sums instead of full FFTs:
+//   A (columns, 2D and 1D): T[x][j] = sum_y z[x][y] cos(2 pi j y / n) (j < k)
+//                          and -sum_y z[x][y] sin(2 pi (j-k) y / n)   (j >= k)
+//   B (rows, 2D): X[u][v] = sum_x e^{-2 pi i u x / n} T[x][v] for the 2k rows
+//                          u in [0, k) and [n - k, n)
+//   mix:          Y[co] = sum_ci X[ci] R[ci][co] per retained mode
+//   D (rows, 2D): c[x][v] = (1/n) sum_u Y[u][v] e^{+2 pi i u x / n}
+//   E (columns, fused into the layer's output kernel):
+//                 s[x][y] = (1/n) sum_v w_v (Re c_v cos - Im c_v sin)(2 pi v y / n)
+//                 with w_0 = 1 and w_v = 2 (the real inverse of a half spectrum)
+// Twiddles come from one table of cos / sin (2 pi q / n), q < n, per level,
+// indexed by (index product) mod n, so no angle is ever large.
+// Activations are [B][C][ny][n] in the cycle's precision; weights follow the
+// flat block layout documented with nmg_smoother_arch.
+#include <cmath>
+
+#include "nmg_internal.h"
+
+namespace nmg {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+nmg_status falloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return NMG_OK;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(NMG_ERR_OOM, std::string("hipMalloc failed for FNO buffers: ") + hipGetErrorString(e));
+    }
+    return NMG_OK;
+}
+
+template <typename T>
+__device__ inline T gelu(T x) {
+    return (T)0.5 * x * ((T)1 + erf(x * (T)0.70710678118654752440));
+}
+
+struct FnoDims {
+    int C, NL, m, ks, kk, dim;  // m = stored modes
+    size_t rm, layer_stride;
+};
+
+inline FnoDims fno_dims(const Ctx* c) {
+    FnoDims d;
+    d.C = c->p.fno_width;
+    d.NL = c->p.fno_layers;
+    d.m = c->p.fno_modes;
+    d.ks = c->p.fno_ksize;
+    d.dim = c->p.dim;
+    d.kk = d.dim == 2 ? d.ks * d.ks : d.ks;
+    d.rm = d.dim == 2 ? (size_t)2 * d.C * d.C * d.m * d.m : (size_t)d.C * d.C * d.m;
+    d.layer_stride = 2 * d.rm + (size_t)d.C * d.C * d.kk + d.C;
+    return d;
+}
+
+template <typename T>
+__device__ inline const T* set_block(const T* wl, size_t stride, const int* ws, int nsets, int img) {
+    const int set = ws ? min(max(ws[img], 0), nsets - 1) : 0;
+    return wl + (size_t)set * stride;
+}
+
+// z[b][c][p] = lift_w[c] * b[p] / ||b|| + lift_b[c]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_lift(const T* __restrict__ bres, const double* __restrict__ nrm2,
+                                                     T* __restrict__ z, const T* __restrict__ wl, size_t stride,
+                                                     const int* __restrict__ ws, int nsets, int C, size_t per) {
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int img = blockIdx.y;
+    if (p >= per) return;
+    const T* w = set_block(wl, stride, ws, nsets, img);
+    const double q = nrm2[img];
+    const T u = q > 0.0 ? (T)(bres[(size_t)img * per + p] / sqrt(q)) : (T)0;
+    for (int c = 0; c < C; ++c) z[((size_t)img * C + c) * per + p] = w[c] * u + w[C + c];
+}
+
+// step A: one block per row (image, channel, x); thread j < 2k
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_dft_cols(const T* __restrict__ z, T* __restrict__ ta,
+                                                         const T* __restrict__ cs, const T* __restrict__ sn, int n,
+                                                         int k) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* row = reinterpret_cast<T*>(smem_raw);
+    const size_t r = blockIdx.x;
+    for (int y = threadIdx.x; y < n; y += kBlock) row[y] = z[r * n + y];
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j >= 2 * k) return;
+    const int f = j < k ? j : j - k;
+    T acc = 0;
+    int q = 0;  // f * y mod n
+    for (int y = 0; y < n; ++y) {
+        acc += row[y] * (j < k ? cs[q] : -sn[q]);
+        q += f;
+        if (q >= n) q -= n;
+    }
+    ta[r * 2 * k + j] = acc;
+}
+
+// step B (2D): X[img][c][u'][v] (re, im) for u' < 2k, v < k
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_dft_rows(const T* __restrict__ ta, T* __restrict__ xh,
+                                                         const T* __restrict__ cs, const T* __restrict__ sn, int n,
+                                                         int k, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const int v = (int)(e % k);
+    const int up = (int)((e / k) % (2 * k));
+    const size_t bc = e / ((size_t)2 * k * k);
+    const int u = up < k ? up : n - 2 * k + up;
+    const T* t = ta + bc * (size_t)n * 2 * k;
+    T xr = 0, xi = 0;
+    int q = 0;
+    for (int x = 0; x < n; ++x) {
+        const T tr = t[(size_t)x * 2 * k + v], ti = t[(size_t)x * 2 * k + k + v];
+        const T c = cs[q], s = sn[q];
+        xr += c * tr + s * ti;
+        xi += c * ti - s * tr;
+        q += u;
+        if (q >= n) q -= n;
+    }
+    xh[2 * e] = xr;
+    xh[2 * e + 1] = xi;
+}
+
+// 1D: X[v] = T[v] + i T[k + v] laid out as (re, im) pairs
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_interleave(const T* __restrict__ ta, T* __restrict__ xh, int k,
+                                                           size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const size_t bc = e / k;
+    const int v = (int)(e % k);
+    xh[2 * e] = ta[bc * 2 * k + v];
+    xh[2 * e + 1] = ta[bc * 2 * k + k + v];
+}
+
+// mode mixing: Y[img][co][mode] = sum_ci X[img][ci][mode] R[..ci][co][mode]
+//   2D: mode = (u' < 2k, v < k), R index [corner][ci][co][u' mod k][v] with the
+//       stored mode count m as the pitch; 1D: mode = v < k, R index [ci][co][v]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_mix(const T* __restrict__ xh, T* __restrict__ yh,
+                                                    const T* __restrict__ wl, size_t stride, size_t r_off,
+                                                    size_t rm, const int* __restrict__ ws, int nsets, int C, int k,
+                                                    int m, int two_d, size_t modes, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const size_t md = e % modes;
+    const int co = (int)((e / modes) % C);
+    const int img = (int)(e / (modes * C));
+    const T* w = set_block(wl, stride, ws, nsets, img) + r_off;
+    size_t ridx_base, cstride;
+    if (two_d) {
+        const int v = (int)(md % k), up = (int)(md / k);
+        const int corner = up < k ? 0 : 1, u = up < k ? up : up - k;
+        ridx_base = ((size_t)corner * C * C + co) * m * m + (size_t)u * m + v;  // + ci * C * m * m
+        cstride = (size_t)C * m * m;
+    } else {
+        ridx_base = (size_t)co * m + md;  // + ci * C * m
+        cstride = (size_t)C * m;
+    }
+    T yr = 0, yi = 0;
+    for (int ci = 0; ci < C; ++ci) {
+        const size_t xi_ = (((size_t)img * C + ci) * modes + md) * 2;
+        const T ar = xh[xi_], ai = xh[xi_ + 1];
+        const T rr = w[ridx_base + ci * cstride], ri = w[rm + ridx_base + ci * cstride];
+        yr += ar * rr - ai * ri;
+        yi += ar * ri + ai * rr;
+    }
+    yh[2 * e] = yr;
+    yh[2 * e + 1] = yi;
+}
+
+// step D (2D): c[img][co][x][v] = (1/n) sum_u' Y[u'][v] e^{+2 pi i u x / n}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_idft_rows(const T* __restrict__ yh, T* __restrict__ cd,
+                                                          const T* __restrict__ cs, const T* __restrict__ sn, int n,
+                                                          int k, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const int v = (int)(e % k);
+    const int x = (int)((e / k) % n);
+    const size_t bc = e / ((size_t)n * k);
+    const T* y = yh + bc * (size_t)2 * k * k * 2;
+    T cr = 0, ci = 0;
+    for (int up = 0; up < 2 * k; ++up) {
+        const int u = up < k ? up : n - 2 * k + up;
+        const int q = (int)(((long long)u * x) % n);
+        const T c = cs[q], s = sn[q];
+        const T yr = y[((size_t)up * k + v) * 2], yi = y[((size_t)up * k + v) * 2 + 1];
+        cr += yr * c - yi * s;
+        ci += yr * s + yi * c;
+    }
+    const T inv = (T)1 / (T)n;
+    cd[2 * e] = cr * inv;
+    cd[2 * e + 1] = ci * inv;
+}
+
+// Output of one Fourier layer: z1 = GELU(s + W z0 + B) with the spectral part
+// s from step E.  cd holds c[img][co][x][v] (2D) or Y[img][co][v] (1D).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_layer_out(const T* __restrict__ z0, T* __restrict__ z1,
+                                                          const T* __restrict__ cd, const T* __restrict__ wl,
+                                                          size_t stride, size_t w_off, const int* __restrict__ ws,
+                                                          int nsets, const T* __restrict__ cs,
+                                                          const T* __restrict__ sn, int C, int ks, int ny, int n,
+                                                          int k) {
+    const size_t per = (size_t)ny * n;
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int co = blockIdx.y, img = blockIdx.z;
+    if (p >= per) return;
+    const int x = (int)(p / n), y = (int)(p % n);
+    const T* w = set_block(wl, stride, ws, nsets, img) + w_off;
+    const int kh = ny > 1 ? ks : 1, kw = ks;
+    const T* Wc = w + (size_t)co * C * kh * kw;
+    const T bias = w[(size_t)C * C * kh * kw + co];
+    // spectral part
+    const T* c = cd + (((size_t)img * C + co) * ny + x) * (size_t)k * 2;
+    T s = 0;
+    int q = 0;
+    for (int v = 0; v < k; ++v) {
+        const T term = c[2 * v] * cs[q] - c[2 * v + 1] * sn[q];
+        s += v == 0 ? term : (T)2 * term;
+        q += y;
+        if (q >= n) q -= n;
+    }
+    s *= (T)1 / (T)n;
+    // convolution (cross-correlation, zero "same" padding)
+    T acc = 0;
+    const int py = kh / 2, px = kw / 2;
+    for (int ci = 0; ci < C; ++ci) {
+        const T* zc = z0 + ((size_t)img * C + ci) * per;
+        const T* wc = Wc + (size_t)ci * kh * kw;
+        for (int dy = 0; dy < kh; ++dy) {
+            const int yy = x + dy - py;
+            if (yy < 0 || yy >= ny) continue;
+            for (int dx = 0; dx < kw; ++dx) {
+                const int xx = y + dx - px;
+                if (xx < 0 || xx >= n) continue;
+                acc += wc[dy * kw + dx] * zc[(size_t)yy * n + xx];
+            }
+        }
+    }
+    z1[((size_t)img * C + co) * per + p] = gelu(s + acc + bias);
+}
+
+// h = ||b|| (sum_c proj_w[c] z[c] + proj_b), written or accumulated into dst
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_project(const T* __restrict__ z, const double* __restrict__ nrm2,
+                                                        T* __restrict__ dst, const T* __restrict__ wl, size_t stride,
+                                                        size_t p_off, const int* __restrict__ ws, int nsets, int C,
+                                                        size_t per, int accumulate) {
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int img = blockIdx.y;
+    if (p >= per) return;
+    const T* w = set_block(wl, stride, ws, nsets, img) + p_off;
+    const double q = nrm2[img];
+    T h = 0;
+    if (q > 0.0) {
+        T acc = w[C];
+        for (int c = 0; c < C; ++c) acc += w[c] * z[((size_t)img * C + c) * per + p];
+        h = (T)sqrt(q) * acc;
+    }
+    T* o = dst + (size_t)img * per + p;
+    *o = accumulate ? *o + h : h;
+}
+
+}  // namespace
+
+size_t fno_weight_count(const nmg_problem& p) {
+    const size_t C = (size_t)p.fno_width, m = (size_t)p.fno_modes;
+    const size_t kk = p.dim == 2 ? (size_t)p.fno_ksize * p.fno_ksize : (size_t)p.fno_ksize;
+    const size_t rm = p.dim == 2 ? 2 * C * C * m * m : C * C * m;
+    return 2 * C + (size_t)p.fno_layers * (2 * rm + C * C * kk + C) + C + 1;
+}
+
+int fno_level_modes(const Ctx* c, int l) { return std::min(c->p.fno_modes, c->n[(size_t)l] / 2); }
+
+template <typename T>
+nmg_status ensure_fno(Ctx* c) {
+    Work<T>& w = work_of<T>(c);
+    if (w.fno_ready) return NMG_OK;
+    if (c->capturing) return fail(NMG_ERR_STATE, "FNO buffers must exist before graph capture");
+    const size_t B = (size_t)c->p.max_batch, C = (size_t)c->p.fno_width;
+    const size_t per0 = level_elems(c, 0);
+    const size_t ny0 = (size_t)c->ny0, n0 = (size_t)c->n[0];
+    const size_t m = (size_t)std::max(1, fno_level_modes(c, 0));
+    NMG_TRY(falloc(&w.fz0, B * C * per0));
+    NMG_TRY(falloc(&w.fz1, B * C * per0));
+    NMG_TRY(falloc(&w.fta, B * C * ny0 * 2 * m));
+    const size_t modes = c->p.dim == 2 ? 2 * m * m : m;
+    NMG_TRY(falloc(&w.fxh, B * C * modes * 2));
+    NMG_TRY(falloc(&w.fyh, B * C * modes * 2));
+    NMG_TRY(falloc(&w.fcd, B * C * ny0 * m * 2));
+    (void)n0;
+    std::vector<double> tab;
+    w.ftab_off.clear();
+    for (int l = 0; l < c->L; ++l) {
+        const int n = c->n[(size_t)l];
+        w.ftab_off.push_back(tab.size());
+        for (int q = 0; q < n; ++q) tab.push_back(std::cos(2.0 * M_PI * q / n));
+        for (int q = 0; q < n; ++q) tab.push_back(std::sin(2.0 * M_PI * q / n));
+    }
+    NMG_TRY(falloc(&w.ftab, tab.size()));
+    std::vector<T> tabT(tab.begin(), tab.end());
+    NMG_HIP(hipMemcpy(w.ftab, tabT.data(), tabT.size() * sizeof(T), hipMemcpyHostToDevice));
+    w.fno_ready = true;
+    return NMG_OK;
+}
+template nmg_status ensure_fno<float>(Ctx*);
+template nmg_status ensure_fno<double>(Ctx*);
+
+template <typename T>
+nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, const T* b, const double* nrm2, T* dst,
+                               int accumulate, Work<T>& w, hipStream_t s) {
+    if (!w.fno_ready) return fail(NMG_ERR_STATE, "FNO buffers not allocated");
+    const FnoDims d = fno_dims(c);
+    const int n = c->n[(size_t)l];
+    const int ny = d.dim == 2 ? n : 1;
+    const size_t per = (size_t)ny * n;
+    const int k = fno_level_modes(c, l);
+    if (k < 1) return fail(NMG_ERR_SHAPE, "FNO needs at least one mode on every smoothing level");
+    const int nsets = c->p.n_weight_sets;
+    const size_t stride = (size_t)c->wcount;
+    const T* wl = w.wts + (size_t)l * nsets * stride;
+    const T* cs = w.ftab + w.ftab_off[(size_t)l];
+    const T* sn = cs + n;
+    const int C = d.C;
+    hipLaunchKernelGGL(k_fno_lift<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, b, nrm2, w.fz0, wl, stride,
+                       ws, nsets, C, per);
+    T* z0 = w.fz0;
+    T* z1 = w.fz1;
+    const size_t modes = d.dim == 2 ? (size_t)2 * k * k : (size_t)k;
+    for (int layer = 0; layer < d.NL; ++layer) {
+        const size_t base = 2 * (size_t)C + (size_t)layer * d.layer_stride;
+        const size_t rows = (size_t)batch * C * ny;
+        hipLaunchKernelGGL(k_fno_dft_cols<T>, dim3((unsigned)rows), dim3(kBlock), n * sizeof(T), s, z0, w.fta, cs, sn,
+                           n, k);
+        const T* xsrc = w.fta;  // 1D: T[img][c][2k] is (re | -im) of X, re-laid out by the mix below
+        if (d.dim == 2) {
+            const size_t cnt = (size_t)batch * C * 2 * k * k;
+            hipLaunchKernelGGL(k_fno_dft_rows<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fta, w.fxh, cs, sn,
+                               n, k, cnt);
+            xsrc = w.fxh;
+        } else {
+            // interleave (re, im) per mode: X[v] = T[v] + i T[k + v]
+            const size_t cnt = (size_t)batch * C * k;
+            hipLaunchKernelGGL(k_fno_interleave<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fta, w.fxh, k, cnt);
+            xsrc = w.fxh;
+        }
+        const size_t mcnt = (size_t)batch * C * modes;
+        hipLaunchKernelGGL(k_fno_mix<T>, dim3(blocks_for(mcnt)), dim3(kBlock), 0, s, xsrc, w.fyh, wl, stride, base,
+                           d.rm, ws, nsets, C, k, d.m, d.dim == 2 ? 1 : 0, modes, mcnt);
+        const T* cdp = w.fyh;
+        if (d.dim == 2) {
+            const size_t cnt = (size_t)batch * C * n * k;
+            hipLaunchKernelGGL(k_fno_idft_rows<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fyh, w.fcd, cs, sn,
+                               n, k, cnt);
+            cdp = w.fcd;
+        }
+        hipLaunchKernelGGL(k_fno_layer_out<T>, dim3(blocks_for(per), C, batch), dim3(kBlock), 0, s, z0, z1, cdp, wl,
+                           stride, base + 2 * d.rm, ws, nsets, cs, sn, C, d.ks, ny, n, k);
+        std::swap(z0, z1);
+    }
+    const size_t p_off = 2 * (size_t)C + (size_t)d.NL * d.layer_stride;
+    hipLaunchKernelGGL(k_fno_project<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, z0, nrm2, dst, wl, stride,
+                       p_off, ws, nsets, C, per, accumulate);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_fno_smoother<float>(const Ctx*, int, int, const int*, const float*, const double*, float*,
+                                               int, Work<float>&, hipStream_t);
+template nmg_status launch_fno_smoother<double>(const Ctx*, int, int, const int*, const double*, const double*,
+                                                double*, int, Work<double>&, hipStream_t);
+
+}  // namespace nmg

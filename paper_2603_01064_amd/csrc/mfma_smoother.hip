@@ -362,6 +362,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
 
 bool mfma_supported(const Ctx* c, std::string* why) {
     const nmg_problem& p = c->p;
+    if (p.smoother_arch != NMG_ARCH_CNN) {
+        if (why) *why = "BF16 MFMA smoother implements the CNN";
+        return false;
+    }
     if (p.dim != 2 || p.ksize != 3) {
         if (why) *why = "BF16 MFMA smoother supports 2D 3x3 networks only";
         return false;

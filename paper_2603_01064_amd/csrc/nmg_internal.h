@@ -109,6 +109,12 @@ struct Work {
     std::vector<size_t> dct_off;
     T* wts = nullptr;    // smoother weights in this precision [L-1][sets][count]
     std::vector<TiledOp<T>> tiled;
+    // FNO smoother: activations ping-pong [B][C][per0], truncated-DFT
+    // intermediates and per-level cos / sin (2 pi q / n) tables
+    bool fno_ready = false;
+    T *fz0 = nullptr, *fz1 = nullptr, *fta = nullptr, *fxh = nullptr, *fyh = nullptr, *fcd = nullptr;
+    T* ftab = nullptr;
+    std::vector<size_t> ftab_off;
 };
 
 // Serving engine: requests wait in a host queue and are admitted into free
@@ -266,6 +272,14 @@ template <typename T>
 nmg_status ensure_work(Ctx* c);
 template <typename T>
 nmg_status ensure_acts(Ctx* c);
+// FNO smoother (fno.hip)
+size_t fno_weight_count(const nmg_problem& p);
+int fno_level_modes(const Ctx* c, int l);
+template <typename T>
+nmg_status ensure_fno(Ctx* c);
+template <typename T>
+nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, const T* b, const double* nrm2, T* dst,
+                               int accumulate, Work<T>& w, hipStream_t s);
 void release_training(const Ctx* c);
 
 size_t level_elems(const Ctx* c, int l);  // ny_l * n_l

@@ -257,6 +257,7 @@ template nmg_status ensure_work<double>(Ctx*);
 template <typename T>
 nmg_status ensure_acts(Ctx* c) {
     NMG_TRY(ensure_work<T>(c));
+    if (c->p.smoother_arch == NMG_ARCH_FNO) return ensure_fno<T>(c);
     Work<T>& w = work_of<T>(c);
     if (w.act0) return NMG_OK;
     if (c->capturing) return fail(NMG_ERR_STATE, "smoother buffers must exist before graph capture");
@@ -277,8 +278,11 @@ size_t request_bytes(const Ctx* c, nmg_precision prec) {
     // direct-convolution activations for FP32 / FP64 cycles
     size_t bytes = fine * (3 * 8 + 2 * 4) + levels * 6 * 8;
     if (prec != NMG_FP64) bytes += levels * 6 * 4;
-    if (prec == NMG_FP64) bytes += fine * 2 * (size_t)c->cmax * 8;
-    if (prec == NMG_FP32) bytes += fine * 2 * (size_t)c->cmax * 4;
+    const size_t tsize = prec == NMG_FP64 ? 8 : 4;
+    if (c->p.smoother_arch == NMG_ARCH_FNO)
+        bytes += fine * 2 * (size_t)c->p.fno_width * tsize;  // activation ping-pong
+    else if (prec != NMG_MIXED)
+        bytes += fine * 2 * (size_t)c->cmax * tsize;
     return bytes;
 }
 
@@ -296,6 +300,14 @@ void free_work(Ctx* c, Work<T>& w) {
     }
     dev_free(w.act0);
     dev_free(w.act1);
+    dev_free(w.fz0);
+    dev_free(w.fz1);
+    dev_free(w.fta);
+    dev_free(w.fxh);
+    dev_free(w.fyh);
+    dev_free(w.fcd);
+    dev_free(w.ftab);
+    w.fno_ready = false;
     dev_free(w.Gd);
     dev_free(w.Md);
     dev_free(w.dct);
@@ -368,7 +380,9 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
             NMG_TRY(launch_sumsq<T>(c, a.batch, per, bres, c->nrm, a.s));
         }
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
-        if (a.o.precision == NMG_MIXED) {
+        if (c->p.smoother_arch == NMG_ARCH_FNO) {
+            NMG_TRY(launch_fno_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
+        } else if (a.o.precision == NMG_MIXED) {
             NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->nrm,
                                          reinterpret_cast<float*>(target), acc, *reinterpret_cast<Work<float>*>(&w),
                                          a.s));
@@ -430,7 +444,7 @@ template <typename T>
 nmg_status run_cycle(Ctx* c, int batch, const double* alpha, const int* ws, const T* y, T* x, bool x_zero,
                      const nmg_cycle_opts& o, hipStream_t s) {
     NMG_TRY(ensure_work<T>(c));
-    if (o.precision != NMG_MIXED) NMG_TRY(ensure_acts<T>(c));
+    if (o.precision != NMG_MIXED || c->p.smoother_arch == NMG_ARCH_FNO) NMG_TRY(ensure_acts<T>(c));
     CycleArgs<T> a{c, &work_of<T>(c), batch, alpha, ws, o, s};
     return cycle<T>(a, 0, x, y, x_zero);
 }
@@ -581,7 +595,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     NMG_TRY(ensure_work<double>(h));
     if (o->precision != NMG_FP64) NMG_TRY(ensure_work<float>(h));
     if (o->precision == NMG_FP64) NMG_TRY(ensure_acts<double>(h));
-    if (o->precision == NMG_FP32) NMG_TRY(ensure_acts<float>(h));
+    if (o->precision == NMG_FP32 || (o->precision == NMG_MIXED && h->p.smoother_arch == NMG_ARCH_FNO))
+        NMG_TRY(ensure_acts<float>(h));
     if (o->precision == NMG_MIXED && h->p.dim == 2 && o->use_fprime) NMG_TRY(prepare_fprime_bf16(h));
     FidxGuard guard{h};
     double* X64 = h->x64;
@@ -842,6 +857,18 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
         c->wcount += p->channels[i] * p->channels[i + 1] * kk;
         c->cmax = std::max(c->cmax, p->channels[i + 1]);
     }
+    if (p->smoother_arch == NMG_ARCH_FNO) {
+        if (p->fno_width < 1 || p->fno_width > 256 || p->fno_layers < 1 || p->fno_layers > 16 || p->fno_modes < 1 ||
+            p->fno_modes > 128 ||
+            p->fno_ksize < 1 || (p->fno_ksize & 1) == 0 || p->fno_ksize > 15)
+            return fail(NMG_ERR_SHAPE, "FNO width (1..256), layers (1..16), modes (1..128) or ksize (odd, <= 15) out of range");
+        for (int l = 0; l + 1 < c->L; ++l)
+            if (c->n[(size_t)l] / 2 < 1) return fail(NMG_ERR_SHAPE, "FNO needs n >= 2 on every smoothing level");
+        c->wcount = (int)fno_weight_count(*p);
+        c->cmax = 1;
+    } else if (p->smoother_arch != NMG_ARCH_CNN) {
+        return fail(NMG_ERR_SHAPE, "unknown smoother architecture");
+    }
     const int nsm = std::max(1, c->L - 1);
     c->kind.assign((size_t)nsm, -1);
     c->omega.assign((size_t)nsm, 0.0);
@@ -1061,6 +1088,8 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
             return launch_jacobi<double>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w64, s);
         NMG_TRY(launch_sumsq<double>(h, batch, per, bb, h->nrm, s));
         NMG_TRY(ensure_acts<double>(h));
+        if (h->p.smoother_arch == NMG_ARCH_FNO)
+            return launch_fno_smoother<double>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w64, s);
         return launch_conv_smoother<double>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w64, s);
     }
     NMG_TRY(ensure_work<float>(h));
@@ -1069,6 +1098,10 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
     if (h->kind[(size_t)level] == 1)
         return launch_jacobi<float>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w32b, s);
     NMG_TRY(launch_sumsq<float>(h, batch, per, bb, h->nrm, s));
+    if (h->p.smoother_arch == NMG_ARCH_FNO) {
+        NMG_TRY(ensure_acts<float>(h));
+        return launch_fno_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
+    }
     if (prec == NMG_MIXED) return launch_mfma_smoother(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
     NMG_TRY(ensure_acts<float>(h));
     return launch_conv_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);

@@ -716,6 +716,7 @@ namespace {
 nmg_status check_training(nmg_handle h, int set, int batch, nmg_mask_kind mask, nmg_precision prec) {
     if (!h) return fail(NMG_ERR_ARG, "null handle");
     if (h->L < 2) return fail(NMG_ERR_SHAPE, "training needs at least two levels");
+    if (h->p.smoother_arch != NMG_ARCH_CNN) return fail(NMG_ERR_STATE, "training supports the CNN smoother only");
     if (batch < 1 || batch > h->p.max_batch) return fail(NMG_ERR_SHAPE, "batch must be in [1, max_batch]");
     if (set < 0 || set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight_set out of range");
     if (mask != NMG_MASK_BAND && mask != NMG_MASK_RAMP && mask != NMG_LOSS_CYCLE)

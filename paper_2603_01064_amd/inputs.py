@@ -107,3 +107,23 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
 def log_uniform(lo: float, hi: float, count: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+
+
+def fno_params(dim: int, width: int, layers: int, modes: int, ksize: int, seed: int) -> dict:
+    """Seeded FNO parameters (float32-representable float64 arrays): lift and
+    projection ~ N(0, 1) and N(0, 1/C), biases ~ N(0, 0.1^2), spectral
+    weights (re, im) ~ N(0, 1/C^2), convolutions He-normal.  Shapes: R_re /
+    R_im [2][C][C][k][k] (2D) or [C][C][k] (1D), W [C][C][ks](x[ks])."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    C = width
+    rshape = (2, C, C, modes, modes) if dim == 2 else (C, C, modes)
+    out = {"lift_w": f32(rng.standard_normal(C)), "lift_b": f32(0.1 * rng.standard_normal(C)), "layers": []}
+    for _ in range(layers):
+        out["layers"].append({
+            "R_re": f32(rng.standard_normal(rshape) / C), "R_im": f32(rng.standard_normal(rshape) / C),
+            "W": f32(math.sqrt(2.0 / (C * ksize ** dim)) * rng.standard_normal((C, C) + (ksize,) * dim)),
+            "B": f32(0.1 * rng.standard_normal(C))})
+    out["proj_w"] = f32(rng.standard_normal(C) / math.sqrt(C))
+    out["proj_b"] = f32(0.1 * rng.standard_normal(()))
+    return out

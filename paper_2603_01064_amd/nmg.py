@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 from dataclasses import dataclass, field
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -34,7 +34,8 @@ class _Problem(ctypes.Structure):
         ("dim", ctypes.c_int), ("n", ctypes.c_int), ("s", ctypes.c_double), ("trunc", ctypes.c_double),
         ("levels", ctypes.c_int), ("max_batch", ctypes.c_int), ("n_layers", ctypes.c_int),
         ("channels", ctypes.c_int * (MAX_LAYERS + 1)), ("ksize", ctypes.c_int), ("n_weight_sets", ctypes.c_int),
-        ("operator_form", ctypes.c_int),
+        ("operator_form", ctypes.c_int), ("smoother_arch", ctypes.c_int), ("fno_width", ctypes.c_int),
+        ("fno_layers", ctypes.c_int), ("fno_modes", ctypes.c_int), ("fno_ksize", ctypes.c_int),
     ]
 
 
@@ -150,6 +151,7 @@ class Problem:
     ksize: int = 3
     n_weight_sets: int = 1
     operator: str = "normal"   # "normal": alpha I + K^T K; "kernel": alpha I + K; "aniso": alpha D + K (1D)
+    fno: Optional[Tuple[int, int, int, int]] = None   # (width C, Fourier layers, modes k, ksize): FNO smoother
 
     def to_c(self) -> _Problem:
         p = _Problem()
@@ -163,9 +165,16 @@ class Problem:
         if self.operator not in forms:
             raise ValueError(f"operator must be one of {sorted(forms)}, not {self.operator!r}")
         p.operator_form = forms[self.operator]
+        if self.fno is not None:
+            p.smoother_arch = 1
+            p.fno_width, p.fno_layers, p.fno_modes, p.fno_ksize = (int(v) for v in self.fno)
         return p
 
     def weight_count(self) -> int:
+        if self.fno is not None:
+            C, nl, k, ks = self.fno
+            rm = 2 * C * C * k * k if self.dim == 2 else C * C * k
+            return 2 * C + nl * (2 * rm + C * C * ks ** self.dim + C) + C + 1
         kk = self.ksize ** self.dim
         return sum(a * b * kk for a, b in zip(self.channels[:-1], self.channels[1:]))
 

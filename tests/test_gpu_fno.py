@@ -1,0 +1,115 @@
+"""FNO smoother (Sec. 3.1; the appendix's network description) on the GPU
+against the oracle: the smoother on every level in FP64 (1e-12) and FP32
+(1e-5), V-cycles with FNO smoothers, and per-right-hand-side weight sets."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+from paper_2603_01064_amd.fno import pack_fno_weights
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _oracle_params(p):
+    t = lambda a: torch.tensor(np.asarray(a), dtype=DT)
+    return {"lift_w": t(p["lift_w"]), "lift_b": t(p["lift_b"]), "proj_w": t(p["proj_w"]), "proj_b": t(p["proj_b"]),
+            "layers": [{"R": torch.complex(t(L["R_re"]), t(L["R_im"])), "W": t(L["W"]), "B": t(L["B"])}
+                       for L in p["layers"]]}
+
+
+def _setup(dim, n, s, L, arch, B=2, sets=1, seed=7700):
+    from paper_2603_01064_amd import nmg
+    nmg.load_library()
+    C, NL, m, ks = arch
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, dim=dim, max_batch=B, n_weight_sets=sets, fno=arch))
+    params = [[inputs.fno_params(dim, C, NL, m, ks, seed + 100 * k + 10 * l) for l in range(L - 1)]
+              for k in range(sets)]
+    for k in range(sets):
+        for l in range(L - 1):
+            flat = pack_fno_weights(params[k][l])
+            assert flat.size == h.problem.weight_count()
+            h.load_smoother_weights(l, k, [flat])
+    H = O.build_hierarchy(n, s, L, dim=dim)
+    return h, H, params
+
+
+def _rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+@pytest.mark.parametrize("dim,n,s,L,arch", [(2, 63, 0.04, 3, (8, 2, 8, 3)), (2, 31, 0.05, 3, (4, 3, 12, 5)),
+                                            (1, 127, 0.02, 3, (6, 2, 16, 5))])
+def test_fno_smoother_every_level(dim, n, s, L, arch):
+    """Mode counts clamp on the coarse levels (k_l = min(k, n_l / 2))."""
+    print(f"case FNO smoother dim={dim} n={n} arch={arch}", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, params = _setup(dim, n, s, L, arch)
+    g = torch.Generator().manual_seed(50)
+    alpha = torch.tensor([1e-2, 1e-3], dtype=DT)
+    for l in range(L - 1):
+        nl = H.levels[l].n
+        b = torch.randn((2,) + (nl,) * dim, dtype=DT, generator=g)
+        b[1] *= 1e-3  # the network sees b / ||b||; h scales with ||b||
+        ref = O.fno_smoother(_oracle_params(params[0][l]), dim, arch[2])(H, l, b, alpha)
+        got = h.apply_smoother(l, b.to(dev), alpha.to(dev), precision="fp64").cpu()
+        assert _rel(got, ref) < 1e-12, l
+        b32 = b.float().double()
+        ref32 = O.fno_smoother(_oracle_params(params[0][l]), dim, arch[2])(H, l, b32, alpha)
+        got32 = h.apply_smoother(l, b.float().to(dev), alpha.to(dev), precision="fp32").cpu().double()
+        print(f"  level {l} (n={nl}, k={O.fno_modes(nl, arch[2])}): fp32 rel err {_rel(got32, ref32):.2e}",
+              flush=True)
+        assert _rel(got32, ref32) < 1e-5, l
+    zero = torch.zeros((1,) + (H.levels[0].n,) * dim, dtype=DT, device=dev)
+    assert float(h.apply_smoother(0, zero, alpha[:1].to(dev), precision="fp64").abs().max()) == 0.0
+    h.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("mixed", 3e-2)])
+def test_fno_vcycle_matches_oracle(prec, tol):
+    """Three V(1,1)+F' cycles with FNO smoothers on every level against the
+    oracle's cycle.  The FNO runs in FP32 inside mixed-precision cycles, whose
+    F' is the BF16 MFMA filter (its rounding, about 1e-3 here, sets the mixed
+    tolerance)."""
+    print(f"case FNO V-cycle {prec}", flush=True)
+    dev = torch.device("cuda:0")
+    dim, n, s, L, arch = 2, 63, 0.04, 3, (8, 2, 8, 3)
+    h, H, params = _setup(dim, n, s, L, arch)
+    S = [O.fno_smoother(_oracle_params(params[0][l]), dim, arch[2]) for l in range(L - 1)]
+    alpha = torch.tensor([1e-2, 1e-3], dtype=DT)
+    y = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(51))
+    if prec != "fp64":
+        y = y.float().double()
+    x = torch.zeros_like(y)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    xd = x.to(dt).to(dev)
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    for c in range(3):
+        x = O.vcycle(H, S, x, y, alpha, 1, 1, True)
+        h.vcycle(y.to(dt).to(dev), xd, ad, nu1=1, nu2=1, use_fprime=True, precision=prec)
+        d = float(O.apply_operator(H, 0, xd.cpu().double() - x, alpha).norm() / y.norm())
+        print(f"  cycle {c}: ||A (x - x_ref)|| / ||y|| = {d:.2e}", flush=True)
+        assert d < tol
+    h.close()
+
+
+def test_fno_weight_sets_per_rhs():
+    """Each right-hand side picks its own FNO weight set; results equal solo runs."""
+    print("case FNO per-RHS weight sets", flush=True)
+    dev = torch.device("cuda:0")
+    dim, n, s, L, arch = 2, 31, 0.05, 3, (4, 2, 6, 3)
+    h, H, params = _setup(dim, n, s, L, arch, B=2, sets=2)
+    b = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(52)).to(dev)
+    alpha = torch.tensor([1e-2, 1e-2], dtype=DT, device=dev)
+    ws = torch.tensor([1, 0], dtype=torch.int32, device=dev)
+    both = h.apply_smoother(0, b, alpha, weight_set=ws, precision="fp64")
+    for i in range(2):
+        solo = h.apply_smoother(0, b[i:i + 1], alpha[i:i + 1], weight_set=ws[i:i + 1], precision="fp64")
+        assert torch.equal(solo[0], both[i])
+        ref = O.fno_smoother(_oracle_params(params[int(ws[i])][0]), dim, arch[2])(H, 0, b[i:i + 1].cpu(),
+                                                                                   alpha[i:i + 1].cpu())
+        assert _rel(both[i:i + 1].cpu(), ref) < 1e-12
+    h.close()

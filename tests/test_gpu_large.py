@@ -1,0 +1,68 @@
+"""The large mixed-precision solve: 2D, s/h = 10.24 (band radius 80 of G_1
+at the finest level), alpha = 1e-4, CNN 1-32-32-32-1 smoothers, right-hand
+sides b = sum of 500 Gaussian blobs.  The FP64-residual refinement carries
+the BF16/FP32 cycle to a relative error of 1e-10 against the exact solution
+(the oracle's eigenbasis solve), on the 255^2 crop problem (same stencil in
+grid units, s = 0.04) and on the full 2047^2 grid (s = 0.005, 8 levels)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2603_01064_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s10.24h_c4.npz")
+ALPHA = 1e-4
+
+
+def _handle(n, s, L, B):
+    from paper_2603_01064_amd import nmg
+    from paper_2603_01064_amd.train_weights import load_weights
+    nmg.load_library()
+    meta, sets = load_weights(WEIGHTS)
+    k = int(np.argmin([abs(np.log(a / ALPHA)) for a in meta["alphas"]]))
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=tuple(meta["channels"]), ksize=3))
+    deepest = meta["levels"] - 2
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [sets[k][min(l, deepest)]])
+    return h, meta["cycle"]
+
+
+def _solve_and_check(n, s, L, B, seed):
+    dev = torch.device("cuda:0")
+    h, cyc = _handle(n, s, L, B)
+    b = torch.tensor(np.stack([inputs.blobs_image(n, seed + i) for i in range(B)]))
+    alpha = torch.full((B,), ALPHA, dtype=DT)
+    kw = dict(nu1=cyc["nu1"], nu2=cyc["nu2"], use_fprime=cyc["use_fprime"])
+    bd, ad = b.to(dev), alpha.to(dev)
+    for prec in ("mixed", "fp32"):
+        x, cycles, _, st = h.solve(bd, ad, rtol=1e-6, max_cycles=300, precision=prec, **kw)
+        r = bd - h.apply_operator(0, x, ad, "fp64")
+        rel = float((r.flatten(1).norm(dim=1) / bd.flatten(1).norm(dim=1)).max())
+        print(f"  {prec} to 1e-6: status {st}, cycles {list(cycles)}, max residual {rel:.2e}", flush=True)
+        assert st == 0 and rel <= 1e-6
+    x, cycles, hist, st = h.solve(bd, ad, rtol=1e-15, max_cycles=300, precision="mixed", history=True, **kw)
+    h.close()
+    H = O.build_hierarchy(n, s, 1, dim=2)
+    ref = O.direct_solve(H, b, alpha)
+    for i in range(B):
+        err = float((x[i].cpu() - ref[i]).norm() / ref[i].norm())
+        last = hist[i][hist[i] >= 0][-1]
+        print(f"  rhs {i}: cycles {int(cycles[i])}, final residual {last:.2e}, error vs exact {err:.2e}",
+              flush=True)
+        assert err <= 1e-10
+
+
+def test_crop_255_error_1e10():
+    print("case large-solve crop 255x255 s/h=10.24", flush=True)
+    _solve_and_check(255, 0.04, 5, 2, 45000)
+
+
+def test_full_2047_error_1e10():
+    print("case large solve 2047x2047 s/h=10.24, 8 levels", flush=True)
+    _solve_and_check(2047, 0.005, 8, 2, 46000)
