@@ -32,6 +32,7 @@ FLOP_PER_PX = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)  # 19,584: three 3x3 layers
 # output when it accumulates into x (no F')
 PLANE_BYTES = 4 * N * N
 BF16_PEAK_TFLOPS = 2500.0
+FP32_VALU_PEAK_TFLOPS = 78.6  # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 x 2.4 GHz
 WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s0.01.npz")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "smoother_mfma_grid255_b64_pmc.txt")
 SMOOTHER_SRC = os.path.join(ROOT, "paper_2603_01064_amd", "csrc", "mfma_smoother.hip")
@@ -134,6 +135,8 @@ def main(argv=None):
     ap.add_argument("--no-mixed-sizes", action="store_true",
                     help="skip the serving stream over grid sides 64..1024 (needs the s = 2.5h weights)")
     ap.add_argument("--mixed-requests", type=int, default=300, help="requests per arrival rate, mixed sizes")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2047x2047 batch-16 solve")
+    ap.add_argument("--no-fno", action="store_true", help="skip the FNO smoother kernel timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 64 MiB device copy before timing (reference kernel for HBM counters)")
     a = ap.parse_args(argv)
@@ -260,6 +263,12 @@ def main(argv=None):
         log("serving: continuous batching on Poisson arrivals")
         res["serving"] = serving(nmg, h, sets, set_alphas, cyc_cfg, batches[a.warmup:], a.max_cycles,
                                  serial=not a.no_serial_baseline)
+    if not a.no_fno:
+        log("FNO smoother kernel timing (255x255, C=64, 5 layers)")
+        res["fno_smoother"] = fno_smoother_timing(nmg)
+    if not a.no_large and os.path.exists(LARGE_WEIGHTS):
+        log("large solve: 2047x2047, batch 16")
+        res["large_solve"] = large_solve(nmg)
     if not a.no_mixed_sizes and os.path.exists(MIXED_WEIGHTS):
         log("serving: grid sides 64..1024 through one pool")
         res["serving_mixed_sizes"] = mixed_sizes_serving(nmg, count=a.mixed_requests, max_cycles=a.max_cycles)
@@ -391,6 +400,99 @@ def serving(nmg, h, sets, set_alphas, cyc_cfg, batches, max_cycles, rates=(20.0,
             h1.close()
             out[f"poisson_{int(rate)}_per_s"]["serial_fp32"] = srep.summary()
     return out
+
+
+LARGE_WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s10.24h_c4.npz")
+
+
+def large_solve(nmg, batch=16, max_cycles=400):
+    """2047^2 unknowns (2048^2 cells), s = 0.005 (s/h = 10.24, band radius 80
+    of G_1), alpha = 1e-4, CNN 1-32-32-32-1 smoothers, 16 right-hand sides
+    b = sum of 500 Gaussian blobs.  Five levels (2047 -> 127) with the exact
+    eigenbasis solve on 127^2: the smoothers are trained per level at 255^2
+    (s/h = 10.24, 5.12, 2.56, 1.28 on levels 1-4), and a hierarchy down to
+    15^2 would need smoothers for levels the training grid does not have.  Times the batched
+    solve to relative residual 1e-6 in mixed precision and in plain FP32,
+    then the mixed solve continued to 1e-14 (its error against the exact
+    solution is checked by the large-solve tests)."""
+    import torch
+
+    from paper_2603_01064_amd import inputs
+    from paper_2603_01064_amd.train_weights import load_weights
+    dev = torch.device("cuda:0")
+    meta, sets = load_weights(LARGE_WEIGHTS)
+    n, s, L, alpha_v = 2047, 0.005, 5, 1e-4
+    k = meta["alphas"].index(min(meta["alphas"], key=lambda v: abs(math.log(v / alpha_v))))
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=batch, channels=tuple(meta["channels"]),
+                                        ksize=3, n_weight_sets=1))
+    deepest = meta["levels"] - 2
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [sets[k][min(l, deepest)]])
+    cyc = meta["cycle"]
+    b = torch.tensor(np.stack([inputs.blobs_image(n, 44000 + i) for i in range(batch)]), device=dev)
+    alpha = torch.full((batch,), alpha_v, dtype=torch.float64, device=dev)
+    out = {"workload": "2047x2047 unknowns, s=0.005 (s/h=10.24), alpha 1e-4, 5 levels to 127x127 (exact eigenbasis "
+                       "coarse solve), CNN 1-32-32-32-1 3x3, batch 16, b = 500 Gaussian blobs (widths U(2,20) px)",
+           "weights": f"trained at 255^2 with s/h = 10.24 (alpha {meta['alphas'][k]:g}); level l uses trained level "
+                      f"min(l, {deepest})"}
+    x = torch.empty_like(b)
+    kw = dict(nu1=cyc["nu1"], nu2=cyc["nu2"], use_fprime=cyc["use_fprime"])
+    h.solve(b[:1], alpha[:1], rtol=1e-6, max_cycles=max_cycles, precision="mixed", **kw)  # capture, factors
+    # the plain FP32 cycle stalls near 2e-5 on this operator (FP32 residuals of a radius-80 band), so
+    # it runs a bounded number of cycles and reports the residual it reached
+    for prec, rtol, cap in (("mixed", 1e-6, max_cycles), ("fp32", 1e-6, 60), ("mixed", 1e-14, max_cycles)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, cycles, hist, st = h.solve(b, alpha, rtol=rtol, max_cycles=cap, precision=prec, x=x,
+                                      history=True, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = b - h.apply_operator(0, x, alpha, "fp64")
+        rel = (r.flatten(1).norm(dim=1) / b.flatten(1).norm(dim=1)).cpu().numpy()
+        key = f"{prec}_to_{rtol:g}"
+        out[key] = {"seconds": round(dt, 3), "solves_per_s": round(batch / dt, 3), "status": int(st),
+                    "max_cycles": cap,
+                    "cycles_mean": round(float(np.mean(cycles)), 2), "cycles_max": int(np.max(cycles)),
+                    "max_rel_residual_fp64": float(rel.max())}
+        log(f"2047^2 {prec} to {rtol:g}: {dt:.2f} s, cycles {np.mean(cycles):.1f}, max residual {rel.max():.2e}")
+    h.close()
+    return out
+
+
+def fno_smoother_timing(nmg, batch=8, reps=3):
+    """One application of the FNO smoother (the appendix's 2D network for
+    h = 1/256: C = 64, 5 Fourier layers, k = 32 modes, 5x5 convolution) to
+    `batch` right-hand sides of 255^2, FP32, seeded weights (a kernel timing:
+    no trained FNO weights ship).  Algorithmic FLOPs per image: the
+    convolutions 2 C^2 ks^2 n^2 per layer plus lift, projection, the
+    truncated DFTs (4 n^2 2k + 8 n (2k) k per channel and direction) and the
+    mode mixing 8 C^2 (2 k^2)."""
+    import torch
+
+    from paper_2603_01064_amd import inputs
+    from paper_2603_01064_amd.fno import pack_fno_weights
+    dev = torch.device("cuda:0")
+    n, C, NL, k, ks = 255, 64, 5, 32, 5
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=0.01, levels=2, max_batch=batch, fno=(C, NL, k, ks)))
+    h.load_smoother_weights(0, 0, [pack_fno_weights(inputs.fno_params(2, C, NL, k, ks, 47000))])
+    b = torch.randn(batch, n, n, dtype=torch.float32, device=dev)
+    alpha = torch.full((batch,), 1e-3, dtype=torch.float64, device=dev)
+    h.apply_smoother(0, b, alpha, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h.apply_smoother(0, b, alpha, precision="fp32")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    h.close()
+    px = n * n
+    per_layer = 2 * C * C * ks * ks * px + C * (4 * px * 2 * k + 8 * n * 2 * k * k) * 2 + 8 * C * C * 2 * k * k
+    flop = batch * (NL * per_layer + 4 * C * px)
+    tf = flop / dt / 1e12
+    return {"workload": f"FNO smoother, 255x255, C={C}, {NL} Fourier layers, k={k}, ks={ks}, batch {batch}, FP32",
+            "ms_per_application": round(1e3 * dt, 2), "gflop_per_application": round(flop / 1e9, 1),
+            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4)}}
 
 
 MIXED_WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s2.5h.npz")

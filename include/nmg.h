@@ -143,8 +143,13 @@ typedef struct {
  * banded factor G_1 = K^T K, the Galerkin factors M_l, G_l of
  * A_l = alpha M_l (x) M_l + G_l (x) G_l, device copies and workspaces for
  * max_batch right-hand sides.  Synchronises.  *out receives the handle.
- * Errors: NMG_ERR_SHAPE (n not 2^k-1, too many levels, bad channels),
- * NMG_ERR_ARG, NMG_ERR_OOM, NMG_ERR_HIP. */
+ * The exact coarsest solve of Algorithm 1 is a dense FP64 Cholesky factor
+ * per alpha when n_L^dim <= 1024.  In 2D, larger coarsest grids (n_L up to
+ * 511) are solved exactly in the simultaneous eigenbasis V of (M_L, G_L),
+ * computed once on the host: x = V [(V^T y V) / (alpha + lam_i lam_j)] V^T,
+ * four FP64 products per right-hand side and nothing to factor per alpha.
+ * Errors: NMG_ERR_SHAPE (n not 2^k-1, too many levels, coarsest grid too
+ * large, bad channels), NMG_ERR_ARG, NMG_ERR_OOM, NMG_ERR_HIP. */
 nmg_status nmg_setup_hierarchy(const nmg_problem* problem, nmg_handle* out);
 
 /* Frees every device and host resource of the handle (NULL is ignored). */

@@ -150,7 +150,72 @@ __global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restri
     }
 }
 
+// One stage of the eigenbasis coarse solve, a batched n x n product
+//   C[b](i, j) = sum_k A(b, i, k) B(b, k, j)   (FP64 accumulation)
+// with element (b, r, c) of an operand at  ptr[b * sb + r * sr + c * sc]
+// (sb = 0 for the shared basis V), so transposes are stride swaps.  With
+// `lam`, the result is divided by alpha[b] + lam_i lam_j (the diagonal of the
+// coarsest operator in that basis).  16 x 16 output tile per workgroup.
+constexpr int kET = 16;
+
+template <typename TA, typename TB, typename TC>
+__global__ void __launch_bounds__(kET * kET) k_eig_stage(const TA* __restrict__ A, size_t sab, int sar, int sac,
+                                                         const TB* __restrict__ B, size_t sbb, int sbr, int sbc,
+                                                         TC* __restrict__ C, const double* __restrict__ lam,
+                                                         const double* __restrict__ alpha, int n) {
+    __shared__ double ta[kET][kET + 1], tb[kET][kET + 1];
+    const int b = blockIdx.z;
+    const int tiles = (n + kET - 1) / kET;
+    const int i0 = (blockIdx.x / tiles) * kET, j0 = (blockIdx.x % tiles) * kET;
+    const int ti = threadIdx.x / kET, tj = threadIdx.x % kET;
+    const TA* Ab = A + (size_t)b * sab;
+    const TB* Bb = B + (size_t)b * sbb;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += kET) {
+        const int ar = i0 + ti, ak = k0 + tj, bk = k0 + ti, bc = j0 + tj;
+        ta[ti][tj] = (ar < n && ak < n) ? (double)Ab[(size_t)ar * sar + (size_t)ak * sac] : 0.0;
+        tb[ti][tj] = (bk < n && bc < n) ? (double)Bb[(size_t)bk * sbr + (size_t)bc * sbc] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kET; ++k) acc += ta[ti][k] * tb[k][tj];
+        __syncthreads();
+    }
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= n || j >= n) return;
+    if (lam) acc /= alpha[b] + lam[i] * lam[j];
+    C[(size_t)b * n * n + (size_t)i * n + j] = (TC)acc;
+}
+
 }  // namespace
+
+// x = V [(V^T y V) / (alpha + lam_i lam_j)] V^T per right-hand side: four
+// batched products through the FP64 stage scratch.
+template <typename T>
+nmg_status launch_eig_coarse(const Ctx* c, int batch, const double* alpha, const T* y, T* x, hipStream_t s) {
+    const int n = c->n[(size_t)c->L - 1];
+    const size_t nn = (size_t)n * n;
+    const int tiles = (n + kET - 1) / kET;
+    const dim3 grid(tiles * tiles, 1, batch), block(kET * kET);
+    double* T1 = c->eigT;
+    double* T2 = c->eigT + (size_t)c->p.max_batch * nn;
+    const double* V = c->eigV;
+    // T1 = V^T y
+    hipLaunchKernelGGL((k_eig_stage<double, T, double>), grid, block, 0, s, V, (size_t)0, 1, n, y, nn, n, 1, T1,
+                       (const double*)nullptr, alpha, n);
+    // T2 = (T1 V) / (alpha + lam lam)
+    hipLaunchKernelGGL((k_eig_stage<double, double, double>), grid, block, 0, s, T1, nn, n, 1, V, (size_t)0, n, 1,
+                       T2, c->eigLam, alpha, n);
+    // T1 = V T2
+    hipLaunchKernelGGL((k_eig_stage<double, double, double>), grid, block, 0, s, V, (size_t)0, n, 1, T2, nn, n, 1,
+                       T1, (const double*)nullptr, alpha, n);
+    // x = T1 V^T
+    hipLaunchKernelGGL((k_eig_stage<double, double, T>), grid, block, 0, s, T1, nn, n, 1, V, (size_t)0, 1, n, x,
+                       (const double*)nullptr, alpha, n);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_eig_coarse<float>(const Ctx*, int, const double*, const float*, float*, hipStream_t);
+template nmg_status launch_eig_coarse<double>(const Ctx*, int, const double*, const double*, double*, hipStream_t);
 
 nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_t s) {
     const int N = c->nc;

@@ -255,6 +255,73 @@ __global__ void __launch_bounds__(kBlock) k_fno_layer_out(const T* __restrict__ 
     z1[((size_t)img * C + co) * per + p] = gelu(s + acc + bias);
 }
 
+// 2D Fourier-layer output on a 16 x 16 pixel tile for TCO output channels:
+// the input tile plus a ks/2 halo is staged in LDS a few input channels at a
+// time; each thread owns one pixel and TCO accumulators, and the weights of
+// a (channel, tap) step are uniform across the workgroup, so they are read
+// through scalar loads and used as scalar operands of the FMAs.
+constexpr int kFT = 16;   // tile side
+constexpr int kFCI = 8;   // input channels staged per step
+
+template <typename T, int TCO>
+__global__ void __launch_bounds__(kFT * kFT) k_fno_layer_out_tiled(
+    const T* __restrict__ z0, T* __restrict__ z1, const T* __restrict__ cd, const T* __restrict__ wl, size_t stride,
+    size_t w_off, const int* __restrict__ ws, int nsets, const T* __restrict__ cs, const T* __restrict__ sn, int C,
+    int ks, int n, int k, int tiles_x) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const int img = blockIdx.z, co0 = blockIdx.y * TCO;
+    const int ty0 = (blockIdx.x / tiles_x) * kFT, tx0 = (blockIdx.x % tiles_x) * kFT;
+    const int tid = threadIdx.x, ly = tid / kFT, lx = tid % kFT;
+    const int x = ty0 + ly, y = tx0 + lx;  // x: row, y: column (as in the oracle's [row][col])
+    const int r = ks / 2, S = kFT + 2 * r, kk = ks * ks;
+    const size_t per = (size_t)n * n;
+    const T* w = set_block(wl, stride, ws, nsets, img) + w_off;
+    T acc[TCO];
+#pragma unroll
+    for (int j = 0; j < TCO; ++j) acc[j] = 0;
+    for (int c0 = 0; c0 < C; c0 += kFCI) {
+        const int cn = min(kFCI, C - c0);
+        __syncthreads();
+        for (int e = tid; e < cn * S * S; e += kFT * kFT) {
+            const int cc = e / (S * S), rem = e % (S * S), sy = rem / S, sx = rem % S;
+            const int gx = ty0 - r + sy, gy = tx0 - r + sx;
+            tile[e] = (gx >= 0 && gx < n && gy >= 0 && gy < n)
+                          ? z0[((size_t)img * C + c0 + cc) * per + (size_t)gx * n + gy]
+                          : (T)0;
+        }
+        __syncthreads();
+        for (int cc = 0; cc < cn; ++cc) {
+            const T* tp = tile + cc * S * S + ly * S + lx;
+            const T* wc = w + (size_t)co0 * C * kk + (size_t)(c0 + cc) * kk;
+            for (int dy = 0; dy < ks; ++dy)
+                for (int dx = 0; dx < ks; ++dx) {
+                    const T v = tp[dy * S + dx];
+                    const int t = dy * ks + dx;
+#pragma unroll
+                    for (int j = 0; j < TCO; ++j) acc[j] += wc[(size_t)j * C * kk + t] * v;
+                }
+        }
+    }
+    if (x >= n || y >= n) return;
+    const T inv = (T)1 / (T)n;
+    const T* bias = w + (size_t)C * C * kk;
+#pragma unroll
+    for (int j = 0; j < TCO; ++j) {
+        const int co = co0 + j;
+        const T* c = cd + (((size_t)img * C + co) * n + x) * (size_t)k * 2;
+        T sp = 0;
+        int q = 0;
+        for (int v = 0; v < k; ++v) {
+            const T term = c[2 * v] * cs[q] - c[2 * v + 1] * sn[q];
+            sp += v == 0 ? term : (T)2 * term;
+            q += y;
+            if (q >= n) q -= n;
+        }
+        z1[((size_t)img * C + co) * per + (size_t)x * n + y] = gelu(sp * inv + acc[j] + bias[co]);
+    }
+}
+
 // h = ||b|| (sum_c proj_w[c] z[c] + proj_b), written or accumulated into dst
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fno_project(const T* __restrict__ z, const double* __restrict__ nrm2,
@@ -369,8 +436,16 @@ nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, co
                                n, k, cnt);
             cdp = w.fcd;
         }
-        hipLaunchKernelGGL(k_fno_layer_out<T>, dim3(blocks_for(per), C, batch), dim3(kBlock), 0, s, z0, z1, cdp, wl,
-                           stride, base + 2 * d.rm, ws, nsets, cs, sn, C, d.ks, ny, n, k);
+        if (d.dim == 2 && C % 16 == 0) {
+            const int tiles_x = (n + kFT - 1) / kFT;
+            const int S = kFT + 2 * (d.ks / 2);
+            hipLaunchKernelGGL((k_fno_layer_out_tiled<T, 16>), dim3(tiles_x * tiles_x, C / 16, batch),
+                               dim3(kFT * kFT), (size_t)kFCI * S * S * sizeof(T), s, z0, z1, cdp, wl, stride,
+                               base + 2 * d.rm, ws, nsets, cs, sn, C, d.ks, n, k, tiles_x);
+        } else {
+            hipLaunchKernelGGL(k_fno_layer_out<T>, dim3(blocks_for(per), C, batch), dim3(kBlock), 0, s, z0, z1, cdp,
+                               wl, stride, base + 2 * d.rm, ws, nsets, cs, sn, C, d.ks, ny, n, k);
+        }
         std::swap(z0, z1);
     }
     const size_t p_off = 2 * (size_t)C + (size_t)d.NL * d.layer_stride;

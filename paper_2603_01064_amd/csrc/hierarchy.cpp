@@ -198,6 +198,92 @@ double alpha_floor_of(const Band& M, const Band& G, int dim) {
     return -gmin * okm;  // okm at or above lambda_max
 }
 
+// Simultaneous diagonalisation of the coarsest level's factors for an exact
+// solve of alpha M (x) M + G (x) G at any alpha: with M = L L^T (Cholesky) and
+// L^-1 G L^-T = Q diag(lam) Q^T (cyclic Jacobi rotations), V = L^-T Q gives
+// V^T M V = I and V^T G V = diag(lam), so the 2D operator becomes diagonal,
+// alpha + lam_i lam_j, in the basis V (x) V.  V is row-major n x n.
+bool coarse_eigenbasis(const Band& M, const Band& G, std::vector<double>& V, std::vector<double>& lam,
+                       std::string& err) {
+    const int n = M.n;
+    std::vector<double> Lc((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = M.get(i, j);
+            for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * n + k] * Lc[(size_t)j * n + k];
+            if (i == j) {
+                if (!(v > 0.0)) {
+                    err = "coarsest mass factor is not positive definite";
+                    return false;
+                }
+                Lc[(size_t)i * n + i] = std::sqrt(v);
+            } else {
+                Lc[(size_t)i * n + j] = v / Lc[(size_t)j * n + j];
+            }
+        }
+    // S = L^-1 G L^-T: W = L^-1 G by forward substitution on columns, S = L^-1 W^T (W^T = G L^-T)
+    std::vector<double> W((size_t)n * n), S((size_t)n * n);
+    for (int col = 0; col < n; ++col)
+        for (int i = 0; i < n; ++i) {
+            double v = G.get(i, col);
+            for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * n + k] * W[(size_t)k * n + col];
+            W[(size_t)i * n + col] = v / Lc[(size_t)i * n + i];
+        }
+    for (int col = 0; col < n; ++col)
+        for (int i = 0; i < n; ++i) {
+            double v = W[(size_t)col * n + i];  // (W^T)[i][col]
+            for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * n + k] * S[(size_t)k * n + col];
+            S[(size_t)i * n + col] = v / Lc[(size_t)i * n + i];
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) S[(size_t)i * n + j] = S[(size_t)j * n + i] = 0.5 * (S[(size_t)i * n + j] + S[(size_t)j * n + i]);
+    // cyclic Jacobi: S <- J^T S J until the off-diagonal part is negligible
+    std::vector<double> Q((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    double scale = 0.0;
+    for (double v : S) scale += v * v;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += 2.0 * S[(size_t)i * n + j] * S[(size_t)i * n + j];
+        if (off <= 1e-30 * scale) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = S[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double theta = (S[(size_t)q * n + q] - S[(size_t)p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double skp = S[(size_t)k * n + p], skq = S[(size_t)k * n + q];
+                    S[(size_t)k * n + p] = c * skp - sn * skq;
+                    S[(size_t)k * n + q] = sn * skp + c * skq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double spk = S[(size_t)p * n + k], sqk = S[(size_t)q * n + k];
+                    S[(size_t)p * n + k] = c * spk - sn * sqk;
+                    S[(size_t)q * n + k] = sn * spk + c * sqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+                    Q[(size_t)k * n + p] = c * qkp - sn * qkq;
+                    Q[(size_t)k * n + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    lam.assign((size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) lam[(size_t)i] = S[(size_t)i * n + i];
+    // V = L^-T Q by back substitution, column by column
+    V.assign((size_t)n * n, 0.0);
+    for (int col = 0; col < n; ++col)
+        for (int i = n - 1; i >= 0; --i) {
+            double v = Q[(size_t)i * n + col];
+            for (int k = i + 1; k < n; ++k) v -= Lc[(size_t)k * n + i] * V[(size_t)k * n + col];
+            V[(size_t)i * n + col] = v / Lc[(size_t)i * n + i];
+        }
+    return true;
+}
+
 bool build_host_hierarchy(int n, double s, double trunc, int levels, int dim, int form, std::vector<HostLevel>& out,
                           int* taps_radius, double* alpha_floor, std::string& err) {
     if (form != NMG_OP_NORMAL && form != NMG_OP_KERNEL && form != NMG_OP_ANISO) {

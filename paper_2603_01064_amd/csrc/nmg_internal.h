@@ -187,6 +187,12 @@ struct Ctx {
     double* cinv = nullptr;            // [max_batch][nc][nc] A_L^{-1} (FP32 / mixed cycles)
     double* cwork = nullptr;           // [max_batch][nc][nc] L^{-1} scratch
     int* flags = nullptr;              // [max_batch] non-SPD / non-finite flags per new factor
+    // coarsest grids beyond the dense factor (2D, n_L^2 > 1024): exact solve in
+    // the simultaneous eigenbasis V of (M_L, G_L), any alpha, no factors
+    bool eig_coarse = false;
+    double* eigV = nullptr;            // [n_L][n_L] row-major
+    double* eigLam = nullptr;          // [n_L]
+    double* eigT = nullptr;            // [2][max_batch][n_L][n_L] stage scratch
     double* alpha_prepared = nullptr;  // [max_batch] alphas of the factors being computed
     int* slot_dev = nullptr;           // [max_batch] cache slots of the factors being computed
     int* coarse_idx = nullptr;         // [max_batch] cache slot of each right-hand side
@@ -321,6 +327,10 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, fl
                               float* t2, hipStream_t s);
 nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
 nmg_status launch_coarse_factor(Ctx* c, int count, const double* alphas, const int* slots, hipStream_t s);
+bool coarse_eigenbasis(const Band& M, const Band& G, std::vector<double>& V, std::vector<double>& lam,
+                       std::string& err);
+template <typename T>
+nmg_status launch_eig_coarse(const Ctx* c, int batch, const double* alpha, const T* y, T* x, hipStream_t s);
 nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_t s);
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);

@@ -411,6 +411,7 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
     Work<T>& w = *a.w;
     if (l == c->L - 1) {
         ProfScope ps(c, a.s, NMG_K_COARSE, l);
+        if (c->eig_coarse) return launch_eig_coarse<T>(c, a.batch, a.alpha, y, x, a.s);
         if (a.o.precision == NMG_FP64) return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
         return launch_coarse_apply_inverse<T>(c, a.batch, y, x, a.s);
     }
@@ -474,6 +475,10 @@ nmg_status check_alpha(const Ctx* h, double a, int slot) {
 nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>& idx, hipStream_t s) {
     const int n = (int)al.size();
     for (int b = 0; b < n; ++b) NMG_TRY(check_alpha(h, al[(size_t)b], b));
+    if (h->eig_coarse) {  // the eigenbasis solve takes alpha directly: nothing to factor
+        idx.assign((size_t)n, 0);
+        return NMG_OK;
+    }
     const long long stamp = ++h->prepare_count;
     const int slots = (int)h->cache_alpha.size();
     for (const auto& sl : h->eng.slot) h->cache_used[(size_t)sl.fidx] = stamp;
@@ -847,7 +852,12 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     c->ny0 = p->dim == 2 ? p->n : 1;
     const int nl = c->n.back();
     c->nc = p->dim == 2 ? nl * nl : nl;
-    if (c->nc > 1024) return fail(NMG_ERR_SHAPE, "coarsest grid too large for the dense Cholesky (n_L^dim > 1024)");
+    if (c->nc > 1024) {
+        if (p->dim != 2 || nl > 511)
+            return fail(NMG_ERR_SHAPE, "coarsest grid too large (dense factor up to 1024 unknowns; in 2D the "
+                                       "eigenbasis solve up to 511^2)");
+        c->eig_coarse = true;
+    }
     // smoother layout
     const int kk = p->dim == 2 ? p->ksize * p->ksize : p->ksize;
     c->wcount = 0;
@@ -898,10 +908,20 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->Gc, Gc.size()));
     NMG_TRY(upload(c->Mc, Mc));
     NMG_TRY(upload(c->Gc, Gc));
-    NMG_TRY(dev_alloc(&c->chol, (size_t)B * c->nc * c->nc));
-    NMG_TRY(dev_alloc(&c->cholT, (size_t)B * c->nc * c->nc));
-    NMG_TRY(dev_alloc(&c->cinv, (size_t)B * c->nc * c->nc));
-    NMG_TRY(dev_alloc(&c->cwork, (size_t)B * c->nc * c->nc));
+    if (c->eig_coarse) {
+        std::vector<double> V, lam;
+        if (!coarse_eigenbasis(hc.M, hc.G, V, lam, err)) return fail(NMG_ERR_NOT_SPD, err);
+        NMG_TRY(dev_alloc(&c->eigV, V.size()));
+        NMG_TRY(dev_alloc(&c->eigLam, lam.size()));
+        NMG_TRY(upload(c->eigV, V));
+        NMG_TRY(upload(c->eigLam, lam));
+        NMG_TRY(dev_alloc(&c->eigT, (size_t)2 * B * nl * nl));
+    } else {
+        NMG_TRY(dev_alloc(&c->chol, (size_t)B * c->nc * c->nc));
+        NMG_TRY(dev_alloc(&c->cholT, (size_t)B * c->nc * c->nc));
+        NMG_TRY(dev_alloc(&c->cinv, (size_t)B * c->nc * c->nc));
+        NMG_TRY(dev_alloc(&c->cwork, (size_t)B * c->nc * c->nc));
+    }
     NMG_TRY(dev_alloc(&c->flags, (size_t)B));
     NMG_TRY(dev_alloc(&c->alpha_prepared, (size_t)B));
     NMG_TRY(dev_alloc(&c->slot_dev, (size_t)B));
@@ -960,6 +980,9 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->cholT);
     dev_free(c->cinv);
     dev_free(c->cwork);
+    dev_free(c->eigV);
+    dev_free(c->eigLam);
+    dev_free(c->eigT);
     dev_free(c->flags);
     dev_free(c->alpha_prepared);
     dev_free(c->slot_dev);

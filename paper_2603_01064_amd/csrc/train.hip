@@ -629,6 +629,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
     NMG_HIP(hipMemcpyAsync(ws_dev, wsv.data(), (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
     LevelBuffers<T>& coarse = work.lv[(size_t)nsm];
     auto coarse_solve = [&](const T* y, T* x) -> nmg_status {
+        if (c->eig_coarse) return launch_eig_coarse<T>(c, batch, alpha, y, x, s);
         if (std::is_same<T, double>::value) return launch_coarse_solve<T>(c, batch, y, x, s);
         return launch_coarse_apply_inverse<T>(c, batch, y, x, s);
     };

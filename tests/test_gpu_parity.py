@@ -451,3 +451,42 @@ def test_solve_fp64_history_matches_oracle_and_dense_solution():
                 assert abs(hist[b, k] - float(hr[b])) <= 1e-9 * float(hr[b]) + 1e-14
     dense = torch.linalg.solve(O.dense_operator(H, 0, alpha_v), y.reshape(2, -1).T).T.reshape(y.shape)
     assert _rel(x.cpu(), dense) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# Exact coarsest solve in the eigenbasis (coarsest grids above 1024 unknowns)
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n,s,L", [(63, 0.04, 1), (255, 0.04, 3), (127, 0.03, 2)])
+def test_eigenbasis_coarse_solve(n, s, L):
+    """Coarsest grids of 63^2 and 127^2 unknowns take the eigenbasis solve: the
+    one-level case against the oracle's dense Cholesky solve, and FP64 neural
+    V-cycles against the oracle's cycle, alphas 1e-2 / 1e-4 in one batch."""
+    print(f"case eigenbasis coarse n={n} L={L}", flush=True)
+    dev = _dev()
+    alpha = torch.tensor([1e-2, 1e-4], dtype=DT)
+    ch = (1, 8, 8, 1)
+    W = _weights(ch, 3, 2, L) if L > 1 else None
+    h = _handle(n, s, L, B=2, channels=ch, W=W)
+    H = O.build_hierarchy(n, s, L, dim=2)
+    y = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(53))
+    ad = alpha.to(dev)
+    h.prepare(ad)
+    if L == 1:
+        ref = O.coarse_solve(H, y, alpha)
+        x = torch.zeros_like(y).to(dev)
+        h.vcycle(y.to(dev), x, ad, precision="fp64")
+        assert _rel(x.cpu(), ref) < 1e-11
+        x32 = torch.zeros(2, n, n, dtype=torch.float32, device=dev)
+        h.vcycle(y.float().to(dev), x32, ad, precision="fp32")
+        assert _rel(x32.cpu().double(), O.coarse_solve(H, y.float().double(), alpha)) < 1e-5
+    else:
+        S = [O.neural_smoother(w, 2) for w in W]
+        x = torch.zeros_like(y)
+        xd = x.clone().to(dev)
+        for _ in range(2):
+            x = O.vcycle(H, S, x, y, alpha, 1, 1, True)
+            h.vcycle(y.to(dev), xd, ad, nu1=1, nu2=1, use_fprime=True, precision="fp64")
+        assert _rel(xd.cpu(), x) < 1e-11
+    h.close()
