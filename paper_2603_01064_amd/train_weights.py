@@ -201,6 +201,7 @@ def main(argv=None):
     ap.add_argument("--init", default=None, help="npz written by this script; its last set initialises training")
     ap.add_argument("--fprime", action="store_true", help="train with F' in the loss (eq. loss_2_modified)")
     ap.add_argument("--steps-per-alpha", type=int, nargs="+", default=None)
+    ap.add_argument("--eval-max-cycles", type=int, default=100, help="cycle limit of the post-training evaluation")
     ap.add_argument("--operator", default="normal", choices=["normal", "kernel"],
                     help="fine operator: alpha I + K^T K (normal) or alpha I (x) I + K (x) K (kernel)")
     a = ap.parse_args(argv)
@@ -225,7 +226,7 @@ def main(argv=None):
                   use_fprime=a.fprime)
         sets.append([h.get_smoother_weights(l) for l in range(L - 1)])
         for nu in ((1, 1), (2, 0), (1, 0)):
-            cyc, st = evaluate(h, av, min(16, a.batch), nu[0], nu[1], a.fprime)
+            cyc, st = evaluate(h, av, min(16, a.batch), nu[0], nu[1], a.fprime, a.eval_max_cycles)
             if cyc is None:
                 print(f"  eval alpha={av:g} V{nu} fprime={a.fprime}: {st}", flush=True)
             else:
