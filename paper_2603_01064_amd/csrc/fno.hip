@@ -18,6 +18,7 @@
 // Activations are [B][C][ny][n] in the cycle's precision; weights follow the
 // flat block layout documented with nmg_smoother_arch.
 #include <cmath>
+#include <type_traits>
 
 #include "nmg_internal.h"
 
@@ -182,6 +183,84 @@ __global__ void __launch_bounds__(kBlock) k_fno_mix(const T* __restrict__ xh, T*
     yh[2 * e + 1] = yi;
 }
 
+// C[M x N] = A[M x K] B[K x N], row-major, 64 x 64 output tile per workgroup,
+// 4 x 4 outputs per thread, K staged 16 at a time in LDS.  Used for the
+// column transforms, whose twiddles form a dense [n x 2k] (forward) or
+// [2k x n] (inverse) matrix per level.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gemm_rm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
+                                                 int M, int N, int K) {
+    __shared__ T As[16][64 + 1], Bs[16][64 + 1];
+    const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+    const size_t m0 = (size_t)blockIdx.x * 64;
+    const int n0 = blockIdx.y * 64;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int kk = e % 16, mm = e / 16;  // A tile: 64 rows x 16 columns
+            const size_t gm = m0 + mm;
+            As[kk][mm] = (gm < (size_t)M && k0 + kk < K) ? A[gm * K + k0 + kk] : (T)0;
+            const int kb = e / 64, nn = e % 64;  // B tile: 16 rows x 64 columns
+            Bs[kb][nn] = (k0 + kb < K && n0 + nn < N) ? B[(size_t)(k0 + kb) * N + n0 + nn] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const size_t gm = m0 + tr * 4 + i;
+        if (gm >= (size_t)M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gn = n0 + tc * 4 + j;
+            if (gn < N) C[gm * N + gn] = acc[i][j];
+        }
+    }
+}
+
+// step D (2D) in split layout for the GEMM inverse: cd[row][v] = Re c_v and
+// cd[row][k + v] = Im c_v with c_v(x) = (1/n) sum_u' Y[u'][v] e^{+2 pi i u x / n}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_idft_rows_split(const T* __restrict__ yh, T* __restrict__ cd,
+                                                                const T* __restrict__ cs, const T* __restrict__ sn,
+                                                                int n, int k, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const int v = (int)(e % k);
+    const size_t row = e / k;  // (img, co, x)
+    const int x = (int)(row % n);
+    const size_t bc = row / n;
+    const T* y = yh + bc * (size_t)2 * k * k * 2;
+    T cr = 0, ci = 0;
+    for (int up = 0; up < 2 * k; ++up) {
+        const int u = up < k ? up : n - 2 * k + up;
+        const int q = (int)(((long long)u * x) % n);
+        const T c = cs[q], s = sn[q];
+        const T yr = y[((size_t)up * k + v) * 2], yi = y[((size_t)up * k + v) * 2 + 1];
+        cr += yr * c - yi * s;
+        ci += yr * s + yi * c;
+    }
+    const T inv = (T)1 / (T)n;
+    cd[row * 2 * k + v] = cr * inv;
+    cd[row * 2 * k + k + v] = ci * inv;
+}
+
 // step D (2D): c[img][co][x][v] = (1/n) sum_u' Y[u'][v] e^{+2 pi i u x / n}
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fno_idft_rows(const T* __restrict__ yh, T* __restrict__ cd,
@@ -322,6 +401,82 @@ __global__ void __launch_bounds__(kFT * kFT) k_fno_layer_out_tiled(
     }
 }
 
+// The same layer output with a 32 x 32 pixel tile and 2 x 2 pixels per
+// thread (compile-time kernel size KS): per staged input channel and kernel
+// row, a thread loads the KS + 1 input values of each of its two rows once
+// and reuses them across the KS taps, its two columns and TCO channels.
+constexpr int kFT2 = 32;
+
+template <typename T, int TCO, int KS, int CI>
+__global__ void __launch_bounds__(256) k_fno_layer_out_t2(
+    const T* __restrict__ z0, T* __restrict__ z1, const T* __restrict__ sp_plane, const T* __restrict__ wl,
+    size_t stride, size_t w_off, const int* __restrict__ ws, int nsets, int C, int n, int tiles_x) {
+    constexpr int R = KS / 2, S = kFT2 + 2 * R, KK = KS * KS;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const int img = blockIdx.z, co0 = blockIdx.y * TCO;
+    const int ty0 = (blockIdx.x / tiles_x) * kFT2, tx0 = (blockIdx.x % tiles_x) * kFT2;
+    const int tid = threadIdx.x, ly = tid / 16, lx = tid % 16;
+    const size_t per = (size_t)n * n;
+    const T* w = set_block(wl, stride, ws, nsets, img) + w_off;
+    T acc[2][2][TCO];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int j = 0; j < TCO; ++j) acc[a][b][j] = 0;
+    for (int c0 = 0; c0 < C; c0 += CI) {
+        const int cn = min(CI, C - c0);
+        __syncthreads();
+        for (int e = tid; e < cn * S * S; e += 256) {
+            const int cc = e / (S * S), rem = e % (S * S), sy = rem / S, sx = rem % S;
+            const int gx = ty0 - R + sy, gy = tx0 - R + sx;
+            tile[e] = (gx >= 0 && gx < n && gy >= 0 && gy < n)
+                          ? z0[((size_t)img * C + c0 + cc) * per + (size_t)gx * n + gy]
+                          : (T)0;
+        }
+        __syncthreads();
+        for (int cc = 0; cc < cn; ++cc) {
+            const T* wc = w + (size_t)co0 * C * KK + (size_t)(c0 + cc) * KK;
+#pragma unroll
+            for (int dy = 0; dy < KS; ++dy) {
+                T in[2][KS + 1];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int t = 0; t <= KS; ++t) in[a][t] = tile[cc * S * S + (2 * ly + a + dy) * S + 2 * lx + t];
+#pragma unroll
+                for (int dx = 0; dx < KS; ++dx)
+#pragma unroll
+                    for (int j = 0; j < TCO; ++j) {
+                        const T wv = wc[(size_t)j * C * KK + dy * KS + dx];
+                        acc[0][0][j] += wv * in[0][dx];
+                        acc[0][1][j] += wv * in[0][dx + 1];
+                        acc[1][0][j] += wv * in[1][dx];
+                        acc[1][1][j] += wv * in[1][dx + 1];
+                    }
+            }
+        }
+    }
+    const T* bias = w + (size_t)C * C * KK;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int x = ty0 + 2 * ly + a;
+        if (x >= n) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int y = tx0 + 2 * lx + b;
+            if (y >= n) continue;
+#pragma unroll
+            for (int j = 0; j < TCO; ++j) {
+                const size_t o = ((size_t)img * C + co0 + j) * per + (size_t)x * n + y;
+                z1[o] = gelu(sp_plane[o] + acc[a][b][j] + bias[co0 + j]);
+            }
+        }
+    }
+}
+
 // h = ||b|| (sum_c proj_w[c] z[c] + proj_b), written or accumulated into dst
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fno_project(const T* __restrict__ z, const double* __restrict__ nrm2,
@@ -370,6 +525,7 @@ nmg_status ensure_fno(Ctx* c) {
     NMG_TRY(falloc(&w.fxh, B * C * modes * 2));
     NMG_TRY(falloc(&w.fyh, B * C * modes * 2));
     NMG_TRY(falloc(&w.fcd, B * C * ny0 * m * 2));
+    NMG_TRY(falloc(&w.fsp, B * C * per0));
     (void)n0;
     std::vector<double> tab;
     w.ftab_off.clear();
@@ -382,6 +538,31 @@ nmg_status ensure_fno(Ctx* c) {
     NMG_TRY(falloc(&w.ftab, tab.size()));
     std::vector<T> tabT(tab.begin(), tab.end());
     NMG_HIP(hipMemcpy(w.ftab, tabT.data(), tabT.size() * sizeof(T), hipMemcpyHostToDevice));
+    // dense twiddle matrices of the column transforms per level:
+    //   forward [n][2k]: cos(2 pi j y / n) | -sin(2 pi j y / n)
+    //   inverse [2k][n]: w_j cos(2 pi j y / n) / n ; -w_j sin(2 pi j y / n) / n  (w_0 = 1, w_j = 2)
+    std::vector<T> mats;
+    w.fmat_off.clear();
+    for (int l = 0; l < c->L; ++l) {
+        const int n = c->n[(size_t)l];
+        const int k = std::max(1, fno_level_modes(c, l));
+        w.fmat_off.push_back(mats.size());
+        for (int y = 0; y < n; ++y)
+            for (int j = 0; j < 2 * k; ++j) {
+                const int f = j < k ? j : j - k;
+                const double a = 2.0 * M_PI * (double)(((long long)f * y) % n) / n;
+                mats.push_back((T)(j < k ? std::cos(a) : -std::sin(a)));
+            }
+        for (int j = 0; j < 2 * k; ++j)
+            for (int y = 0; y < n; ++y) {
+                const int f = j < k ? j : j - k;
+                const double wgt = (f == 0 ? 1.0 : 2.0) / n;
+                const double a = 2.0 * M_PI * (double)(((long long)f * y) % n) / n;
+                mats.push_back((T)(j < k ? wgt * std::cos(a) : -wgt * std::sin(a)));
+            }
+    }
+    NMG_TRY(falloc(&w.fmat, mats.size()));
+    NMG_HIP(hipMemcpy(w.fmat, mats.data(), mats.size() * sizeof(T), hipMemcpyHostToDevice));
     w.fno_ready = true;
     return NMG_OK;
 }
@@ -412,8 +593,10 @@ nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, co
     for (int layer = 0; layer < d.NL; ++layer) {
         const size_t base = 2 * (size_t)C + (size_t)layer * d.layer_stride;
         const size_t rows = (size_t)batch * C * ny;
-        hipLaunchKernelGGL(k_fno_dft_cols<T>, dim3((unsigned)rows), dim3(kBlock), n * sizeof(T), s, z0, w.fta, cs, sn,
-                           n, k);
+        const T* fwd = w.fmat + w.fmat_off[(size_t)l];
+        const T* inv_m = fwd + (size_t)n * 2 * k;
+        hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((2 * k + 63) / 64)), dim3(256),
+                           0, s, z0, fwd, w.fta, (int)rows, 2 * k, n);
         const T* xsrc = w.fta;  // 1D: T[img][c][2k] is (re | -im) of X, re-laid out by the mix below
         if (d.dim == 2) {
             const size_t cnt = (size_t)batch * C * 2 * k * k;
@@ -430,13 +613,38 @@ nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, co
         hipLaunchKernelGGL(k_fno_mix<T>, dim3(blocks_for(mcnt)), dim3(kBlock), 0, s, xsrc, w.fyh, wl, stride, base,
                            d.rm, ws, nsets, C, k, d.m, d.dim == 2 ? 1 : 0, modes, mcnt);
         const T* cdp = w.fyh;
-        if (d.dim == 2) {
+        const bool t2 = d.dim == 2 && C % 16 == 0 && (d.ks == 3 || d.ks == 5 || d.ks == 7);
+        if (t2) {
+            // inverse rows in split layout, then the inverse columns as one GEMM into the spectral plane
+            const size_t cnt = (size_t)batch * C * n * k;
+            hipLaunchKernelGGL(k_fno_idft_rows_split<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fyh, w.fcd, cs,
+                               sn, n, k, cnt);
+            hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((n + 63) / 64)),
+                               dim3(256), 0, s, w.fcd, inv_m, w.fsp, (int)rows, n, 2 * k);
+        } else if (d.dim == 2) {
             const size_t cnt = (size_t)batch * C * n * k;
             hipLaunchKernelGGL(k_fno_idft_rows<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fyh, w.fcd, cs, sn,
                                n, k, cnt);
             cdp = w.fcd;
         }
-        if (d.dim == 2 && C % 16 == 0) {
+        bool done = false;
+        if (t2) {
+            const int tiles_x = (n + kFT2 - 1) / kFT2;
+            constexpr int CI = sizeof(T) == 4 ? 8 : 4;
+            auto go = [&](auto ks_tag) {
+                constexpr int KS = decltype(ks_tag)::value;
+                constexpr int S = kFT2 + 2 * (KS / 2);
+                hipLaunchKernelGGL((k_fno_layer_out_t2<T, 16, KS, CI>), dim3(tiles_x * tiles_x, C / 16, batch),
+                                   dim3(256), (size_t)CI * S * S * sizeof(T), s, z0, z1, w.fsp, wl, stride,
+                                   base + 2 * d.rm, ws, nsets, C, n, tiles_x);
+            };
+            if (d.ks == 3) go(std::integral_constant<int, 3>{});
+            if (d.ks == 5) go(std::integral_constant<int, 5>{});
+            if (d.ks == 7) go(std::integral_constant<int, 7>{});
+            done = true;
+        }
+        if (done) {
+        } else if (d.dim == 2 && C % 16 == 0) {
             const int tiles_x = (n + kFT - 1) / kFT;
             const int S = kFT + 2 * (d.ks / 2);
             hipLaunchKernelGGL((k_fno_layer_out_tiled<T, 16>), dim3(tiles_x * tiles_x, C / 16, batch),

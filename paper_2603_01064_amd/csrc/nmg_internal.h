@@ -115,6 +115,9 @@ struct Work {
     T *fz0 = nullptr, *fz1 = nullptr, *fta = nullptr, *fxh = nullptr, *fyh = nullptr, *fcd = nullptr;
     T* ftab = nullptr;
     std::vector<size_t> ftab_off;
+    T* fsp = nullptr;             // spectral part of a layer's output [B][C][per0]
+    T* fmat = nullptr;            // per level dense column-transform matrices
+    std::vector<size_t> fmat_off;
 };
 
 // Serving engine: requests wait in a host queue and are admitted into free

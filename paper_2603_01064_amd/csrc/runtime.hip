@@ -307,6 +307,8 @@ void free_work(Ctx* c, Work<T>& w) {
     dev_free(w.fyh);
     dev_free(w.fcd);
     dev_free(w.ftab);
+    dev_free(w.fsp);
+    dev_free(w.fmat);
     w.fno_ready = false;
     dev_free(w.Gd);
     dev_free(w.Md);

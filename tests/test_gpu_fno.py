@@ -41,11 +41,15 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dim,n,s,L,arch", [(2, 63, 0.04, 3, (8, 2, 8, 3)), (2, 31, 0.05, 3, (4, 3, 12, 5)),
-                                            (1, 127, 0.02, 3, (6, 2, 16, 5)), (2, 63, 0.04, 3, (32, 2, 8, 5))])
+                                            (1, 127, 0.02, 3, (6, 2, 16, 5)), (2, 63, 0.04, 3, (32, 2, 8, 5)),
+                                            (2, 63, 0.04, 3, (16, 2, 6, 3)), (2, 63, 0.04, 3, (16, 1, 6, 7)),
+                                            (2, 31, 0.05, 3, (16, 1, 4, 9))])
 def test_fno_smoother_every_level(dim, n, s, L, arch):
-    """Mode counts clamp on the coarse levels (k_l = min(k, n_l / 2)); widths
-    that are multiples of 16 run the LDS-tiled 2D layer kernel (ragged
-    16 x 16 tiles at 63 and 31)."""
+    """Mode counts clamp on the coarse levels (k_l = min(k, n_l / 2)).  Widths
+    that are multiples of 16 run the LDS-tiled 2D layer kernels: 32 x 32
+    tiles with 2 x 2 pixels per thread for 3 x 3, 5 x 5 and 7 x 7
+    convolutions, 16 x 16 tiles otherwise (9 x 9 here); the tiles are ragged
+    at 63 and 31."""
     print(f"case FNO smoother dim={dim} n={n} arch={arch}", flush=True)
     dev = torch.device("cuda:0")
     h, H, params = _setup(dim, n, s, L, arch)
