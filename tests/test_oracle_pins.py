@@ -731,3 +731,27 @@ def test_fno_forward_1d_brute_force():
         z = new
     ref = [sum(float(p["proj_w"][c]) * z[c][x] for c in range(C)) + float(p["proj_b"]) for x in range(n)]
     assert torch.allclose(got[0], torch.tensor(ref, dtype=DT), rtol=0, atol=1e-12)
+
+
+def test_jacobi_reduction_matches_paper_printed_values():
+    """Sec. 2.2 prints the weighted-Jacobi (omega = 1/2) reduction factors of the
+    lowest and highest frequency modes of the periodic tridiag(-1, 2+alpha, -1);
+    the fixture holds those expressions evaluated at four alphas.  Brute force:
+    the error propagation S = I - omega D^-1 A applied to the constant and the
+    alternating vector."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "jacobi_reduction_sec2_2.txt")
+    rows = [list(map(float, ln.split())) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 4
+    n, omega = 16, 0.5
+    for alpha, red_low, red_high in rows:
+        A = (2 + alpha) * torch.eye(n, dtype=DT)
+        for i in range(n):
+            A[i, (i + 1) % n] = A[i, (i - 1) % n] = -1.0
+        S = torch.eye(n, dtype=DT) - omega * A / (2 + alpha)
+        smooth = torch.ones(n, dtype=DT)
+        osc = torch.tensor([(-1.0) ** j for j in range(n)], dtype=DT)
+        mu_low = float((S @ smooth)[0] / smooth[0])
+        mu_high = float((S @ osc)[0] / osc[0])
+        assert abs((1 - mu_low) - red_low) < 1e-15
+        assert abs((1 - mu_high) - red_high) < 1e-15
