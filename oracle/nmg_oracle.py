@@ -615,7 +615,8 @@ def solve(H: Hierarchy, smoothers: Sequence[Callable], y: torch.Tensor, alpha: t
 
 
 def level_losses(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e: torch.Tensor,
-                 alpha: torch.Tensor, mask_kind: str = "ramp", use_fprime: bool = False):
+                 alpha: torch.Tensor, mask_kind: str = "ramp", use_fprime: bool = False,
+                 make_smoother: Optional[Callable] = None):
     """Per-level losses ``L_l`` for a batch of true solutions ``e`` (``y = A e``).
 
     The cycle runs once from zero with pre-smoothing only.  For level ``l``
@@ -634,7 +635,8 @@ def level_losses(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e: tor
     losses = []
     for l in range(H.L - 1):
         b = yl.detach()  # x* = 0 at every level of a cycle started from zero
-        h = neural_smoother(weights[l], H.dim)(H, l, b, alpha)
+        sm = make_smoother(weights[l]) if make_smoother else neural_smoother(weights[l], H.dim)
+        h = sm(H, l, b, alpha)
         err = e - resolved - prolong_to_finest(H, l, h)
         m = loss_mask(N, l + 1, mask_kind, H.dim)
         losses.append(((m * dct_forward(err, C, H.dim)) ** 2).sum() / Nb)
@@ -653,6 +655,37 @@ def level_loss_grads(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e:
     total = sum(losses)
     total.backward()
     grads = [[w.grad.detach().clone() for w in lw] for lw in ws]
+    return torch.stack([x.detach() for x in losses]), grads
+
+
+def fno_from_real(p: dict) -> dict:
+    """FNO parameters with the spectral weights as real and imaginary parts
+    (``R_re``, ``R_im``, as the library stores them) turned into the complex
+    ``R`` of :func:`fno_forward`; autograd flows to the real parts."""
+    return {"lift_w": p["lift_w"], "lift_b": p["lift_b"], "proj_w": p["proj_w"], "proj_b": p["proj_b"],
+            "layers": [{"R": torch.complex(L["R_re"], L["R_im"]), "W": L["W"], "B": L["B"]} for L in p["layers"]]}
+
+
+def fno_level_loss_grads(H: Hierarchy, params: Sequence[dict], e: torch.Tensor, alpha: torch.Tensor, modes: int,
+                         mask_kind: str = "ramp", use_fprime: bool = False):
+    """Level-wise losses with FNO smoothers and ``dL_l/dtheta_l`` for every
+    real parameter tensor of level ``l`` (same keys as ``params[l]``)."""
+    leaves = []
+
+    def leaf(t):
+        t = t.detach().clone().requires_grad_(True)
+        leaves.append(t)
+        return t
+
+    ps = [{"lift_w": leaf(p["lift_w"]), "lift_b": leaf(p["lift_b"]), "proj_w": leaf(p["proj_w"]),
+           "proj_b": leaf(p["proj_b"]),
+           "layers": [{k: leaf(L[k]) for k in ("R_re", "R_im", "W", "B")} for L in p["layers"]]} for p in params]
+    losses = level_losses(H, ps, e, alpha, mask_kind, use_fprime,
+                          make_smoother=lambda p: fno_smoother(fno_from_real(p), H.dim, modes))
+    sum(losses).backward()
+    grads = [{"lift_w": p["lift_w"].grad, "lift_b": p["lift_b"].grad, "proj_w": p["proj_w"].grad,
+              "proj_b": p["proj_b"].grad,
+              "layers": [{k: L[k].grad for k in ("R_re", "R_im", "W", "B")} for L in p["layers"]]} for p in ps]
     return torch.stack([x.detach() for x in losses]), grads
 
 

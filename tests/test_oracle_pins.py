@@ -755,3 +755,38 @@ def test_jacobi_reduction_matches_paper_printed_values():
         mu_high = float((S @ osc)[0] / osc[0])
         assert abs((1 - mu_low) - red_low) < 1e-15
         assert abs((1 - mu_high) - red_high) < 1e-15
+
+
+def test_fno_level_loss_gradient_central_differences():
+    """Level-wise loss with FNO smoothers: the autograd gradient of every
+    parameter kind (lift, spectral re/im, convolution, bias, projection)
+    against central differences."""
+    n, s, L, dim = 15, 0.08, 2, 2
+    H = O.build_hierarchy(n, s, L, dim=dim)
+    C, NL, m, ks = 3, 2, 3, 3
+    p = {k: (torch.tensor(v) if not isinstance(v, list) else v)
+         for k, v in inputs.fno_params(dim, C, NL, m, ks, 60).items()}
+    p["layers"] = [{k: torch.tensor(v) for k, v in Ly.items()} for Ly in p["layers"]]
+    e = torch.randn(2, n, n, dtype=DT, generator=torch.Generator().manual_seed(61))
+    a = torch.tensor([1e-2, 1e-3], dtype=DT)
+    losses, grads = O.fno_level_loss_grads(H, [p], e, a, m, "ramp", True)
+    rng = np.random.default_rng(3)
+    eps = 1e-6
+
+    def loss_with(path, idx, delta):
+        q = {"lift_w": p["lift_w"].clone(), "lift_b": p["lift_b"].clone(), "proj_w": p["proj_w"].clone(),
+             "proj_b": p["proj_b"].clone(), "layers": [{k: v.clone() for k, v in Ly.items()} for Ly in p["layers"]]}
+        t = q[path[0]] if len(path) == 1 else q["layers"][path[1]][path[2]]
+        t.reshape(-1)[idx] += delta
+        return float(O.level_losses(H, [q], e, a, "ramp", True,
+                                    make_smoother=lambda w: O.fno_smoother(O.fno_from_real(w), dim, m))[0])
+
+    paths = [("lift_w",), ("lift_b",), ("proj_w",), ("proj_b",)] + \
+        [("layers", i, k) for i in range(NL) for k in ("R_re", "R_im", "W", "B")]
+    for path in paths:
+        g = grads[0][path[0]] if len(path) == 1 else grads[0]["layers"][path[1]][path[2]]
+        for _ in range(2):
+            idx = int(rng.integers(0, g.numel()))
+            fd = (loss_with(path, idx, eps) - loss_with(path, idx, -eps)) / (2 * eps)
+            gv = float(g.reshape(-1)[idx])
+            assert abs(fd - gv) <= 1e-6 * max(1.0, abs(gv)), (path, idx, fd, gv)
