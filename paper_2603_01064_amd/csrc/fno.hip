@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_fno_mix(const T* __restrict__ xh, T*
 // [2k x n] (inverse) matrix per level.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gemm_rm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
-                                                 int M, int N, int K) {
+                                                 int M, int N, int K, int transB = 0) {
     __shared__ T As[16][64 + 1], Bs[16][64 + 1];
     const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
     const size_t m0 = (size_t)blockIdx.x * 64;
@@ -205,7 +205,9 @@ __global__ void __launch_bounds__(256) k_gemm_rm(const T* __restrict__ A, const 
             const size_t gm = m0 + mm;
             As[kk][mm] = (gm < (size_t)M && k0 + kk < K) ? A[gm * K + k0 + kk] : (T)0;
             const int kb = e / 64, nn = e % 64;  // B tile: 16 rows x 64 columns
-            Bs[kb][nn] = (k0 + kb < K && n0 + nn < N) ? B[(size_t)(k0 + kb) * N + n0 + nn] : (T)0;
+            Bs[kb][nn] = (k0 + kb < K && n0 + nn < N)
+                             ? (transB ? B[(size_t)(n0 + nn) * K + k0 + kb] : B[(size_t)(k0 + kb) * N + n0 + nn])
+                             : (T)0;
         }
         __syncthreads();
 #pragma unroll
@@ -498,6 +500,304 @@ __global__ void __launch_bounds__(kBlock) k_fno_project(const T* __restrict__ z,
     *o = accumulate ? *o + h : h;
 }
 
+
+// ---------------------------------------------------------------------------
+// Training: forward with stored activations, and the hand-written adjoint of
+// the FNO for the level-wise loss (weights only; the smoother input b_l is a
+// constant of level l's loss).  Every transform of a Fourier layer is a real
+// linear map, so its adjoint is the transposed map:
+//   forward  Z -> TA = Z Fc -> X (rows) -> Y = mix(X, R) -> CDs (inverse rows,
+//            split re | im) -> S = CDs Finv;  pre = S + W * Z + B;  Z' = GELU(pre)
+//   adjoint  gS = gPre -> gCDs = gS Finv^T -> gY -> (gX, dR) -> gTA -> gZ += gTA Fc^T
+//            plus the transposed convolution, dW and dB.
+// ---------------------------------------------------------------------------
+
+// 1D: interleaved (re, im) pairs -> split layout (re block | im block); the
+// adjoint of k_fno_interleave
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_deinterleave(const T* __restrict__ xi, T* __restrict__ sp, int k,
+                                                             size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const size_t bc = e / k;
+    const int v = (int)(e % k);
+    sp[bc * 2 * k + v] = xi[2 * e];
+    sp[bc * 2 * k + k + v] = xi[2 * e + 1];
+}
+
+// pre = S + W * z + B and z' = GELU(pre) (any dim; direct convolution)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_pre(const T* __restrict__ z0, const T* __restrict__ sp_plane,
+                                                    T* __restrict__ pre, T* __restrict__ z1, const T* __restrict__ wl,
+                                                    size_t stride, size_t w_off, const int* __restrict__ ws, int nsets,
+                                                    int C, int ks, int ny, int n) {
+    const size_t per = (size_t)ny * n;
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int co = blockIdx.y, img = blockIdx.z;
+    if (p >= per) return;
+    const int x = (int)(p / n), y = (int)(p % n);
+    const T* w = set_block(wl, stride, ws, nsets, img) + w_off;
+    const int kh = ny > 1 ? ks : 1, kw = ks;
+    const T* Wc = w + (size_t)co * C * kh * kw;
+    T acc = w[(size_t)C * C * kh * kw + co];
+    for (int ci = 0; ci < C; ++ci) {
+        const T* zc = z0 + ((size_t)img * C + ci) * per;
+        for (int dy = 0; dy < kh; ++dy) {
+            const int yy = x + dy - kh / 2;
+            if (yy < 0 || yy >= ny) continue;
+            for (int dx = 0; dx < kw; ++dx) {
+                const int xx = y + dx - kw / 2;
+                if (xx < 0 || xx >= n) continue;
+                acc += Wc[((size_t)ci * kh + dy) * kw + dx] * zc[(size_t)yy * n + xx];
+            }
+        }
+    }
+    const size_t o = ((size_t)img * C + co) * per + p;
+    const T v = sp_plane[o] + acc;
+    pre[o] = v;
+    z1[o] = gelu(v);
+}
+
+// g_out = sign ||b|| upstream (per pixel); gZ[c] = proj_w[c] g_out
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_gout(const T* __restrict__ up, const double* __restrict__ nrm2,
+                                                     T* __restrict__ gout, T* __restrict__ gz,
+                                                     const T* __restrict__ wl, size_t stride, size_t p_off,
+                                                     const int* __restrict__ ws, int nsets, int C, size_t per, T sign) {
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int img = blockIdx.y;
+    if (p >= per) return;
+    const T* w = set_block(wl, stride, ws, nsets, img) + p_off;
+    const T g = sign * (T)sqrt(nrm2[img]) * up[(size_t)img * per + p];
+    gout[(size_t)img * per + p] = g;
+    for (int c = 0; c < C; ++c) gz[((size_t)img * C + c) * per + p] = w[c] * g;
+}
+
+// out[c] += sum_img sum_p A[img][c][p] * (B ? B[img][p] * scale(img) : 1), scale = 1/||b||
+// when nrm2 is given; one workgroup per c, fixed reduction order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_sum_prod(const T* __restrict__ A, const T* __restrict__ Bv,
+                                                         const double* __restrict__ nrm2, T* __restrict__ out, int C,
+                                                         size_t per, int batch) {
+    __shared__ double red[kBlock];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int img = 0; img < batch; ++img) {
+        const T* a = A + ((size_t)img * C + c) * per;
+        const T* bv = Bv ? Bv + (size_t)img * per : nullptr;
+        double part = 0.0;
+        for (size_t p = threadIdx.x; p < per; p += kBlock) part += (double)a[p] * (bv ? (double)bv[p] : 1.0);
+        if (bv && nrm2) part *= nrm2[img] > 0.0 ? 1.0 / sqrt(nrm2[img]) : 0.0;
+        acc += part;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] += (T)red[0];
+}
+
+// gPre = gZ * GELU'(pre), GELU'(x) = Phi(x) + x phi(x)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_gelu_bwd(const T* __restrict__ gz, const T* __restrict__ pre,
+                                                         T* __restrict__ gp, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    const T x = pre[e];
+    const T cdf = (T)0.5 * ((T)1 + erf(x * (T)0.70710678118654752440));
+    const T pdf = (T)0.39894228040143267794 * exp((T)-0.5 * x * x);
+    gp[e] = gz[e] * (cdf + x * pdf);
+}
+
+// dW[co][ci][t] += sum_img sum_p gPre[img][co][p] Z[img][ci][p + off(t)];
+// one workgroup per (co, ci), KK partial sums per thread
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_wgrad(const T* __restrict__ gp, const T* __restrict__ z,
+                                                      T* __restrict__ dW, int C, int ks, int ny, int n, int batch) {
+    __shared__ double red[kBlock];
+    const int co = blockIdx.x / C, ci = blockIdx.x % C;
+    const int kh = ny > 1 ? ks : 1, kw = ks, kk = kh * kw;
+    const size_t per = (size_t)ny * n;
+    double acc[49];
+    for (int t = 0; t < kk; ++t) acc[t] = 0.0;
+    for (int img = 0; img < batch; ++img) {
+        const T* g = gp + ((size_t)img * C + co) * per;
+        const T* zc = z + ((size_t)img * C + ci) * per;
+        for (size_t p = threadIdx.x; p < per; p += kBlock) {
+            const double gv = g[p];
+            const int x = (int)(p / n), y = (int)(p % n);
+            for (int dy = 0; dy < kh; ++dy) {
+                const int yy = x + dy - kh / 2;
+                if (yy < 0 || yy >= ny) continue;
+                for (int dx = 0; dx < kw; ++dx) {
+                    const int xx = y + dx - kw / 2;
+                    if (xx < 0 || xx >= n) continue;
+                    acc[dy * kw + dx] += gv * (double)zc[(size_t)yy * n + xx];
+                }
+            }
+        }
+    }
+    for (int t = 0; t < kk; ++t) {
+        red[threadIdx.x] = acc[t];
+        __syncthreads();
+        for (int k = kBlock / 2; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dW[((size_t)co * C + ci) * kk + t] += (T)red[0];
+        __syncthreads();
+    }
+}
+
+// gZ[img][ci][p] = gS[img][ci][p] + sum_co sum_t W[co][ci][t] gPre[img][co][p - off(t)]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_conv_t_add(const T* __restrict__ gp, const T* __restrict__ gs,
+                                                           T* __restrict__ gz, const T* __restrict__ wl, size_t stride,
+                                                           size_t w_off, const int* __restrict__ ws, int nsets, int C,
+                                                           int ks, int ny, int n) {
+    const size_t per = (size_t)ny * n;
+    const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int ci = blockIdx.y, img = blockIdx.z;
+    if (p >= per) return;
+    const int x = (int)(p / n), y = (int)(p % n);
+    const T* w = set_block(wl, stride, ws, nsets, img) + w_off;
+    const int kh = ny > 1 ? ks : 1, kw = ks;
+    T acc = gs[((size_t)img * C + ci) * per + p];
+    for (int co = 0; co < C; ++co) {
+        const T* g = gp + ((size_t)img * C + co) * per;
+        const T* wc = w + ((size_t)co * C + ci) * kh * kw;
+        for (int dy = 0; dy < kh; ++dy) {
+            const int yy = x - dy + kh / 2;
+            if (yy < 0 || yy >= ny) continue;
+            for (int dx = 0; dx < kw; ++dx) {
+                const int xx = y - dx + kw / 2;
+                if (xx < 0 || xx >= n) continue;
+                acc += wc[dy * kw + dx] * g[(size_t)yy * n + xx];
+            }
+        }
+    }
+    gz[((size_t)img * C + ci) * per + p] = acc;
+}
+
+// adjoint of k_fno_idft_rows_split (2D): gY[bc][u'][v] (re, im) from gCDs
+//   cr = (1/n) sum_u' (yr c - yi s), ci = (1/n) sum_u' (yr s + yi c), (c, s) of 2 pi u x / n
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_idft_rows_split_adj(const T* __restrict__ gcd, T* __restrict__ gy,
+                                                                    const T* __restrict__ cs, const T* __restrict__ sn,
+                                                                    int n, int k, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;  // (bc, u', v)
+    if (e >= count) return;
+    const int v = (int)(e % k);
+    const int up = (int)((e / k) % (2 * k));
+    const size_t bc = e / ((size_t)2 * k * k);
+    const int u = up < k ? up : n - 2 * k + up;
+    T gr = 0, gi = 0;
+    int q = 0;
+    for (int x = 0; x < n; ++x) {
+        const T a = gcd[(bc * n + x) * 2 * k + v], b = gcd[(bc * n + x) * 2 * k + k + v];
+        gr += a * cs[q] + b * sn[q];
+        gi += -a * sn[q] + b * cs[q];
+        q += u;
+        if (q >= n) q -= n;
+    }
+    const T inv = (T)1 / (T)n;
+    gy[2 * e] = gr * inv;
+    gy[2 * e + 1] = gi * inv;
+}
+
+// adjoint of k_fno_dft_rows (2D): gTA[bc][x][j] from gX[bc][u'][v]
+//   Xr = sum_x (c Tr + s Ti), Xi = sum_x (c Ti - s Tr)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_dft_rows_adj(const T* __restrict__ gx, T* __restrict__ gta,
+                                                             const T* __restrict__ cs, const T* __restrict__ sn, int n,
+                                                             int k, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;  // (bc, x, v)
+    if (e >= count) return;
+    const int v = (int)(e % k);
+    const int x = (int)((e / k) % n);
+    const size_t bc = e / ((size_t)n * k);
+    T gtr = 0, gti = 0;
+    for (int up = 0; up < 2 * k; ++up) {
+        const int u = up < k ? up : n - 2 * k + up;
+        const int q = (int)(((long long)u * x) % n);
+        const T gr = gx[((bc * 2 * k + up) * k + v) * 2], gi = gx[((bc * 2 * k + up) * k + v) * 2 + 1];
+        gtr += cs[q] * gr - sn[q] * gi;
+        gti += sn[q] * gr + cs[q] * gi;
+    }
+    gta[(bc * n + x) * 2 * k + v] = gtr;
+    gta[(bc * n + x) * 2 * k + k + v] = gti;
+}
+
+// adjoint of the mode mixing: gX[img][ci][m] = sum_co conj-style products with R
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_mix_adj_x(const T* __restrict__ gy, T* __restrict__ gx,
+                                                          const T* __restrict__ wl, size_t stride, size_t r_off,
+                                                          size_t rm, const int* __restrict__ ws, int nsets, int C,
+                                                          int k, int m, int two_d, size_t modes, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;  // (img, ci, md)
+    if (e >= count) return;
+    const size_t md = e % modes;
+    const int ci = (int)((e / modes) % C);
+    const int img = (int)(e / (modes * C));
+    const T* w = set_block(wl, stride, ws, nsets, img) + r_off;
+    size_t base;
+    if (two_d) {
+        const int v = (int)(md % k), up = (int)(md / k);
+        const int corner = up < k ? 0 : 1, u = up < k ? up : up - k;
+        base = (((size_t)corner * C + ci) * C) * m * m + (size_t)u * m + v;  // + co * m * m
+    } else {
+        base = (size_t)ci * C * m + md;  // + co * m
+    }
+    const size_t cst = two_d ? (size_t)m * m : (size_t)m;
+    T ar = 0, ai = 0;
+    for (int co = 0; co < C; ++co) {
+        const size_t yi = (((size_t)img * C + co) * modes + md) * 2;
+        const T gr = gy[yi], gi = gy[yi + 1];
+        const T rr = w[base + co * cst], ri = w[rm + base + co * cst];
+        ar += rr * gr + ri * gi;
+        ai += -ri * gr + rr * gi;
+    }
+    gx[2 * e] = ar;
+    gx[2 * e + 1] = ai;
+}
+
+// dR: dRr[ci][co][m] += sum_img (Xr gYr + Xi gYi), dRi += sum_img (-Xi gYr + Xr gYi)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_mix_adj_r(const T* __restrict__ x, const T* __restrict__ gy,
+                                                          T* __restrict__ dr, size_t rm, int C, int k, int m,
+                                                          int two_d, size_t modes, int batch, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;  // (ci, co, md)
+    if (e >= count) return;
+    const size_t md = e % modes;
+    const int co = (int)((e / modes) % C);
+    const int ci = (int)(e / (modes * C));
+    double sr = 0.0, si = 0.0;
+    for (int img = 0; img < batch; ++img) {
+        const size_t xi_ = (((size_t)img * C + ci) * modes + md) * 2;
+        const size_t yi_ = (((size_t)img * C + co) * modes + md) * 2;
+        const double xr = x[xi_], xim = x[xi_ + 1], gr = gy[yi_], gi = gy[yi_ + 1];
+        sr += xr * gr + xim * gi;
+        si += -xim * gr + xr * gi;
+    }
+    size_t idx;
+    if (two_d) {
+        const int v = (int)(md % k), up = (int)(md / k);
+        const int corner = up < k ? 0 : 1, u = up < k ? up : up - k;
+        idx = (((size_t)corner * C + ci) * C + co) * m * m + (size_t)u * m + v;
+    } else {
+        idx = ((size_t)ci * C + co) * m + md;
+    }
+    dr[idx] += (T)sr;
+    dr[rm + idx] += (T)si;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_zero(T* __restrict__ p, size_t count) {
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < count) p[e] = 0;
+}
 }  // namespace
 
 size_t fno_weight_count(const nmg_problem& p) {
@@ -666,5 +966,139 @@ template nmg_status launch_fno_smoother<float>(const Ctx*, int, int, const int*,
                                                int, Work<float>&, hipStream_t);
 template nmg_status launch_fno_smoother<double>(const Ctx*, int, int, const int*, const double*, const double*,
                                                 double*, int, Work<double>&, hipStream_t);
+
+template <typename T>
+static nmg_status ensure_fno_train(Ctx* c, Work<T>& w) {
+    NMG_TRY(ensure_fno<T>(c));
+    if (w.ftr_ready) return NMG_OK;
+    const size_t B = (size_t)c->p.max_batch, C = (size_t)c->p.fno_width, NL = (size_t)c->p.fno_layers;
+    const size_t per0 = level_elems(c, 0), ny0 = (size_t)c->ny0;
+    const size_t m = (size_t)std::max(1, fno_level_modes(c, 0));
+    const size_t modes = c->p.dim == 2 ? 2 * m * m : m;
+    NMG_TRY(falloc(&w.ftz, (NL + 1) * B * C * per0));
+    NMG_TRY(falloc(&w.ftp, NL * B * C * per0));
+    NMG_TRY(falloc(&w.ftx, NL * B * C * modes * 2));
+    NMG_TRY(falloc(&w.ftgz, B * C * per0));
+    NMG_TRY(falloc(&w.ftgp, B * C * per0));
+    NMG_TRY(falloc(&w.ftgs, B * C * per0));
+    NMG_TRY(falloc(&w.ftga, B * C * ny0 * 2 * m));
+    NMG_TRY(falloc(&w.ftgx, B * C * modes * 2));
+    NMG_TRY(falloc(&w.ftgy, B * C * modes * 2));
+    NMG_TRY(falloc(&w.ftgo, B * per0));
+    w.ftr_ready = true;
+    return NMG_OK;
+}
+
+template <typename T>
+nmg_status fno_backward(Ctx* c, Work<T>& w, int l, int set, int batch, const T* b, const double* nrm2,
+                        const T* upstream, T sign, int accumulate, T* grad, hipStream_t s) {
+    if (c->capturing) return fail(NMG_ERR_STATE, "FNO training cannot run inside a graph capture");
+    NMG_TRY(ensure_fno_train<T>(c, w));
+    const FnoDims d = fno_dims(c);
+    const int n = c->n[(size_t)l];
+    const int ny = d.dim == 2 ? n : 1;
+    const size_t per = (size_t)ny * n, per0 = level_elems(c, 0);
+    const int k = fno_level_modes(c, l);
+    const int C = d.C;
+    const size_t stride = (size_t)c->wcount;
+    const int nsets = c->p.n_weight_sets;
+    const T* wl = w.wts + (size_t)l * nsets * stride + (size_t)set * stride;  // this set only
+    const T* cs = w.ftab + w.ftab_off[(size_t)l];
+    const T* sn = cs + n;
+    const T* fwd = w.fmat + w.fmat_off[(size_t)l];
+    const T* inv_m = fwd + (size_t)n * 2 * k;
+    const size_t modes = d.dim == 2 ? (size_t)2 * k * k : (size_t)k;
+    const size_t m0 = (size_t)std::max(1, fno_level_modes(c, 0));
+    const size_t modes0 = d.dim == 2 ? 2 * m0 * m0 : m0;
+    const size_t rows = (size_t)batch * C * ny;
+    const size_t plane = (size_t)c->p.max_batch * C * per0;  // stride of the per-layer stores
+    auto Z = [&](int i) { return w.ftz + (size_t)i * plane; };
+    auto P = [&](int i) { return w.ftp + (size_t)i * plane; };
+    auto X = [&](int i) { return w.ftx + (size_t)i * c->p.max_batch * C * modes0 * 2; };
+    const int* ws = nullptr;  // one weight set for the whole batch: wl already points at it
+    if (!accumulate) hipLaunchKernelGGL(k_fno_zero<T>, dim3(blocks_for(stride)), dim3(kBlock), 0, s, grad, stride);
+    // ---- forward with stored activations
+    hipLaunchKernelGGL(k_fno_lift<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, b, nrm2, Z(0), wl, stride, ws,
+                       1, C, per);
+    for (int i = 0; i < d.NL; ++i) {
+        const size_t base = 2 * (size_t)C + (size_t)i * d.layer_stride;
+        hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((2 * k + 63) / 64)), dim3(256),
+                           0, s, Z(i), fwd, w.fta, (int)rows, 2 * k, n, 0);
+        const size_t xc = (size_t)batch * C * modes;
+        if (d.dim == 2)
+            hipLaunchKernelGGL(k_fno_dft_rows<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.fta, X(i), cs, sn, n, k,
+                               xc);
+        else
+            hipLaunchKernelGGL(k_fno_interleave<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.fta, X(i), k, xc);
+        hipLaunchKernelGGL(k_fno_mix<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, X(i), w.fyh, wl, stride, base, d.rm,
+                           ws, 1, C, k, d.m, d.dim == 2 ? 1 : 0, modes, xc);
+        if (d.dim == 2) {
+            const size_t cnt = (size_t)batch * C * n * k;
+            hipLaunchKernelGGL(k_fno_idft_rows_split<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.fyh, w.fcd, cs,
+                               sn, n, k, cnt);
+        } else {
+            hipLaunchKernelGGL(k_fno_deinterleave<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.fyh, w.fcd, k, xc);
+        }
+        hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((n + 63) / 64)), dim3(256), 0,
+                           s, w.fcd, inv_m, w.fsp, (int)rows, n, 2 * k, 0);
+        hipLaunchKernelGGL(k_fno_pre<T>, dim3(blocks_for(per), C, batch), dim3(kBlock), 0, s, Z(i), w.fsp, P(i),
+                           Z(i + 1), wl, stride, base + 2 * d.rm, ws, 1, C, d.ks, ny, n);
+    }
+    // ---- adjoint
+    const size_t p_off = 2 * (size_t)C + (size_t)d.NL * d.layer_stride;
+    hipLaunchKernelGGL(k_fno_gout<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, upstream, nrm2, w.ftgo, w.ftgz,
+                       wl, stride, p_off, ws, 1, C, per, sign);
+    hipLaunchKernelGGL(k_fno_sum_prod<T>, dim3(C), dim3(kBlock), 0, s, Z(d.NL), w.ftgo, (const double*)nullptr,
+                       grad + p_off, C, per, batch);
+    hipLaunchKernelGGL(k_fno_sum_prod<T>, dim3(1), dim3(kBlock), 0, s, w.ftgo, (const T*)nullptr,
+                       (const double*)nullptr, grad + p_off + C, 1, per, batch);
+    const size_t tot = (size_t)batch * C * per;
+    for (int i = d.NL - 1; i >= 0; --i) {
+        const size_t base = 2 * (size_t)C + (size_t)i * d.layer_stride;
+        hipLaunchKernelGGL(k_fno_gelu_bwd<T>, dim3(blocks_for(tot)), dim3(kBlock), 0, s, w.ftgz, P(i), w.ftgp, tot);
+        // bias and convolution weights
+        hipLaunchKernelGGL(k_fno_sum_prod<T>, dim3(C), dim3(kBlock), 0, s, w.ftgp, (const T*)nullptr,
+                           (const double*)nullptr, grad + base + 2 * d.rm + (size_t)C * C * d.kk, C, per, batch);
+        hipLaunchKernelGGL(k_fno_wgrad<T>, dim3(C * C), dim3(kBlock), 0, s, w.ftgp, Z(i), grad + base + 2 * d.rm, C,
+                           d.ks, ny, n, batch);
+        // spectral path: gCDs = gPre Finv^T, then the adjoint inverse rows
+        hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((2 * k + 63) / 64)), dim3(256),
+                           0, s, w.ftgp, inv_m, w.ftga, (int)rows, 2 * k, n, 1);
+        const size_t xc = (size_t)batch * C * modes;
+        if (d.dim == 2)
+            hipLaunchKernelGGL(k_fno_idft_rows_split_adj<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.ftga, w.ftgy,
+                               cs, sn, n, k, xc);
+        else
+            hipLaunchKernelGGL(k_fno_interleave<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.ftga, w.ftgy, k, xc);
+        const size_t rc = (size_t)C * C * modes;
+        hipLaunchKernelGGL(k_fno_mix_adj_r<T>, dim3(blocks_for(rc)), dim3(kBlock), 0, s, X(i), w.ftgy, grad + base,
+                           d.rm, C, k, d.m, d.dim == 2 ? 1 : 0, modes, batch, rc);
+        hipLaunchKernelGGL(k_fno_mix_adj_x<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.ftgy, w.ftgx, wl, stride,
+                           base, d.rm, ws, 1, C, k, d.m, d.dim == 2 ? 1 : 0, modes, xc);
+        if (d.dim == 2) {
+            const size_t cnt = (size_t)batch * C * n * k;
+            hipLaunchKernelGGL(k_fno_dft_rows_adj<T>, dim3(blocks_for(cnt)), dim3(kBlock), 0, s, w.ftgx, w.ftga, cs,
+                               sn, n, k, cnt);
+        } else {
+            hipLaunchKernelGGL(k_fno_deinterleave<T>, dim3(blocks_for(xc)), dim3(kBlock), 0, s, w.ftgx, w.ftga, k, xc);
+        }
+        hipLaunchKernelGGL(k_gemm_rm<T>, dim3((unsigned)((rows + 63) / 64), (unsigned)((n + 63) / 64)), dim3(256), 0,
+                           s, w.ftga, fwd, w.ftgs, (int)rows, n, 2 * k, 1);
+        // gZ of the layer input = spectral part + transposed convolution
+        hipLaunchKernelGGL(k_fno_conv_t_add<T>, dim3(blocks_for(per), C, batch), dim3(kBlock), 0, s, w.ftgp, w.ftgs,
+                           w.ftgz, wl, stride, base + 2 * d.rm, ws, 1, C, d.ks, ny, n);
+    }
+    // lift: u = b / ||b||
+    hipLaunchKernelGGL(k_fno_sum_prod<T>, dim3(C), dim3(kBlock), 0, s, w.ftgz, b, nrm2, grad, C, per, batch);
+    hipLaunchKernelGGL(k_fno_sum_prod<T>, dim3(C), dim3(kBlock), 0, s, w.ftgz, (const T*)nullptr,
+                       (const double*)nullptr, grad + C, C, per, batch);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status fno_backward<float>(Ctx*, Work<float>&, int, int, int, const float*, const double*, const float*,
+                                        float, int, float*, hipStream_t);
+template nmg_status fno_backward<double>(Ctx*, Work<double>&, int, int, int, const double*, const double*,
+                                         const double*, double, int, double*, hipStream_t);
+
 
 }  // namespace nmg

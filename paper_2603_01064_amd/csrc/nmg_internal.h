@@ -116,6 +116,11 @@ struct Work {
     T* ftab = nullptr;
     std::vector<size_t> ftab_off;
     T* fsp = nullptr;             // spectral part of a layer's output [B][C][per0]
+    // FNO training: per-layer activations Z_0..Z_NL, pre-activations, spectra,
+    // and the adjoint's work planes
+    bool ftr_ready = false;
+    T *ftz = nullptr, *ftp = nullptr, *ftx = nullptr, *ftgz = nullptr, *ftgp = nullptr, *ftga = nullptr;
+    T *ftgx = nullptr, *ftgy = nullptr, *ftgo = nullptr, *ftgs = nullptr;
     T* fmat = nullptr;            // per level dense column-transform matrices
     std::vector<size_t> fmat_off;
 };
@@ -289,6 +294,12 @@ nmg_status ensure_fno(Ctx* c);
 template <typename T>
 nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, const T* b, const double* nrm2, T* dst,
                                int accumulate, Work<T>& w, hipStream_t s);
+// Weight gradient of the FNO smoother of level l (weight set `set`) for the
+// upstream gradient dL/dh (scaled by `sign`) of h = ||b|| N(b / ||b||);
+// accumulates into grad (the level's block) unless `accumulate` is 0.
+template <typename T>
+nmg_status fno_backward(Ctx* c, Work<T>& w, int l, int set, int batch, const T* b, const double* nrm2,
+                        const T* upstream, T sign, int accumulate, T* grad, hipStream_t s);
 void release_training(const Ctx* c);
 
 size_t level_elems(const Ctx* c, int l);  // ny_l * n_l

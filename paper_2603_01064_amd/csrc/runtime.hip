@@ -309,6 +309,17 @@ void free_work(Ctx* c, Work<T>& w) {
     dev_free(w.ftab);
     dev_free(w.fsp);
     dev_free(w.fmat);
+    dev_free(w.ftz);
+    dev_free(w.ftp);
+    dev_free(w.ftx);
+    dev_free(w.ftgz);
+    dev_free(w.ftgp);
+    dev_free(w.ftga);
+    dev_free(w.ftgx);
+    dev_free(w.ftgy);
+    dev_free(w.ftgo);
+    dev_free(w.ftgs);
+    w.ftr_ready = false;
     w.fno_ready = false;
     dev_free(w.Gd);
     dev_free(w.Md);

@@ -523,7 +523,7 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
-    if (!mixed) NMG_TRY(ensure_acts<T>(c));
+    if (!mixed || c->p.smoother_arch == NMG_ARCH_FNO) NMG_TRY(ensure_acts<T>(c));
     const int L = c->L;
     const int nsm = L - 1;
     const int N = c->n[0];
@@ -538,7 +538,10 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
     for (int l = 0; l < nsm; ++l) {
         const size_t per = level_elems(c, l);
         NMG_TRY(launch_sumsq<T>(c, batch, per, tw.b[(size_t)l], tw.nrm[(size_t)l], s));
-        if (mixed) {
+        if (c->p.smoother_arch == NMG_ARCH_FNO) {
+            NMG_TRY(launch_fno_smoother<T>(c, l, batch, ws_dev, tw.b[(size_t)l], tw.nrm[(size_t)l], tw.h[(size_t)l], 0,
+                                           work, s));
+        } else if (mixed) {
             NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
                                          tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
                                          *reinterpret_cast<Work<float>*>(&work), s));
@@ -584,7 +587,11 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
         // g_h = (I_l^1)^T gE; dL/dh_l = -g_h, so the network-output delta is -||b_l|| g_h
         T* gh = work.lv[(size_t)l].h;
         NMG_TRY(prolong_chain_T<T>(c, work, l, batch, gE, gh, s));
-        NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)(-1), zero_grad ? 0 : 1, s));
+        if (c->p.smoother_arch == NMG_ARCH_FNO)
+            NMG_TRY(fno_backward<T>(c, work, l, set, batch, tw.b[(size_t)l], tw.nrm[(size_t)l], gh, (T)(-1),
+                                    zero_grad ? 0 : 1, grad_ptr<T>(c, l, set), s));
+        else
+            NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)(-1), zero_grad ? 0 : 1, s));
         // accumulate the correction of this level on the finest grid
         const T* hc = use_fprime ? tw.hc[(size_t)l] : tw.h[(size_t)l];
         NMG_TRY(prolong_chain<T>(c, work, l, batch, hc, tw.F1, s));
@@ -616,7 +623,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
-    if (!mixed) NMG_TRY(ensure_acts<T>(c));
+    if (!mixed || c->p.smoother_arch == NMG_ARCH_FNO) NMG_TRY(ensure_acts<T>(c));
     NMG_TRY(nmg_prepare(static_cast<nmg_handle>(c), batch, alpha, s));  // coarse factors of these alphas
     const int L = c->L;
     const int nsm = L - 1;
@@ -638,7 +645,10 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
     for (int l = 0; l < nsm; ++l) {
         const size_t per = level_elems(c, l);
         NMG_TRY(launch_sumsq<T>(c, batch, per, tw.b[(size_t)l], tw.nrm[(size_t)l], s));
-        if (mixed) {
+        if (c->p.smoother_arch == NMG_ARCH_FNO) {
+            NMG_TRY(launch_fno_smoother<T>(c, l, batch, ws_dev, tw.b[(size_t)l], tw.nrm[(size_t)l], tw.h[(size_t)l], 0,
+                                           work, s));
+        } else if (mixed) {
             NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
                                          tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
                                          *reinterpret_cast<Work<float>*>(&work), s));
@@ -717,7 +727,11 @@ namespace {
 nmg_status check_training(nmg_handle h, int set, int batch, nmg_mask_kind mask, nmg_precision prec) {
     if (!h) return fail(NMG_ERR_ARG, "null handle");
     if (h->L < 2) return fail(NMG_ERR_SHAPE, "training needs at least two levels");
-    if (h->p.smoother_arch != NMG_ARCH_CNN) return fail(NMG_ERR_STATE, "training supports the CNN smoother only");
+    if (h->p.smoother_arch == NMG_ARCH_FNO) {
+        if (mask == NMG_LOSS_CYCLE) return fail(NMG_ERR_STATE, "the combined loss supports the CNN smoother only");
+        const int kk = h->p.dim == 2 ? h->p.fno_ksize * h->p.fno_ksize : h->p.fno_ksize;
+        if (kk > 49) return fail(NMG_ERR_SHAPE, "FNO training supports convolutions of at most 49 taps");
+    }
     if (batch < 1 || batch > h->p.max_batch) return fail(NMG_ERR_SHAPE, "batch must be in [1, max_batch]");
     if (set < 0 || set >= h->p.n_weight_sets) return fail(NMG_ERR_ARG, "weight_set out of range");
     if (mask != NMG_MASK_BAND && mask != NMG_MASK_RAMP && mask != NMG_LOSS_CYCLE)

@@ -119,3 +119,66 @@ def test_fno_weight_sets_per_rhs():
                                                                                    alpha[i:i + 1].cpu())
         assert _rel(both[i:i + 1].cpu(), ref) < 1e-12
     h.close()
+
+
+# --------------------------------------------------------------------------
+# Training: the hand-written FNO adjoint of the level-wise loss
+# --------------------------------------------------------------------------
+
+
+def _flat_grads(g):
+    parts = [g["lift_w"], g["lift_b"]]
+    for Ly in g["layers"]:
+        parts += [Ly["R_re"], Ly["R_im"], Ly["W"], Ly["B"]]
+    parts += [g["proj_w"], g["proj_b"].reshape(1)]
+    return torch.cat([t.reshape(-1) for t in parts])
+
+
+def _oracle_real(p):
+    t = lambda a: torch.tensor(np.asarray(a), dtype=DT)
+    return {"lift_w": t(p["lift_w"]), "lift_b": t(p["lift_b"]), "proj_w": t(p["proj_w"]), "proj_b": t(p["proj_b"]),
+            "layers": [{k: t(L[k]) for k in ("R_re", "R_im", "W", "B")} for L in p["layers"]]}
+
+
+@pytest.mark.parametrize("dim,n,s,L,arch,use_fp", [(2, 31, 0.05, 3, (4, 2, 6, 3), True),
+                                                   (2, 31, 0.05, 3, (4, 1, 10, 3), False),
+                                                   (1, 63, 0.03, 3, (4, 2, 8, 5), True)])
+def test_fno_loss_gradient_matches_oracle(dim, n, s, L, arch, use_fp):
+    """FP64 level losses 1e-12 and every level's gradient 1e-10 against the
+    oracle's autograd (modes clamp on the 15-point level in the second case);
+    FP32 within 1e-4."""
+    print(f"case FNO loss gradient dim={dim} n={n} arch={arch}", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, params = _setup(dim, n, s, L, arch, B=2)
+    e = torch.tensor(inputs.iid_normal((2,) + (n,) * dim, 3100))
+    alpha = torch.tensor([1e-2, 1e-3], dtype=DT)
+    ref_l, ref_g = O.fno_level_loss_grads(H, [_oracle_real(p) for p in params[0]], e, alpha, arch[2], "ramp", use_fp)
+    got = h.loss_grad(e.to(dev), alpha.to(dev), mask="ramp", use_fprime=use_fp, precision="fp64")
+    for l in range(L - 1):
+        assert abs(got[l] - float(ref_l[l])) <= 1e-12 * abs(float(ref_l[l]))
+        g = torch.tensor(h.get_gradient(l))
+        r = _flat_grads(ref_g[l])
+        err = float((g - r).norm() / r.norm())
+        print(f"  level {l}: loss {got[l]:.6e} grad rel err {err:.2e}", flush=True)
+        assert err < 1e-10
+    got32 = h.loss_grad(e.float().to(dev), alpha.to(dev), mask="ramp", use_fprime=use_fp, precision="fp32")
+    for l in range(L - 1):
+        g = torch.tensor(h.get_gradient(l))
+        r = _flat_grads(ref_g[l])
+        assert float((g - r).norm() / r.norm()) < 1e-4
+        assert abs(got32[l] - float(ref_l[l])) <= 1e-4 * abs(float(ref_l[l]))
+    h.close()
+
+
+def test_fno_training_reduces_the_loss():
+    print("case FNO training 20 steps", flush=True)
+    dev = torch.device("cuda:0")
+    h, H, params = _setup(2, 31, 0.05, 3, (8, 2, 6, 3), B=8)
+    e = torch.tensor(inputs.iid_normal((8, 31, 31), 3101)).float().to(dev)
+    alpha = torch.full((8,), 1e-2, dtype=DT, device=dev)
+    first = h.train_step(e, alpha, mask="ramp", use_fprime=True, precision="fp32", lr=1e-3)
+    for _ in range(20):
+        last = h.train_step(e, alpha, mask="ramp", use_fprime=True, precision="fp32", lr=1e-3)
+    print(f"  losses {first} -> {last}", flush=True)
+    assert float(np.sum(last)) < float(np.sum(first))
+    h.close()
