@@ -202,18 +202,24 @@ def main(argv=None):
     ap.add_argument("--fprime", action="store_true", help="train with F' in the loss (eq. loss_2_modified)")
     ap.add_argument("--steps-per-alpha", type=int, nargs="+", default=None)
     ap.add_argument("--eval-max-cycles", type=int, default=100, help="cycle limit of the post-training evaluation")
+    ap.add_argument("--fno", type=int, nargs=4, default=None, metavar=("C", "LAYERS", "MODES", "KSIZE"),
+                    help="train FNO smoothers (width, Fourier layers, modes, convolution size) instead of the CNN")
     ap.add_argument("--operator", default="normal", choices=["normal", "kernel"],
                     help="fine operator: alpha I + K^T K (normal) or alpha I (x) I + K (x) K (kernel)")
     a = ap.parse_args(argv)
     nmg.load_library()
     prob = nmg.Problem(n=a.n, s=a.s, levels=a.levels, dim=2, max_batch=a.batch, channels=tuple(a.channels),
-                       ksize=3, n_weight_sets=1, operator=a.operator)
+                       ksize=3, n_weight_sets=1, operator=a.operator, fno=tuple(a.fno) if a.fno else None)
     h = nmg.setup_hierarchy(prob)
     L = a.levels
     if a.init:
         _, init_sets = load_weights(a.init)
         for l in range(L - 1):
             h.load_smoother_weights(l, 0, [init_sets[-1][l]])
+    elif a.fno:
+        from .fno import pack_fno_weights
+        for l in range(L - 1):
+            h.load_smoother_weights(l, 0, [pack_fno_weights(inputs.fno_params(2, *a.fno, a.seed + 10 * l))])
     else:
         for l in range(L - 1):
             h.load_smoother_weights(l, 0, inputs.he_normal_weights(tuple(a.channels), 3, 2, a.seed + 10 * l))
@@ -235,7 +241,7 @@ def main(argv=None):
     meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=alphas,
                 steps=a.steps_per_alpha or [a.steps] * len(alphas), batch=a.batch, lr=a.lr, mask=a.mask,
                 rollout=a.rollout, precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init,
-                operator=a.operator)
+                operator=a.operator, fno=list(a.fno) if a.fno else None)
     save_weights(a.out, meta, sets)
     print(f"wrote {a.out}", flush=True)
     h.close()
