@@ -521,14 +521,15 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
     """Serving stream of 2D solves with grid side uniform over 64..1024,
     s = 2.5 grid spacings, alpha log-uniform in [1e-5, 1e-2], box-image
     right-hand sides and Poisson arrivals, through one pool (one handle per
-    side, 2 GiB budget) with the BF16/FP32/FP64 cycle to 1e-6; the serial
+    side, 2 GiB budget) with the BF16/FP32/FP64 cycle to 1e-6 (weight set
+    per request by `select_set`); the serial
     plain-FP32 one-request-at-a-time solver runs the first requests of the
     lowest-rate trace."""
     import torch
 
     from paper_2603_01064_amd import inputs
     from paper_2603_01064_amd.serve import serve_pool_requests, serve_serially
-    from paper_2603_01064_amd.train_weights import load_weights
+    from paper_2603_01064_amd.train_weights import load_weights, select_set
     dev = torch.device("cuda:0")
     meta, sets = load_weights(MIXED_WEIGHTS)
     set_alphas = list(meta["alphas"])
@@ -542,7 +543,7 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
     rng = np.random.default_rng(41000)
     member = rng.integers(0, len(MIXED_SIDES), size=count)
     alpha = inputs.log_uniform(1e-5, 1e-2, count, seed=41001)
-    ws = np.array([set_alphas.index(min(set_alphas, key=lambda v: abs(math.log(v / a)))) for a in alpha])
+    ws = np.array([select_set(set_alphas, a) for a in alpha])
     b, x = [], []
     for i in range(count):
         h, side = handles[member[i]], MIXED_SIDES[member[i]]
@@ -571,6 +572,11 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
                                   for m, sd in enumerate(MIXED_SIDES) if ((member == m) & ok).any()}
         summ["mean_cycles_by_side"] = {str(sd): round(float(rep.cycles[member == m].mean()), 2)
                                        for m, sd in enumerate(MIXED_SIDES) if (member == m).any()}
+        summ["converged_by_side"] = {str(sd): f"{int(((member == m) & ok).sum())}/{int((member == m).sum())}"
+                                     for m, sd in enumerate(MIXED_SIDES)}
+        bad = ~ok
+        summ["not_converged_alpha_range"] = ([float(alpha[bad].min()), float(alpha[bad].max())]
+                                             if bad.any() else None)
         out[f"poisson_{int(rate)}_per_s"] = summ
         log(f"mixed-size serving at {rate:g}/s: {summ['solves_per_s']} solves/s, p50 {summ['p50_ms']} ms, "
             f"p99 {summ['p99_ms']} ms, converged {summ['converged']}/{summ['requests']}")

@@ -33,7 +33,8 @@ class ServeReport:
         return {"requests": int(self.latency_ms.size), "converged": int(ok.sum()),
                 "solves_per_s": round(float(self.latency_ms.size / self.wall_s), 2) if self.wall_s > 0 else None,
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "mean_cycles": round(float(self.cycles.mean()), 2), "engine_steps": int(self.steps)}
+                "mean_cycles": round(float(self.cycles.mean()), 2), "engine_steps": int(self.steps),
+                "status_counts": {str(int(v)): int((self.status == v).sum()) for v in np.unique(self.status)}}
 
 
 def serve_requests(handle, b, x, alpha, weight_set, arrivals, *, rtol=1e-6, max_cycles=200, nu1=1, nu2=1,

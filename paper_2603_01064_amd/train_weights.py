@@ -52,6 +52,18 @@ def load_weights(path: str):
     return meta, sets
 
 
+def select_set(set_alphas, alpha: float) -> int:
+    """Weight set for a request with regularisation `alpha`: the smallest
+    trained alpha that is at least alpha / 2 (the largest set if none is).
+    Measured at 255^2, s = 2.5h: a set trained at alpha_k keeps converging
+    for requests down to alpha_k / 10 (more slowly) but diverges for
+    requests more than about twice alpha_k."""
+    ok = [i for i, a in enumerate(set_alphas) if a >= alpha / 2]
+    if not ok:
+        return max(range(len(set_alphas)), key=lambda i: set_alphas[i])
+    return min(ok, key=lambda i: set_alphas[i])
+
+
 def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: torch.Generator,
             precision: str, use_fprime: bool = False) -> torch.Tensor:
     """DataGeneration of Algorithm 5: each sample is run through k ~ U{0..K}
