@@ -311,7 +311,9 @@ nmg_status nmg_request_bytes(nmg_handle h, nmg_precision precision, size_t* byte
  * thread-safe. */
 typedef struct nmg_pool_ctx* nmg_pool;
 nmg_status nmg_pool_create(size_t hbm_budget_bytes, nmg_pool* out);
-void nmg_pool_destroy(nmg_pool p);  /* waits for the members' streams */
+/* Waits for the members' streams; requests still queued or in flight are
+ * abandoned (their members' serving state is reset). */
+void nmg_pool_destroy(nmg_pool p);
 /* Adds a handle (with no serving work of its own); *member_out = its index. */
 nmg_status nmg_pool_add(nmg_pool p, nmg_handle h, int* member_out);
 /* Queues request `id` (unique among the pool's queued and running requests)

@@ -68,6 +68,7 @@ void nmg_pool_destroy(nmg_pool p) {
             (void)hipStreamDestroy(m.s);
         }
         if (m.retired) (void)hipEventDestroy(m.retired);
+        (void)nmg_serve_reset(m.h);  // requests still in flight are abandoned
     }
     delete p;
 }
@@ -141,6 +142,9 @@ nmg_status nmg_pool_step(nmg_pool p, double rtol, int max_cycles, const nmg_cycl
         NMG_HIP(hipEventSynchronize(m.retired));
         const double now = p->now_ms();
         for (auto& r : out) {
+            if (count >= capacity)
+                return fail(NMG_ERR_STATE, "more finished requests than the result capacity (a member handle "
+                                           "received requests outside the pool)");
             auto it = p->running.find(r.id);
             if (it != p->running.end()) {
                 r.latency_ms = now - it->second.t_submit;
