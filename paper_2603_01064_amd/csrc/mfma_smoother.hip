@@ -82,6 +82,8 @@ struct Geo {
     static constexpr int bufB = H(2) * kP * 64;
     static constexpr int lds = in_bytes + bufA + bufB;
     static constexpr int RPT = (NREC + 255) / 256;  // records per thread
+    // output rows per register block in the hidden layers (accumulators: 8 RB VGPRs)
+    static constexpr int RB = NL == 3 ? 7 : 2;
 };
 
 typedef float float2v __attribute__((ext_vector_type(2)));
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     const int img = blockIdx.y;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: kept in an SGPR
     const int ln = lane & 15;   // N index (pixel within group)
     const int lg = lane >> 4;   // K group / output row group
 
@@ -143,25 +145,60 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     const int set = ws ? min(max(ws[img], 0), nsets - 1) : 0;
     const uint16_t* wp = wlevel + (size_t)set * set_stride;
 
+    // weights through a buffer resource over this set's block: one VGPR
+    // offset (the lane's) and a uniform byte offset per load, so no per-lane
+    // 64-bit address is kept per weight operand
+    const __amdgpu_buffer_rsrc_t wres =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(wp), (short)0, (int)(set_stride * 2), 0x00020000);
+    auto wload = [&](int lane_bytes, int elem_off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(wres, lane_bytes, elem_off * 2, 0);
+        bf16x8 o;
+        __builtin_memcpy(&o, &v, 16);
+        return o;
+    };
     short4v w1[2];
-    for (int nb = 0; nb < 2; ++nb) w1[nb] = *reinterpret_cast<const short4v*>(wp + (nb * 64 + lane) * 4);
-    bf16x8 wh[NH][9][2];
-    for (int h = 0; h < NH; ++h)
+    for (int nb = 0; nb < 2; ++nb) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(wres, lane * 8, nb * 64 * 4 * 2, 0);
+        __builtin_memcpy(&w1[nb], &v, 8);
+    }
+    // hidden-layer weights: with one hidden layer they stay in registers for
+    // the whole kernel; with two, only the layer being evaluated is held (72
+    // VGPRs) and the next one is reloaded from the cache, which keeps the
+    // kernel within 256 VGPRs
+    constexpr bool kResident = NH == 1;
+    bf16x8 wh[kResident ? NH : 1][9][2];
+    auto load_hidden = [&](int slot, int h) {
+        // the opaque copy of the layer offset keeps a per-tile reload inside
+        // the tile loop (hoisted, both layers would be held again)
+        int base = kFirstElems + h * kHiddenElems;
+        if constexpr (!kResident) asm volatile("" : "+s"(base));
+#pragma unroll
         for (int t = 0; t < 9; ++t)
-            for (int nb = 0; nb < 2; ++nb)
-                wh[h][t][nb] = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)h * kHiddenElems +
-                                                                ((t * 2 + nb) * 64 + lane) * 8);
-    const bf16x8 wl = *reinterpret_cast<const bf16x8*>(wp + kFirstElems + (size_t)NH * kHiddenElems + lane * 8);
-
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) wh[slot][t][nb] = wload(lane * 16, base + (t * 2 + nb) * 64 * 8);
+    };
+    if constexpr (kResident)
+        for (int h = 0; h < NH; ++h) load_hidden(h, h);
+    const bf16x8 wl = wload(lane * 16, kFirstElems + NH * kHiddenElems);
     // per-lane constants for 16-aligned pixel groups (column = 16 k + ln): the
     // operand chunk offsets of pixels ln, ln+1, ln+2 and the output chunk
     // offsets of channels nb*16 + 4*lg .. +3
     const int swz0 = swz(ln, lg), swz1 = swz(ln + 1, lg), swz2 = swz(ln + 2, lg);
+    // first-layer record offsets of this lane (tap row dy = min(lane/16, 2)):
+    // row groups read pixel ln of a row, column groups row ln of a column
+    const int rec_row = (min(lg, 2) * G::RW + ln) * 8;
+    const int rec_col = ((ln + min(lg, 2)) * G::RW) * 8;
     int out_off[2];
     for (int nb = 0; nb < 2; ++nb) {
         const int co = nb * 16 + lg * 4;
         out_off[nb] = swz(ln, co >> 3) + (co & 7) * 2;
     }
+    // first-layer row group k of this wave is group wave + 4 k: row (wave >> 1) + 2 k,
+    // pixels (wave & 1) * 16 + ln, so its operand and output addresses are these
+    // per-lane bases plus a multiple of k that fits an LDS immediate offset
+    const int rec_wave = rec_row + ((wave >> 1) * G::RW + (wave & 1) * 16) * 8;
+    int st_wave[2];
+    for (int nb = 0; nb < 2; ++nb) st_wave[nb] = ((wave >> 1) * kP + (wave & 1) * 16 + ln) * 64 + out_off[nb];
 
     const size_t per = (size_t)n * n;
     const float* src = bres + (size_t)img * per;
@@ -171,133 +208,209 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
 
     // input values of this thread's first-layer records (three per record),
-    // loaded one tile ahead so the global latency overlaps the layers
+    // loaded one tile ahead so the global latency overlaps the layers.  The
+    // image is read through a buffer resource: a load whose offset lies past
+    // the image returns zero, so a tap outside the image takes an out-of-range
+    // offset instead of a branch (the launch keeps n*n*4 below 2^31).
+    const __amdgpu_buffer_rsrc_t sres =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(src), (short)0, (int)(per * 4), 0x00020000);
     float pv[G::RPT][3];
-    auto load_records = [&](int tile) {
+    auto load_records = [&](int tile, int t_id) {
         const int ty0 = (tile / tiles_x) * TH, tx0 = (tile % tiles_x) * TW;
 #pragma unroll
         for (int k = 0; k < G::RPT; ++k) {
-            const int e = tid + k * kThreads;
+            const int e = t_id + k * kThreads;
             const int r = e / RW, c = e - (e / RW) * RW;
             const int gy = ty0 - NL + r, gx = tx0 - NL + c;
-            const bool row_ok = e < G::NREC && gy >= 0 && gy < n;
-            const float* rp = src + (size_t)(row_ok ? gy : 0) * n;
+            // (bitwise tests: no short-circuit branches)
+            const bool row_ok = (tile < tiles_per_img) & (e < G::NREC) & ((unsigned)gy < (unsigned)n);
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                pv[k][d] = (tile < tiles_per_img && row_ok && gx + d >= 0 && gx + d < n) ? rp[gx + d] : 0.f;
+            for (int d = 0; d < 3; ++d) {
+                const bool ok = row_ok & ((unsigned)(gx + d) < (unsigned)n);
+                const int off = ok ? (gy * n + gx + d) * 4 : (int)0x80000000;
+                pv[k][d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sres, off, 0, 0));
+            }
         }
     };
-    load_records(blockIdx.x);
+    load_records(blockIdx.x, tid);
 
     for (int tile = blockIdx.x; tile < tiles_per_img; tile += gridDim.x) {
+        // per-tile copies of the lane indices: the per-lane index arithmetic of
+        // the first and last layers is redone every tile instead of being kept
+        // live (or spilled) across the loop
+        int tid_t = tid;
+        asm volatile("" : "+v"(tid_t));
+        const int ln_t = tid_t & 15, lg_t = (tid_t >> 4) & 3;
         const int ty0 = (tile / tiles_x) * TH, tx0 = (tile % tiles_x) * TW;
         // ---- records of this tile (scaled by 1/||b||, zero outside the image)
 #pragma unroll
         for (int k = 0; k < G::RPT; ++k) {
-            const int e = tid + k * kThreads;
+            const int e = tid_t + k * kThreads;
             if (e < G::NREC)
                 *reinterpret_cast<uint2*>(recs + e * 8) =
                     make_uint2(pack2_bf16(pv[k][0] * inv, pv[k][1] * inv), pack2_bf16(pv[k][2] * inv, 0.f));
         }
-        load_records(tile + gridDim.x);
+        load_records(tile + gridDim.x, tid_t);
         __syncthreads();
         // tiles whose input region lies inside the image need no zero masking
         const bool interior = ty0 >= NL && tx0 >= NL && ty0 + TH + NL <= n && tx0 + TW + NL <= n;
+        if constexpr (!kResident) load_hidden(0, 0);
         auto layers = [&](auto edge_tag) {
             constexpr bool EDGE = decltype(edge_tag)::value;
-            // ---- first layer 1 -> 32 on region W(1) x H(1) (flattened groups of 16);
-            //      operand K slot (lane/16, j) is tap (dy, dx) = (lane/16, j)
+            // ---- first layer 1 -> 32 on region W(1) x H(1) = 34 x 16.  Groups
+            //      0 .. 2 H(1) - 1 are the two 16-pixel halves of a row; the last
+            //      W(1) - 32 groups are columns 32, 33 (16 rows each), so every
+            //      address is a uniform part plus a per-lane constant.  Operand K
+            //      slot (lane/16, j) is tap (dy, dx) = (lane/16, j); the slots of
+            //      lane group 3 have zero weights and read a (finite) record of
+            //      row dy = 2 instead.
             {
                 constexpr int S = G::W(1), HH = G::H(1), HALO = NL - 1;
-                constexpr int npx = S * HH, ngr = (npx + 15) / 16;
+                static_assert(HH == 16 && S > 32 && S <= 48, "first-layer group layout");
+                constexpr int NROWG = 2 * HH, ngr = NROWG + (S - 32);
+                static_assert(NROWG % 4 == 0, "row groups fill whole rounds of the four waves");
                 constexpr int GPW = (ngr + 3) / 4;  // groups per wave
-                // all of a wave's groups are independent: operands first, then the
-                // MFMAs, then the stores, fully unrolled so their latencies overlap
-                short4v bop[GPW];
-                int pry[GPW], prx[GPW];
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) {
-                    const int q = (wave + 4 * k) * 16 + ln;
-                    const bool live = q < npx;
-                    const int qc = live ? q : npx - 1;
-                    pry[k] = live ? q / S : -1;
-                    prx[k] = qc - (qc / S) * S;
-                    const int ryc = qc / S;
-                    bop[k] = short4v{0, 0, 0, 0};
-                    if (lg < 3 && wave + 4 * k < ngr)
-                        bop[k] = *reinterpret_cast<const short4v*>(recs + ((ryc + lg) * RW + prx[k]) * 8);
-                }
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) {
-                    if (wave + 4 * k >= ngr) break;
+                auto operand = [&](int k) {
+                    const int gi = wave + 4 * k;
+                    short4v v = short4v{0, 0, 0, 0};
+                    if (4 * k < NROWG)  // row group: row gi / 2, pixels (gi & 1) * 16 + ln
+                        v = *reinterpret_cast<const short4v*>(recs + rec_wave + k * (2 * RW * 8));
+                    else if (gi < ngr)  // column group: column 32 + gi - NROWG, rows ln
+                        v = *reinterpret_cast<const short4v*>(recs + (32 + gi - NROWG) * 8 + rec_col);
+                    return v;
+                };
+                auto compute_store = [&](int k, short4v bop) {
+                    const int gi = wave + 4 * k;
                     floatx4 acc[2];
 #pragma unroll
                     for (int nb = 0; nb < 2; ++nb) {
                         acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop[k], acc[nb], 0, 0, 0);
+                        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[nb], bop, acc[nb], 0, 0, 0);
                     }
-                    if (pry[k] >= 0) {
-                        const int ry = pry[k], rx = prx[k];
-                        bool inside = true;
-                        if constexpr (EDGE) {
-                            const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
-                            inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
-                        }
+                    const bool rowg = 4 * k < NROWG;
+                    const int ry = rowg ? gi >> 1 : ln_t;
+                    const int rx = rowg ? (gi & 1) * 16 + ln_t : 32 + gi - NROWG;
+                    bool inside = true;
+                    if constexpr (EDGE) {
+                        const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                        inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                    }
 #pragma unroll
-                        for (int nb = 0; nb < 2; ++nb) {
-                            const int co = nb * 16 + lg * 4;
-                            const uint2 v = inside ? relu_pack4(acc[nb]) : make_uint2(0u, 0u);
-                            *reinterpret_cast<uint2*>(bufA + act_addr(ry, rx, co >> 3) + (co & 7) * 2) = v;
-                        }
+                    for (int nb = 0; nb < 2; ++nb) {
+                        // row groups start at a multiple of 16 pixels: the swizzle is the lane's
+                        const int co = nb * 16 + lg_t * 4;
+                        char* o = rowg ? bufA + st_wave[nb] + k * (2 * kP * 64)
+                                       : bufA + (ry * kP + rx) * 64 + swz(rx, co >> 3) + (co & 7) * 2;
+                        *reinterpret_cast<uint2*>(o) = inside ? relu_pack4(acc[nb]) : make_uint2(0u, 0u);
+                    }
+                };
+                if constexpr (NL == 3) {
+                    // all of a wave's groups are independent: operands first, then the
+                    // MFMAs, then the stores, fully unrolled so their latencies overlap
+                    short4v bop[GPW];
+#pragma unroll
+                    for (int k = 0; k < GPW; ++k) bop[k] = operand(k);
+#pragma unroll
+                    for (int k = 0; k < GPW; ++k) {
+                        if (4 * k >= NROWG && wave + 4 * k >= ngr) break;
+                        compute_store(k, bop[k]);
+                    }
+                } else {
+                    // fewer registers: one group's operand in flight ahead of the MFMAs
+                    short4v cur = operand(0);
+#pragma unroll
+                    for (int k = 0; k < GPW; ++k) {
+                        if (4 * k >= NROWG && wave + 4 * k >= ngr) break;
+                        const short4v nxt = k + 1 < GPW ? operand(k + 1) : cur;
+                        compute_store(k, cur);
+                        cur = nxt;
                     }
                 }
             }
             __syncthreads();
-            // ---- hidden layers 32 -> 32: groups are 16 consecutive pixels of a row
+            // ---- hidden layers 32 -> 32.  Wave w computes the 16 pixels of column
+            //      half (w & 1) in the output rows [(w >> 1) R, (w >> 1) R + R),
+            //      R = HH / 2, in blocks of at most RB rows: it reads each input row
+            //      of a block once (taps dx = 0, 1, 2 as three shifted operands) and
+            //      applies it to the up to three output rows that use it, so one
+            //      LDS operand read feeds up to six MFMAs.
+            auto hidden = [&](auto hc) {
+                constexpr int H = decltype(hc)::value;
+                constexpr int layer = 2 + H;
+                constexpr int S = G::W(layer), HH = G::H(layer), HALO = NL - layer;
+                constexpr int R = HH / 2;
+                static_assert(HH % 2 == 0 && S <= 32 && R <= 4 * G::RB, "hidden-layer wave split");
+                const char* ain = (H & 1) ? bufB : bufA;
+                char* aout = (H & 1) ? bufA : bufB;
+                const int rx = (wave & 1) * 16 + ln;
+                const int rbase = (wave >> 1) * R;
+                // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
+                const char* a0 = ain + rx * 64 + swz0;
+                const char* a1 = ain + (rx + 1) * 64 + swz1;
+                const char* a2 = ain + (rx + 2) * 64 + swz2;
+                auto block = [&](auto nc, int r0) {
+                    constexpr int RBk = decltype(nc)::value;
+                    floatx4 acc[RBk][2];
 #pragma unroll
-            for (int h = 0; h < NH; ++h) {
-                const int layer = 2 + h;
-                const int S = TW + 2 * (NL - layer), HH = TH + 2 * (NL - layer), HALO = NL - layer;
-                const int ngr = HH * 2;  // S <= 32: two groups per row
-                const char* ain = (h & 1) ? bufB : bufA;
-                char* aout = (h & 1) ? bufA : bufB;
-                constexpr int GPWH = (2 * G::H(2) + 3) / 4;  // groups per wave, largest hidden region
+                    for (int r = 0; r < RBk; ++r)
+                        for (int nb = 0; nb < 2; ++nb) acc[r][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    // input rows are software-pipelined one ahead; the scheduling
+                    // barriers keep the compiler from hoisting every row's reads
+                    // to the top (which would hold all of them in registers)
+                    auto read_row = [&](int i, bf16x8* bx) {
+                        const int off = (r0 + i) * kP * 64;
+                        bx[0] = *reinterpret_cast<const bf16x8*>(a0 + off);
+                        bx[1] = *reinterpret_cast<const bf16x8*>(a1 + off);
+                        bx[2] = *reinterpret_cast<const bf16x8*>(a2 + off);
+                    };
+                    bf16x8 bnext[3];
+                    read_row(0, bnext);
 #pragma unroll
-                for (int k = 0; k < GPWH; ++k) {
-                    const int gi = wave + 4 * k;
-                    if (gi >= ngr) break;
-                    const int ry = gi >> 1, rx0 = (gi & 1) * 16;
-                    const int rx = rx0 + ln;
-                    // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
-                    const char* a0 = ain + (ry * kP + rx) * 64 + swz0;
-                    const char* a1 = ain + (ry * kP + rx + 1) * 64 + swz1;
-                    const char* a2 = ain + (ry * kP + rx + 2) * 64 + swz2;
-                    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                    for (int i = 0; i < RBk + 2; ++i) {
+                        bf16x8 bx[3] = {bnext[0], bnext[1], bnext[2]};
+                        if (i + 1 < RBk + 2) read_row(i + 1, bnext);
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy) {
-                        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(a0 + dy * kP * 64);
-                        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(a1 + dy * kP * 64);
-                        const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(a2 + dy * kP * 64);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][0], b0, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3][1], b0, acc1, 0, 0, 0);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][0], b1, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 1][1], b1, acc1, 0, 0, 0);
-                        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][0], b2, acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[h][dy * 3 + 2][1], b2, acc1, 0, 0, 0);
+                        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                            for (int dy = 0; dy < 3; ++dy) {
+                                const int r = i - dy;  // output row of this block fed by tap (dy, dx)
+                                if (r < 0 || r >= RBk) continue;
+#pragma unroll
+                                for (int nb = 0; nb < 2; ++nb)
+                                    acc[r][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[kResident ? H : 0][dy * 3 + dx][nb], bx[dx],
+                                                                                         acc[r][nb], 0, 0, 0);
+                            }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                     if (rx < S) {
-                        bool inside = true;
-                        if constexpr (EDGE) {
-                            const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
-                            inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+#pragma unroll
+                        for (int r = 0; r < RBk; ++r) {
+                            const int ry = r0 + r;
+                            bool inside = true;
+                            if constexpr (EDGE) {
+                                const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                                inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                            }
+                            char* o = aout + (ry * kP + rx) * 64;
+                            *reinterpret_cast<uint2*>(o + out_off[0]) =
+                                inside ? relu_pack4(acc[r][0]) : make_uint2(0u, 0u);
+                            *reinterpret_cast<uint2*>(o + out_off[1]) =
+                                inside ? relu_pack4(acc[r][1]) : make_uint2(0u, 0u);
                         }
-                        char* o = aout + (ry * kP + rx) * 64;
-                        *reinterpret_cast<uint2*>(o + out_off[0]) = inside ? relu_pack4(acc0) : make_uint2(0u, 0u);
-                        *reinterpret_cast<uint2*>(o + out_off[1]) = inside ? relu_pack4(acc1) : make_uint2(0u, 0u);
                     }
-                }
+                };
+                constexpr int RB = G::RB, NBLK = (R + RB - 1) / RB;
+                block(std::integral_constant<int, (R < RB ? R : RB)>{}, rbase);
+                if constexpr (NBLK > 1) block(std::integral_constant<int, (R - RB < RB ? R - RB : RB)>{}, rbase + RB);
+                if constexpr (NBLK > 2)
+                    block(std::integral_constant<int, (R - 2 * RB < RB ? R - 2 * RB : RB)>{}, rbase + 2 * RB);
+                if constexpr (NBLK > 3) block(std::integral_constant<int, R - 3 * RB>{}, rbase + 3 * RB);
+                if constexpr (!kResident && H + 1 < NH) load_hidden(0, H + 1);
                 __syncthreads();
-            }
+            };
+            hidden(std::integral_constant<int, 0>{});
+            if constexpr (NH > 1) hidden(std::integral_constant<int, 1>{});
             // ---- last layer 32 -> 1: Z[t][p] on region W(NL-1) x H(NL-1) (tap planes,
             //      so both the stores and the 9-tap gather are unit-stride), then gather
             {
@@ -336,7 +449,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < (TH * TW + kThreads - 1) / kThreads; ++k) {
-                    const int e = tid + k * kThreads;
+                    const int e = tid_t + k * kThreads;
                     if (e >= TH * TW) break;
                     const int oy = e / TW, ox = e - (e / TW) * TW;
                     const int gy = ty0 + oy, gx = tx0 + ox;
@@ -441,6 +554,8 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
     if (!mfma_supported(c, &why)) return fail(NMG_ERR_STATE, why);
     if (!c->wbf) return fail(NMG_ERR_STATE, "no weights loaded for the BF16 smoother");
     const int n = c->n[(size_t)l];
+    if ((size_t)n * n * sizeof(float) >= ((size_t)1 << 31))
+        return fail(NMG_ERR_SHAPE, "BF16 smoother: one image of this level exceeds 2 GiB");
     const uint16_t* wl = c->wbf + (size_t)l * c->p.n_weight_sets * c->wbf_stride;
     if (c->p.n_layers == 3) {
         using G = Geo<3>;
