@@ -122,7 +122,7 @@ __device__ inline uint32_t pack2_bf16(float a, float b) {
 // LDS allows two workgroups (8 waves) per CU, so up to 256 VGPRs cost no occupancy.
 template <int NL>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NL == 3 ? 1 : 2, 2))) k_smoother_mfma(const float* __restrict__ bres,
-                                                            const double* __restrict__ nrm2, float* __restrict__ dst,
+                                                            const double* __restrict__ nrm2, int nparts, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
                                                             size_t set_stride, const int* __restrict__ ws, int nsets,
                                                             int n, int tiles_x, int tiles_per_img) {
@@ -203,7 +203,14 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     const size_t per = (size_t)n * n;
     const float* src = bres + (size_t)img * per;
     float* out = dst + (size_t)img * per;
-    const double nb2 = nrm2[img];
+    // ||b||^2: given, or the sum of this image's partial sums in their order
+    double nb2;
+    if (nparts > 0) {
+        nb2 = 0.0;
+        for (int i = 0; i < nparts; ++i) nb2 += nrm2[(size_t)img * nparts + i];
+    } else {
+        nb2 = nrm2[img];
+    }
     const float nbf = (float)sqrt(nb2);
     const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
 
@@ -548,7 +555,7 @@ nmg_status repack_bf16(Ctx* c, int level, int weight_set) {
 }
 
 nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b, const double* nrm2,
-                                float* dst, int accumulate, Work<float>& w, hipStream_t s) {
+                                int nparts, float* dst, int accumulate, Work<float>& w, hipStream_t s) {
     (void)w;
     std::string why;
     if (!mfma_supported(c, &why)) return fail(NMG_ERR_STATE, why);
@@ -562,13 +569,13 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
         hipLaunchKernelGGL((k_smoother_mfma<3>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
+                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
         hipLaunchKernelGGL((k_smoother_mfma<4>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
+                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     }
     NMG_HIP(hipGetLastError());
     return NMG_OK;

@@ -314,6 +314,9 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
 constexpr int kNormChunksPerRhs = 32;
 template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s);
+// first stage only: c->norm_part[b][kNormChunksPerRhs]
+template <typename T>
+nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s);
 template <typename T>
 nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s);
 template <typename T>
@@ -328,8 +331,12 @@ nmg_status launch_axpy(int batch, size_t elems, const T* src, T* dst, int accumu
 template <typename T>
 nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, const T* b, const double* nrm2,
                                 T* dst, int accumulate, Work<T>& w, hipStream_t s);
+// nparts == 0: nrm2[b] is ||b||^2 of image b; nparts > 0: nrm2 holds the
+// [batch][nparts] partial sums of launch_sumsq_part, which the kernel adds in
+// the order k_sumsq_final uses (same value, one launch fewer)
 nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b,
-                                const double* nrm2, float* dst, int accumulate, Work<float>& w, hipStream_t s);
+                                const double* nrm2, int nparts, float* dst, int accumulate, Work<float>& w,
+                                hipStream_t s);
 template <typename T>
 nmg_status launch_jacobi(const Ctx* c, int l, int batch, const double* alpha, double omega, const T* b, T* dst,
                          int accumulate, Work<T>& w, hipStream_t s);

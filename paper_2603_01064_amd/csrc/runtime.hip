@@ -388,17 +388,22 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
         NMG_TRY(launch_jacobi<T>(c, l, a.batch, a.alpha, c->omega[(size_t)l], bres, target, acc, w, a.s));
     } else {
+        // the BF16 kernel adds the per-image partial sums itself
+        const bool mfma = c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
         {
             ProfScope ps(c, a.s, NMG_K_NORM, l);
-            NMG_TRY(launch_sumsq<T>(c, a.batch, per, bres, c->nrm, a.s));
+            if (mfma)
+                NMG_TRY(launch_sumsq_part<T>(c, a.batch, per, bres, a.s));
+            else
+                NMG_TRY(launch_sumsq<T>(c, a.batch, per, bres, c->nrm, a.s));
         }
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
         if (c->p.smoother_arch == NMG_ARCH_FNO) {
             NMG_TRY(launch_fno_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
         } else if (a.o.precision == NMG_MIXED) {
-            NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->nrm,
-                                         reinterpret_cast<float*>(target), acc, *reinterpret_cast<Work<float>*>(&w),
-                                         a.s));
+            NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->norm_part,
+                                         kNormChunksPerRhs, reinterpret_cast<float*>(target), acc,
+                                         *reinterpret_cast<Work<float>*>(&w), a.s));
         } else {
             NMG_TRY(launch_conv_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
         }
@@ -1133,12 +1138,16 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
     float* oo = (float*)out;
     if (h->kind[(size_t)level] == 1)
         return launch_jacobi<float>(h, level, batch, alpha, h->omega[(size_t)level], bb, oo, 0, h->w32b, s);
+    if (prec == NMG_MIXED && h->p.smoother_arch != NMG_ARCH_FNO) {
+        // as in the cycle: the BF16 kernel adds the per-image partial sums itself
+        NMG_TRY(launch_sumsq_part<float>(h, batch, per, bb, s));
+        return launch_mfma_smoother(h, level, batch, ws, bb, h->norm_part, kNormChunksPerRhs, oo, 0, h->w32b, s);
+    }
     NMG_TRY(launch_sumsq<float>(h, batch, per, bb, h->nrm, s));
     if (h->p.smoother_arch == NMG_ARCH_FNO) {
         NMG_TRY(ensure_acts<float>(h));
         return launch_fno_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
     }
-    if (prec == NMG_MIXED) return launch_mfma_smoother(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
     NMG_TRY(ensure_acts<float>(h));
     return launch_conv_smoother<float>(h, level, batch, ws, bb, h->nrm, oo, 0, h->w32b, s);
 }

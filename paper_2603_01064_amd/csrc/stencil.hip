@@ -987,6 +987,13 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
 }
 
 template <typename T>
+nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, c->norm_part, elems);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+
+template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s) {
     double* part = c->norm_part;
     hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, part, elems);
@@ -1062,6 +1069,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
     template nmg_status launch_operator<T>(const Ctx*, int, int, const double*, const T*, const T*, T*, int,     \
                                            Work<T>&, hipStream_t);                                               \
     template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t);                \
+    template nmg_status launch_sumsq_part<T>(const Ctx*, int, size_t, const T*, hipStream_t);                    \
     template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                     \
     template nmg_status launch_prolong_transpose<T>(const Ctx*, int, int, const T*, T*, hipStream_t);            \
     template nmg_status launch_prolong_add<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                  \

@@ -543,7 +543,7 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
                                            work, s));
         } else if (mixed) {
             NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
-                                         tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
+                                         tw.nrm[(size_t)l], 0, reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
                                          *reinterpret_cast<Work<float>*>(&work), s));
         } else {
             NMG_TRY(launch_conv_smoother<T>(c, l, batch, ws_dev, tw.b[(size_t)l], tw.nrm[(size_t)l], tw.h[(size_t)l],
@@ -650,7 +650,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
                                            work, s));
         } else if (mixed) {
             NMG_TRY(launch_mfma_smoother(c, l, batch, ws_dev, reinterpret_cast<const float*>(tw.b[(size_t)l]),
-                                         tw.nrm[(size_t)l], reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
+                                         tw.nrm[(size_t)l], 0, reinterpret_cast<float*>(tw.h[(size_t)l]), 0,
                                          *reinterpret_cast<Work<float>*>(&work), s));
         } else {
             NMG_TRY(launch_conv_smoother<T>(c, l, batch, ws_dev, tw.b[(size_t)l], tw.nrm[(size_t)l], tw.h[(size_t)l],
