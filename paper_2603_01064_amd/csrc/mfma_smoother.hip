@@ -12,10 +12,13 @@
 // as K:
 //   first layer   1 -> 32 : K = 9 taps (padded to 16), v_mfma 16x16x16 bf16
 //   hidden layers 32 -> 32: per tap K = 32 channels,    v_mfma 16x16x32 bf16
-//   last layer    32 -> 1 : Z[p][t] = sum_c act[p][c] w[c][t] with t as M,
+//   last layer    32 -> 1 : Z[p][t] = sum_c act[p][c] w[c][t] with t as M, taken
+//                           in the epilogue of the last hidden layer with its
+//                           accumulators as the operand (no LDS round trip),
 //                           then out[p] = sum_t Z[p + off(t)][t]
 // Weights are packed once per weight set into the per-lane operand order and
-// kept in registers while a workgroup walks the tiles of its image.
+// kept in registers while a workgroup walks the tiles of its image (with two
+// hidden layers, the weights of one hidden layer at a time).
 #include <type_traits>
 #include <vector>
 
@@ -55,7 +58,8 @@ __device__ inline int act_addr(int r, int c, int g) { return (r * kP + c) * 64 +
 // Packed weight block (uint16 bf16) per (level, set):
 //   first : [nb 2][lane 64][4]          co = nb*16 + lane%16, tap (dy, dx) = (lane/16, j), 0 if dy or dx is 3
 //   hidden: [layer][tap 9][nb 2][lane 64][8]  co = nb*16 + lane%16, ci = 8*(lane/16)+j
-//   last  : [lane 64][8]                t = lane%16 (0 if >= 9), ci = 8*(lane/16)+j
+//   last  : [lane 64][8]                t = lane%16 (0 if >= 9), ci = 4*(lane/16)+j (j < 4),
+//                                       16+4*(lane/16)+j-4 (j >= 4): the accumulator order
 constexpr int kFirstElems = 2 * 64 * 4;
 constexpr int kHiddenElems = 9 * 2 * 64 * 8;
 constexpr int kLastElems = 64 * 8;
@@ -349,6 +353,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                 static_assert(HH % 2 == 0 && S <= 32 && R <= 4 * G::RB, "hidden-layer wave split");
                 const char* ain = (H & 1) ? bufB : bufA;
                 char* aout = (H & 1) ? bufA : bufB;
+                // the last hidden layer feeds the last layer from registers; its
+                // Z planes take the buffer this layer does not read
+                constexpr bool LAST = H == NH - 1;
+                constexpr int ZP = 32, ZN = HH * ZP;  // Z pixel pitch, pixels per tap plane
+                float* Z = reinterpret_cast<float*>(aout);
                 const int rx = (wave & 1) * 16 + ln;
                 const int rbase = (wave >> 1) * R;
                 // taps dx = 1, 2 read pixels rx+1, rx+2, whose swizzle uses (ln+dx) & 3
@@ -390,7 +399,40 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                             }
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                    if (rx < S) {
+                    if constexpr (LAST) {
+                        // last layer 32 -> 1 straight from the accumulators: lane (ln, lg)
+                        // holds channels 4 lg .. 4 lg + 3 and 16 + 4 lg .. 16 + 4 lg + 3 of
+                        // pixel ln, which are K slots 8 lg .. 8 lg + 7 of the last-layer
+                        // weights as packed.  Z[t][p] = sum_c act[p][c] w[c][t] (taps
+                        // t = 4 lg + i) goes to tap planes, so these stores and the 9-tap
+                        // gather are unit-stride.
+#pragma unroll
+                        for (int r = 0; r < RBk; ++r) {
+                            const int ry = r0 + r;
+                            bool inside = true;
+                            if constexpr (EDGE) {
+                                const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
+                                inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                            }
+                            const uint2 p0 = inside ? relu_pack4(acc[r][0]) : make_uint2(0u, 0u);
+                            const uint2 p1 = inside ? relu_pack4(acc[r][1]) : make_uint2(0u, 0u);
+                            const uint4 pk = make_uint4(p0.x, p0.y, p1.x, p1.y);
+                            bf16x8 bl;
+                            __builtin_memcpy(&bl, &pk, 16);
+                            floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bl, z, 0, 0, 0);
+                            if (rx < S && lg_t < 3) {
+                                // only taps 0..8 exist
+                                float* zp = Z + (lg_t * 4) * ZN + ry * ZP + rx;
+                                zp[0] = z[0];
+                                if (lg_t < 2) {
+                                    zp[ZN] = z[1];
+                                    zp[2 * ZN] = z[2];
+                                    zp[3 * ZN] = z[3];
+                                }
+                            }
+                        }
+                    } else if (rx < S) {
 #pragma unroll
                         for (int r = 0; r < RBk; ++r) {
                             const int ry = r0 + r;
@@ -418,42 +460,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
             };
             hidden(std::integral_constant<int, 0>{});
             if constexpr (NH > 1) hidden(std::integral_constant<int, 1>{});
-            // ---- last layer 32 -> 1: Z[t][p] on region W(NL-1) x H(NL-1) (tap planes,
-            //      so both the stores and the 9-tap gather are unit-stride), then gather
+            // ---- out[p] = ||b|| sum_t Z[t][p + off(t)] (the Z planes were written by
+            //      the last hidden layer, before its barrier)
             {
-                constexpr int S = G::W(NL - 1), HH = G::H(NL - 1);
-                constexpr int ngr = HH * 2;
-                constexpr int ZP = 32;          // Z pixel pitch
-                constexpr int ZN = HH * ZP;     // pixels per tap plane
-                const char* ain = (NH & 1) ? bufB : bufA;
-                float* Z = reinterpret_cast<float*>((NH & 1) ? bufA : bufB);
-                constexpr int GPW = (ngr + 3) / 4;
-                bf16x8 bl[GPW];
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) {
-                    const int gi = wave + 4 * k;
-                    const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
-                    if (gi < ngr) bl[k] = *reinterpret_cast<const bf16x8*>(ain + (ry * kP + rx) * 64 + swz0);
-                }
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) {
-                    const int gi = wave + 4 * k;
-                    if (gi >= ngr) break;
-                    const int ry = gi >> 1, rx = (gi & 1) * 16 + ln;
-                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, bl[k], acc, 0, 0, 0);
-                    if (rx < S && lg < 3) {
-                        // lane group lg holds taps 4 lg .. 4 lg + 3; only taps 0..8 exist
-                        float* zp = Z + (lg * 4) * ZN + ry * ZP + rx;
-                        zp[0] = acc[0];
-                        if (lg < 2) {
-                            zp[ZN] = acc[1];
-                            zp[2 * ZN] = acc[2];
-                            zp[3 * ZN] = acc[3];
-                        }
-                    }
-                }
-                __syncthreads();
+                constexpr int HH = G::H(NL - 1);
+                constexpr int ZP = 32, ZN = HH * ZP;
+                const float* Z = reinterpret_cast<const float*>((NH & 1) ? bufB : bufA);
 #pragma unroll
                 for (int k = 0; k < (TH * TW + kThreads - 1) / kThreads; ++k) {
                     const int e = tid_t + k * kThreads;
@@ -476,7 +488,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
             layers(std::false_type{});
         else
             layers(std::true_type{});
-        __syncthreads();
+        // no barrier here: the next tile writes the records (read only by this
+        // tile's first layer, behind its barrier) and then waits at its own
+        // first barrier, which every wave reaches only after this gather
     }
 }
 
@@ -544,9 +558,11 @@ nmg_status repack_bf16(Ctx* c, int level, int weight_set) {
                     }
     }
     const float* wl = w.data() + c->layer_off[(size_t)c->p.n_layers - 1];  // [1][32][3][3]
+    // K slot (lane/16, j) of the last layer is the channel that the hidden
+    // layer's accumulators put there: 4 (lane/16) + j, then 16 + 4 (lane/16) + j - 4
     for (int lane = 0; lane < 64; ++lane)
         for (int j = 0; j < 8; ++j) {
-            const int t = lane % 16, ci = 8 * (lane / 16) + j;
+            const int t = lane % 16, g = lane / 16, ci = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
             pk[kFirstElems + (size_t)NH * kHiddenElems + (size_t)lane * 8 + j] = t < 9 ? f2bf(wl[ci * 9 + t]) : 0;
         }
     const size_t dst = ((size_t)level * c->p.n_weight_sets + weight_set) * stride;
