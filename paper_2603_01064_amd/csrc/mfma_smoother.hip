@@ -580,16 +580,23 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
     if ((size_t)n * n * sizeof(float) >= ((size_t)1 << 31))
         return fail(NMG_ERR_SHAPE, "BF16 smoother: one image of this level exceeds 2 GiB");
     const uint16_t* wl = c->wbf + (size_t)l * c->p.n_weight_sets * c->wbf_stride;
+    // one resident round of workgroups (two per CU) over the batch: the
+    // workgroups have equal work, so a second, partial round would leave
+    // most CUs idle at its end
+    int dev = 0, cus = 0;
+    NMG_HIP(hipGetDevice(&dev));
+    NMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    auto grid_x = [&](int tiles) { return std::max(1, std::min(tiles, std::max(1, 2 * cus) / batch)); };
     if (c->p.n_layers == 3) {
         using G = Geo<3>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
-        const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
+        const int per_img = grid_x(tiles);
         hipLaunchKernelGGL((k_smoother_mfma<3>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
-        const int per_img = std::max(1, std::min(tiles, (1024 + batch - 1) / batch));
+        const int per_img = grid_x(tiles);
         hipLaunchKernelGGL((k_smoother_mfma<4>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
                            nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
     }
