@@ -138,7 +138,17 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     char* bufA = smem + G::in_bytes;
     char* bufB = bufA + G::bufA;
 
-    const int img = blockIdx.y;
+    // XCD-aware assignment: workgroups are dispatched round-robin over the 8
+    // XCDs by linear id, so the (image, workgroup-in-image) pairs are numbered
+    // XCD-major; the workgroups of one image then run on one XCD and share its
+    // L2 (tile halos, and output cache lines split between neighbouring tiles)
+    int img, wgi;
+    {
+        const int G = gridDim.x * gridDim.y, i = blockIdx.x + blockIdx.y * gridDim.x;
+        const int p = G % 8 == 0 ? (i % 8) * (G / 8) + i / 8 : i;
+        img = p / gridDim.x;
+        wgi = p - img * gridDim.x;
+    }
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: kept in an SGPR
@@ -243,9 +253,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
             }
         }
     };
-    load_records(blockIdx.x, tid);
+    load_records(wgi, tid);
 
-    for (int tile = blockIdx.x; tile < tiles_per_img; tile += gridDim.x) {
+    for (int tile = wgi; tile < tiles_per_img; tile += gridDim.x) {
         // per-tile copies of the lane indices: the per-lane index arithmetic of
         // the first and last layers is redone every tile instead of being kept
         // live (or spilled) across the loop
