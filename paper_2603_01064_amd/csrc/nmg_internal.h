@@ -318,7 +318,10 @@ nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, doubl
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s);
 template <typename T>
-nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s);
+nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s,
+                           double* norm_part = nullptr);
+// number of partial sums launch_restrict writes per image for level l -> l + 1
+int restrict_norm_parts(const Ctx* c, int l);
 template <typename T>
 nmg_status launch_prolong_transpose(const Ctx* c, int l, int batch, const T* g, T* out, hipStream_t s);
 template <typename T>

@@ -371,8 +371,10 @@ struct CycleArgs {
     hipStream_t s;
 };
 
+// parts_ready > 0: c->norm_part already holds that many partial sums of
+// ||y||^2 per right-hand side (written by the restriction that produced y)
 template <typename T>
-nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
+nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int parts_ready = 0) {
     Ctx* c = a.c;
     Work<T>& w = *a.w;
     const size_t per = level_elems(c, l);
@@ -390,7 +392,9 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
     } else {
         // the BF16 kernel adds the per-image partial sums itself
         const bool mfma = c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
-        {
+        const bool have_parts = mfma && x_zero && parts_ready > 0;
+        const int nparts = have_parts ? parts_ready : kNormChunksPerRhs;
+        if (!have_parts) {
             ProfScope ps(c, a.s, NMG_K_NORM, l);
             if (mfma)
                 NMG_TRY(launch_sumsq_part<T>(c, a.batch, per, bres, a.s));
@@ -402,7 +406,7 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
             NMG_TRY(launch_fno_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
         } else if (a.o.precision == NMG_MIXED) {
             NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->norm_part,
-                                         kNormChunksPerRhs, reinterpret_cast<float*>(target), acc,
+                                         nparts, reinterpret_cast<float*>(target), acc,
                                          *reinterpret_cast<Work<float>*>(&w), a.s));
         } else {
             NMG_TRY(launch_conv_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
@@ -424,7 +428,7 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
 }
 
 template <typename T>
-nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
+nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int parts_ready = 0) {
     Ctx* c = a.c;
     Work<T>& w = *a.w;
     if (l == c->L - 1) {
@@ -438,7 +442,7 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
         NMG_TRY(launch_zero<T>(x, (size_t)a.batch * per, a.s));
     }
     for (int k = 0; k < a.o.nu1; ++k) {
-        NMG_TRY(smooth_step<T>(a, l, x, y, x_zero));
+        NMG_TRY(smooth_step<T>(a, l, x, y, x_zero, k == 0 ? parts_ready : 0));
         x_zero = false;
     }
     LevelBuffers<T>& lb = w.lv[(size_t)l];
@@ -446,11 +450,17 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero) {
         ProfScope ps(c, a.s, NMG_K_OPERATOR, l);
         NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, lb.b, 0, w, a.s));
     }
+    // the restriction also writes the first stage of ||y_{l+1}||^2 when the next
+    // level starts with a BF16 neural smoothing step on it
+    const bool fuse_norm = l + 1 < c->L - 1 && a.o.nu1 > 0 && c->kind[(size_t)l + 1] == 0 &&
+                           a.o.precision == NMG_MIXED && c->p.smoother_arch != NMG_ARCH_FNO;
     {
         ProfScope ps(c, a.s, NMG_K_RESTRICT, l);
-        NMG_TRY(launch_restrict<T>(c, l, a.batch, lb.b, w.lv[(size_t)l + 1].y, a.s));
+        NMG_TRY(launch_restrict<T>(c, l, a.batch, lb.b, w.lv[(size_t)l + 1].y, a.s,
+                                   fuse_norm ? c->norm_part : nullptr));
     }
-    NMG_TRY(cycle<T>(a, l + 1, w.lv[(size_t)l + 1].x, w.lv[(size_t)l + 1].y, true));
+    NMG_TRY(cycle<T>(a, l + 1, w.lv[(size_t)l + 1].x, w.lv[(size_t)l + 1].y, true,
+                     fuse_norm ? restrict_norm_parts(c, l) : 0));
     {
         ProfScope ps(c, a.s, NMG_K_PROLONG, l);
         NMG_TRY(launch_prolong_add<T>(c, l, a.batch, w.lv[(size_t)l + 1].x, x, a.s));

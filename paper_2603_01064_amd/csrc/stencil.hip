@@ -9,6 +9,8 @@
 // values (Sec. 2.3).
 #include <type_traits>
 
+#include <algorithm>
+
 #include "nmg_internal.h"
 
 namespace nmg {
@@ -127,31 +129,46 @@ __device__ inline void restrict_taps(int i, int* idx, T* w) {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r, T* __restrict__ yc, int nf, int nc,
-                                                     int two_d, T scale) {
+                                                     int two_d, T scale, double* __restrict__ part) {
     const int rows_c = two_d ? nc : 1;
     const size_t perc = (size_t)rows_c * nc;
-    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= perc) return;
     const int b = blockIdx.y;
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
-    const int i = (int)(e / nc), j = (int)(e % nc);
-    int ij[3], ii[3];
-    T wj[3], wi[3];
-    restrict_taps<T>(j, ij, wj);
-    restrict_taps<T>(i, ii, wi);
     const T* src = r + (size_t)b * perf;
-    T acc = 0;
-    if (two_d) {
-        for (int a = 0; a < 3; ++a) {
-            const T* row = src + (size_t)ii[a] * nf;
-            T ra = 0;
-            for (int c = 0; c < 3; ++c) ra += wj[c] * row[ij[c]];
-            acc += wi[a] * ra;
+    double sq = 0.0;
+    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < perc; e += (size_t)gridDim.x * kBlock) {
+        const int i = (int)(e / nc), j = (int)(e % nc);
+        int ij[3], ii[3];
+        T wj[3], wi[3];
+        restrict_taps<T>(j, ij, wj);
+        restrict_taps<T>(i, ii, wi);
+        T acc = 0;
+        if (two_d) {
+            for (int a = 0; a < 3; ++a) {
+                const T* row = src + (size_t)ii[a] * nf;
+                T ra = 0;
+                for (int c = 0; c < 3; ++c) ra += wj[c] * row[ij[c]];
+                acc += wi[a] * ra;
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) acc += wj[c] * src[ij[c]];
         }
-    } else {
-        for (int c = 0; c < 3; ++c) acc += wj[c] * src[ij[c]];
+        const T v = scale * acc;
+        yc[(size_t)b * perc + e] = v;
+        sq += (double)v * (double)v;
     }
-    yc[(size_t)b * perc + e] = scale * acc;
+    // optional: this block's partial sum of squares of the output (the first
+    // stage of ||yc||^2, for a consumer that adds the gridDim.x partials)
+    if (part) {
+        __shared__ double red[kBlock];
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+    }
 }
 
 // Linear interpolation and correction: x += P e (2D: P e P^T).
@@ -1002,12 +1019,18 @@ nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, doubl
     return NMG_OK;
 }
 
+int restrict_norm_parts(const Ctx* c, int l) {
+    return (int)std::min<unsigned>(blocks_for(level_elems(c, l + 1)), (unsigned)kNormChunksPerRhs);
+}
+
 template <typename T>
-nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s) {
+nmg_status launch_restrict(const Ctx* c, int l, int batch, const T* r, T* yc, hipStream_t s, double* norm_part) {
     const int nf = c->n[l], nc = c->n[l + 1];
     const size_t perc = level_elems(c, l + 1);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(perc), batch), dim3(kBlock), 0, s, r, yc, nf, nc,
-                       c->p.dim == 2 ? 1 : 0, (T)1);
+    // with partial sums: at most kNormChunksPerRhs blocks per image, grid-stride
+    const unsigned gx = norm_part ? (unsigned)restrict_norm_parts(c, l) : blocks_for(perc);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(gx, batch), dim3(kBlock), 0, s, r, yc, nf, nc, c->p.dim == 2 ? 1 : 0,
+                       (T)1, norm_part);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -1018,7 +1041,7 @@ nmg_status launch_prolong_transpose(const Ctx* c, int l, int batch, const T* g, 
     const int nf = c->n[l], nc = c->n[l + 1];
     const size_t perc = level_elems(c, l + 1);
     hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(perc), batch), dim3(kBlock), 0, s, g, out, nf, nc,
-                       c->p.dim == 2 ? 1 : 0, (T)(c->p.dim == 2 ? 4 : 2));
+                       c->p.dim == 2 ? 1 : 0, (T)(c->p.dim == 2 ? 4 : 2), (double*)nullptr);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -1070,7 +1093,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
                                            Work<T>&, hipStream_t);                                               \
     template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t);                \
     template nmg_status launch_sumsq_part<T>(const Ctx*, int, size_t, const T*, hipStream_t);                    \
-    template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                     \
+    template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t, double*);            \
     template nmg_status launch_prolong_transpose<T>(const Ctx*, int, int, const T*, T*, hipStream_t);            \
     template nmg_status launch_prolong_add<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                  \
     template nmg_status launch_axpy<T>(int, size_t, const T*, T*, int, hipStream_t);                             \
