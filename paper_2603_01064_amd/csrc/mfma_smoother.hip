@@ -140,12 +140,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
 
     // XCD-aware assignment: workgroups are dispatched round-robin over the 8
     // XCDs by linear id, so the (image, workgroup-in-image) pairs are numbered
-    // XCD-major; the workgroups of one image then run on one XCD and share its
-    // L2 (tile halos, and output cache lines split between neighbouring tiles)
+    // XCD-major (XCD x takes the contiguous range of its G/8 or G/8 + 1
+    // workgroups); the workgroups of one image then run on one XCD, or two,
+    // and share its L2 (tile halos, and output cache lines split between
+    // neighbouring tiles)
     int img, wgi;
     {
         const int G = gridDim.x * gridDim.y, i = blockIdx.x + blockIdx.y * gridDim.x;
-        const int p = G % 8 == 0 ? (i % 8) * (G / 8) + i / 8 : i;
+        const int x = i % 8, q = G / 8, rem = G % 8;
+        const int p = x * q + min(x, rem) + i / 8;
         img = p / gridDim.x;
         wgi = p - img * gridDim.x;
     }
