@@ -127,3 +127,39 @@ def test_pool_budget_bounds_bytes_in_flight():
     pool.close()
     h63.close()
     h255.close()
+
+
+def test_pool_close_with_requests_in_flight_resets_members():
+    """Closing a pool while requests are queued and running abandons them and
+    resets its members' serving state.  The handle then serves a request of
+    its own with the solo solve's result, and joins a new pool."""
+    print("case pool close with requests in flight", flush=True)
+    nmg = _nmg()
+    dev = torch.device("cuda:0")
+    h63 = _jacobi_handle(nmg, 63, 0.04, 4, 4, 0.1)
+    pool = nmg.Pool(64 << 30)
+    pool.add(h63)
+    for i in range(6):
+        b = _rhs(h63, 63, 0.3, 2900 + i, dev)
+        pool.submit(0, b, torch.zeros_like(b), 0.3, rid=i)
+    kw = dict(rtol=1e-6, max_cycles=300, precision="fp32")
+    # one outer iteration: all six handed to the member, whose four slots run
+    assert pool.step(**kw) == []
+    assert pool.pending()[:2] == (0, 6)
+    assert h63.serve_pending() == (2, 4)
+    pool.close()
+    assert h63.serve_pending() == (0, 0)
+    b = _rhs(h63, 63, 0.3, 2950, dev)
+    x = torch.zeros_like(b)
+    h63.serve_submit(b, x, 0.3, rid=50)
+    done = []
+    while not done:
+        done = h63.serve_step(**kw)
+    assert len(done) == 1 and int(done[0].id) == 50 and int(done[0].status) == 0
+    xs, cs, _, st = h63.solve(b[None], torch.tensor([0.3], dtype=DT, device=dev), **kw)
+    assert st == 0 and int(cs[0]) == int(done[0].cycles)
+    assert torch.equal(xs[0], x)
+    pool2 = nmg.Pool(64 << 30)
+    pool2.add(h63)
+    pool2.close()
+    h63.close()
