@@ -44,7 +44,8 @@ inline uint16_t f2bf_h(float f) {
 // 64 (i) x 128 (j); wave w computes rows 32*(w/2).. and columns 64*(w%2).. as
 // 2 x 4 MFMA blocks.  Each k-step of 32 stages the A tile (in) and the B
 // tile (Mat) in LDS with the 16-byte chunk of row r stored at chunk ^ (r & 3)
-// to spread the fragment reads over banks.
+// to spread the fragment reads over banks; four k-steps are staged per
+// barrier pair.
 //   IN  0: in is the FP32 n x n level array (rounded to BF16 while staging)
 //       1: in is a BF16 npad x npad intermediate (zero padded)
 //   OUT 0: BF16 npad x npad intermediate; 1: the same times the ramp mask;
@@ -60,8 +61,11 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__
                                                         const uint16_t* __restrict__ mat,
                                                         const float* __restrict__ ramp, int n, int npad,
                                                         int tiles_j, int accumulate) {
-    __shared__ __attribute__((aligned(16))) char As[kTI * kKS * 2];
-    __shared__ __attribute__((aligned(16))) char Bs[kTJ * kKS * 2];
+    // kKC K steps of 32 are staged per barrier pair: every thread has all of
+    // its loads of a 128-wide K chunk in flight at once
+    constexpr int kKC = 4;
+    __shared__ __attribute__((aligned(16))) char As[kKC][kTI * kKS * 2];
+    __shared__ __attribute__((aligned(16))) char Bs[kKC][kTJ * kKS * 2];
     const int b = blockIdx.y;
     const int ti = blockIdx.x / tiles_j, tj = blockIdx.x % tiles_j;
     const int tid = threadIdx.x;
@@ -74,34 +78,43 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__
         for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     // staging roles: A: row tid/4, chunk tid%4 (8 values); B: rows tid/4 and 64 + tid/4
     const int sr = tid >> 2, sc = tid & 3;
-    for (int k0 = 0; k0 < npad; k0 += kKS) {
-        {
-            const int i = i0 + sr, k = k0 + sc * 8;
+    for (int k0 = 0; k0 < npad; k0 += kKS * kKC) {  // npad is a multiple of 128
+        uint4 areg[kKC], breg[kKC][2];
+#pragma unroll
+        for (int s = 0; s < kKC; ++s) {
+            const int i = i0 + sr, k = k0 + s * kKS + sc * 8;
             if constexpr (IN == 0) {
                 const float* src = reinterpret_cast<const float*>(in_v) + (size_t)b * n * n;
                 float v[8];
                 for (int q = 0; q < 8; ++q) v[q] = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
-                *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) = make_uint4(
-                    pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+                areg[s] = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]),
+                                     pack_bf16(v[6], v[7]));
             } else {
                 const uint16_t* src = reinterpret_cast<const uint16_t*>(in_v) + (size_t)b * npad * npad;
-                *reinterpret_cast<uint4*>(As + frag_off(sr, sc)) =
-                    *reinterpret_cast<const uint4*>(src + (size_t)i * npad + k);
+                areg[s] = *reinterpret_cast<const uint4*>(src + (size_t)i * npad + k);
             }
             for (int h = 0; h < 2; ++h) {
-                const int jr = sr + 64 * h;
-                const int j = j0 + jr;  // < npad by construction
-                *reinterpret_cast<uint4*>(Bs + frag_off(jr, sc)) =
-                    *reinterpret_cast<const uint4*>(mat + (size_t)j * npad + k0 + sc * 8);
+                const int j = j0 + sr + 64 * h;  // < npad by construction
+                breg[s][h] = *reinterpret_cast<const uint4*>(mat + (size_t)j * npad + k);
             }
         }
+#pragma unroll
+        for (int s = 0; s < kKC; ++s) {
+            *reinterpret_cast<uint4*>(As[s] + frag_off(sr, sc)) = areg[s];
+            for (int h = 0; h < 2; ++h) *reinterpret_cast<uint4*>(Bs[s] + frag_off(sr + 64 * h, sc)) = breg[s][h];
+        }
         __syncthreads();
-        bf16x8 af[2], bfr[4];
-        for (int r = 0; r < 2; ++r) af[r] = *reinterpret_cast<const bf16x8*>(As + frag_off(wi + r * 16 + ln, lg));
-        for (int c = 0; c < 4; ++c) bfr[c] = *reinterpret_cast<const bf16x8*>(Bs + frag_off(wj + c * 16 + ln, lg));
-        for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int s = 0; s < kKC; ++s) {
+            bf16x8 af[2], bfr[4];
+            for (int r = 0; r < 2; ++r)
+                af[r] = *reinterpret_cast<const bf16x8*>(As[s] + frag_off(wi + r * 16 + ln, lg));
             for (int c = 0; c < 4; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
+                bfr[c] = *reinterpret_cast<const bf16x8*>(Bs[s] + frag_off(wj + c * 16 + ln, lg));
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 4; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfr[c], acc[r][c], 0, 0, 0);
+        }
         __syncthreads();
     }
     for (int r = 0; r < 2; ++r)
