@@ -53,6 +53,18 @@ What the paper fixes and how each piece is pinned (tests marked ``not gpu``):
 * Combined loss (Sec. 3.2 eq. "loss_1"): pinned by the two-grid error
   propagation identity built from dense matrices and by central finite
   differences of the joint gradient over all levels.
+* Level-wise loss value: pinned by rebuilding every level's unresolved error
+  from the recorded cycle with direct hat-function interpolation to the
+  finest grid and measuring its band energy in the eigenbasis of the
+  Neumann second-difference matrix (the DCT-II basis found another way).
+* FNO smoother wrapper ``||b|| N(b/||b||)``: pinned by a pure-Python
+  evaluation of the whole FNO on a small 1D grid with the norm summed by
+  hand, its degree-one homogeneity (the network itself has biases, so only
+  the wrapper makes it homogeneous) and ``h = 0`` at ``b = 0``.
+* Training data (Algorithm 5 DataGeneration): pinned by a dense textbook
+  damped-Jacobi cycle (the rollout is then linear, ``e <- E e``), by one
+  rollout with the exact finest-level smoother (the error vanishes), and by
+  ``y = A e`` against the dense operator.
 
 Parity unpinned: iteration counts of trained or seeded neural cycles (the
 paper prints no worked values for them); they are compared GPU-vs-oracle only.
@@ -656,6 +668,31 @@ def level_loss_grads(H: Hierarchy, weights: Sequence[Sequence[torch.Tensor]], e:
     total.backward()
     grads = [[w.grad.detach().clone() for w in lw] for lw in ws]
     return torch.stack([x.detach() for x in losses]), grads
+
+
+def data_generation(H: Hierarchy, smoothers: Sequence[Callable], e: torch.Tensor, alpha: torch.Tensor,
+                    k: Sequence[int], nu1: int = 1, nu2: int = 0, use_fprime: bool = False):
+    """Training pairs of the DataGeneration procedure of Algorithm 5.
+
+    Sample ``i`` starts from the drawn error ``e_i`` and goes through
+    ``k[i]`` rollout cycles with the current smoothers (Algorithm 5 draws
+    ``k[i]`` uniformly from ``1..K``; the caller draws it and passes it in):
+    ``e_i <- e_i - MG(0, A e_i)``, after which the right-hand side is
+    ``y_i = A e_i`` again.  Reading of the printed update ``y <- y - A x``:
+    the pair is kept consistent, ``y = A x`` (taken literally it would turn
+    ``y`` into ``A MG(0, y)``, which no longer matches ``x``).  The cycle is
+    the one the smoothers are trained in, V(nu1, nu2) with or without
+    ``F'``.  No gradient flows through the rollout.  Returns ``(e, y)``."""
+    out = e.detach().clone()
+    with torch.no_grad():
+        for i in range(out.shape[0]):
+            ei = out[i:i + 1]
+            ai = alpha[i:i + 1]
+            for _ in range(int(k[i])):
+                yi = apply_operator(H, 0, ei, ai)
+                ei = ei - vcycle(H, smoothers, torch.zeros_like(ei), yi, ai, nu1, nu2, use_fprime)
+            out[i] = ei[0]
+        return out, apply_operator(H, 0, out, alpha)
 
 
 def fno_from_real(p: dict) -> dict:

@@ -551,6 +551,87 @@ def test_level_loss_gradient_matches_central_differences():
                 assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (l, li, idx, fd, g)
 
 
+def _hat_interp_to_finest(N, nl):
+    """Linear interpolation from a level of nl points straight to the finest
+    grid of N points (nested grids, zero boundary): the coarse hat function
+    of node i evaluated at fine node p.  N + 1 = 2^j (nl + 1)."""
+    q = (N + 1) // (nl + 1)
+    Q = np.zeros((N, nl))
+    for p in range(N):
+        for i in range(nl):
+            Q[p, i] = max(0.0, 1.0 - abs((p + 1) - (i + 1) * q) / q)
+    return Q
+
+
+def _neumann_cosine_basis(n):
+    """Eigenvectors of the second-difference matrix with reflecting ends
+    (diag 1, 2, ..., 2, 1; off-diagonals -1), ordered by eigenvalue
+    2 - 2 cos(pi k / n): column k is the DCT-II basis vector of frequency k
+    (up to sign), found without the cosine formula."""
+    T = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    T[0, 0] = T[-1, -1] = 1.0
+    lam, V = np.linalg.eigh(T)
+    assert np.all(np.diff(lam) > 1e-9)
+    return V
+
+
+def _mask_from_bands(N, lev, kind):
+    """m_l on the finest grid of N points for level lev (1-based), from the
+    band definitions of Sec. 2.3 and the ramp of Sec. 3.2 in exact rationals:
+    omega / pi = max(k1, k2) / N."""
+    from fractions import Fraction as Fr
+    m = np.zeros((N, N))
+    top = Fr(1, 2 ** (lev - 1))
+    for k1 in range(N):
+        for k2 in range(N):
+            w = Fr(max(k1, k2), N)
+            if kind == "band":
+                m[k1, k2] = 1.0 if (Fr(1, 2 ** lev) < w <= top) else 0.0
+            elif w <= top:
+                m[k1, k2] = math.sqrt(float(w / top))
+    return m
+
+
+@pytest.mark.parametrize("kind", ["band", "ramp"])
+@pytest.mark.parametrize("use_fp", [False, True])
+def test_level_losses_value_from_cycle_record(kind, use_fp):
+    """eq. loss_2_modified / eq. loss_3, value by another route.  The cycle
+    from zero with pre-smoothing only records (level, b_l, h_l); the level-l
+    unresolved error e - sum_{k<l} I_k F'_k(h_k) - I_l h_l is formed with
+    direct hat-function interpolation, F'_k on the level grid and the masked
+    energy both use the reflecting second-difference eigenbasis, and the
+    masks come from the band definitions.  A wrong mask level, h used where
+    F'(h) belongs (or the reverse), a missing residual update between levels
+    or a wrong batch normalisation fails it."""
+    N, L = 31, 4
+    H, W, S = _setup(n=N, L=L)
+    e = torch.randn(3, N, N, dtype=DT, generator=torch.Generator().manual_seed(25))
+    a = torch.tensor([1e-2, 1e-3, 1e-4], dtype=DT)
+    got = torch.stack(O.level_losses(H, W, e, a, kind, use_fp)).numpy()
+    rec = []
+    O.vcycle(H, S, torch.zeros_like(e), O.apply_operator(H, 0, e, a), a, 1, 0, use_fp, record=rec)
+    assert [r[0] for r in rec] == list(range(L - 1))
+    V = _neumann_cosine_basis(N)
+    ref = []
+    resolved = np.zeros((3, N, N))
+    for (l, b, h) in rec:
+        nl = h.shape[-1]
+        Q = _hat_interp_to_finest(N, nl)
+        hn = h.numpy()
+        err = e.numpy() - resolved - np.einsum("pi,bij,qj->bpq", Q, hn, Q)
+        m = _mask_from_bands(N, l + 1, kind)
+        ref.append(sum(float(((m * (V.T @ err[i] @ V)) ** 2).sum()) for i in range(3)) / 3)
+        if use_fp:
+            Vl = _neumann_cosine_basis(nl)
+            kk = np.arange(nl)
+            mp = np.sqrt(np.maximum(kk[:, None], kk[None, :]) / nl)
+            hn = np.stack([Vl @ (mp * (Vl.T @ hn[i] @ Vl)) @ Vl.T for i in range(3)])
+        resolved = resolved + np.einsum("pi,bij,qj->bpq", Q, hn, Q)
+    ref = np.array(ref)
+    assert np.all(ref > 0)
+    assert np.allclose(got, ref, rtol=1e-11, atol=0), (got, ref)
+
+
 def test_level_loss_gradient_ignores_later_levels():
     """dL_l/dtheta_k = 0 for k > l and the update of theta_l uses L_l only."""
     H, W, _ = _setup(n=15, L=3, ch=(1, 4, 4, 1))
@@ -604,6 +685,67 @@ def test_cycle_loss_gradient_matches_central_differences(use_fp):
                 g = float(grads[l][li][idx])
                 assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (l, li, idx, fd, g)
     assert float(grads[0][0].abs().max()) > 0 and float(grads[1][0].abs().max()) > 0
+
+
+def _dense_jacobi_setup(n, s, alpha, L):
+    K = O.conv_matrix(n, s)
+    A1 = torch.kron(K, K).T @ torch.kron(K, K) + alpha * torch.eye(n * n, dtype=DT)
+    As, Ps = [A1.numpy()], []
+    nl = n
+    for _ in range(L - 1):
+        nc = (nl - 1) // 2
+        P1 = _hat_interp_to_finest(nl, nc)  # one level: nl + 1 = 2 (nc + 1)
+        P2 = np.kron(P1, P1)
+        As.append(P2.T @ As[-1] @ P2 / 4.0)
+        Ps.append(P2)
+        nl = nc
+    omegas = []
+    for l in range(L - 1):
+        Dm = np.diag(1.0 / np.diag(As[l]))
+        omegas.append(0.8 / float(np.max(np.abs(np.linalg.eigvals(Dm @ As[l])))))
+    return As, Ps, omegas
+
+
+def test_data_generation_linear_rollout_matches_textbook_cycle():
+    """Algorithm 5 DataGeneration with a linear (damped-Jacobi) smoother: the
+    rollout is e <- e - MG(0, A e), i.e. k applications of the error
+    propagator, computed here with the dense textbook cycle.  Per-sample
+    rollout counts differ (k = 1, 3, 2) and y = A e holds afterwards."""
+    n, s, alpha, L = 15, 0.06, 1e-2, 3
+    As, Ps, omegas = _dense_jacobi_setup(n, s, alpha, L)
+    H = O.build_hierarchy(n, s, L, dim=2)
+    e0 = torch.randn(3, n, n, dtype=DT, generator=torch.Generator().manual_seed(26))
+    a = torch.full((3,), alpha, dtype=DT)
+    ks = [1, 3, 2]
+    for nu1, nu2 in ((1, 0), (1, 1)):
+        e, y = O.data_generation(H, [O.jacobi_smoother(omegas)] * (L - 1), e0, a, ks, nu1, nu2, False)
+        for i in range(3):
+            v = e0[i].reshape(-1).numpy()
+            for _ in range(ks[i]):
+                v = v - _textbook_jacobi_vcycle(As, Ps, omegas, np.zeros(n * n), As[0] @ v, 0, nu1, nu2)
+            assert np.allclose(e[i].reshape(-1).numpy(), v, rtol=0, atol=1e-12 * np.abs(v).max())
+            assert np.allclose(y[i].reshape(-1).numpy(), As[0] @ e[i].reshape(-1).numpy(), rtol=0,
+                               atol=1e-12 * np.abs(y[i].numpy()).max())
+        # the rollout contracts the error in the A-norm (convergent symmetric cycle)
+        if nu2 == 1:
+            An = lambda t: float(t.reshape(-1).numpy() @ As[0] @ t.reshape(-1).numpy())
+            assert all(An(e[i]) < An(e0[i]) for i in range(3))
+
+
+def test_data_generation_exact_smoother_leaves_no_error():
+    """With the exact finest-level smoother S = A^{-1} one rollout cycle
+    removes the whole error; k = 0 leaves the sample unchanged."""
+    H, _, Sn = _setup(L=3)
+    a = torch.tensor([1e-3, 1e-3], dtype=DT)
+    Ad = O.dense_operator(H, 0, 1e-3)
+
+    def exact(Hh, l, b, alpha):
+        return torch.linalg.solve(Ad, b.reshape(b.shape[0], -1).T).T.reshape(b.shape)
+
+    e0 = torch.randn(2, H.n, H.n, dtype=DT, generator=torch.Generator().manual_seed(27))
+    e, y = O.data_generation(H, [exact, Sn[1]], e0, a, [1, 0], 1, 0, False)
+    assert float(e[0].abs().max()) < 1e-10 * float(e0[0].abs().max())
+    assert torch.equal(e[1], e0[1])
 
 
 def test_adam_matches_library():
@@ -699,20 +841,23 @@ def test_spectral_conv_single_mode_closed_form():
     assert float(O.spectral_conv(z, R, k, 1).abs().max()) < 1e-13
 
 
-def test_fno_forward_1d_brute_force():
-    """Whole FNO on a 7-point grid from pure-Python loops: lift, Fourier
-    layers (DFT sums, mode mixing, real inverse, convolution with bias, GELU)
-    and projection."""
-    n, C, k, ks, nl = 7, 2, 3, 3, 2
-    g = torch.Generator().manual_seed(34)
-    p = {"lift_w": torch.randn(C, dtype=DT, generator=g), "lift_b": torch.randn(C, dtype=DT, generator=g),
-         "proj_w": torch.randn(C, dtype=DT, generator=g), "proj_b": torch.randn((), dtype=DT, generator=g),
-         "layers": [{"R": _rand_complex((C, C, k), 35 + i), "W": torch.randn(C, C, ks, dtype=DT, generator=g),
-                     "B": torch.randn(C, dtype=DT, generator=g)} for i in range(nl)]}
-    xin = torch.randn(1, n, dtype=DT, generator=g)
-    got = O.fno_forward(p, xin, 1, k)
+def _fno_1d_params(C, k, ks, nl, seed):
+    g = torch.Generator().manual_seed(seed)
+    return {"lift_w": torch.randn(C, dtype=DT, generator=g), "lift_b": torch.randn(C, dtype=DT, generator=g),
+            "proj_w": torch.randn(C, dtype=DT, generator=g), "proj_b": torch.randn((), dtype=DT, generator=g),
+            "layers": [{"R": _rand_complex((C, C, k), seed + 1 + i), "W": torch.randn(C, C, ks, dtype=DT, generator=g),
+                        "B": torch.randn(C, dtype=DT, generator=g)} for i in range(nl)]}
+
+
+def _fno_1d_brute(p, xin, k):
+    """The whole 1D FNO from pure-Python loops: lift, Fourier layers (DFT
+    sums, mode mixing, real inverse, convolution with bias, GELU) and
+    projection.  xin: list of n floats."""
+    n = len(xin)
+    C = p["lift_w"].numel()
+    ks = p["layers"][0]["W"].shape[-1]
     gel = lambda v: 0.5 * v * (1.0 + math.erf(v / math.sqrt(2.0)))
-    z = [[float(p["lift_w"][c]) * float(xin[0, x]) + float(p["lift_b"][c]) for x in range(n)] for c in range(C)]
+    z = [[float(p["lift_w"][c]) * xin[x] + float(p["lift_b"][c]) for x in range(n)] for c in range(C)]
     for L in p["layers"]:
         X = [[sum(z[c][x] * complex(math.cos(-2 * math.pi * m * x / n), math.sin(-2 * math.pi * m * x / n))
                   for x in range(n)) for m in range(k)] for c in range(C)]
@@ -729,8 +874,61 @@ def test_fno_forward_1d_brute_force():
                 row.append(gel(sp + cv))
             new.append(row)
         z = new
-    ref = [sum(float(p["proj_w"][c]) * z[c][x] for c in range(C)) + float(p["proj_b"]) for x in range(n)]
+    return [sum(float(p["proj_w"][c]) * z[c][x] for c in range(C)) + float(p["proj_b"]) for x in range(n)]
+
+
+def test_fno_forward_1d_brute_force():
+    """Whole FNO on a 7-point grid from pure-Python loops."""
+    n, k = 7, 3
+    p = _fno_1d_params(2, k, 3, 2, 34)
+    xin = torch.randn(1, n, dtype=DT, generator=torch.Generator().manual_seed(40))
+    got = O.fno_forward(p, xin, 1, k)
+    ref = _fno_1d_brute(p, [float(v) for v in xin[0]], k)
     assert torch.allclose(got[0], torch.tensor(ref, dtype=DT), rtol=0, atol=1e-12)
+
+
+def test_fno_smoother_wrapper_brute_force():
+    """h = ||b|| N(b / ||b||) with the FNO as N (Algorithm 2's smoothing step
+    with the neural operator of Sec. 3.1): the norm summed by hand, the
+    network evaluated by pure-Python loops, the product formed last.  The
+    FNO has biases, so N itself is not homogeneous and a wrapper that skips
+    the normalisation or the final scaling fails here."""
+    n, k = 9, 3
+    p = _fno_1d_params(2, k, 3, 2, 41)
+    g = torch.Generator().manual_seed(42)
+    b = torch.randn(2, n, dtype=DT, generator=g) * torch.tensor([[3.0], [0.02]], dtype=DT)
+    got = O.fno_smoother(p, 1, k)(None, 0, b, torch.ones(2, dtype=DT))
+    for i in range(2):
+        vals = [float(v) for v in b[i]]
+        nb = math.sqrt(sum(v * v for v in vals))
+        ref = [nb * v for v in _fno_1d_brute(p, [v / nb for v in vals], k)]
+        assert torch.allclose(got[i], torch.tensor(ref, dtype=DT), rtol=0, atol=1e-12 * max(1.0, nb))
+    # the unnormalised network differs (biases), so the check above has teeth
+    assert float((O.fno_forward(p, b, 1, k) - got).abs().max()) > 1e-3
+
+
+def test_fno_smoother_wrapper_homogeneous_and_zero_2d():
+    """2D: the wrapper uses the Frobenius norm of the whole image (one scale
+    per right-hand side), so h(c b) = c h(b) for c > 0 per sample, and b = 0
+    gives h = 0 exactly."""
+    n, dim, C, NL, m, ks = 9, 2, 3, 2, 3, 3
+    q = inputs.fno_params(dim, C, NL, m, ks, 43)
+    p = {k: torch.tensor(v) for k, v in q.items() if k != "layers"}
+    p["layers"] = [{kk: torch.tensor(v) for kk, v in Ly.items()} for Ly in q["layers"]]
+    p = O.fno_from_real(p)
+    S = O.fno_smoother(p, dim, m)
+    b = torch.randn(3, n, n, dtype=DT, generator=torch.Generator().manual_seed(44))
+    b[2] = 0.0
+    a = torch.ones(3, dtype=DT)
+    h = S(None, 0, b, a)
+    c = torch.tensor([2.5, 0.125, 7.0], dtype=DT).reshape(3, 1, 1)
+    hc = S(None, 0, c * b, a)
+    assert torch.allclose(hc[:2], c[:2] * h[:2], rtol=1e-12, atol=1e-14)
+    assert float(h[2].abs().max()) == 0.0 and float(hc[2].abs().max()) == 0.0
+    # per-image Frobenius norm: scaling one row of an image is not a rescale
+    nb = float(math.sqrt(sum(float(v) ** 2 for v in b[0].reshape(-1))))
+    ref0 = nb * O.fno_forward(p, (b[0] / nb).unsqueeze(0), dim, m)[0]
+    assert torch.allclose(h[0], ref0, rtol=1e-12, atol=1e-14)
 
 
 def test_jacobi_reduction_matches_paper_printed_values():
