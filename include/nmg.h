@@ -42,6 +42,7 @@ typedef struct nmg_ctx* nmg_handle;
 typedef enum {
     NMG_OK = 0,
     NMG_NOT_CONVERGED = 1,
+    NMG_DIVERGED = 2,        /* per right-hand side: residual beyond the guard */
     NMG_ERR_ARG = -1,        /* bad argument value or NULL pointer        */
     NMG_ERR_SHAPE = -2,      /* n, levels, batch or layer shapes invalid  */
     NMG_ERR_OOM = -3,        /* device allocation failed                  */
@@ -225,6 +226,21 @@ nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, 
 nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
                       const void* y, void* x, const nmg_cycle_opts* opts, void* stream);
 
+/* A right-hand side whose relative residual ||b - A x|| / ||b|| exceeds
+ * this factor has diverged (a smoother that does not fit its operator): it
+ * is retired with status NMG_DIVERGED and leaves the others untouched. */
+#define NMG_DIVERGENCE_FACTOR 1.0e6
+
+/* Per right-hand-side outcome of nmg_solve. */
+typedef struct {
+    int cycles;           /* outer iterations applied                                */
+    int status;           /* NMG_OK, NMG_NOT_CONVERGED (max_cycles reached),
+                             NMG_DIVERGED or NMG_ERR_NONFINITE (NaN/Inf residual)  */
+    double rel_residual;  /* ||b - A x||_2 / ||b||_2 of the returned x in FP64 (the
+                             check that retired it; 0 for b = 0)                   */
+    double done_ms;       /* host ms from entry to that check                      */
+} nmg_solve_stats;
+
 /* Outer iteration x^{t+1} = MG(x^t, b) from x^0 = 0 until
  * ||b - A x||_2 / ||b||_2 <= rtol per right-hand side or max_cycles
  * (Sec. 2.3; stopping rule of Sec. 4).  b, x: device double[B][n]([n]).
@@ -233,20 +249,22 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha_dev, const in
  * NMG_FP32 iterates in plain FP32 and converts at the end.  Converged
  * right-hand sides are frozen: they leave the batch, so every cycle runs on
  * the active ones only, and each result is the same as when that
- * right-hand side is solved alone.  weight_set_dev entries must lie in
- * [0, n_weight_sets) (NMG_ERR_ARG otherwise).  cycles_host (int[batch], may be NULL)
- * receives cycles used; history_host (double[batch][max_cycles+1], may be
- * NULL) receives the relative residual before each cycle (unused entries
- * set to -1); done_ms_host (double[batch], may be NULL) receives the host
- * time in ms from entry to the residual check that found each right-hand
- * side converged (-1 if it never did).  Synchronises once per cycle.
- * Returns NMG_NOT_CONVERGED if any right-hand side missed rtol,
- * NMG_ERR_NONFINITE on NaN/Inf residuals, NMG_ERR_STATE while serving
- * requests are queued or active (it runs on the same engine). */
+ * right-hand side is solved alone.  A right-hand side whose residual turns
+ * non-finite or grows beyond NMG_DIVERGENCE_FACTOR ||b|| leaves the batch
+ * the same way, with its own status; the others go on.  weight_set_dev
+ * entries must lie in [0, n_weight_sets) (NMG_ERR_ARG otherwise).
+ * stats_host (nmg_solve_stats[batch], may be NULL) receives each right-hand
+ * side's outcome; history_host (double[batch][max_cycles+1], may be NULL)
+ * receives the relative residual before each cycle (unused entries -1).
+ * x holds the last iterate of every right-hand side, whatever its status.
+ * Synchronises once per cycle.  Returns NMG_OK when every right-hand side
+ * converged, NMG_NOT_CONVERGED (a warning: see stats_host for which one
+ * and why) otherwise, NMG_ERR_STATE while serving requests are queued or
+ * active (it runs on the same engine). */
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
                      const double* b_dev, double* x_dev, double rtol, int max_cycles,
-                     const nmg_cycle_opts* opts, int* cycles_host, double* history_host,
-                     double* done_ms_host, void* stream);
+                     const nmg_cycle_opts* opts, nmg_solve_stats* stats_host, double* history_host,
+                     void* stream);
 
 /* ---- serving: continuous batching ----------------------------------------
  *
@@ -260,7 +278,7 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha_dev, const int
 
 typedef struct {
     long long id;         /* the caller's request id */
-    int status;           /* NMG_OK, NMG_NOT_CONVERGED or NMG_ERR_NONFINITE */
+    int status;           /* NMG_OK, NMG_NOT_CONVERGED, NMG_DIVERGED or NMG_ERR_NONFINITE */
     int cycles;           /* outer iterations applied */
     double rel_residual;  /* ||b - A x||_2 / ||b||_2 when it left (0 for b = 0) */
     double latency_ms;    /* host time from submission to the check that finished it */
@@ -275,11 +293,13 @@ nmg_status nmg_serve_submit(nmg_handle h, long long id, double alpha, int weight
 
 /* One engine step on `stream`: admits queued requests into free slots
  * (copies b, factors new alphas), checks every active request against
- * rtol / max_cycles, writes the iterates of finished requests to their x_dev
- * and reports them in done (host array of at least max_batch entries;
- * *n_done = count), then runs one outer iteration on the remaining ones.
- * opts->precision must stay the same while requests are active.
- * Synchronises the stream. */
+ * rtol / max_cycles and the divergence guard, writes the iterates of
+ * finished requests to their x_dev and reports them in done (host array of
+ * at least max_batch entries; *n_done = count), then enqueues one outer
+ * iteration on the remaining ones.  Returns once the solutions in done are
+ * written (their latency_ms is taken then); the iteration it enqueued may
+ * still be running on the stream, and the next step waits for it.
+ * opts->precision must stay the same while requests are active. */
 nmg_status nmg_serve_step(nmg_handle h, double rtol, int max_cycles, const nmg_cycle_opts* opts,
                           nmg_request_result* done, int* n_done, void* stream);
 
@@ -355,6 +375,28 @@ nmg_status nmg_pool_pending(nmg_pool p, int* queued, int* active, size_t* bytes_
 nmg_status nmg_loss_grad(nmg_handle h, int weight_set, int batch, const double* alpha_dev,
                          const void* e_dev, nmg_mask_kind mask, int use_fprime,
                          nmg_precision precision, int zero_grad, double* losses_host, void* stream);
+
+/* Training pairs of Algorithm 5 (procedure DataGeneration), in place:
+ * sample i of e (device [B][n]([n]), double for NMG_FP64 else float) goes
+ * through k_host[i] rollout cycles e_i <- e_i - MG(0, A e_i) with the
+ * current smoothers and the cycle of opts (Algorithm 5 uses V(1, 0), with
+ * F' in the filtered variant), no gradients.  Afterwards y (same layout, or
+ * NULL) receives A e, so (e, y) is a consistent pair again: the reading of
+ * the procedure's right-hand-side update.  Algorithm 5 draws k_i uniformly
+ * from 1..K; the caller draws them (host int[batch], each in [0, 64]).
+ * alpha_dev / weight_set_dev as for nmg_vcycle; the coarse factors are
+ * formed as nmg_prepare does.  NMG_ERR_STATE while serving requests are
+ * active (it uses the engine's slot tables).  Synchronises. */
+nmg_status nmg_rollout(nmg_handle h, int batch, const double* alpha_dev, const int* weight_set_dev,
+                       const int* k_host, void* e_dev, void* y_dev, const nmg_cycle_opts* opts, void* stream);
+
+/* The forward half of nmg_loss_grad: the same losses (level-wise, or the
+ * combined loss for NMG_LOSS_CYCLE) for the same arguments, without the
+ * adjoint; the gradient buffers are left as they are.  For evaluation and
+ * for a loss whose gradient is not needed.  Synchronises. */
+nmg_status nmg_loss_forward(nmg_handle h, int weight_set, int batch, const double* alpha_dev,
+                            const void* e_dev, nmg_mask_kind mask, int use_fprime,
+                            nmg_precision precision, double* losses_host, void* stream);
 
 /* Copies the gradient of (level, weight_set) filled by the last
  * nmg_loss_grad to the host as doubles (layout as nmg_load_smoother_weights). */

@@ -7,7 +7,9 @@ Forward evaluates the per-level losses of Sec. 3.2 eq. loss_2_modified (2D:
 Sec. 3.3 eq. loss_3) for a batch of true solutions with the handle's cycle
 (pre-smoothing only, from zero); backward returns the hand-written adjoint
 that the library computed in the same call (``nmg_loss_grad``), scaled by the
-incoming loss gradients.  Level ``l``'s loss is differentiated with respect to
+incoming loss gradients.  When no weight needs a gradient (evaluation, or
+inside ``torch.no_grad()``) forward calls ``nmg_loss_forward`` instead and
+the adjoint is never computed.  Level ``l``'s loss is differentiated with respect to
 its own smoother only (Algorithm 5 updates each level from its own loss; the
 corrections of earlier levels enter as constants), so for weights
 ``theta_l`` the backward result is ``sum_l' g_l' dL_l'/dtheta_l =
@@ -41,6 +43,9 @@ class LevelwiseSpectralLoss(torch.autograd.Function):
             raise ValueError(f"expected {handle.problem.levels - 1} level weight tensors, got {len(level_weights)}")
         for l, w in enumerate(level_weights):
             handle.load_smoother_weights(l, weight_set, [w.detach().to("cpu", torch.float32).numpy()])
+        if not any(ctx.needs_input_grad[7:]):
+            return torch.from_numpy(handle.loss_forward(e, alpha, weight_set=weight_set, mask=mask,
+                                                        use_fprime=use_fprime, precision=precision))
         losses = handle.loss_grad(e, alpha, weight_set=weight_set, mask=mask, use_fprime=use_fprime,
                                   precision=precision)
         grads = [torch.from_numpy(handle.get_gradient(l, weight_set)).to(w.device, w.dtype)
@@ -76,6 +81,10 @@ class CycleLoss(torch.autograd.Function):
             raise ValueError(f"expected {handle.problem.levels - 1} level weight tensors, got {len(level_weights)}")
         for l, w in enumerate(level_weights):
             handle.load_smoother_weights(l, weight_set, [w.detach().to("cpu", torch.float32).numpy()])
+        if not any(ctx.needs_input_grad[6:]):
+            losses = handle.loss_forward(e, alpha, weight_set=weight_set, mask="cycle", use_fprime=use_fprime,
+                                         precision=precision)
+            return torch.tensor(float(losses[0]), dtype=torch.float64)
         losses = handle.loss_grad(e, alpha, weight_set=weight_set, mask="cycle", use_fprime=use_fprime,
                                   precision=precision)
         grads = [torch.from_numpy(handle.get_gradient(l, weight_set)).to(w.device, w.dtype)

@@ -262,6 +262,7 @@ struct Ctx {
     int stamp_next = 0;
     double wall_khz = 0.0;
     hipStream_t cap_stream = nullptr;
+    hipEvent_t serve_retired = nullptr;  // copy-out of finished serving requests
 };
 
 // Records a start event on construction and a stop event on destruction
@@ -376,9 +377,11 @@ nmg_status check_opts(const Ctx* c, const nmg_cycle_opts* o);
 nmg_status check_alpha(const Ctx* h, double a, int slot);
 // One continuous-batching step on stream s; `retired`, when given, is
 // recorded on s once the solutions of the requests returned in `done` have
-// been written (before the next iteration is launched).
+// been written (before the next iteration is launched).  submit_ms, when
+// given, receives each returned request's submission time (engine clock).
 nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts* o,
-                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired = nullptr);
+                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired = nullptr,
+                       std::vector<double>* submit_ms = nullptr);
 // Device bytes one request slot of the handle occupies in a solve of the
 // given precision (engine planes plus the cycle's level buffers).
 size_t request_bytes(const Ctx* c, nmg_precision prec);
@@ -388,6 +391,8 @@ nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const do
 template <typename X, typename T>
 nmg_status launch_refine_update(int batch, size_t per, X* x, const T* d, const double* rn2, const int* active,
                                 hipStream_t s);
+template <typename T>
+nmg_status launch_rollout_sub(int batch, size_t per, T* e, const T* d, const int* k, int j, hipStream_t s);
 nmg_status repack_bf16(Ctx* c, int level, int weight_set);
 
 }  // namespace nmg

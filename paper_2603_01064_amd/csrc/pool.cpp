@@ -132,19 +132,31 @@ nmg_status nmg_pool_step(nmg_pool p, double rtol, int max_cycles, const nmg_cycl
         return fail(NMG_ERR_ARG, "result capacity below the requests in flight");
     // ---- one outer iteration for every member with work; members whose
     // requests finished wait only for the copy-out of those solutions
+    // every early return below first reports the requests already handed
+    // back in done[0..count), so a failing member never loses finished ones
     int count = 0;
     for (size_t mi = 0; mi < p->members.size(); ++mi) {
         auto& m = p->members[mi];
         if (m.h->eng.queue.empty() && m.h->eng.slot.empty()) continue;
         std::vector<nmg_request_result> out;
-        NMG_TRY(nmg::engine_step(m.h, rtol, max_cycles, o, out, m.s, m.retired));
+        const nmg_status st = nmg::engine_step(m.h, rtol, max_cycles, o, out, m.s, m.retired);
+        if (st < 0) {
+            *n_done = count;
+            return st;
+        }
         if (out.empty()) continue;
-        NMG_HIP(hipEventSynchronize(m.retired));
+        const hipError_t ev = hipEventSynchronize(m.retired);
+        if (ev != hipSuccess) {
+            *n_done = count;
+            return nmg::hip_fail(ev, "hipEventSynchronize(retired)", __FILE__, __LINE__);
+        }
         const double now = p->now_ms();
         for (auto& r : out) {
-            if (count >= capacity)
+            if (count >= capacity) {
+                *n_done = count;
                 return fail(NMG_ERR_STATE, "more finished requests than the result capacity (a member handle "
                                            "received requests outside the pool)");
+            }
             auto it = p->running.find(r.id);
             if (it != p->running.end()) {
                 r.latency_ms = now - it->second.t_submit;

@@ -129,6 +129,27 @@ nmg_status launch_refine_update(int batch, size_t per, X* x, const T* d, const d
     return NMG_OK;
 }
 
+// Rollout step j of the training-data generation: e[b] -= d[b] for the
+// samples still rolling out (j < k[b]); the others keep their error.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_rollout_sub(T* __restrict__ e, const T* __restrict__ d,
+                                                        const int* __restrict__ k, int j, size_t per) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= per || j >= k[b]) return;
+    e[(size_t)b * per + i] -= d[(size_t)b * per + i];
+}
+
+template <typename T>
+nmg_status launch_rollout_sub(int batch, size_t per, T* e, const T* d, const int* k, int j, hipStream_t s) {
+    dim3 grid((unsigned)((per + kBlock - 1) / kBlock), batch);
+    hipLaunchKernelGGL((k_rollout_sub<T>), grid, dim3(kBlock), 0, s, e, d, k, j, per);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_rollout_sub<double>(int, size_t, double*, const double*, const int*, int, hipStream_t);
+template nmg_status launch_rollout_sub<float>(int, size_t, float*, const float*, const int*, int, hipStream_t);
+
 template nmg_status launch_refine_scale<double, double>(int, size_t, const double*, double*, const double*,
                                                         const double*, double, int*, hipStream_t);
 template nmg_status launch_refine_scale<double, float>(int, size_t, const double*, float*, const double*,

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "nmg_internal.h"
@@ -487,6 +488,8 @@ using namespace nmg;
 
 namespace nmg {
 
+constexpr int kMaxRollout = 64;  // rollout cycles per training sample
+
 // Coarse factors are cached per alpha value (exact match): U distinct alphas
 // need at most U factorizations, and alphas seen before cost nothing.  idx
 // receives the cache slot of every alpha.  Slots used by requests the
@@ -617,7 +620,8 @@ struct FidxGuard {
 
 // One step of the serving engine (see nmg_serve_step).
 nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts* o,
-                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired) {
+                       std::vector<nmg_request_result>& done, hipStream_t s, hipEvent_t retired,
+                       std::vector<double>* submit_ms) {
     Engine& E = h->eng;
     const int B = h->p.max_batch;
     const size_t per = level_elems(h, 0);
@@ -706,6 +710,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     for (int i = 0; i < m; ++i) E.slot[(size_t)(k - m + i)].bn2 = bn2n[(size_t)i];
     const double now = E.now_ms();
     const double tol2 = rtol * rtol;
+    const double kDiverge2 = NMG_DIVERGENCE_FACTOR * NMG_DIVERGENCE_FACTOR;
     // ---- retire finished requests
     std::vector<char> keep((size_t)k, 0);
     int nfin = 0, nkeep = 0;
@@ -720,6 +725,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             if (sl.hist && sl.cycles < sl.hist_len) sl.hist[sl.cycles] = bb > 0 ? std::sqrt(q / bb) : 0.0;
             if (!(q > tol2 * bb))
                 status = NMG_OK;
+            else if (q > kDiverge2 * bb)
+                status = NMG_DIVERGED;
             else if (sl.cycles >= max_cycles)
                 status = NMG_NOT_CONVERGED;
         }
@@ -735,6 +742,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         res.rel_residual = (std::isfinite(q) && bb > 0) ? std::sqrt(q / bb) : (bb > 0 ? q : 0.0);
         res.latency_ms = now - sl.t_submit;
         done.push_back(res);
+        if (submit_ms) submit_ms->push_back(sl.t_submit);
         hi[(size_t)2 * B + nfin] = i;
         h->pin_ptr[nfin] = sl.x;
         ++nfin;
@@ -989,6 +997,8 @@ void nmg_destroy(nmg_handle h) {
     release_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
+    if (c->serve_retired) (void)hipEventDestroy(c->serve_retired);
+    c->serve_retired = nullptr;
     if (c->stamps) (void)hipFree(c->stamps);
     c->stamps = nullptr;
     release_training(c);
@@ -1194,12 +1204,53 @@ nmg_status nmg_vcycle(nmg_handle h, int batch, const double* alpha, const int* w
     return run_cycle<float>(h, batch, alpha, ws, (const float*)y, (float*)x, false, *o, s);
 }
 
+nmg_status nmg_rollout(nmg_handle h, int batch, const double* alpha, const int* ws, const int* k_host, void* e,
+                       void* y, const nmg_cycle_opts* o, void* stream) {
+    NMG_TRY(check_handle(h));
+    NMG_TRY(check_batch(h, batch));
+    NMG_TRY(check_opts(h, o));
+    if (!alpha || !k_host || !e) return fail(NMG_ERR_ARG, "null pointer");
+    if (!h->eng.queue.empty() || !h->eng.slot.empty())
+        return fail(NMG_ERR_STATE, "serving requests are queued or active on this handle");
+    int kmax = 0;
+    for (int i = 0; i < batch; ++i) {
+        if (k_host[i] < 0 || k_host[i] > kMaxRollout)
+            return fail(NMG_ERR_ARG, "rollout count out of [0, 64] (sample " + std::to_string(i) + ")");
+        kmax = std::max(kmax, k_host[i]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    NMG_TRY(nmg_prepare(h, batch, alpha, stream));
+    // the engine's slot tables are idle (no serving work): per-sample counts
+    int* kdev = h->slot_i;
+    NMG_HIP(hipMemcpyAsync(kdev, k_host, (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
+    const size_t per = level_elems(h, 0);
+    auto run = [&](auto* ep, auto* yp) -> nmg_status {
+        using T = std::remove_pointer_t<decltype(ep)>;
+        NMG_TRY(ensure_work<T>(h));
+        Work<T>& w = work_of<T>(h);
+        for (int j = 0; j < kmax; ++j) {
+            // d = MG(0, A e); e -= d where j < k
+            NMG_TRY(launch_operator<T>(h, 0, batch, alpha, ep, nullptr, w.lv[0].y, 1, w, s));
+            NMG_TRY(run_cycle<T>(h, batch, alpha, ws, w.lv[0].y, w.lv[0].x, true, *o, s));
+            NMG_TRY(launch_rollout_sub<T>(batch, per, ep, w.lv[0].x, kdev, j, s));
+        }
+        if (yp) NMG_TRY(launch_operator<T>(h, 0, batch, alpha, ep, nullptr, yp, 1, w, s));
+        return NMG_OK;
+    };
+    if (o->precision == NMG_FP64)
+        NMG_TRY(run((double*)e, (double*)y));
+    else
+        NMG_TRY(run((float*)e, (float*)y));
+    NMG_HIP(hipStreamSynchronize(s));
+    return NMG_OK;
+}
+
 nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws, const double* b, double* x,
-                     double rtol, int max_cycles, const nmg_cycle_opts* o, int* cycles_host, double* history_host,
-                     double* done_ms_host, void* stream) {
+                     double rtol, int max_cycles, const nmg_cycle_opts* o, nmg_solve_stats* stats,
+                     double* history_host, void* stream) {
     const double t_entry = h ? h->eng.now_ms() : 0.0;
-    if (done_ms_host)
-        for (int i = 0; i < batch && i < (h ? h->p.max_batch : 0); ++i) done_ms_host[i] = -1.0;
+    if (stats)
+        for (int i = 0; i < batch && i < (h ? h->p.max_batch : 0); ++i) stats[i] = {0, NMG_NOT_CONVERGED, -1.0, -1.0};
     NMG_TRY(check_handle(h));
     NMG_TRY(check_batch(h, batch));
     NMG_TRY(check_opts(h, o));
@@ -1237,16 +1288,25 @@ nmg_status nmg_solve(nmg_handle h, int batch, const double* alpha, const int* ws
         h->eng.any_ws = false;
         return st;
     }
-    bool nonfinite = false, missed = false;
+    // the last step retired every request and synchronised after their copy-out
+    int bad = 0;
     for (const auto& r : done) {
         const int i = (int)r.id;
-        if (cycles_host) cycles_host[i] = r.cycles;
-        if (done_ms_host && r.status == NMG_OK) done_ms_host[i] = r.latency_ms;
-        nonfinite = nonfinite || r.status == NMG_ERR_NONFINITE;
-        missed = missed || r.status == NMG_NOT_CONVERGED;
+        if (stats) stats[i] = {r.cycles, r.status, r.rel_residual, r.latency_ms};
+        bad += r.status != NMG_OK;
     }
-    if (nonfinite) return fail(NMG_ERR_NONFINITE, "non-finite residual");
-    if (missed) return fail(NMG_NOT_CONVERGED, "not converged within max_cycles");
+    if (bad) {
+        int first = -1, fst = 0;
+        for (const auto& r : done)
+            if (r.status != NMG_OK && (first < 0 || (int)r.id < first)) {
+                first = (int)r.id;
+                fst = r.status;
+            }
+        const char* why = fst == NMG_DIVERGED ? "diverged" : (fst == NMG_ERR_NONFINITE ? "non-finite residual"
+                                                                                         : "max_cycles reached");
+        return fail(NMG_NOT_CONVERGED, std::to_string(bad) + " right-hand side(s) did not converge (first: " +
+                                           std::to_string(first) + ", " + why + ")");
+    }
     return NMG_OK;
 }
 
@@ -1267,8 +1327,17 @@ nmg_status nmg_serve_step(nmg_handle h, double rtol, int max_cycles, const nmg_c
     NMG_TRY(check_opts(h, o));
     if (!done || !n_done) return fail(NMG_ERR_ARG, "null result array");
     if (!(rtol > 0.0) || max_cycles < 0) return fail(NMG_ERR_ARG, "rtol must be > 0 and max_cycles >= 0");
+    if (!h->serve_retired) NMG_HIP(hipEventCreateWithFlags(&h->serve_retired, hipEventDisableTiming));
     std::vector<nmg_request_result> out;
-    NMG_TRY(engine_step(h, rtol, max_cycles, o, out, (hipStream_t)stream));
+    std::vector<double> t_sub;
+    NMG_TRY(engine_step(h, rtol, max_cycles, o, out, (hipStream_t)stream, h->serve_retired, &t_sub));
+    if (!out.empty()) {
+        // wait for the copy-out of the finished solutions only (the next
+        // iteration queued behind it keeps running); latency ends here
+        NMG_HIP(hipEventSynchronize(h->serve_retired));
+        const double now = h->eng.now_ms();
+        for (size_t i = 0; i < out.size(); ++i) out[i].latency_ms = now - t_sub[i];
+    }
     for (size_t i = 0; i < out.size(); ++i) done[i] = out[i];
     *n_done = (int)out.size();
     return NMG_OK;

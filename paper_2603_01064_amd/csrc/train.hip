@@ -31,14 +31,31 @@ constexpr int kChunk = 4096;  // pixels per weight-gradient partial
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// One convolution layer for training: out = act(scale_b * conv(in)), stored
+// Round to the nearest BF16 value (ties to even), returned as float: the
+// rounding the mixed-precision smoother applies to its network input,
+// weights and hidden activations.  Finite inputs only.
+__device__ __forceinline__ float bf16_round(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+template <typename T>
+__device__ __forceinline__ T maybe_bf16(T v, int bf) {
+    return bf ? (T)bf16_round((float)v) : v;
+}
+
+// One convolution layer for training: out = act(conv(scale_b * in)), stored
 // for every channel (no final ||b|| scaling).  scale_b = 1/sqrt(nrm2[b]) when
-// `first` (the input is b), else 1.
+// `first` (the input is b), else 1.  bf != 0 repeats the mixed-precision
+// forward: the network input b/||b|| and the weights are rounded to BF16,
+// products are summed in FP32, and a hidden output is rounded to BF16 after
+// its ReLU (so the backward pass differentiates the network whose loss the
+// forward reported).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_conv_train(const T* __restrict__ in, T* __restrict__ out,
                                                        const T* __restrict__ W, int cin, int cout, int kh, int kw,
                                                        int ny, int n, int relu, int first,
-                                                       const double* __restrict__ nrm2) {
+                                                       const double* __restrict__ nrm2, int bf) {
     const size_t per = (size_t)ny * n;
     const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= per) return;
@@ -47,6 +64,11 @@ __global__ void __launch_bounds__(kBlock) k_conv_train(const T* __restrict__ in,
     const int py = kh / 2, px = kw / 2;
     const T* src = in + (size_t)b * cin * per;
     const T* w = W + (size_t)co * cin * kh * kw;
+    T sc = (T)1;
+    if (first) {
+        const double nb = sqrt(nrm2[b]);
+        sc = nb > 0.0 ? (T)(1.0 / nb) : (T)0;
+    }
     T acc = 0;
     for (int ci = 0; ci < cin; ++ci)
         for (int dy = 0; dy < kh; ++dy) {
@@ -55,14 +77,13 @@ __global__ void __launch_bounds__(kBlock) k_conv_train(const T* __restrict__ in,
             for (int dx = 0; dx < kw; ++dx) {
                 const int xx = x + dx - px;
                 if (xx < 0 || xx >= n) continue;
-                acc += w[(ci * kh + dy) * kw + dx] * src[(size_t)ci * per + (size_t)yy * n + xx];
+                T v = src[(size_t)ci * per + (size_t)yy * n + xx];
+                if (first) v = maybe_bf16(v * sc, bf);
+                acc += maybe_bf16(w[(ci * kh + dy) * kw + dx], bf) * v;
             }
         }
-    if (first) {
-        const double nb = sqrt(nrm2[b]);
-        acc *= nb > 0.0 ? (T)(1.0 / nb) : (T)0;
-    }
     if (relu && acc < (T)0) acc = (T)0;
+    if (relu) acc = maybe_bf16(acc, bf);
     out[((size_t)b * cout + co) * per + e] = acc;
 }
 
@@ -71,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_train(const T* __restrict__ in,
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const T* __restrict__ dout, const T* __restrict__ a_in,
                                                           T* __restrict__ din, const T* __restrict__ W, int cin,
-                                                          int cout, int kh, int kw, int ny, int n) {
+                                                          int cout, int kh, int kw, int ny, int n, int bf) {
     const size_t per = (size_t)ny * n;
     const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= per) return;
@@ -93,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const T* __restrict__ 
             for (int dx = 0; dx < kw; ++dx) {
                 const int xx = x - dx + px;
                 if (xx < 0 || xx >= n) continue;
-                acc += w[dy * kw + dx] * d[(size_t)yy * n + xx];
+                acc += maybe_bf16(w[dy * kw + dx], bf) * d[(size_t)yy * n + xx];
             }
         }
     }
@@ -107,7 +128,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_conv_wgrad(const T* __restrict__ dout, const T* __restrict__ in,
                                                        T* __restrict__ part, int cin, int cout, int kh, int kw,
                                                        int ny, int n, int batch, int first,
-                                                       const double* __restrict__ nrm2) {
+                                                       const double* __restrict__ nrm2, int bf) {
     __shared__ T red[kBlock];
     const size_t per = (size_t)ny * n;
     const int co = blockIdx.y, ci = blockIdx.z;
@@ -122,10 +143,11 @@ __global__ void __launch_bounds__(kBlock) k_conv_wgrad(const T* __restrict__ dou
         const int b = (int)(q / per);
         const size_t e = q % per;
         const int y = (int)(e / n), x = (int)(e % n);
-        T g = dout[((size_t)b * cout + co) * per + e];
+        const T g = dout[((size_t)b * cout + co) * per + e];
+        T sc = (T)1;
         if (first) {
             const double nb = sqrt(nrm2[b]);
-            g *= nb > 0.0 ? (T)(1.0 / nb) : (T)0;
+            sc = nb > 0.0 ? (T)(1.0 / nb) : (T)0;
         }
         const T* src = in + ((size_t)b * cin + ci) * per;
         for (int dy = 0; dy < kh; ++dy) {
@@ -134,7 +156,9 @@ __global__ void __launch_bounds__(kBlock) k_conv_wgrad(const T* __restrict__ dou
             for (int dx = 0; dx < kw; ++dx) {
                 const int xx = x + dx - px;
                 if (xx < 0 || xx >= n) continue;
-                acc[dy * kw + dx] += g * src[(size_t)yy * n + xx];
+                T v = src[(size_t)yy * n + xx];
+                if (first) v = maybe_bf16(v * sc, bf);
+                acc[dy * kw + dx] += g * v;
             }
         }
     }
@@ -468,9 +492,13 @@ float* grad_ptr<float>(Ctx* c, int l, int set) {
     return c->g32 + ((size_t)l * c->p.n_weight_sets + set) * c->wcount;
 }
 
+// bf != 0: the network of the mixed-precision forward (BF16 operands, FP32
+// sums; see k_conv_train), differentiated through its roundings as if they
+// were the identity.
 template <typename T>
 static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int l, int set, int batch,
-                                    const T* upstream, T sign, int accumulate, hipStream_t s, T* din0 = nullptr) {
+                                    const T* upstream, T sign, int accumulate, hipStream_t s, T* din0 = nullptr,
+                                    int bf = 0) {
     const int n = c->n[(size_t)l];
     const int ny = c->p.dim == 2 ? n : 1;
     const int kh = c->p.dim == 2 ? c->p.ksize : 1, kw = c->p.ksize;
@@ -485,7 +513,7 @@ static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int
         const int cin = c->p.channels[i], cout = c->p.channels[i + 1];
         hipLaunchKernelGGL(k_conv_train<T>, dim3(blocks_for(per), cout, batch), dim3(kBlock), 0, s, src,
                            tw.acts[(size_t)i], Wbase + c->layer_off[(size_t)i], cin, cout, kh, kw, ny, n, 1,
-                           i == 0 ? 1 : 0, nrm2);
+                           i == 0 ? 1 : 0, nrm2, bf);
         src = tw.acts[(size_t)i];
     }
     // delta at the network output: sign * ||b|| * upstream
@@ -500,26 +528,28 @@ static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int
         const T* in = i == 0 ? tw.b[(size_t)l] : tw.acts[(size_t)i - 1];
         const int cnt = cin * cout * kh * kw;
         hipLaunchKernelGGL(k_conv_wgrad<T>, dim3(chunks, cout, cin), dim3(kBlock), 0, s, dcur, in, tw.part, cin, cout,
-                           kh, kw, ny, n, batch, i == 0 ? 1 : 0, nrm2);
+                           kh, kw, ny, n, batch, i == 0 ? 1 : 0, nrm2, bf);
         hipLaunchKernelGGL((k_reduce_chunks<T, T>), dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, s, tw.part,
                            gbase + c->layer_off[(size_t)i], cnt, chunks, accumulate);
         if (i > 0) {
             hipLaunchKernelGGL(k_conv_bwd_data<T>, dim3(blocks_for(per), cin, batch), dim3(kBlock), 0, s, dcur,
                                tw.acts[(size_t)i - 1], dnext, Wbase + c->layer_off[(size_t)i], cin, cout, kh, kw, ny,
-                               n);
+                               n, bf);
             std::swap(dcur, dnext);
         } else if (din0) {  // gradient at the network input u = b / ||b||
             hipLaunchKernelGGL(k_conv_bwd_data<T>, dim3(blocks_for(per), cin, batch), dim3(kBlock), 0, s, dcur,
-                               (const T*)nullptr, din0, Wbase + c->layer_off[0], cin, cout, kh, kw, ny, n);
+                               (const T*)nullptr, din0, Wbase + c->layer_off[0], cin, cout, kh, kw, ny, n, bf);
         }
     }
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
 
+// backward = false evaluates the losses only (nmg_loss_forward).
 template <typename T>
 nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const double* alpha, const T* e, int mask,
-                          int use_fprime, bool mixed, int zero_grad, double* losses_host, hipStream_t s) {
+                          int use_fprime, bool mixed, int zero_grad, double* losses_host, hipStream_t s,
+                          bool backward = true) {
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
@@ -576,22 +606,25 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
         T* G = two_d ? tw.F1 : tw.F2;
         hipLaunchKernelGGL(k_mask_loss<T>, dim3(batch), dim3(kBlock), 0, s, X, G, tw.lossb, N, two_d, l,
                            mask == NMG_MASK_RAMP ? 1 : 0, (T)(2.0 / batch));
-        // gE = C^T G C
-        T* gE = tw.E;
-        if (two_d) {
-            NMG_TRY(launch_dense_axis<T>(G, tw.F2, C, N, N, batch, 0, 1, s));
-            NMG_TRY(launch_dense_axis<T>(tw.F2, gE, C, N, N, batch, 1, 1, s));
-        } else {
-            NMG_TRY(launch_dense_axis<T>(G, gE, C, N, 1, batch, 0, 1, s));
+        if (backward) {
+            // gE = C^T G C
+            T* gE = tw.E;
+            if (two_d) {
+                NMG_TRY(launch_dense_axis<T>(G, tw.F2, C, N, N, batch, 0, 1, s));
+                NMG_TRY(launch_dense_axis<T>(tw.F2, gE, C, N, N, batch, 1, 1, s));
+            } else {
+                NMG_TRY(launch_dense_axis<T>(G, gE, C, N, 1, batch, 0, 1, s));
+            }
+            // g_h = (I_l^1)^T gE; dL/dh_l = -g_h, so the network-output delta is -||b_l|| g_h
+            T* gh = work.lv[(size_t)l].h;
+            NMG_TRY(prolong_chain_T<T>(c, work, l, batch, gE, gh, s));
+            if (c->p.smoother_arch == NMG_ARCH_FNO)
+                NMG_TRY(fno_backward<T>(c, work, l, set, batch, tw.b[(size_t)l], tw.nrm[(size_t)l], gh, (T)(-1),
+                                        zero_grad ? 0 : 1, grad_ptr<T>(c, l, set), s));
+            else
+                NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)(-1), zero_grad ? 0 : 1, s, nullptr,
+                                             mixed ? 1 : 0));
         }
-        // g_h = (I_l^1)^T gE; dL/dh_l = -g_h, so the network-output delta is -||b_l|| g_h
-        T* gh = work.lv[(size_t)l].h;
-        NMG_TRY(prolong_chain_T<T>(c, work, l, batch, gE, gh, s));
-        if (c->p.smoother_arch == NMG_ARCH_FNO)
-            NMG_TRY(fno_backward<T>(c, work, l, set, batch, tw.b[(size_t)l], tw.nrm[(size_t)l], gh, (T)(-1),
-                                    zero_grad ? 0 : 1, grad_ptr<T>(c, l, set), s));
-        else
-            NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)(-1), zero_grad ? 0 : 1, s));
         // accumulate the correction of this level on the finest grid
         const T* hc = use_fprime ? tw.hc[(size_t)l] : tw.h[(size_t)l];
         NMG_TRY(prolong_chain<T>(c, work, l, batch, hc, tw.F1, s));
@@ -601,6 +634,23 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
         double tot = 0.0;
         for (int b = 0; b < batch; ++b) tot += lossb[(size_t)b];
         if (losses_host) losses_host[l] = tot / batch;
+    }
+    return NMG_OK;
+}
+
+// losses_host[0] = (1/B) sum_b ||E_b||^2 of the combined loss, the other
+// entries 0 (synchronises).
+template <typename T>
+static nmg_status finish_cycle_loss(const Ctx*, TrainWork<T>& tw, int batch, int nsm, double* losses_host,
+                                    hipStream_t s) {
+    std::vector<double> lossb((size_t)batch);
+    NMG_HIP(hipMemcpyAsync(lossb.data(), tw.lossb, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    NMG_HIP(hipStreamSynchronize(s));
+    if (losses_host) {
+        double total = 0.0;
+        for (int b = 0; b < batch; ++b) total += lossb[(size_t)b];
+        losses_host[0] = total / batch;
+        for (int l = 1; l < nsm; ++l) losses_host[l] = 0.0;
     }
     return NMG_OK;
 }
@@ -619,7 +669,8 @@ nmg_status loss_grad_impl(Ctx* c, Work<T>& work, int set, int batch, const doubl
 // with R^T = P / 2^d.  A_l and A_{L-1}^{-1} are symmetric.
 template <typename T>
 nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const double* alpha, const T* e,
-                           int use_fprime, bool mixed, int zero_grad, double* losses_host, hipStream_t s) {
+                           int use_fprime, bool mixed, int zero_grad, double* losses_host, hipStream_t s,
+                           bool backward = true) {
     TrainState& ts = train_state(c);
     TrainWork<T>& tw = tw_of<T>(ts);
     NMG_TRY(ensure_train<T>(c, tw));
@@ -674,6 +725,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
     NMG_TRY(prolong_chain<T>(c, work, nsm, batch, coarse.x, tw.F1, s));
     hipLaunchKernelGGL(k_error<T>, dim3(blocks_for(fine)), dim3(kBlock), 0, s, e, tw.acc, tw.F1, tw.E, fine);
     NMG_TRY(launch_sumsq<T>(c, batch, per0, tw.E, tw.lossb, s));
+    if (!backward) return finish_cycle_loss(c, tw, batch, nsm, losses_host, s);
     // ---- adjoint
     auto gbuf = [&](int l) -> T* { return l == 0 ? tw.E : (l < nsm ? tw.hc[(size_t)l] : coarse.y); };
     hipLaunchKernelGGL(k_axpby<T>, dim3(blocks_for(fine)), dim3(kBlock), 0, s, tw.E, tw.E, tw.E,
@@ -697,7 +749,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
             gh = lb.h;
         }
         NMG_TRY(smoother_backward<T>(c, work, tw, l, set, batch, gh, (T)1, zero_grad ? 0 : 1, s,
-                                     l > 0 ? tw.F1 : nullptr));
+                                     l > 0 ? tw.F1 : nullptr, mixed ? 1 : 0));
         if (l > 0) {
             hipLaunchKernelGGL(k_dot2<T>, dim3(batch), dim3(kBlock), 0, s, gh, tw.h[(size_t)l], tw.b[(size_t)l],
                                tw.F1, tw.dots, tw.dots + batch, per);
@@ -706,16 +758,7 @@ nmg_status cycle_loss_impl(Ctx* c, Work<T>& work, int set, int batch, const doub
         }
     }
     NMG_HIP(hipGetLastError());
-    std::vector<double> lossb((size_t)batch);
-    NMG_HIP(hipMemcpyAsync(lossb.data(), tw.lossb, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
-    NMG_HIP(hipStreamSynchronize(s));
-    if (losses_host) {
-        double total = 0.0;
-        for (int b = 0; b < batch; ++b) total += lossb[(size_t)b];
-        losses_host[0] = total / batch;
-        for (int l = 1; l < nsm; ++l) losses_host[l] = 0.0;
-    }
-    return NMG_OK;
+    return finish_cycle_loss(c, tw, batch, nsm, losses_host, s);
 }
 
 }  // namespace nmg
@@ -774,6 +817,28 @@ nmg_status nmg_loss_grad(nmg_handle h, int set, int batch, const double* alpha, 
                                       prec == NMG_MIXED, zero_grad, losses_host, s));
     h->grad_is_fp64 = false;
     return NMG_OK;
+}
+
+nmg_status nmg_loss_forward(nmg_handle h, int set, int batch, const double* alpha, const void* e,
+                            nmg_mask_kind mask, int use_fprime, nmg_precision prec, double* losses_host,
+                            void* stream) {
+    NMG_TRY(check_training(h, set, batch, mask, prec));
+    if (!alpha || !e) return fail(NMG_ERR_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == NMG_FP64) {
+        NMG_TRY(ensure_work<double>(h));
+        if (mask == NMG_LOSS_CYCLE)
+            return cycle_loss_impl<double>(h, h->w64, set, batch, alpha, (const double*)e, use_fprime, false, 0,
+                                           losses_host, s, false);
+        return loss_grad_impl<double>(h, h->w64, set, batch, alpha, (const double*)e, mask, use_fprime, false, 0,
+                                      losses_host, s, false);
+    }
+    NMG_TRY(ensure_work<float>(h));
+    if (mask == NMG_LOSS_CYCLE)
+        return cycle_loss_impl<float>(h, h->w32b, set, batch, alpha, (const float*)e, use_fprime, prec == NMG_MIXED,
+                                      0, losses_host, s, false);
+    return loss_grad_impl<float>(h, h->w32b, set, batch, alpha, (const float*)e, mask, use_fprime, prec == NMG_MIXED,
+                                 0, losses_host, s, false);
 }
 
 nmg_status nmg_get_gradient(nmg_handle h, int level, int set, double* grad_host, size_t count) {

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnmg.so")
 
 NMG_OK = 0
 NMG_NOT_CONVERGED = 1
+NMG_DIVERGED = 2
+NMG_ERR_NONFINITE = -5
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 MASK = {"band": 0, "ramp": 1, "cycle": 2}  # "cycle": the combined loss eq. loss_1
 MAX_LAYERS = 7
@@ -43,6 +45,12 @@ class RequestResult(ctypes.Structure):
     """``nmg_request_result``: one finished serving request."""
     _fields_ = [("id", ctypes.c_longlong), ("status", ctypes.c_int), ("cycles", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    """``nmg_solve_stats``: the outcome of one right-hand side of a solve."""
+    _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("done_ms", ctypes.c_double)]
 
 
 class _CycleOpts(ctypes.Structure):
@@ -74,8 +82,10 @@ def load_library():
         "nmg_apply_smoother": (S, [P, I, I, P, P, P, P, I, P]),
         "nmg_apply_fprime": (S, [P, I, I, P, P, I, P]),
         "nmg_vcycle": (S, [P, I, P, P, P, P, ctypes.POINTER(_CycleOpts), P]),
-        "nmg_solve": (S, [P, I, P, P, P, P, D, I, ctypes.POINTER(_CycleOpts), P, P, P, P]),
+        "nmg_solve": (S, [P, I, P, P, P, P, D, I, ctypes.POINTER(_CycleOpts), P, P, P]),
         "nmg_loss_grad": (S, [P, I, I, P, P, I, I, I, I, P, P]),
+        "nmg_loss_forward": (S, [P, I, I, P, P, I, I, I, P, P]),
+        "nmg_rollout": (S, [P, I, P, P, P, P, P, ctypes.POINTER(_CycleOpts), P]),
         "nmg_get_gradient": (S, [P, I, I, P, Z]),
         "nmg_adam_step": (S, [P, I, D, D, D, D, P]),
         "nmg_train_step": (S, [P, I, I, P, P, I, I, I, D, P, P]),
@@ -303,7 +313,10 @@ class Handle:
               nu2: int = 1, use_fprime: bool = False, precision: str = "mixed", x=None, history: bool = False,
               done_ms=None):
         """Returns ``(x, cycles, history_or_None, status)``; ``done_ms`` (a float64
-        NumPy array of length B) receives per right-hand-side convergence times."""
+        NumPy array of length B) receives per right-hand-side convergence times
+        (-1 where a right-hand side did not converge).  The per right-hand-side
+        outcome (cycles, status, final relative residual, time) of the last solve
+        is kept in ``self.last_stats`` as a dict of NumPy arrays."""
         import torch
         B = alpha.numel()
         shape = self.level_shape(0, B)
@@ -316,15 +329,22 @@ class Handle:
         if weight_set is not None:
             _require(weight_set, torch.int32, (B,), "weight_set")
             ws = _ptr(weight_set)
-        cycles = np.zeros(B, dtype=np.int32)
+        stats = (SolveStats * B)()
         hist = np.empty((B, max_cycles + 1), dtype=np.float64) if history else None
         o = _CycleOpts(nu1, nu2, 1 if use_fprime else 0, PRECISION[precision])
         st = _check(_lib.nmg_solve(self.ptr, B, _ptr(alpha), ws, _ptr(b), _ptr(x), float(rtol), int(max_cycles),
-                                   ctypes.byref(o), cycles.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.byref(o), stats,
                                    hist.ctypes.data_as(ctypes.c_void_p) if hist is not None else ctypes.c_void_p(),
-                                   done_ms.ctypes.data_as(ctypes.c_void_p) if done_ms is not None
-                                   else ctypes.c_void_p(), _stream()))
-        return x, cycles, hist, st
+                                   _stream()))
+        self.last_stats = {
+            "cycles": np.array([r.cycles for r in stats], dtype=np.int32),
+            "status": np.array([r.status for r in stats], dtype=np.int32),
+            "rel_residual": np.array([r.rel_residual for r in stats], dtype=np.float64),
+            "done_ms": np.array([r.done_ms for r in stats], dtype=np.float64),
+        }
+        if done_ms is not None:
+            done_ms[:] = np.where(self.last_stats["status"] == NMG_OK, self.last_stats["done_ms"], -1.0)
+        return x, self.last_stats["cycles"].copy(), hist, st
 
     # -- serving (continuous batching) --------------------------------------
     def serve_submit(self, b, x, alpha: float, weight_set: int = 0, rid: int | None = None) -> int:
@@ -377,6 +397,41 @@ class Handle:
                                   PRECISION[precision], int(zero_grad), losses.ctypes.data_as(ctypes.c_void_p),
                                   _stream()))
         return losses
+
+    def loss_forward(self, e, alpha, weight_set: int = 0, mask: str = "ramp", use_fprime: bool = False,
+                     precision: str = "fp64") -> np.ndarray:
+        """The losses of :meth:`loss_grad` without the adjoint (gradients untouched)."""
+        import torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        B = alpha.numel()
+        _require(e, dt, self.level_shape(0, B), "e")
+        _require(alpha, torch.float64, (B,), "alpha")
+        losses = np.zeros(max(1, self.problem.levels - 1), dtype=np.float64)
+        _check(_lib.nmg_loss_forward(self.ptr, weight_set, B, _ptr(alpha), _ptr(e), MASK[mask], int(use_fprime),
+                                     PRECISION[precision], losses.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return losses
+
+    def rollout(self, e, alpha, k, weight_set=None, nu1: int = 1, nu2: int = 0, use_fprime: bool = False,
+                precision: str = "fp32"):
+        """Algorithm 5 DataGeneration in place on ``e``: sample ``i`` goes
+        through ``k[i]`` cycles ``e <- e - MG(0, A e)``; returns ``y = A e``."""
+        import torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        B = alpha.numel()
+        _require(e, dt, self.level_shape(0, B), "e")
+        _require(alpha, torch.float64, (B,), "alpha")
+        ks = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(-1))
+        if ks.size != B:
+            raise ValueError(f"k must have {B} entries")
+        ws = ctypes.c_void_p()
+        if weight_set is not None:
+            _require(weight_set, torch.int32, (B,), "weight_set")
+            ws = _ptr(weight_set)
+        y = torch.empty_like(e)
+        o = _CycleOpts(nu1, nu2, 1 if use_fprime else 0, PRECISION[precision])
+        _check(_lib.nmg_rollout(self.ptr, B, _ptr(alpha), ws, ks.ctypes.data_as(ctypes.c_void_p), _ptr(e), _ptr(y),
+                                ctypes.byref(o), _stream()))
+        return y
 
     def get_gradient(self, level: int, weight_set: int = 0) -> np.ndarray:
         out = np.empty(self.problem.weight_count(), dtype=np.float64)

@@ -65,27 +65,27 @@ def select_set(set_alphas, alpha: float) -> int:
 
 
 def rollout(h: nmg.Handle, e: torch.Tensor, alpha: torch.Tensor, K: int, gen: torch.Generator,
-            precision: str, use_fprime: bool = False) -> torch.Tensor:
-    """DataGeneration of Algorithm 5: each sample is run through k ~ U{0..K}
-    cycles of the current smoothers (e <- e - NMG(0, A e)) without gradients;
-    samples are rescaled to unit RMS so every batch has the same scale."""
+            precision: str, use_fprime: bool = False, rescale: bool = False) -> torch.Tensor:
+    """DataGeneration of Algorithm 5 on the device (``nmg_rollout``): each
+    sample draws k ~ U{1..K} and goes through k cycles e <- e - NMG(0, A e)
+    of the current smoothers (V(1, 0), F' as in training), without
+    gradients.  ``rescale`` (off by default, not part of Algorithm 5) brings
+    every sample back to unit RMS afterwards, so rolled-out samples weigh as
+    much in the loss as fresh ones (the loss is homogeneous of degree two)."""
     if K <= 0:
         return e
     B = e.shape[0]
-    ks = torch.randint(0, K + 1, (B,), generator=gen).to(e.device)
-    h.prepare(alpha)
-    for j in range(K):
-        y = h.apply_operator(0, e, alpha, precision="fp32")
-        d = torch.zeros_like(e)
-        h.vcycle(y, d, alpha, nu1=1, nu2=0, use_fprime=use_fprime, precision=precision)
-        upd = (ks > j).to(e.dtype).reshape(B, 1, 1)
-        e = e - upd * d
+    ks = torch.randint(1, K + 1, (B,), generator=gen)
+    h.rollout(e, alpha, ks.numpy(), nu1=1, nu2=0, use_fprime=use_fprime, precision=precision)
+    if not rescale:
+        return e
     rms = e.reshape(B, -1).norm(dim=1) / (e[0].numel() ** 0.5)
     return e / rms.clamp_min(1e-30).reshape(B, 1, 1)
 
 
 def train_set(h: nmg.Handle, alpha_value: float, steps: int, batch: int, lr: float, mask: str, seed: int,
-              rollout_K: int = 0, log_every: int = 100, precision: str = "fp32", use_fprime: bool = False):
+              rollout_K: int = 0, log_every: int = 100, precision: str = "fp32", use_fprime: bool = False,
+              rollout_rescale: bool = False):
     dev = torch.device("cuda:0")
     n = h.problem.n
     alpha = torch.full((batch,), alpha_value, dtype=torch.float64, device=dev)
@@ -94,7 +94,8 @@ def train_set(h: nmg.Handle, alpha_value: float, steps: int, batch: int, lr: flo
     t0 = time.time()
     for step in range(steps):
         e = torch.randn((batch, n, n), generator=gen, dtype=torch.float32).to(dev)
-        e = rollout(h, e, alpha, rollout_K, gen, "mixed" if precision == "mixed" else "fp32", use_fprime)
+        e = rollout(h, e, alpha, rollout_K, gen, "mixed" if precision == "mixed" else "fp32", use_fprime,
+                    rollout_rescale)
         cur_lr = lr * (0.1 ** (step / max(1, steps)))  # decays by 10x over the run
         losses = h.train_step(e, alpha, mask=mask, use_fprime=use_fprime, precision=precision, lr=cur_lr)
         hist.append(losses.tolist())
@@ -206,7 +207,9 @@ def main(argv=None):
     ap.add_argument("--mask", default="ramp", choices=["ramp", "band", "cycle"],
                     help="level-wise spectral loss with the ramp or band mask, or the combined loss of the whole "
                          "cycle (eq. loss_1, all levels trained jointly)")
-    ap.add_argument("--rollout", type=int, default=0)
+    ap.add_argument("--rollout", type=int, default=0, help="K of Algorithm 5: k ~ U{1..K} rollout cycles per sample")
+    ap.add_argument("--rollout-rescale", action="store_true",
+                    help="rescale rolled-out samples to unit RMS (not part of Algorithm 5)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--seed", type=int, default=7000)
     ap.add_argument("--out", required=True)
@@ -241,7 +244,7 @@ def main(argv=None):
         steps = a.steps_per_alpha[k] if a.steps_per_alpha else a.steps
         print(f"training alpha={av:g} ({steps} steps, batch {a.batch}, mask {a.mask}, fprime {a.fprime})", flush=True)
         train_set(h, av, steps, a.batch, a.lr, a.mask, a.seed + 1000 * k, a.rollout, precision=a.precision,
-                  use_fprime=a.fprime)
+                  use_fprime=a.fprime, rollout_rescale=a.rollout_rescale)
         sets.append([h.get_smoother_weights(l) for l in range(L - 1)])
         for nu in ((1, 1), (2, 0), (1, 0)):
             cyc, st = evaluate(h, av, min(16, a.batch), nu[0], nu[1], a.fprime, a.eval_max_cycles)
@@ -252,7 +255,7 @@ def main(argv=None):
                       f"status {st}", flush=True)
     meta = dict(n=a.n, s=a.s, levels=L, channels=list(a.channels), ksize=3, alphas=alphas,
                 steps=a.steps_per_alpha or [a.steps] * len(alphas), batch=a.batch, lr=a.lr, mask=a.mask,
-                rollout=a.rollout, precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init,
+                rollout=a.rollout, rollout_rescale=bool(a.rollout_rescale), precision=a.precision, seed=a.seed, use_fprime=bool(a.fprime), init=a.init,
                 operator=a.operator, fno=list(a.fno) if a.fno else None)
     save_weights(a.out, meta, sets)
     print(f"wrote {a.out}", flush=True)

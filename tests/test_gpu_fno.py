@@ -182,3 +182,22 @@ def test_fno_training_reduces_the_loss():
     print(f"  losses {first} -> {last}", flush=True)
     assert float(np.sum(last)) < float(np.sum(first))
     h.close()
+
+
+@pytest.mark.parametrize("n", [127, 255])
+def test_fno_at_the_benchmarked_architecture(n):
+    """The network the benchmark times (the appendix's h = 1/256 network:
+    C = 64, 5 Fourier layers, k = 32, 5 x 5 convolution) at 127^2 and at the
+    timed 255^2, FP32 against the oracle on the finest level."""
+    print(f"case FNO C=64 5 layers k=32 ks=5 at {n}x{n}", flush=True)
+    dev = torch.device("cuda:0")
+    arch = (64, 5, 32, 5)
+    h, H, params = _setup(2, n, 0.01, 2, arch, B=1, seed=47000)
+    b = torch.randn(1, n, n, dtype=DT, generator=torch.Generator().manual_seed(52)).float().double()
+    alpha = torch.tensor([1e-3], dtype=DT)
+    ref = O.fno_smoother(_oracle_params(params[0][0]), 2, arch[2])(H, 0, b, alpha)
+    got = h.apply_smoother(0, b.float().to(dev), alpha.to(dev), precision="fp32").cpu().double()
+    err = _rel(got, ref)
+    print(f"  fp32 rel err {err:.2e}", flush=True)
+    assert err < 1e-5
+    h.close()

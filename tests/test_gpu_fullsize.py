@@ -107,6 +107,45 @@ def test_fullsize_vcycle_sampled_against_oracle(setup, prec, tol):
         assert abs(r_gpu - r_ref) <= 0.1 * r_ref + tol
 
 
+def test_fullsize_fp32_cycle_iterate(setup):
+    """The plain FP32 V(1,1)+F' cycle from zero on all 64 right-hand sides in
+    the benchmark's launch configuration, compared on the iterate x itself
+    with the FP64 oracle cycle (FP32-stored weights, FP32-rounded input) for
+    every right-hand side with alpha in {1e-2, 1e-3}.  (At alpha = 1e-4 the
+    cycle amplifies the input's rounding along the eigenvectors of A near
+    alpha by up to 1/alpha, so the iterate is compared through the operator
+    there, in the sampled test above.)"""
+    print("case full-size FP32 V-cycle iterate 255x255 x 64", flush=True)
+    S = setup
+    h, dev, cyc = S["h"], S["dev"], S["meta"]["cycle"]
+    ad = S["alpha"].to(dev)
+    ws = torch.tensor(S["wsel"], dtype=torch.int32, device=dev)
+    h.prepare(ad)
+    y = S["b"].float().to(dev)
+    x = torch.zeros_like(y)
+    h.vcycle(y, x, ad, weight_set=ws, nu1=cyc["nu1"], nu2=cyc["nu2"], use_fprime=cyc["use_fprime"],
+             precision="fp32")
+    xs = x.cpu().double()
+    Ws = {}
+    errs = []
+    for i in range(S["B"]):
+        ai = S["alpha"][i:i + 1]
+        if float(ai) < 1e-3 * 0.99:
+            continue
+        k = S["wsel"][i]
+        if k not in Ws:
+            W = [_split(S["sets"][k][l]) for l in range(S["L"] - 1)]
+            Ws[k] = [O.neural_smoother(w, 2) for w in W]
+        yi = S["b"][i:i + 1].float().double()
+        ref = O.vcycle(S["H"], Ws[k], torch.zeros_like(yi), yi, ai, cyc["nu1"], cyc["nu2"], cyc["use_fprime"])
+        errs.append((float((xs[i:i + 1] - ref).norm() / ref.norm()), i, float(ai)))
+    worst = max(errs)
+    print(f"  {len(errs)} right-hand sides, max rel err of x {worst[0]:.2e} (rhs {worst[1]}, alpha {worst[2]:g}), "
+          f"mean {sum(e[0] for e in errs) / len(errs):.2e}", flush=True)
+    assert len(errs) >= 30
+    assert worst[0] < 1e-5
+
+
 def test_fullsize_solve_residual_every_rhs(setup):
     """The benchmark's solve (64 right-hand sides, mixed precision, rtol 1e-6):
     every returned solution meets the tolerance in FP64 on the GPU, and the

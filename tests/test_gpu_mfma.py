@@ -122,6 +122,31 @@ def test_fprime_every_precision(n, L):
     h.close()
 
 
+@pytest.mark.parametrize("n", [127, 511, 1023, 2047])
+def test_fprime_bf16_large_grids(n):
+    """The BF16 F' at the level sizes the mixed-size serving pool and the
+    large solve run (127^2 .. 2047^2; four batched MFMA passes): against its
+    stage-by-stage BF16 emulation (tight) and the FP64 oracle (stated)."""
+    print(f"case fprime bf16 n={n}", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=2.56 / (n + 1), levels=2, max_batch=1, channels=(1, 32, 32, 1),
+                                        ksize=3))
+    x = torch.randn(1, n, n, dtype=DT, generator=torch.Generator().manual_seed(61)).float().double()
+    gmx = h.apply_fprime(0, x.float().to(dev), "mixed").cpu().double()
+    C = _bf(O.dct2_matrix(n))
+    m = O.fprime_mask(n, 2)
+    t = (_bf(x) @ C.T).transpose(1, 2)
+    u = (_bf(t) @ C.T).transpose(1, 2) * m
+    v = (_bf(u) @ C).transpose(1, 2)
+    emul = (_bf(v) @ C).transpose(1, 2)
+    ref = O.fprime(x, 2)
+    ee, er = _rel(gmx, emul), _rel(gmx, ref)
+    print(f"  mixed-vs-emulation {ee:.1e} mixed-vs-oracle {er:.1e}", flush=True)
+    assert ee < 1e-3 and er < 3e-2
+    h.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
 def test_solve_fp32_and_mixed_reach_tolerance(prec):
     """Damped-Jacobi cycle (no learned weights) on 31x31: the plain FP32 and
