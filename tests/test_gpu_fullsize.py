@@ -111,10 +111,19 @@ def test_fullsize_fp32_cycle_iterate(setup):
     """The plain FP32 V(1,1)+F' cycle from zero on all 64 right-hand sides in
     the benchmark's launch configuration, compared on the iterate x itself
     with the FP64 oracle cycle (FP32-stored weights, FP32-rounded input) for
-    every right-hand side with alpha in {1e-2, 1e-3}.  (At alpha = 1e-4 the
-    cycle amplifies the input's rounding along the eigenvectors of A near
-    alpha by up to 1/alpha, so the iterate is compared through the operator
-    there, in the sampled test above.)"""
+    every right-hand side with alpha in {1e-2, 1e-3}.
+
+    Tolerance.  The oracle is given the same FP32-rounded input, so what is
+    left is FP32 rounding inside the cycle.  Each finest-level residual
+    y - A x is formed in FP32, with an absolute error of about u ||y||
+    (u = 2^-24), and the coarse-grid correction maps it back through A^-1,
+    whose norm is 1/alpha relative to ||A|| (cond(A) = (||G||^2 + alpha)/alpha
+    with ||G|| <= 1 for the row-normalised Gaussian).  A V(1,1) cycle forms two
+    finest-level residuals, so the forward error of x is bounded by about
+    2 u cond(A): 1.2e-5 at alpha = 1e-2 and 1.2e-4 at alpha = 1e-3, which
+    the test asserts per alpha.  The plain 1e-5 is asserted on the backward
+    error ||A (x - x_ref)|| / ||y|| of all 64 right-hand sides, alpha = 1e-4
+    included (where 2 u cond(A) exceeds 1e-3)."""
     print("case full-size FP32 V-cycle iterate 255x255 x 64", flush=True)
     S = setup
     h, dev, cyc = S["h"], S["dev"], S["meta"]["cycle"]
@@ -127,23 +136,39 @@ def test_fullsize_fp32_cycle_iterate(setup):
              precision="fp32")
     xs = x.cpu().double()
     Ws = {}
-    errs = []
+    refs = {}
     for i in range(S["B"]):
         ai = S["alpha"][i:i + 1]
-        if float(ai) < 1e-3 * 0.99:
-            continue
         k = S["wsel"][i]
         if k not in Ws:
             W = [_split(S["sets"][k][l]) for l in range(S["L"] - 1)]
             Ws[k] = [O.neural_smoother(w, 2) for w in W]
         yi = S["b"][i:i + 1].float().double()
-        ref = O.vcycle(S["H"], Ws[k], torch.zeros_like(yi), yi, ai, cyc["nu1"], cyc["nu2"], cyc["use_fprime"])
-        errs.append((float((xs[i:i + 1] - ref).norm() / ref.norm()), i, float(ai)))
-    worst = max(errs)
-    print(f"  {len(errs)} right-hand sides, max rel err of x {worst[0]:.2e} (rhs {worst[1]}, alpha {worst[2]:g}), "
-          f"mean {sum(e[0] for e in errs) / len(errs):.2e}", flush=True)
-    assert len(errs) >= 30
-    assert worst[0] < 1e-5
+        refs[i] = O.vcycle(S["H"], Ws[k], torch.zeros_like(yi), yi, ai, cyc["nu1"], cyc["nu2"], cyc["use_fprime"])
+    errs = {}
+    for i in range(S["B"]):
+        ai = S["alpha"][i:i + 1]
+        if float(ai) < 1e-3 * 0.99:
+            continue
+        ref = refs[i]
+        errs.setdefault(round(float(ai), 12), []).append((float((xs[i:i + 1] - ref).norm() / ref.norm()), i))
+    u = 2.0 ** -24
+    assert sum(len(v) for v in errs.values()) >= 30
+    for a, e in sorted(errs.items()):
+        worst = max(e)
+        bound = 2 * u * (1 + a) / a
+        print(f"  alpha {a:g}: {len(e)} right-hand sides, max rel err of x {worst[0]:.2e} (rhs {worst[1]}), "
+              f"mean {sum(v[0] for v in e) / len(e):.2e}; tolerance 2 u cond(A) = {bound:.2e}", flush=True)
+        assert worst[0] < bound
+    # The backward error of every right-hand side (all three alphas), which
+    # conditioning does not amplify, at the plain FP32 tolerance.
+    worst_bw = 0.0
+    for i in range(S["B"]):
+        ai = S["alpha"][i:i + 1]
+        yi = S["b"][i:i + 1].float().double()
+        worst_bw = max(worst_bw, float(O.apply_operator(S["H"], 0, xs[i:i + 1] - refs[i], ai).norm() / yi.norm()))
+    print(f"  all 64 right-hand sides: max ||A(x - x_ref)||/||y|| {worst_bw:.2e}", flush=True)
+    assert worst_bw < 1e-5
 
 
 def test_fullsize_solve_residual_every_rhs(setup):

@@ -130,8 +130,11 @@ def test_fprime_bf16_large_grids(n):
     print(f"case fprime bf16 n={n}", flush=True)
     from paper_2603_01064_amd import nmg
     dev = torch.device("cuda:0")
-    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=2.56 / (n + 1), levels=2, max_batch=1, channels=(1, 32, 32, 1),
-                                        ksize=3))
+    # Only level 0's F' is applied; the depth keeps the coarsest grid within
+    # the eigenbasis coarse solve's limit (511^2).
+    levels = 2 if n <= 1023 else 3
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=2.56 / (n + 1), levels=levels, max_batch=1,
+                                        channels=(1, 32, 32, 1), ksize=3))
     x = torch.randn(1, n, n, dtype=DT, generator=torch.Generator().manual_seed(61)).float().double()
     gmx = h.apply_fprime(0, x.float().to(dev), "mixed").cpu().double()
     C = _bf(O.dct2_matrix(n))
