@@ -213,6 +213,7 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
 nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, void* out,
                             nmg_precision precision, void* stream);
 
+
 /* ---- the cycle ---------------------------------------------------------- */
 
 /* x <- MG(x, y): one V(nu1, nu2) cycle on the finest level with initial
@@ -465,6 +466,17 @@ nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* id
  * which 0 = M_l, 1 = G_l; out double[n_l][2 r + 1], *radius receives r
  * (call with out == NULL to query the radius). */
 nmg_status nmg_debug_factor(nmg_handle h, int level, int which, double* out, int* radius);
+
+/* Test switches that change how results are computed but not their values.
+ *   NMG_DEBUG_FP32_HANDOFF, value 1: in mixed-precision cycles with F' the
+ *     BF16 smoother writes h as FP32 and F' rounds it to BF16 itself (the
+ *     path of nmg_apply_fprime) instead of receiving the zero-padded BF16
+ *     plane the smoother writes directly on levels above 64^2.  Both give
+ *     bit-identical iterates.  Value 0 (default) restores the direct plane.
+ * Takes effect for cycles launched afterwards (captured solve graphs are
+ * dropped).  NMG_ERR_ARG for an unknown option. */
+typedef enum { NMG_DEBUG_FP32_HANDOFF = 1 } nmg_debug_opt;
+nmg_status nmg_debug_option(nmg_handle h, int option, int value);
 
 #ifdef __cplusplus
 }

@@ -2,13 +2,24 @@
 //
 //   F'(H) = C^T (m' .* (C H C^T)) C,   C = orthonormal DCT-II of the level size
 //
-// is evaluated as four batched "row GEMMs with transposed store"
-//   out[b][j][i] = sum_k in[b][i][k] Mat[j][k]
-// (Mat = C for the forward pair, C^T for the inverse pair); storing each
-// product transposed turns the left multiplication into another right
-// multiplication.  The ramp mask sqrt(max(k1, k2) / n) is applied in the
-// epilogue of the second pass and the last pass accumulates into x.
-// Inputs are rounded to BF16, products accumulate in FP32.
+// Operands are BF16, products accumulate in FP32, and every product
+// contracts along the contiguous index of both operands.  Three forms:
+//  * padded sizes NP <= 512 (levels 65..511): two fused launches.  A
+//    workgroup owns a column block I of the result; it forms
+//    P = A[I,:] H^T into LDS and then A P^T, i.e. the columns I of A H A^T.
+//    The first launch (A = C) applies the ramp mask sqrt(max(k1, k2) / n) and
+//    stores the masked spectrum as BF16; the second (A = C^T) adds C^T M C
+//    into x.
+//  * NP >= 1024: four batched "row GEMMs with transposed store"
+//      out[b][j][i] = sum_k in[b][i][k] Mat[j][k]
+//    (storing each product transposed turns the left multiplication into
+//    another right multiplication), mask in the second pass's epilogue.
+//  * n <= 64: one workgroup per image with the intermediate in LDS.
+// All three accumulate each dot product over the same ascending K steps of
+// 32 and round the same intermediates to BF16, so they give the same values
+// (and a result does not depend on the batch it is computed in).
+// The input is a zero-padded BF16 NP x NP plane per image: the BF16 smoother
+// writes it directly; FP32 inputs are rounded into it first.
 #include <vector>
 
 #include "nmg_internal.h"
@@ -46,8 +57,7 @@ inline uint16_t f2bf_h(float f) {
 // tile (Mat) in LDS with the 16-byte chunk of row r stored at chunk ^ (r & 3)
 // to spread the fragment reads over banks; four k-steps are staged per
 // barrier pair.
-//   IN  0: in is the FP32 n x n level array (rounded to BF16 while staging)
-//       1: in is a BF16 npad x npad intermediate (zero padded)
+// in is a zero-padded BF16 npad x npad plane;
 //   OUT 0: BF16 npad x npad intermediate; 1: the same times the ramp mask;
 //       2: FP32 n x n result, stored or added (accumulate) into out
 // BF16 intermediates are exactly the values the next pass would have rounded
@@ -56,7 +66,7 @@ constexpr int kTI = 64, kTJ = 128, kKS = 32;
 
 __device__ inline int frag_off(int row, int chunk) { return row * 64 + ((chunk ^ (row & 3)) << 4); }
 
-template <int IN, int OUT>
+template <int OUT>
 __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__ in_v, void* __restrict__ out_v,
                                                         const uint16_t* __restrict__ mat,
                                                         const float* __restrict__ ramp, int n, int npad,
@@ -83,16 +93,8 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__
 #pragma unroll
         for (int s = 0; s < kKC; ++s) {
             const int i = i0 + sr, k = k0 + s * kKS + sc * 8;
-            if constexpr (IN == 0) {
-                const float* src = reinterpret_cast<const float*>(in_v) + (size_t)b * n * n;
-                float v[8];
-                for (int q = 0; q < 8; ++q) v[q] = (i < n && k + q < n) ? src[(size_t)i * n + k + q] : 0.f;
-                areg[s] = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]),
-                                     pack_bf16(v[6], v[7]));
-            } else {
-                const uint16_t* src = reinterpret_cast<const uint16_t*>(in_v) + (size_t)b * npad * npad;
-                areg[s] = *reinterpret_cast<const uint4*>(src + (size_t)i * npad + k);
-            }
+            const uint16_t* src = reinterpret_cast<const uint16_t*>(in_v) + (size_t)b * npad * npad;
+            areg[s] = *reinterpret_cast<const uint4*>(src + (size_t)i * npad + k);
             for (int h = 0; h < 2; ++h) {
                 const int j = j0 + sr + 64 * h;  // < npad by construction
                 breg[s][h] = *reinterpret_cast<const uint4*>(mat + (size_t)j * npad + k);
@@ -142,6 +144,204 @@ __global__ void __launch_bounds__(kThreads) k_rowgemm_t(const void* __restrict__
                 *reinterpret_cast<uint2*>(dst + ib) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
             }
         }
+}
+
+// Fragment-tiled BF16 layout of an NP x NP plane (NP <= 512): element (r, k)
+// sits in the 1 KB tile ((r >> 4) * (NP / 32) + (k >> 5)) at lane
+// (r & 15) + 16 ((k & 31) >> 3), element k & 7.  One tile is exactly one
+// 16 x 32 MFMA operand fragment (lane = row + 16 * K group of 8), so every
+// operand load is 1 KB of contiguous memory and LDS fragment reads need no
+// swizzle.  The smoother writes this layout directly.
+__device__ __host__ inline size_t tiled_off(int np, int r, int k) {
+    return ((size_t)((r >> 4) * (np >> 5) + (k >> 5)) << 9) + (size_t)(((r & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7));
+}
+
+// One half of F' for padded sizes NP <= 512 on tiled planes.  Workgroup
+// (image, column block I = [I0, I0 + CB)):
+//   step 1  P[i][k]      = sum_m A[I0 + i][m] in[k][m]     CB x NP, BF16 in LDS
+//   step 2  R[j][I0 + i] = sum_k A[j][k] P[i][k]            NP x CB
+// STAGE 0 (A = C, in = H): R = C H C^T on columns I; masked by the ramp and
+//   stored as BF16 into the tiled spectrum plane (zero outside n x n).
+// STAGE 1 (A = C^T, in = that spectrum M): R = C^T M C on columns I, stored
+//   or added into the FP32 n x n level array, row by row through LDS so the
+//   global accesses are coalesced.
+// The MFMA M dimension is i: the CB rows shared by the WAVES waves (rows of
+// A staged whole in LDS for step 1, then P in their place).  N is the
+// wave's NP / WAVES private rows (image rows in step 1, rows of A in step
+// 2), loaded straight into operand registers.  The 2 NP / 32 K steps of
+// those rows (step 1's, then step 2's) form one stream read through a ring
+// of KCH register slots: the first KCH are issued at the start, and each
+// slot is refilled with the step KCH ahead as soon as its products are
+// issued.  With KCH = NP / 32 all of step 1 is in flight at once and step 2
+// loads while step 1 computes.
+template <int NP, int CB, int WAVES, int KCH, int STAGE>
+__global__ void __launch_bounds__(64 * WAVES) k_fprime_tiled(const uint16_t* __restrict__ in, void* __restrict__ out,
+                                                             const uint16_t* __restrict__ A,
+                                                             const float* __restrict__ ramp, int n, int accumulate) {
+    constexpr int NTH = 64 * WAVES;
+    constexpr int KST = NP / 32;            // K steps of 32
+    constexpr int NBLK = NP / CB;
+    constexpr int MT = CB / 16;
+    constexpr int NWR = NP / WAVES;         // private rows per wave
+    constexpr int NT = NWR / 16;
+    constexpr int APT = (CB / 16) * KST * 64 / NTH;  // 16-byte pieces of the staged rows of A per thread
+    constexpr int PB = CB * NP * 2;                  // bytes of P (and of the staged rows of A)
+    constexpr int OPITCH = CB + 4;                   // floats per LDS row of the STAGE 1 output
+    constexpr int OB = STAGE == 1 ? NP * OPITCH * 4 : 0;
+    constexpr int LB = PB > OB ? PB : OB;
+    static_assert((CB / 16) * KST * 64 % NTH == 0 && APT > 0 && NWR % 16 == 0 && NP % CB == 0, "F' tile shape");
+    __shared__ __attribute__((aligned(16))) char Ls[LB];
+
+    // XCD-aware numbering (workgroups go round-robin over the 8 XCDs by linear
+    // id): the column blocks of one image run on one XCD and share its L2
+    int img, blk;
+    {
+        const int G = gridDim.x, i = blockIdx.x;
+        const int x = i % 8, q = G / 8, rem = G % 8;
+        const int p = x * q + min(x, rem) + i / 8;
+        img = p / NBLK;
+        blk = p - img * NBLK;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ln = lane & 15, lg = lane >> 4;
+    const int I0 = blk * CB;
+    const int wrow = wave * NWR;
+    const uint16_t* src = in + (size_t)img * NP * NP;
+    // fragment (rows 16 g .. 16 g + 15, K step st) of a tiled plane
+    auto frag = [&](const uint16_t* base, int g, int st) {
+        return *reinterpret_cast<const bf16x8*>(base + ((size_t)(g * KST + st) << 9) + lane * 8);
+    };
+
+    // rows I of A: CB / 16 row groups of KST contiguous tiles
+    const uint16_t* Ab = A + ((size_t)(I0 >> 4) * KST << 9);
+    // (two named registers, not an array: an array here was moved to LDS)
+    static_assert(APT <= 2, "staging pieces per thread");
+    const uint4 ar0 = *reinterpret_cast<const uint4*>(Ab + (size_t)tid * 8);
+    uint4 ar1 = ar0;
+    if constexpr (APT == 2) ar1 = *reinterpret_cast<const uint4*>(Ab + (size_t)(tid + NTH) * 8);
+    static_assert(KCH >= 1 && KCH <= KST, "register ring depth");
+    bf16x8 pv[NT][KCH];
+    // stream step t: K step t of the image rows (t < KST), else K step t - KST of the rows of A
+    auto fetch = [&](int t) {
+        if (t >= 2 * KST) return;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            pv[nt][t % KCH] = t < KST ? frag(src, (wrow >> 4) + nt, t) : frag(A, (wrow >> 4) + nt, t - KST);
+    };
+#pragma unroll
+    for (int t = 0; t < KCH; ++t) fetch(t);
+    *reinterpret_cast<uint4*>(Ls + tid * 16) = ar0;
+    if constexpr (APT == 2) *reinterpret_cast<uint4*>(Ls + (tid + NTH) * 16) = ar1;
+    __syncthreads();
+
+    floatx4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // ---- step 1: P = A[I, :] in^T
+#pragma unroll
+    for (int st = 0; st < KST; ++st) {
+        bf16x8 af[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = *reinterpret_cast<const bf16x8*>(Ls + ((mt * KST + st) << 10) + lane * 16);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], pv[nt][st % KCH], acc[mt][nt], 0, 0, 0);
+        fetch(st + KCH);
+        // keep each refill behind the products that free its registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();  // every wave has read its last rows of A from LDS
+    // P[i][k] into LDS in the tiled layout: acc[mt][nt][q] is row i = 16 mt + 4 lg + q,
+    // column k = wrow + 16 nt + ln
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int k = wrow + nt * 16 + ln;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int il = lg * 4 + q;
+                const int off = ((mt * KST + (k >> 5)) << 10) + ((il + 16 * ((k & 31) >> 3)) << 4) + (k & 7) * 2;
+                *reinterpret_cast<uint16_t*>(Ls + off) = (uint16_t)pack_bf16(acc[mt][nt][q], 0.f);
+            }
+            acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    __syncthreads();
+    // ---- step 2: R[j][I0 + i] = sum_k A[j][k] P[i][k]
+#pragma unroll
+    for (int st = 0; st < KST; ++st) {
+        bf16x8 af[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = *reinterpret_cast<const bf16x8*>(Ls + ((mt * KST + st) << 10) + lane * 16);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], pv[nt][(KST + st) % KCH], acc[mt][nt], 0,
+                                                                      0, 0);
+        if constexpr (KCH < KST) {
+            fetch(KST + st + KCH);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // ---- epilogue: acc[mt][nt][q] = R[j][i], j = wrow + 16 nt + ln, i = I0 + 16 mt + 4 lg + q
+    if constexpr (STAGE == 0) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int j = wrow + nt * 16 + ln;
+                const int ib = I0 + mt * 16 + lg * 4;
+                float v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = ib + q;
+                    v[q] = (i < n && j < n) ? acc[mt][nt][q] * ramp[i > j ? i : j] : 0.f;
+                }
+                // four consecutive columns share one 16-byte group of the tile
+                uint16_t* dst = reinterpret_cast<uint16_t*>(out) + (size_t)img * NP * NP + tiled_off(NP, j, ib);
+                *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+            }
+    } else {
+        __syncthreads();  // every wave has read P
+        float* O = reinterpret_cast<float*>(Ls);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                *reinterpret_cast<floatx4*>(O + (wrow + nt * 16 + ln) * OPITCH + mt * 16 + lg * 4) = acc[mt][nt];
+        __syncthreads();
+        float* xb = reinterpret_cast<float*>(out) + (size_t)img * n * n;
+#pragma unroll 4
+        for (int e = tid; e < NP * CB; e += NTH) {
+            const int j = e / CB, i = e % CB;
+            if (j < n && I0 + i < n) {
+                const float v = O[j * OPITCH + i];
+                float* d = xb + (size_t)j * n + I0 + i;
+                *d = accumulate ? *d + v : v;
+            }
+        }
+    }
+}
+
+// FP32 n x n images -> zero-padded BF16 NP x NP planes (round to nearest
+// even), tiled (NP <= 512) or row-major
+__global__ void __launch_bounds__(kThreads) k_bf16_pad(const float* __restrict__ in, uint16_t* __restrict__ out, int n,
+                                                       int np, int tiled) {
+    const int b = blockIdx.y;
+    const size_t e = ((size_t)blockIdx.x * kThreads + threadIdx.x) * 2;  // two columns per thread
+    if (e >= (size_t)np * np) return;
+    const int i = (int)(e / np), k = (int)(e % np);
+    const float* src = in + (size_t)b * n * n + (size_t)i * n;
+    const float v0 = (i < n && k < n) ? src[k] : 0.f;
+    const float v1 = (i < n && k + 1 < n) ? src[k + 1] : 0.f;
+    const size_t o = tiled ? tiled_off(np, i, k) : e;  // k even: both columns in one 16-byte group
+    *reinterpret_cast<uint32_t*>(out + (size_t)b * np * np + o) = pack_bf16(v0, v1);
 }
 
 // The same four products for a level with NP = n rounded up to 32 <= 64:
@@ -232,6 +432,17 @@ nmg_status prepare_fprime_bf16(Ctx* c) {
                 Ct[(size_t)i * npad + k] = f2bf_h(v);
             }
         }
+        if (fprime_tiled_layout(n)) {
+            // the two-launch kernels read C and C^T in the fragment-tiled layout
+            std::vector<uint16_t> Ctl(C.size()), Cttl(Ct.size());
+            for (int r = 0; r < npad; ++r)
+                for (int k = 0; k < npad; ++k) {
+                    Ctl[tiled_off(npad, r, k)] = C[(size_t)r * npad + k];
+                    Cttl[tiled_off(npad, r, k)] = Ct[(size_t)r * npad + k];
+                }
+            C.swap(Ctl);
+            Ct.swap(Cttl);
+        }
         c->dctbf_off.push_back(all.size());
         all.insert(all.end(), C.begin(), C.end());
         all.insert(all.end(), Ct.begin(), Ct.end());
@@ -261,16 +472,44 @@ nmg_status prepare_fprime_bf16(Ctx* c) {
     return NMG_OK;
 }
 
-// dst (+)= F'(h) on level l for a 2D float cycle; t1/t2 are level-sized scratch.
-nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, float* dst, int accumulate,
-                              float* t1, float* t2, hipStream_t s) {
+namespace {
+
+template <int NP, int CB, int WAVES, int KCH>
+void launch_tiled_pair(int batch, const uint16_t* hb, uint16_t* spec, float* dst, const uint16_t* C,
+                       const uint16_t* Ct, const float* rp, int n, int accumulate, hipStream_t s) {
+    const dim3 grid((unsigned)(NP / CB * batch));
+    hipLaunchKernelGGL((k_fprime_tiled<NP, CB, WAVES, KCH, 0>), grid, dim3(64 * WAVES), 0, s, hb, (void*)spec, C, rp,
+                       n, 0);
+    hipLaunchKernelGGL((k_fprime_tiled<NP, CB, WAVES, KCH, 1>), grid, dim3(64 * WAVES), 0, s, spec, (void*)dst, Ct, rp,
+                       n, accumulate);
+}
+
+}  // namespace
+
+bool fprime_tiled_layout(int n) { return n > 64 && (n + 127) / 128 * 128 <= 512; }
+
+size_t fprime_mfma_scratch_bytes(int n, int batch) {
+    if (n <= 64) return 0;
+    const size_t np = (size_t)(n + 127) / 128 * 128;
+    return 2 * (size_t)batch * np * np * sizeof(uint16_t);
+}
+
+// dst (+)= F'(h) on level l for a 2D float cycle.  The input is either the
+// FP32 level array h or, when hb is given, its zero-padded BF16 NP x NP plane.
+// t1 and t2 are scratch_bytes each and need batch * NP * NP BF16 values each
+// (levels above 64^2); hb may be t1.
+nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, const uint16_t* hb, float* dst,
+                              int accumulate, void* t1, void* t2, size_t scratch_bytes, hipStream_t s) {
     const int n = c->n[(size_t)l];
     const int npad = (n + 127) / 128 * 128;
-    const int ti = npad / kTI, tj = npad / kTJ;
+    if (!c->dctbf || !c->ramp) return fail(NMG_ERR_STATE, "BF16 DCT tables are not built");
+    if (n > 64 && 2 * scratch_bytes < fprime_mfma_scratch_bytes(n, batch))
+        return fail(NMG_ERR_SHAPE, "F' scratch too small for this level size and batch");
     const uint16_t* C = c->dctbf + c->dctbf_off[(size_t)l];
     const uint16_t* Ct = C + (size_t)npad * npad;
+    const float* rp = c->ramp + c->ramp_off[(size_t)l];
     if (n <= 64) {
-        const float* rp = c->ramp + c->ramp_off[(size_t)l];
+        if (!h) return fail(NMG_ERR_ARG, "F' on levels up to 64^2 takes the FP32 level array");
         if (n <= 32)
             hipLaunchKernelGGL(k_fprime_small<32>, dim3(batch), dim3(kThreads), 0, s, h, dst, C, Ct, rp, n, npad,
                                accumulate);
@@ -280,15 +519,33 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, fl
         NMG_HIP(hipGetLastError());
         return NMG_OK;
     }
-    if ((size_t)npad * npad * 2 > (size_t)n * n * 4)
-        return fail(NMG_ERR_SHAPE, "F' scratch too small for this level size");
-    dim3 grid((unsigned)(ti * tj), (unsigned)batch);
-    const float* rp = c->ramp + c->ramp_off[(size_t)l];
-    // BF16 intermediates (npad x npad per image) live in the level scratch buffers
-    hipLaunchKernelGGL((k_rowgemm_t<0, 0>), grid, dim3(kThreads), 0, s, h, t1, C, rp, n, npad, tj, 0);
-    hipLaunchKernelGGL((k_rowgemm_t<1, 1>), grid, dim3(kThreads), 0, s, t1, t2, C, rp, n, npad, tj, 0);
-    hipLaunchKernelGGL((k_rowgemm_t<1, 0>), grid, dim3(kThreads), 0, s, t2, t1, Ct, rp, n, npad, tj, 0);
-    hipLaunchKernelGGL((k_rowgemm_t<1, 2>), grid, dim3(kThreads), 0, s, t1, dst, Ct, rp, n, npad, tj, accumulate);
+    uint16_t* b1 = reinterpret_cast<uint16_t*>(t1);
+    uint16_t* b2 = reinterpret_cast<uint16_t*>(t2);
+    const bool tiled = fprime_tiled_layout(n);
+    if (!hb) {
+        const size_t pairs = (size_t)npad * npad / 2;
+        hipLaunchKernelGGL(k_bf16_pad, dim3((unsigned)((pairs + kThreads - 1) / kThreads), (unsigned)batch),
+                           dim3(kThreads), 0, s, h, b1, n, npad, tiled ? 1 : 0);
+        hb = b1;
+    }
+    if (hb == b2) return fail(NMG_ERR_ARG, "F' input plane overlaps its scratch");
+    if (npad == 128) {
+        launch_tiled_pair<128, 32, 8, 4>(batch, hb, b2, dst, C, Ct, rp, n, accumulate, s);
+    } else if (npad == 256) {
+        launch_tiled_pair<256, 32, 8, 8>(batch, hb, b2, dst, C, Ct, rp, n, accumulate, s);
+    } else if (npad == 512) {
+        launch_tiled_pair<512, 32, 16, 8>(batch, hb, b2, dst, C, Ct, rp, n, accumulate, s);
+    } else if (tiled) {
+        return fail(NMG_ERR_SHAPE, "F' on MFMA: unsupported padded size " + std::to_string(npad));
+    } else {
+        const int ti = npad / kTI, tj = npad / kTJ;
+        dim3 grid((unsigned)(ti * tj), (unsigned)batch);
+        // hb -> b2 -> b1 (masked) -> b2 -> dst; hb is dead after the first pass
+        hipLaunchKernelGGL((k_rowgemm_t<0>), grid, dim3(kThreads), 0, s, hb, b2, C, rp, n, npad, tj, 0);
+        hipLaunchKernelGGL((k_rowgemm_t<1>), grid, dim3(kThreads), 0, s, b2, b1, C, rp, n, npad, tj, 0);
+        hipLaunchKernelGGL((k_rowgemm_t<0>), grid, dim3(kThreads), 0, s, b1, b2, Ct, rp, n, npad, tj, 0);
+        hipLaunchKernelGGL((k_rowgemm_t<2>), grid, dim3(kThreads), 0, s, b2, dst, Ct, rp, n, npad, tj, accumulate);
+    }
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

@@ -129,7 +129,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                                                             const double* __restrict__ nrm2, int nparts, float* __restrict__ dst,
                                                             int accumulate, const uint16_t* __restrict__ wlevel,
                                                             size_t set_stride, const int* __restrict__ ws, int nsets,
-                                                            int n, int tiles_x, int tiles_per_img) {
+                                                            int n, int tiles_x, int tiles_per_img,
+                                                            uint16_t* __restrict__ dstb, int bpitch, int btiled) {
     constexpr int NH = NL - 2;
     using G = Geo<NL>;
     constexpr int TW = G::TW, TH = G::TH, RW = G::RW;
@@ -485,12 +486,26 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                     if (e >= TH * TW) break;
                     const int oy = e / TW, ox = e - (e / TW) * TW;
                     const int gy = ty0 + oy, gx = tx0 + ox;
-                    if (!EDGE || (gy < n && gx < n)) {
+                    const bool in_img = !EDGE || (gy < n && gx < n);
+                    float v = 0.f;
+                    if (in_img) {
                         const float* zb = Z + oy * ZP + ox;
-                        float v = 0.f;
 #pragma unroll
                         for (int t = 0; t < 9; ++t) v += zb[t * ZN + (t / 3) * ZP + t % 3];
                         v *= nbf;
+                    }
+                    if (bpitch > 0) {
+                        // zero-padded BF16 plane for the MFMA filter F' (the tiles
+                        // cover the padding too; the host checks it), row-major or
+                        // in the filter's fragment-tiled layout: 1 KB tiles of
+                        // 16 rows x 32 columns, lane (row & 15) + 16 ((col & 31) >> 3)
+                        if (gy < bpitch && gx < bpitch) {
+                            const size_t o = btiled ? ((size_t)((gy >> 4) * (bpitch >> 5) + (gx >> 5)) << 9) +
+                                                          (size_t)(((gy & 15) + 16 * ((gx & 31) >> 3)) * 8 + (gx & 7))
+                                                    : (size_t)gy * bpitch + gx;
+                            dstb[(size_t)img * bpitch * bpitch + o] = (uint16_t)pack2_bf16(v, 0.f);
+                        }
+                    } else if (in_img) {
                         float* o = out + (size_t)gy * n + gx;
                         *o = accumulate ? *o + v : v;
                     }
@@ -584,7 +599,8 @@ nmg_status repack_bf16(Ctx* c, int level, int weight_set) {
 }
 
 nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b, const double* nrm2,
-                                int nparts, float* dst, int accumulate, Work<float>& w, hipStream_t s) {
+                                int nparts, float* dst, int accumulate, Work<float>& w, hipStream_t s, uint16_t* dstb,
+                                int bpitch, bool btiled) {
     (void)w;
     std::string why;
     if (!mfma_supported(c, &why)) return fail(NMG_ERR_STATE, why);
@@ -592,6 +608,9 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
     const int n = c->n[(size_t)l];
     if ((size_t)n * n * sizeof(float) >= ((size_t)1 << 31))
         return fail(NMG_ERR_SHAPE, "BF16 smoother: one image of this level exceeds 2 GiB");
+    if (dstb && !mfma_smoother_covers(c, l, bpitch))
+        return fail(NMG_ERR_SHAPE, "BF16 smoother: its tiles do not cover the padded output plane");
+    if (!dstb) bpitch = 0;
     const uint16_t* wl = c->wbf + (size_t)l * c->p.n_weight_sets * c->wbf_stride;
     // one resident round of workgroups (two per CU) over the batch: the
     // workgroups have equal work, so a second, partial round would leave
@@ -605,16 +624,31 @@ nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, c
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = grid_x(tiles);
         hipLaunchKernelGGL((k_smoother_mfma<3>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
+                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles,
+                           dstb, bpitch, btiled ? 1 : 0);
     } else {
         using G = Geo<4>;
         const int tiles_x = (n + G::TW - 1) / G::TW, tiles = tiles_x * ((n + G::TH - 1) / G::TH);
         const int per_img = grid_x(tiles);
         hipLaunchKernelGGL((k_smoother_mfma<4>), dim3((unsigned)per_img, (unsigned)batch), dim3(kThreads), G::lds, s, b,
-                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles);
+                           nrm2, nparts, dst, accumulate, wl, c->wbf_stride, ws, c->p.n_weight_sets, n, tiles_x, tiles,
+                           dstb, bpitch, btiled ? 1 : 0);
     }
     NMG_HIP(hipGetLastError());
     return NMG_OK;
+}
+
+bool mfma_smoother_covers(const Ctx* c, int l, int pitch) {
+    const int n = c->n[(size_t)l];
+    int tw, th;
+    if (c->p.n_layers == 3) {
+        tw = Geo<3>::TW;
+        th = Geo<3>::TH;
+    } else {
+        tw = Geo<4>::TW;
+        th = Geo<4>::TH;
+    }
+    return pitch >= n && (n + tw - 1) / tw * tw >= pitch && (n + th - 1) / th * th >= pitch;
 }
 
 size_t mfma_lds_bytes(int n_layers) { return n_layers == 3 ? Geo<3>::lds : Geo<4>::lds; }

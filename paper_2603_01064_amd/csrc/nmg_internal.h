@@ -180,6 +180,7 @@ struct Ctx {
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     std::vector<int> adam_step;        // per set
+    bool dbg_fp32_handoff = false;     // nmg_debug_option NMG_DEBUG_FP32_HANDOFF
     uint16_t* dctbf = nullptr;         // BF16 DCT-II matrices C and C^T per level (padded)
     std::vector<size_t> dctbf_off;
     float* ramp = nullptr;             // sqrt(k / n_l) per level (F' mask)
@@ -338,9 +339,14 @@ nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, c
 // nparts == 0: nrm2[b] is ||b||^2 of image b; nparts > 0: nrm2 holds the
 // [batch][nparts] partial sums of launch_sumsq_part, which the kernel adds in
 // the order k_sumsq_final uses (same value, one launch fewer)
+// dstb != nullptr: write h as a zero-padded BF16 bpitch x bpitch plane per
+// image (the input of the MFMA filter F', fragment-tiled when btiled)
+// instead of the FP32 array dst
 nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b,
                                 const double* nrm2, int nparts, float* dst, int accumulate, Work<float>& w,
-                                hipStream_t s);
+                                hipStream_t s, uint16_t* dstb = nullptr, int bpitch = 0, bool btiled = false);
+// whether the smoother's tiles of level l cover a padded pitch x pitch plane
+bool mfma_smoother_covers(const Ctx* c, int l, int pitch);
 template <typename T>
 nmg_status launch_jacobi(const Ctx* c, int l, int batch, const double* alpha, double omega, const T* b, T* dst,
                          int accumulate, Work<T>& w, hipStream_t s);
@@ -348,8 +354,13 @@ template <typename T>
 nmg_status launch_fprime(const Ctx* c, int l, int batch, const T* h, T* dst, int accumulate, Work<T>& w,
                          hipStream_t s);
 nmg_status prepare_fprime_bf16(Ctx* c);
-nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, float* dst, int accumulate, float* t1,
-                              float* t2, hipStream_t s);
+nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, const uint16_t* hb, float* dst,
+                              int accumulate, void* t1, void* t2, size_t scratch_bytes, hipStream_t s);
+// scratch bytes launch_fprime_mfma needs (t1 + t2) for `batch` images of side n
+size_t fprime_mfma_scratch_bytes(int n, int batch);
+// whether the BF16 F' input plane of a level of side n uses the fragment-tiled
+// layout (sides 65..511) rather than row-major
+bool fprime_tiled_layout(int n);
 nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
 nmg_status launch_coarse_factor(Ctx* c, int count, const double* alphas, const int* slots, hipStream_t s);
 bool coarse_eigenbasis(const Band& M, const Band& G, std::vector<double>& V, std::vector<double>& lam,

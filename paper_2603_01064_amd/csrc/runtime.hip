@@ -387,6 +387,12 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, in
     }
     T* target = a.o.use_fprime ? w.lv[(size_t)l].h : x;
     const int acc = a.o.use_fprime ? 0 : (x_zero ? 0 : 1);
+    // the BF16 smoother feeds the MFMA filter F' a zero-padded BF16 plane
+    // (in the level's first F' scratch buffer) on levels above 64^2
+    const bool mfma_sm = c->kind[(size_t)l] == 0 && c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
+    const int n_l = c->n[(size_t)l], np_l = (n_l + 127) / 128 * 128;
+    const bool bf_plane = !c->dbg_fp32_handoff && mfma_sm && a.o.use_fprime && c->p.dim == 2 && n_l > 64 && mfma_smoother_covers(c, l, np_l) &&
+                          (size_t)np_l * np_l * 2 <= level_elems(c, l) * sizeof(T);
     if (c->kind[(size_t)l] == 1) {
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
         NMG_TRY(launch_jacobi<T>(c, l, a.batch, a.alpha, c->omega[(size_t)l], bres, target, acc, w, a.s));
@@ -408,7 +414,9 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, in
         } else if (a.o.precision == NMG_MIXED) {
             NMG_TRY(launch_mfma_smoother(c, l, a.batch, a.ws, reinterpret_cast<const float*>(bres), c->norm_part,
                                          nparts, reinterpret_cast<float*>(target), acc,
-                                         *reinterpret_cast<Work<float>*>(&w), a.s));
+                                         *reinterpret_cast<Work<float>*>(&w), a.s,
+                                         bf_plane ? reinterpret_cast<uint16_t*>(w.lv[(size_t)l].t1) : nullptr,
+                                         bf_plane ? np_l : 0, fprime_tiled_layout(n_l)));
         } else {
             NMG_TRY(launch_conv_smoother<T>(c, l, a.batch, a.ws, bres, c->nrm, target, acc, w, a.s));
         }
@@ -418,9 +426,10 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, in
         if (a.o.precision == NMG_MIXED && c->p.dim == 2) {
             NMG_TRY(prepare_fprime_bf16(c));
             NMG_TRY(launch_fprime_mfma(c, l, a.batch, reinterpret_cast<const float*>(w.lv[(size_t)l].h),
-                                       reinterpret_cast<float*>(x), x_zero ? 0 : 1,
-                                       reinterpret_cast<float*>(w.lv[(size_t)l].t1),
-                                       reinterpret_cast<float*>(w.lv[(size_t)l].t2), a.s));
+                                       bf_plane ? reinterpret_cast<const uint16_t*>(w.lv[(size_t)l].t1) : nullptr,
+                                       reinterpret_cast<float*>(x), x_zero ? 0 : 1, w.lv[(size_t)l].t1,
+                                       w.lv[(size_t)l].t2, (size_t)c->p.max_batch * level_elems(c, l) * sizeof(T),
+                                       a.s));
         } else {
             NMG_TRY(launch_fprime<T>(c, l, a.batch, w.lv[(size_t)l].h, x, x_zero ? 0 : 1, w, a.s));
         }
@@ -982,6 +991,10 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->xs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->bs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->loss_dev, (size_t)nsm));
+    if (p->dim == 2) {
+        // the BF16 filter's tables
+        NMG_TRY(prepare_fprime_bf16(c.get()));
+    }
     NMG_HIP(hipDeviceSynchronize());
     *out = c.release();
     return NMG_OK;
@@ -1186,8 +1199,9 @@ nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, 
     NMG_TRY(ensure_work<float>(h));
     if (prec == NMG_MIXED && h->p.dim == 2) {
         NMG_TRY(prepare_fprime_bf16(h));
-        return launch_fprime_mfma(h, level, batch, (const float*)in, (float*)out, 0, h->w32b.lv[(size_t)level].t1,
-                                  h->w32b.lv[(size_t)level].t2, s);
+        return launch_fprime_mfma(h, level, batch, (const float*)in, nullptr, (float*)out, 0,
+                                  h->w32b.lv[(size_t)level].t1, h->w32b.lv[(size_t)level].t2,
+                                  (size_t)h->p.max_batch * level_elems(h, level) * sizeof(float), s);
     }
     return launch_fprime<float>(h, level, batch, (const float*)in, (float*)out, 0, h->w32b, s);
 }
@@ -1380,6 +1394,15 @@ nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* id
     dev_free(di);
     dev_free(dw);
     return st;
+}
+
+nmg_status nmg_debug_option(nmg_handle h, int option, int value) {
+    NMG_TRY(check_handle(h));
+    if (option != NMG_DEBUG_FP32_HANDOFF) return fail(NMG_ERR_ARG, "unknown debug option");
+    h->dbg_fp32_handoff = value != 0;
+    NMG_HIP(hipDeviceSynchronize());
+    release_graphs(h);
+    return NMG_OK;
 }
 
 nmg_status nmg_set_graphs(nmg_handle h, int enable) {

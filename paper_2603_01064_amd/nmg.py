@@ -109,6 +109,7 @@ def load_library():
         "nmg_profile_query": (S, [P, I, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "nmg_debug_transfer_map": (S, [P, I, I, P, P]),
         "nmg_debug_factor": (S, [P, I, I, P, P]),
+        "nmg_debug_option": (S, [P, I, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name, None)
@@ -458,6 +459,10 @@ class Handle:
     # -- profiling ---------------------------------------------------------
     KERNELS = {"smoother": 0, "operator": 1, "restrict": 2, "prolong": 3, "coarse": 4, "fprime": 5, "refine": 6,
                "norm": 7}
+
+    def debug_option(self, option: int, value: int) -> None:
+        """``nmg_debug_option`` (1 = NMG_DEBUG_FP32_HANDOFF)."""
+        _check(_lib.nmg_debug_option(self.ptr, int(option), int(value)))
 
     def set_graphs(self, enable: bool) -> None:
         """Replay solve iterations as captured HIP graphs (default) or launch eagerly."""

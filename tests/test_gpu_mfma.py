@@ -97,6 +97,38 @@ def test_mixed_vcycle_error_stated():
     h.close()
 
 
+@pytest.mark.parametrize("n,L,B,ch", [(127, 3, 3, (1, 32, 32, 1)), (255, 5, 8, (1, 32, 32, 1)),
+                                      (255, 4, 5, (1, 32, 32, 32, 1)), (511, 4, 2, (1, 32, 32, 1))])
+def test_mixed_cycle_bf16_plane_equals_fp32_handoff(n, L, B, ch):
+    """In mixed-precision cycles with F' the BF16 smoother hands the MFMA
+    filter a zero-padded BF16 plane on levels above 64^2 (the filter rounds
+    an FP32 input to exactly those values itself).  Two V(1,1)+F' cycles are
+    compared bit for bit with the same cycles run with the FP32 handoff
+    (NMG_DEBUG_FP32_HANDOFF), which the F' parity tests cover."""
+    print(f"case bf16 plane handoff n={n} L={L} B={B} layers={len(ch) - 1}", flush=True)
+    from paper_2603_01064_amd import nmg
+    dev = torch.device("cuda:0")
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=2.56 / (n + 1), levels=L, max_batch=B, channels=ch, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, inputs.he_normal_weights(ch, 3, 2, 7300 + 10 * l))
+    alpha = torch.tensor([1e-2, 1e-3, 1e-4] * B, dtype=DT)[:B].to(dev)
+    h.prepare(alpha)
+    y = torch.randn(B, n, n, dtype=torch.float32, generator=torch.Generator().manual_seed(52)).to(dev)
+    outs = []
+    for handoff in (0, 1):
+        h.debug_option(1, handoff)
+        x = torch.zeros_like(y)
+        for _ in range(2):
+            h.vcycle(y, x, alpha, nu1=1, nu2=1, use_fprime=True, precision="mixed")
+        torch.cuda.synchronize()
+        outs.append(x.cpu())
+    h.close()
+    assert bool(torch.isfinite(outs[0]).all()) and float(outs[0].abs().max()) > 0
+    diff = int((outs[0] != outs[1]).sum())
+    print(f"  differing elements: {diff} of {outs[0].numel()}", flush=True)
+    assert torch.equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("n,L", [(63, 3), (255, 5)])
 def test_fprime_every_precision(n, L):
     """F'(h) = C^T (m' .* (C h C^T)) C: FP64 / FP32 against the oracle, the BF16
