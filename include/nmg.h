@@ -213,6 +213,26 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
 nmg_status nmg_apply_fprime(nmg_handle h, int level, int batch, const void* in, void* out,
                             nmg_precision precision, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as nmg_apply_fprime with NMG_MIXED on a 2D handle (BF16 MFMA, FP32
+ * accumulation, bit-identical results), with its two BF16 intermediate
+ * planes in a fixed 16 MiB device array that the library holds on each GPU
+ * it runs on until the process ends, instead of handle buffers.  The call
+ * allocates nothing: the BF16 DCT tables are built by nmg_setup_hierarchy,
+ * which also resolves the array's address on its device (a first call on
+ * another device resolves it there).  in, out: device float [batch][n][n]
+ * of level `level`, caller-owned, not overlapping; out is overwritten.
+ * Levels above 64^2 need 4 * batch * NP^2 bytes, NP = n rounded up to 128
+ * (batch <= 64 at 255^2, <= 16 at 511^2, <= 4 at 1023^2, <= 1 at 2047^2);
+ * larger requests fail with NMG_ERR_SHAPE and a message naming the limit.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap in
+ * time on one GPU, from any handle or stream, race and must be serialised
+ * by the caller.  NMG_ERR_ARG for a 1D handle, a bad level or NULL
+ * pointers. */
+nmg_status nmg_apply_fprime_noalloc(nmg_handle h, int level, int batch, const float* in, float* out,
+                                    void* stream);
 
 /* ---- the cycle ---------------------------------------------------------- */
 

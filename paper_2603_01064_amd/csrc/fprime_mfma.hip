@@ -20,6 +20,7 @@
 // (and a result does not depend on the batch it is computed in).
 // The input is a zero-padded BF16 NP x NP plane per image: the BF16 smoother
 // writes it directly; FP32 inputs are rounded into it first.
+#include <mutex>
 #include <vector>
 
 #include "nmg_internal.h"
@@ -550,4 +551,65 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, co
     return NMG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// No-allocation F' (nmg_apply_fprime_noalloc): its two BF16 scratch planes
+// live in this file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel: it
+// uses the device address hipGetSymbolAddress returns for each device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+nmg_status fprime_noalloc_init() {
+    int dev = 0;
+    NMG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NMG_ERR_STATE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return NMG_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(NMG_ERR_HIP, std::string("hipGetSymbolAddress of the F' scratch failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+    return NMG_OK;
+}
+
 }  // namespace nmg
+
+using namespace nmg;
+
+extern "C" nmg_status nmg_apply_fprime_noalloc(nmg_handle h, int level, int batch, const float* in, float* out,
+                                               void* stream) {
+    if (!h) return fail(NMG_ERR_ARG, "null handle");
+    if (batch < 1 || batch > h->p.max_batch) return fail(NMG_ERR_SHAPE, "batch must be in [1, max_batch]");
+    if (!in || !out) return fail(NMG_ERR_ARG, "null pointer");
+    if (level < 0 || level >= h->L) return fail(NMG_ERR_ARG, "level out of range");
+    if (h->p.dim != 2) return fail(NMG_ERR_ARG, "the no-allocation F' is the 2D BF16 filter");
+    const int n = h->n[(size_t)level];
+    const size_t need = fprime_mfma_scratch_bytes(n, batch);
+    if (need > kNoAllocScratchBytes)
+        return fail(NMG_ERR_SHAPE, "no-allocation F' needs " + std::to_string(need) + " bytes of scratch for " +
+                                       std::to_string(batch) + " images of side " + std::to_string(n) +
+                                       "; the limit is " + std::to_string(kNoAllocScratchBytes) +
+                                       " (4 * batch * NP^2 bytes, NP = side rounded up to 128)");
+    // first call on a device that no handle was set up on
+    NMG_TRY(fprime_noalloc_init());
+    int dev = 0;
+    NMG_HIP(hipGetDevice(&dev));
+    char* base;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = static_cast<char*>(g_scratch_ptr[dev]);
+    }
+    const size_t half = kNoAllocScratchBytes / 2;
+    return launch_fprime_mfma(h, level, batch, in, nullptr, out, 0, base, base + half, half, (hipStream_t)stream);
+}
+

@@ -361,6 +361,9 @@ size_t fprime_mfma_scratch_bytes(int n, int batch);
 // whether the BF16 F' input plane of a level of side n uses the fragment-tiled
 // layout (sides 65..511) rather than row-major
 bool fprime_tiled_layout(int n);
+// resolves the device address of the no-allocation F' scratch on the current
+// device (once per device)
+nmg_status fprime_noalloc_init();
 nmg_status launch_export_maps(const Ctx* c, int l, int kind, int32_t* idx, float* w, hipStream_t s);
 nmg_status launch_coarse_factor(Ctx* c, int count, const double* alphas, const int* slots, hipStream_t s);
 bool coarse_eigenbasis(const Band& M, const Band& G, std::vector<double>& V, std::vector<double>& lam,

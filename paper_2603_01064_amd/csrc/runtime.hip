@@ -992,8 +992,10 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->bs32, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->loss_dev, (size_t)nsm));
     if (p->dim == 2) {
-        // the BF16 filter's tables
+        // the BF16 filter's tables, and the device address of the scratch
+        // of nmg_apply_fprime_noalloc on this device
         NMG_TRY(prepare_fprime_bf16(c.get()));
+        NMG_TRY(fprime_noalloc_init());
     }
     NMG_HIP(hipDeviceSynchronize());
     *out = c.release();

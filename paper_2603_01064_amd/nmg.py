@@ -110,6 +110,7 @@ def load_library():
         "nmg_debug_transfer_map": (S, [P, I, I, P, P]),
         "nmg_debug_factor": (S, [P, I, I, P, P]),
         "nmg_debug_option": (S, [P, I, I]),
+        "nmg_apply_fprime_noalloc": (S, [P, I, I, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name, None)
@@ -290,6 +291,16 @@ class Handle:
         _require(h, dt, self.level_shape(level, B), "h")
         out = torch.empty_like(h)
         _check(_lib.nmg_apply_fprime(self.ptr, level, B, _ptr(h), _ptr(out), PRECISION[precision], _stream()))
+        return out
+
+    def apply_fprime_noalloc(self, level: int, h, out):
+        """``nmg_apply_fprime_noalloc``: the BF16 ``F'_l(h)`` into the caller's
+        ``out`` with the library's fixed device scratch (no allocation)."""
+        import torch
+        B = h.shape[0]
+        _require(h, torch.float32, self.level_shape(level, B), "h")
+        _require(out, torch.float32, self.level_shape(level, B), "out")
+        _check(_lib.nmg_apply_fprime_noalloc(self.ptr, level, B, _ptr(h), _ptr(out), _stream()))
         return out
 
     def vcycle(self, y, x, alpha, weight_set=None, nu1: int = 1, nu2: int = 1, use_fprime: bool = False,
