@@ -22,7 +22,7 @@ FLAGS = [
     "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 SOURCES = ["hierarchy.cpp", "stencil.hip", "smoother.hip", "coarse.hip", "fprime.hip", "fprime_mfma.hip",
-           "refine.hip", "mfma_smoother.hip", "train.hip", "runtime.hip", "pool.cpp", "fno.hip"]
+           "refine.hip", "mfma_smoother.hip", "train.hip", "train_mfma.hip", "runtime.hip", "pool.cpp", "fno.hip"]
 
 
 def _compile(src: str) -> str:

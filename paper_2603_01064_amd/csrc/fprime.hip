@@ -41,6 +41,98 @@ __global__ void __launch_bounds__(kBlock) k_dense_axis(const T* __restrict__ in,
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// The same axis transforms of n x n images as LDS-tiled batched products
+// OUT_b = A_b B_b (r, c < n): element (r, k) of A at A[r sar + k sak] and
+// element (k, c) of B at B[k sbk + c sbc], with per-image strides (0 for the
+// shared transform matrix).  A workgroup computes a 64 x 64 output tile, each
+// thread 4 x 4 of it, over K chunks of 16 staged in LDS.  apply_mask scales
+// output (r, c) by the ramp sqrt(max(r, c) / n).
+constexpr int kGT = 64, kGK = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axis_gemm(const T* __restrict__ A, const T* __restrict__ B,
+                                                      T* __restrict__ out, int n, size_t a_img, size_t b_img,
+                                                      int sar, int sak, int sbk, int sbc, int tiles, int apply_mask) {
+    __shared__ T As[kGK][kGT + 1];
+    __shared__ T Bs[kGK][kGT + 1];
+    const int img = blockIdx.y;
+    const int r0 = (blockIdx.x / tiles) * kGT, c0 = (blockIdx.x % tiles) * kGT;
+    const T* Ab = A + (size_t)img * a_img;
+    const T* Bb = B + (size_t)img * b_img;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int k0 = 0; k0 < n; k0 += kGK) {
+        // 64 x 16 of A and 16 x 64 of B: four elements of each per thread
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            {
+                const int r = e / kGK, k = e % kGK;
+                const int gr = r0 + r, gk = k0 + k;
+                As[k][r] = (gr < n && gk < n) ? Ab[(size_t)gr * sar + (size_t)gk * sak] : (T)0;
+            }
+            {
+                const int k = e / kGT, c = e % kGT;
+                const int gk = k0 + k, gc = c0 + c;
+                Bs[k][c] = (gk < n && gc < n) ? Bb[(size_t)gk * sbk + (size_t)gc * sbc] : (T)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGK; ++k) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    T* o = out + (size_t)img * n * n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + ty * 4 + i;
+        if (r >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tx * 4 + j;
+            if (c >= n) continue;
+            T v = acc[i][j];
+            if (apply_mask) v *= (T)sqrt((double)(r > c ? r : c) / (double)n);
+            o[(size_t)r * n + c] = v;
+        }
+    }
+}
+
+// One axis pass of a 2D transform through k_axis_gemm:
+//   row axis: out[b][i][k] = sum_j Op(k, j) in[b][i][j]
+//   col axis: out[b][k][j] = sum_i Op(k, i) in[b][i][j]
+// Op(k, j) = C[k][j] (forward) or C[j][k] (inverse).
+template <typename T>
+void axis_pass(const T* in, T* out, const T* C, int n, int batch, int col_axis, int inverse, int apply_mask,
+               hipStream_t s) {
+    const int tiles = (n + kGT - 1) / kGT;
+    const size_t img = (size_t)n * n;
+    dim3 grid((unsigned)(tiles * tiles), (unsigned)batch);
+    if (!col_axis) {
+        // OUT = IN M with M[j][k] = Op(k, j)
+        hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(kBlock), 0, s, in, C, out, n, img, (size_t)0, n, 1,
+                           inverse ? n : 1, inverse ? 1 : n, tiles, apply_mask);
+    } else {
+        // OUT = Mc IN with Mc[k][i] = Op(k, i)
+        hipLaunchKernelGGL(k_axis_gemm<T>, grid, dim3(kBlock), 0, s, C, in, out, n, (size_t)0, img,
+                           inverse ? 1 : n, inverse ? n : 1, n, 1, tiles, apply_mask);
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -57,10 +149,10 @@ nmg_status launch_fprime(const Ctx* c, int l, int batch, const T* h, T* dst, int
         hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, h, t1, C, n, ny, 0, 0, 1);
         hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, t1, t2, C, n, ny, 0, 1, 0);
     } else {
-        hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, h, t1, C, n, ny, 0, 0, 0);
-        hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, t1, t2, C, n, ny, 1, 0, 1);
-        hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, t2, t1, C, n, ny, 0, 1, 0);
-        hipLaunchKernelGGL(k_dense_axis<T>, grid, dim3(kBlock), 0, s, t1, t2, C, n, ny, 1, 1, 0);
+        axis_pass<T>(h, t1, C, n, batch, 0, 0, 0, s);
+        axis_pass<T>(t1, t2, C, n, batch, 1, 0, 1, s);
+        axis_pass<T>(t2, t1, C, n, batch, 0, 1, 0, s);
+        axis_pass<T>(t1, t2, C, n, batch, 1, 1, 0, s);
     }
     NMG_HIP(hipGetLastError());
     return launch_axpy<T>(batch, per, t2, dst, accumulate, s);
@@ -70,8 +162,11 @@ template <typename T>
 nmg_status launch_dense_axis(const T* in, T* out, const T* C, int n, int ny, int batch, int col_axis, int inverse,
                              hipStream_t s) {
     const size_t per = (size_t)ny * n;
-    hipLaunchKernelGGL(k_dense_axis<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, in, out, C, n, ny, col_axis,
-                       inverse, 0);
+    if (ny == n)
+        axis_pass<T>(in, out, C, n, batch, col_axis, inverse, 0, s);
+    else
+        hipLaunchKernelGGL(k_dense_axis<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, in, out, C, n, ny,
+                           col_axis, inverse, 0);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

@@ -346,46 +346,62 @@ __global__ void __launch_bounds__(kThreads) k_bf16_pad(const float* __restrict__
 }
 
 // The same four products for a level with NP = n rounded up to 32 <= 64:
-// one workgroup per image keeps the whole (BF16) intermediate in LDS, so the
-// filter is one launch.  Every pass computes out[j][i] = sum_k Mat[j][k]
-// in[i][k] tile by tile with the K steps of the four-launch kernel in the
-// same order, and rounds its result to BF16 exactly where that kernel
-// stages its operand, so both give the same values.
+// one workgroup per image keeps the whole (BF16) intermediate, the image and
+// both DCT matrices in LDS, so the filter is one launch that reads global
+// memory once.  Every pass computes out[j][i] = sum_k Mat[j][k] in[i][k]
+// tile by tile with the K steps of the larger kernels in the same order, and
+// rounds its result to BF16 exactly where they stage their operands, so all
+// forms give the same values.  LDS rows keep their 16-byte chunk c at
+// c ^ (row & SW), which spreads the 16 rows of a fragment read over the banks.
+constexpr int kSmallThreads = 512;
+
 template <int NP>
-__global__ void __launch_bounds__(kThreads) k_fprime_small(const float* __restrict__ in, float* __restrict__ dst,
-                                                           const uint16_t* __restrict__ C,
-                                                           const uint16_t* __restrict__ Ct,
-                                                           const float* __restrict__ ramp, int n, int mstride,
-                                                           int accumulate) {
+__global__ void __launch_bounds__(kSmallThreads) k_fprime_small(const float* __restrict__ in, float* __restrict__ dst,
+                                                                const uint16_t* __restrict__ C,
+                                                                const uint16_t* __restrict__ Ct,
+                                                                const float* __restrict__ ramp, int n, int mstride,
+                                                                int accumulate) {
     constexpr int NT = NP / 16;             // 16 x 16 output tiles per side
     constexpr int KS = NP / 32;             // K steps
     constexpr int RB = NP * 2;              // bytes per BF16 row
+    constexpr int CPR = NP / 8;             // 16-byte chunks per row
+    constexpr int SW = CPR < 8 ? CPR - 1 : 7;
+    constexpr int WAVES = kSmallThreads / 64;
     __shared__ __attribute__((aligned(16))) char buf[2][NP * RB];
+    __shared__ __attribute__((aligned(16))) char mats[2][NP * RB];
+    __shared__ float rp[NP];
     const int b = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ln = lane & 15, lg = lane >> 4;
     const float* src = in + (size_t)b * n * n;
-    // stage H (rows i, columns k) as BF16, zero beyond n
-    for (int e = tid; e < NP * NP / 2; e += kThreads) {
+    auto off = [](int r, int ch) { return r * RB + ((ch ^ (r & SW)) << 4); };
+    // C and C^T (rows of the padded tables), the ramp, and H as BF16 (zero beyond n)
+    for (int e = tid; e < 2 * NP * CPR; e += kSmallThreads) {
+        const int m = e / (NP * CPR), r = (e / CPR) % NP, ch = e % CPR;
+        const uint16_t* M = m == 0 ? C : Ct;
+        *reinterpret_cast<uint4*>(mats[m] + off(r, ch)) = *reinterpret_cast<const uint4*>(M + (size_t)r * mstride + ch * 8);
+    }
+    if (tid < NP) rp[tid] = tid < n ? ramp[tid] : 0.f;
+    for (int e = tid; e < NP * NP / 2; e += kSmallThreads) {
         const int i = e / (NP / 2), k = (e % (NP / 2)) * 2;
         const float v0 = (i < n && k < n) ? src[(size_t)i * n + k] : 0.f;
         const float v1 = (i < n && k + 1 < n) ? src[(size_t)i * n + k + 1] : 0.f;
-        *reinterpret_cast<uint32_t*>(buf[0] + i * RB + k * 2) = pack_bf16(v0, v1);
+        *reinterpret_cast<uint32_t*>(buf[0] + off(i, k >> 3) + (k & 7) * 2) = pack_bf16(v0, v1);
     }
     __syncthreads();
 #pragma unroll 1
     for (int pass = 0; pass < 4; ++pass) {
-        const uint16_t* M = pass < 2 ? C : Ct;
+        const char* M = mats[pass < 2 ? 0 : 1];
         const char* cur = buf[pass & 1];
         char* nxt = buf[(pass + 1) & 1];
-        for (int t = wave; t < NT * NT; t += 4) {
+        for (int t = wave; t < NT * NT; t += WAVES) {
             const int tj = t / NT, ti = t % NT;  // output rows j (M), columns i (N)
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const int k0 = ks * 32 + lg * 8;
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(M + (size_t)(tj * 16 + ln) * mstride + k0);
-                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(cur + (ti * 16 + ln) * RB + k0 * 2);
+                const int ch = ks * 4 + lg;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(M + off(tj * 16 + ln, ch));
+                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(cur + off(ti * 16 + ln, ch));
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
             }
             const int i = ti * 16 + ln;
@@ -393,14 +409,10 @@ __global__ void __launch_bounds__(kThreads) k_fprime_small(const float* __restri
             for (int q = 0; q < 4; ++q) {
                 const int j = tj * 16 + lg * 4 + q;
                 float v = acc[q];
-                if (pass == 1) v = (i < n && j < n) ? v * ramp[i > j ? i : j] : 0.f;
+                if (pass == 1) v = (i < n && j < n) ? v * rp[i > j ? i : j] : 0.f;
                 if (pass < 3) {
                     // next pass reads row j, column i
-                    const float2v f = {v, 0.f};
-                    const bf16x2 p = __builtin_convertvector(f, bf16x2);
-                    uint16_t u;
-                    __builtin_memcpy(&u, &p, 2);
-                    *reinterpret_cast<uint16_t*>(nxt + j * RB + i * 2) = u;
+                    *reinterpret_cast<uint16_t*>(nxt + off(j, i >> 3) + (i & 7) * 2) = (uint16_t)pack_bf16(v, 0.f);
                 } else if (i < n && j < n) {
                     float* o = dst + (size_t)b * n * n + (size_t)j * n + i;
                     *o = accumulate ? *o + v : v;
@@ -512,11 +524,11 @@ nmg_status launch_fprime_mfma(const Ctx* c, int l, int batch, const float* h, co
     if (n <= 64) {
         if (!h) return fail(NMG_ERR_ARG, "F' on levels up to 64^2 takes the FP32 level array");
         if (n <= 32)
-            hipLaunchKernelGGL(k_fprime_small<32>, dim3(batch), dim3(kThreads), 0, s, h, dst, C, Ct, rp, n, npad,
+            hipLaunchKernelGGL(k_fprime_small<32>, dim3(batch), dim3(kSmallThreads), 0, s, h, dst, C, Ct, rp, n, npad,
                                accumulate);
         else
-            hipLaunchKernelGGL(k_fprime_small<64>, dim3(batch), dim3(kThreads), 0, s, h, dst, C, Ct, rp, n, npad,
-                               accumulate);
+            hipLaunchKernelGGL(k_fprime_small<64>, dim3(batch), dim3(kSmallThreads), 0, s, h, dst, C, Ct, rp, n,
+                               npad, accumulate);
         NMG_HIP(hipGetLastError());
         return NMG_OK;
     }

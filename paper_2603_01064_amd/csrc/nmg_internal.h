@@ -345,6 +345,34 @@ nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, c
 nmg_status launch_mfma_smoother(const Ctx* c, int l, int batch, const int* ws, const float* b,
                                 const double* nrm2, int nparts, float* dst, int accumulate, Work<float>& w,
                                 hipStream_t s, uint16_t* dstb = nullptr, int bpitch = 0, bool btiled = false);
+// Fused FP64 refinement residual on level 0 (x += ||r|| d for active slots,
+// r = y - A x, ||r||^2 into nrm2); false when it does not apply (nothing launched)
+bool refine_residual_fusable(const Ctx* c, const Work<double>& w);
+template <typename D>
+bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double* x, const D* d,
+                            const double* rn2, const int* active, const double* y, double* out, double* nrm2,
+                            Work<double>& w, hipStream_t s);
+// Mixed-precision backward of the CNN smoother on MFMA (train_mfma.hip):
+// buffers and weights of one level and weight set.
+struct MfmaBackwardArgs {
+    int n = 0, batch = 0, accumulate = 0;
+    const float* b = nullptr;        // smoother input of the level [B][n][n]
+    const double* nrm2 = nullptr;    // ||b||^2 per right-hand side
+    const float* W = nullptr;        // FP32 master weights of the level and set (layer_off order)
+    float* grad = nullptr;           // weight gradient, same order (stored or added)
+    const float* dout = nullptr;     // delta at the network output [B][n][n]
+    float* din0 = nullptr;           // optional: gradient at the network input u = b / ||b||
+    std::vector<uint16_t*> acts;     // n_layers - 1 activation record buffers [B][n*n][32] BF16
+    uint16_t *d0 = nullptr, *d1 = nullptr;  // delta record buffers, same shape
+    uint16_t* wpk = nullptr;         // packed hidden-layer weights (mfma_backward_wpk_elems)
+    float* part = nullptr;           // weight-gradient partials
+    size_t part_count = 0;
+    double* reduce_tmp = nullptr;    // mfma_backward_reduce_elems doubles
+};
+size_t mfma_backward_reduce_elems();
+bool mfma_backward_supported(const Ctx* c);
+size_t mfma_backward_wpk_elems(const Ctx* c);
+nmg_status smoother_backward_mfma(const Ctx* c, const MfmaBackwardArgs& a, hipStream_t s);
 // whether the smoother's tiles of level l cover a padded pitch x pitch plane
 bool mfma_smoother_covers(const Ctx* c, int l, int pitch);
 template <typename T>

@@ -836,11 +836,26 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             Work<double>& w = h->w64;
             NMG_TRY(launch_refine_scale<double, double>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
             NMG_TRY(run_cycle<double>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            // the update inside the residual's row pass, the norm inside its column pass
+            if (refine_residual_fusable(h, h->w64)) {
+                ProfScope ps(h, st, NMG_K_REFINE, 0);
+                (void)launch_refine_residual<double>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
+                                                  h->nrm2, h->w64, st);
+                NMG_HIP(hipGetLastError());
+                return NMG_OK;
+            }
             NMG_TRY(launch_refine_update<double, double>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
         } else {
             Work<float>& w = h->w32b;
             NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
             NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            if (refine_residual_fusable(h, h->w64)) {
+                ProfScope ps(h, st, NMG_K_REFINE, 0);
+                (void)launch_refine_residual<float>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
+                                                  h->nrm2, h->w64, st);
+                NMG_HIP(hipGetLastError());
+                return NMG_OK;
+            }
             NMG_TRY(launch_refine_update<double, float>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
         }
         return residual(kk, st);

@@ -108,11 +108,12 @@ __global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, 
     if (threadIdx.x == 0) part[(size_t)b * kNormChunks + ch] = red[0];
 }
 
-__global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch) {
+// nparts partials per right-hand side (row stride kNormChunks), added in order
+__global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch, int nparts) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     double acc = 0.0;
-    for (int c = 0; c < kNormChunks; ++c) acc += part[(size_t)b * kNormChunks + c];
+    for (int c = 0; c < nparts; ++c) acc += part[(size_t)b * kNormChunks + c];
     out[b] = acc;
 }
 
@@ -699,11 +700,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerBlock = 4;
 
-template <typename T, int TP>
-__global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, T* __restrict__ tg,
+// With dcorr: the refinement update x += ||r|| d of right-hand sides marked
+// active is applied to x (in place) as the rows are staged.  Every image
+// element is staged by exactly one workgroup (rows are split between them and
+// a row pass needs no neighbouring rows), so each is updated once, and the
+// column pass that follows reads the updated x.
+template <typename T, int TP, typename D = T>
+__global__ void __launch_bounds__(kBlock) k_rows_fixed(T* x, T* __restrict__ tg,
                                                        T* __restrict__ tm, const T* __restrict__ taps, int rg,
                                                        const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
-                                                       const T* __restrict__ mt, int m_ident, int n) {
+                                                       const T* __restrict__ mt, int m_ident, int n,
+                                                       const D* __restrict__ dcorr = nullptr,
+                                                       const double* __restrict__ rn2 = nullptr,
+                                                       const int* __restrict__ active = nullptr) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* rows = reinterpret_cast<T*>(smem_raw);
     const int LW = (n + TP + 4 + 3) & ~3;  // staged column c <-> image column c - rg
@@ -715,12 +724,15 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, 
     }
     const int b = blockIdx.y, r0 = blockIdx.x * kRowsPerBlock;
     const size_t per = (size_t)n * n;
-    const T* xs = x + (size_t)b * per;
+    T* xs = x + (size_t)b * per;
+    const bool upd = dcorr && active[b];
+    const T rho = upd ? (T)sqrt(rn2[b]) : (T)0;
     // staging: wave w loads row r0 + w, lane-contiguous, eight loads per lane in flight
     {
         const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
         const int gi = r0 + r;
-        const T* src = xs + (size_t)(gi < n ? gi : 0) * n;
+        const size_t roff = (size_t)(gi < n ? gi : 0) * n;
+        T* src = xs + roff;
         static_assert(kRowsPerBlock * 64 == kBlock, "one wave per staged row");
         for (int q0 = 0; q0 * 64 < LW; q0 += 8) {
             T v[8];
@@ -728,6 +740,16 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, 
             for (int u = 0; u < 8; ++u) {
                 const int c = lane + 64 * (q0 + u), gj = c - rg;
                 v[u] = (c < LW && gi < n && gj >= 0 && gj < n) ? src[gj] : (T)0;
+            }
+            if (upd) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = lane + 64 * (q0 + u), gj = c - rg;
+                    if (c < LW && gi < n && gj >= 0 && gj < n) {
+                        v[u] += rho * (T)dcorr[(size_t)b * per + roff + gj];
+                        src[gj] = v[u];
+                    }
+                }
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -770,13 +792,18 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(const T* __restrict__ x, 
     }
 }
 
+// With part: this tile's sum of squares of its outputs (FP64, fixed order:
+// each thread's rows in order, then a fixed tree over the threads) goes to
+// part[b * kNormChunks + tile], the first stage of ||out||^2 with a partial
+// layout that depends only on the level size.
 template <typename T, int TP>
 __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg, const T* __restrict__ tm,
                                                        const T* __restrict__ x, const T* __restrict__ y,
                                                        T* __restrict__ out, const double* __restrict__ alpha, int n,
                                                        int mode, const T* __restrict__ taps, int rg,
                                                        const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
-                                                       const T* __restrict__ mt, int m_ident, int tiles_x) {
+                                                       const T* __restrict__ mt, int m_ident, int tiles_x,
+                                                       double* __restrict__ part = nullptr) {
     constexpr int TH = 64, TW = 64, OC = 16;  // 4 x 64 threads, 16 rows each
     constexpr int XH = TH + TP;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
@@ -818,15 +845,17 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     __syncthreads();
     const int jj = tid % TW, ii = (tid / TW) * OC;
     const int j = j0 + jj;
-    if (j >= n) return;
+    // (threads of columns beyond n compute on zeros and store nothing: every
+    // thread reaches the partial-sum barrier below)
+    const bool colok = j < n;
     // the right-hand side (and x for M = I) of this thread's outputs, loaded before the pass
     T yv[OC], xv[OC];
 #pragma unroll
     for (int o = 0; o < OC; ++o) {
         const int i = i0 + ii + o;
         const size_t idx = (size_t)b * per + (size_t)i * n + j;
-        yv[o] = (mode == 0 && i < n) ? y[idx] : (T)0;
-        xv[o] = (m_ident && i < n) ? x[idx] : (T)0;
+        yv[o] = (mode == 0 && colok && i < n) ? y[idx] : (T)0;
+        xv[o] = (m_ident && colok && i < n) ? x[idx] : (T)0;
     }
     T g[OC];
 #pragma unroll
@@ -851,10 +880,11 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
         }
     }
     const T a = (T)alpha[b];
+    double sq = 0.0;
 #pragma unroll
     for (int o = 0; o < OC; ++o) {
         const int i = i0 + ii + o;
-        if (i >= n) break;
+        if (i >= n || !colok) break;
         // corner rows occur only in the first and last tile rows, for a quarter of
         // the threads; computed in place they cost no registers elsewhere
         T corr = 0;
@@ -873,7 +903,20 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
             mv = mt[0] * c[0] + mt[1] * c[TW] + mt[2] * c[2 * TW];
         }
         const T ax = a * mv + (g[o] + corr);
-        out[idx] = mode == 0 ? yv[o] - ax : ax;
+        const T r = mode == 0 ? yv[o] - ax : ax;
+        out[idx] = r;
+        sq += (double)r * (double)r;
+    }
+    if (part) {
+        __syncthreads();  // every thread is done with the staged tile
+        double* red = reinterpret_cast<double*>(smem_raw);
+        red[tid] = sq;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) part[(size_t)b * kNormChunks + blockIdx.x] = red[0];
     }
 }
 
@@ -904,16 +947,17 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             T* tg = w.lv[l].t1;
             T* tm = w.lv[l].t2;
             const int LW = (n + TP + 4 + 3) & ~3;
+            // (no update: x is only read)
             hipLaunchKernelGGL((k_rows_fixed<T, TP>), dim3((n + kRowsPerBlock - 1) / kRowsPerBlock, batch),
                                dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(T), s,
-                               x, tg, tm, op.tg, op.rg,
-                               op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n);
+                               const_cast<T*>(x), tg, tm, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n,
+                               (const T*)nullptr, (const double*)nullptr, (const int*)nullptr);
             const int tiles_x = (n + 63) / 64, tiles_y = (n + 63) / 64;
             const size_t lds = ((size_t)(64 + TP) * 64 + (op.m_ident ? 0 : (size_t)68 * 64) +
                                 2 * (size_t)op.rc * op.rc) * sizeof(T);
             hipLaunchKernelGGL((k_cols_fixed<T, TP>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, tg, tm,
                                x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident,
-                               tiles_x);
+                               tiles_x, (double*)nullptr);
         };
         go2(std::integral_constant<int, 8>{});
         go2(std::integral_constant<int, 12>{});
@@ -1003,6 +1047,66 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
     return NMG_OK;
 }
 
+// The FP64 refinement residual of one outer iteration, fused: x += ||r|| d
+// for active right-hand sides inside the row pass, r = y - A x with the first
+// stage of ||r||^2 in the column pass, then the per-image sums.  Returns
+// false (and launches nothing) where the two-launch tile form does not apply
+// or the partials would not fit; the caller then runs the separate kernels.
+bool refine_residual_fusable(const Ctx* c, const Work<double>& w) {
+    const int n = c->n[0];
+    const TiledOp<double>& op = w.tiled[0];
+    const int tiles_x = (n + 63) / 64;
+    static const int kTaps[] = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 84, 164};
+    bool tp_ok = false;
+    for (int t : kTaps) tp_ok = tp_ok || op.rgp == t;
+    return c->p.dim == 2 && op.ok && op.m_ident && tp_ok && tiles_x * tiles_x <= kNormChunks;
+}
+
+template <typename D>
+bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double* x, const D* d,
+                            const double* rn2, const int* active, const double* y, double* out, double* nrm2,
+                            Work<double>& w, hipStream_t s) {
+    const int l = 0, n = c->n[l];
+    const TiledOp<double>& op = w.tiled[(size_t)l];
+    const int tiles_x = (n + 63) / 64, tiles = tiles_x * tiles_x;
+    if (!refine_residual_fusable(c, w)) return false;
+    bool launched = false;
+    auto go = [&](auto tp_tag) {
+        constexpr int TP = decltype(tp_tag)::value;
+        if (launched || op.rgp != TP) return;
+        launched = true;
+        double* tg = w.lv[l].t1;
+        const int LW = (n + TP + 4 + 3) & ~3;
+        hipLaunchKernelGGL((k_rows_fixed<double, TP, D>), dim3((n + kRowsPerBlock - 1) / kRowsPerBlock, batch),
+                           dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(double), s,
+                           x, tg, (double*)nullptr, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n, d, rn2,
+                           active);
+        const size_t lds = ((size_t)(64 + TP) * 64 + 2 * (size_t)op.rc * op.rc) * sizeof(double);
+        hipLaunchKernelGGL((k_cols_fixed<double, TP>), dim3(tiles, batch), dim3(kBlock), lds, s, tg,
+                           (const double*)nullptr, x, y, out, alpha, n, 0, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
+                           op.m_ident, tiles_x, c->norm_part);
+        hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, c->norm_part, nrm2, batch, tiles);
+    };
+    go(std::integral_constant<int, 8>{});
+    go(std::integral_constant<int, 12>{});
+    go(std::integral_constant<int, 16>{});
+    go(std::integral_constant<int, 20>{});
+    go(std::integral_constant<int, 24>{});
+    go(std::integral_constant<int, 28>{});
+    go(std::integral_constant<int, 32>{});
+    go(std::integral_constant<int, 36>{});
+    go(std::integral_constant<int, 40>{});
+    go(std::integral_constant<int, 44>{});
+    go(std::integral_constant<int, 48>{});
+    go(std::integral_constant<int, 84>{});
+    go(std::integral_constant<int, 164>{});
+    return launched;
+}
+template bool launch_refine_residual<float>(const Ctx*, int, const double*, double*, const float*, const double*,
+                                            const int*, const double*, double*, double*, Work<double>&, hipStream_t);
+template bool launch_refine_residual<double>(const Ctx*, int, const double*, double*, const double*, const double*,
+                                             const int*, const double*, double*, double*, Work<double>&, hipStream_t);
+
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s) {
     hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, c->norm_part, elems);
@@ -1014,7 +1118,7 @@ template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s) {
     double* part = c->norm_part;
     hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, part, elems);
-    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch);
+    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch, kNormChunks);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }

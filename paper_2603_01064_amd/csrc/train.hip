@@ -16,6 +16,7 @@
 // then the standard convolution / ReLU backward with the activations of the
 // level recomputed from b_l / ||b_l||.  Weight gradients are reduced over
 // pixels and right-hand sides with fixed-order two-stage sums.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -330,6 +331,9 @@ struct TrainWork {
     size_t part_count = 0;
     double* lossb = nullptr;    // [B]
     double* dots = nullptr;     // [2B] per-RHS dot products of the cycle-loss adjoint
+    T* mf_dout = nullptr;       // MFMA backward: delta at the network output [B][per0]
+    uint16_t* mf_wpk = nullptr; // MFMA backward: packed hidden-layer weights
+    double* mf_red = nullptr;   // MFMA backward: first stage of the weight-gradient sums
 };
 
 template <typename T>
@@ -387,6 +391,9 @@ static void free_train_work(TrainWork<T>& w) {
     f(w.part);
     f(w.lossb);
     f(w.dots);
+    f(w.mf_dout);
+    f(w.mf_wpk);
+    f(w.mf_red);
     w.ready = false;
 }
 
@@ -445,9 +452,18 @@ static nmg_status ensure_train(const Ctx* c, TrainWork<T>& w) {
         maxlayer = std::max(maxlayer, (size_t)c->p.channels[i] * c->p.channels[i + 1] * kk);
     }
     w.part_count = chunks * maxlayer;
+    // the MFMA backward's 32 -> 32 weight gradient keeps up to four partials
+    // of maxlayer values per image
+    if (std::is_same<T, float>::value && mfma_backward_supported(c))
+        w.part_count = std::max(w.part_count, (size_t)B * 4 * maxlayer);
     NMG_TRY(talloc(&w.part, w.part_count));
     NMG_TRY(talloc(&w.lossb, (size_t)B));
     NMG_TRY(talloc(&w.dots, (size_t)2 * B));
+    if (std::is_same<T, float>::value && mfma_backward_supported(c)) {
+        NMG_TRY(talloc(&w.mf_dout, fine));
+        NMG_TRY(talloc(&w.mf_wpk, mfma_backward_wpk_elems(c)));
+        NMG_TRY(talloc(&w.mf_red, mfma_backward_reduce_elems()));
+    }
     w.ready = true;
     return NMG_OK;
 }
@@ -507,6 +523,31 @@ static nmg_status smoother_backward(Ctx* c, Work<T>& work, TrainWork<T>& tw, int
     const T* Wbase = work.wts + ((size_t)l * c->p.n_weight_sets + set) * c->wcount;
     T* gbase = grad_ptr<T>(c, l, set);
     const double* nrm2 = tw.nrm[(size_t)l];
+    if constexpr (std::is_same<T, float>::value) {
+        if (bf && tw.mf_dout && mfma_backward_supported(c)) {
+            // BF16 activations and deltas on MFMA
+            hipLaunchKernelGGL(k_scale_by_norm<T>, dim3(blocks_for(per), batch), dim3(kBlock), 0, s, upstream,
+                               tw.mf_dout, nrm2, sign, per);
+            MfmaBackwardArgs a;
+            a.n = n;
+            a.batch = batch;
+            a.accumulate = accumulate;
+            a.b = tw.b[(size_t)l];
+            a.nrm2 = nrm2;
+            a.W = Wbase;
+            a.grad = gbase;
+            a.dout = tw.mf_dout;
+            a.din0 = din0;
+            for (auto* p : tw.acts) a.acts.push_back(reinterpret_cast<uint16_t*>(p));
+            a.d0 = reinterpret_cast<uint16_t*>(tw.d0);
+            a.d1 = reinterpret_cast<uint16_t*>(tw.d1);
+            a.wpk = tw.mf_wpk;
+            a.part = tw.part;
+            a.part_count = tw.part_count;
+            a.reduce_tmp = tw.mf_red;
+            return smoother_backward_mfma(c, a, s);
+        }
+    }
     // recompute activations a_1 .. a_{NL-1}
     const T* src = tw.b[(size_t)l];
     for (int i = 0; i + 1 < NL; ++i) {

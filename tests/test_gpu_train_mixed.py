@@ -37,13 +37,18 @@ def _flat(ws):
     return torch.cat([w.reshape(-1) for w in ws])
 
 
-@pytest.mark.parametrize("n,L,mask,use_fp", [(31, 4, "ramp", True), (63, 3, "band", False), (63, 4, "ramp", True)])
-def test_mixed_loss_and_gradient(n, L, mask, use_fp):
-    print(f"case mixed training {n}x{n} L={L} mask={mask} fprime={use_fp}", flush=True)
+@pytest.mark.parametrize("n,L,mask,use_fp,ch", [(31, 4, "ramp", True, (1, 32, 32, 1)),
+                                                 (63, 3, "band", False, (1, 32, 32, 1)),
+                                                 (63, 4, "ramp", True, (1, 32, 32, 1)),
+                                                 (31, 3, "ramp", True, (1, 32, 32, 32, 1))])
+def test_mixed_loss_and_gradient(n, L, mask, use_fp, ch):
+    """The backward runs on MFMA with BF16 activations and BF16 deltas, so the
+    gradient carries their rounding on top of the emulation's (a few 1e-3)."""
+    print(f"case mixed training {n}x{n} L={L} mask={mask} fprime={use_fp} layers={len(ch) - 1}", flush=True)
     from paper_2603_01064_amd import nmg
     nmg.load_library()
     dev = torch.device("cuda:0")
-    ch, B, s = (1, 32, 32, 1), 4, 0.04
+    B, s = 4, 0.04
     W = [[torch.tensor(w).float().double() for w in inputs.he_normal_weights(ch, 3, 2, 7600 + 10 * l)]
          for l in range(L - 1)]
     h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=ch, ksize=3))
@@ -70,5 +75,46 @@ def test_mixed_loss_and_gradient(n, L, mask, use_fp):
         print(f"  level {l}: loss vs BF16 emulation {le:.1e}, vs FP64 oracle {lr:.1e}; gradient vs emulation "
               f"{ge:.1e}, vs FP64 oracle {gr:.1e} (emulation vs oracle {ger:.1e})", flush=True)
         assert le < 2e-3 and lr < 5e-2
+        assert ge < 2e-2 and gr < 2e-1
+    h.close()
+
+
+@pytest.mark.parametrize("use_fp", [True, False])
+def test_mixed_cycle_loss_and_gradient(use_fp):
+    """The combined loss eq. loss_1 in mixed precision (every level's network
+    backward on MFMA, including the gradient at its input): the loss and the
+    joint gradient against the same cycle with the BF16-rounding emulation of
+    each smoother (FP64 sums, straight-through roundings), and against the
+    FP64 oracle (stated, loose)."""
+    print(f"case mixed cycle loss 31x31 L=3 fprime={use_fp}", flush=True)
+    from paper_2603_01064_amd import nmg
+    nmg.load_library()
+    dev = torch.device("cuda:0")
+    n, L, ch, B, s = 31, 3, (1, 32, 32, 1), 4, 0.04
+    W = [[torch.tensor(w).float().double() for w in inputs.he_normal_weights(ch, 3, 2, 7700 + 10 * l)]
+         for l in range(L - 1)]
+    h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=ch, ksize=3))
+    for l in range(L - 1):
+        h.load_smoother_weights(l, 0, [w.numpy() for w in W[l]])
+    H = O.build_hierarchy(n, s, L, dim=2)
+    e = torch.tensor(inputs.iid_normal((B, n, n), 3300)).float().double()
+    alpha = torch.tensor([1e-2, 1e-3, 1e-3, 1e-4], dtype=DT)
+    got = h.loss_grad(e.float().to(dev), alpha.to(dev), mask="cycle", use_fprime=use_fp, precision="mixed")
+    gg = [torch.tensor(h.get_gradient(l)) for l in range(L - 1)]
+    ws = [[w.clone().requires_grad_(True) for w in lw] for lw in W]
+    y = O.apply_operator(H, 0, e, alpha)
+    x = O.vcycle(H, [_emulated(lw) for lw in ws], torch.zeros_like(e), y, alpha, 1, 0, use_fp)
+    em_loss = ((e - x) ** 2).sum() / B
+    em_loss.backward()
+    em_g = [_flat([w.grad for w in lw]) for lw in ws]
+    ref_loss, ref_g = O.cycle_loss_grads(H, W, e, alpha, use_fp)
+    le = abs(got[0] - float(em_loss)) / float(em_loss)
+    lr = abs(got[0] - float(ref_loss)) / float(ref_loss)
+    print(f"  loss vs emulation {le:.1e}, vs FP64 oracle {lr:.1e}", flush=True)
+    assert le < 2e-3 and lr < 5e-2
+    for l in range(L - 1):
+        ge = float((gg[l] - em_g[l]).norm() / em_g[l].norm())
+        gr = float((gg[l] - _flat(ref_g[l])).norm() / _flat(ref_g[l]).norm())
+        print(f"  level {l}: gradient vs emulation {ge:.1e}, vs FP64 oracle {gr:.1e}", flush=True)
         assert ge < 2e-2 and gr < 2e-1
     h.close()
