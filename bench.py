@@ -64,6 +64,16 @@ def traffic_per_image():
     return None
 
 
+def smoother_bytes_per_image(use_fprime):
+    """Algorithmic HBM bytes of one level-1 smoother application to one image:
+    the FP32 input plane is read; with F' next, the output is the zero-padded
+    (N + 1)^2 BF16 plane that the F' kernel reads, else the FP32 plane
+    x + S(r), read and written."""
+    if use_fprime:
+        return PLANE_BYTES + 2 * (N + 1) * (N + 1)
+    return 3 * PLANE_BYTES
+
+
 def make_inputs(steps, seed0=20000):
     from paper_2603_01064_amd import inputs
     out = []
@@ -247,7 +257,7 @@ def main(argv=None):
             "kernel": "k_smoother_mfma<3> on level 1 (255x255, BF16 CNN 1-32-32-1)",
             "avg_launch_ms": round(avg_ms, 4), "launches": sm_n, "images_per_launch": round(mean_images, 2),
             "flop_per_launch": round(FLOP_PER_PX * N * N * mean_images),
-            "algorithmic_bytes_per_launch": round((2 if cyc_cfg["use_fprime"] else 3) * PLANE_BYTES * mean_images)}
+            "algorithmic_bytes_per_launch": round(smoother_bytes_per_image(cyc_cfg["use_fprime"]) * mean_images)}
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(1e3 * elapsed / a.steps, 3), "higher_is_better": True,

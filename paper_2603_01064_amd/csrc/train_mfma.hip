@@ -250,12 +250,12 @@ __global__ void __launch_bounds__(kThreads) k_tr_first_din(const uint16_t* __res
     din[(size_t)img * per + q] = acc;
 }
 
-// Weight-gradient partials of a one-channel layer over a contiguous range of
-// the batch's pixels:
+// Weight-gradient partials of a one-channel layer over a run of rows of one
+// image (workgroup g: image g / wpi, rows [(g % wpi) rpw, + rpw)):
 //   FIRST: dW_1[c][t] = sum_p D[p][c] u[p + off(t)],  u = BF16(b / ||b||)
 //   else : dW_l[c][t] = sum_p d_out[p] a[p + off(t)][c]
-// Thread (group g, channel c) sums the nine taps of channel c over pixels
-// p0 + g, p0 + g + 8, ...; the eight groups are then added in order.
+// Thread (group k, channel c) sums the nine taps of channel c over columns
+// k, k + 8, ... of each row; the eight groups are then added in order.
 // part[blockIdx.x][c * 9 + t] (the layer's [Cout][Cin][3][3] order).
 constexpr int kSmallGroups = kThreads / kC;  // 8
 
@@ -263,55 +263,42 @@ template <int FIRST>
 __global__ void __launch_bounds__(kThreads) k_tr_wgrad_small(const float* __restrict__ plane,
                                                              const double* __restrict__ nrm2,
                                                              const uint16_t* __restrict__ rec,
-                                                             float* __restrict__ part, int n, size_t total,
-                                                             size_t chunk) {
+                                                             float* __restrict__ part, int n, int wpi, int rpw) {
     __shared__ float red[kSmallGroups][kC * 9];
-    const int c = threadIdx.x % kC, g = threadIdx.x / kC;
-    const size_t per = (size_t)n * n;
-    const size_t p0 = (size_t)blockIdx.x * chunk, p1 = p0 + chunk < total ? p0 + chunk : total;
+    const int c = threadIdx.x % kC, k = threadIdx.x / kC;
+    const int img = blockIdx.x / wpi;
+    const int y0 = (blockIdx.x % wpi) * rpw, y1 = y0 + rpw < n ? y0 + rpw : n;
+    const size_t base = (size_t)img * n * n;
+    float sc = 0.f;
+    if constexpr (FIRST) {
+        const double nb = sqrt(nrm2[img]);
+        sc = nb > 0.0 ? (float)(1.0 / nb) : 0.f;
+    }
     float acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = 0.f;
-    int cur_img = -1;
-    float sc = 0.f;
-    for (size_t P = p0 + g; P < p1; P += kSmallGroups) {
-        const int img = (int)(P / per);
-        const size_t p = P - (size_t)img * per;
-        const int y = (int)(p / n), x = (int)(p % n);
-        const size_t base = (size_t)img * per;
-        if constexpr (FIRST) {
-            if (img != cur_img) {
-                cur_img = img;
-                const double nb = sqrt(nrm2[img]);
-                sc = nb > 0.0 ? (float)(1.0 / nb) : 0.f;
-            }
-            const float gv = bf2f(rec[P * kC + c]);
+    for (int y = y0; y < y1; ++y) {
+#pragma unroll 2
+        for (int x = k; x < n; x += kSmallGroups) {
+            const size_t p = base + (size_t)y * n + x;
+            const float gv = FIRST ? bf2f(rec[p * kC + c]) : plane[p];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
                 const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-                const float u = (yy >= 0 && yy < n && xx >= 0 && xx < n)
-                                    ? round_bf(plane[base + (size_t)yy * n + xx] * sc)
-                                    : 0.f;
-                acc[t] += gv * u;
-            }
-        } else {
-            const float gv = plane[P];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-                const float av = (yy >= 0 && yy < n && xx >= 0 && xx < n)
-                                     ? bf2f(rec[(base + (size_t)yy * n + xx) * kC + c])
-                                     : 0.f;
-                acc[t] += gv * av;
+                const bool in = yy >= 0 && yy < n && xx >= 0 && xx < n;
+                const size_t q = base + (size_t)yy * n + xx;
+                float v = 0.f;
+                if (in) v = FIRST ? round_bf(plane[q] * sc) : bf2f(rec[q * kC + c]);
+                acc[t] += gv * v;
             }
         }
     }
 #pragma unroll
-    for (int t = 0; t < 9; ++t) red[g][c * 9 + t] = acc[t];
+    for (int t = 0; t < 9; ++t) red[k][c * 9 + t] = acc[t];
     __syncthreads();
     for (int q = threadIdx.x; q < kC * 9; q += kThreads) {
         float s = 0.f;
-        for (int k = 0; k < kSmallGroups; ++k) s += red[k][q];
+        for (int j = 0; j < kSmallGroups; ++j) s += red[j][q];
         part[(size_t)blockIdx.x * (kC * 9) + q] = s;
     }
 }
@@ -463,14 +450,19 @@ nmg_status smoother_backward_mfma(const Ctx* c, const MfmaBackwardArgs& a, hipSt
         hipLaunchKernelGGL(k_tr_reduce2, dim3(gx), dim3(kThreads), 0, s, a.reduce_tmp,
                            a.grad + c->layer_off[(size_t)layer], cnt, groups, a.accumulate);
     };
-    // one-channel layers: chunks of pixels, at most 1024 partials
-    const size_t small_chunks = std::min<size_t>({(size_t)1024, a.part_count / (kC * 9), total});
-    const size_t small_len = (total + small_chunks - 1) / small_chunks;
-    const int small_used = (int)((total + small_len - 1) / small_len);
+    // one-channel layers: runs of rpw rows, at most 4096 partials
+    // (batch * ceil(n / rpw) can exceed batch * n / rpw by up to batch)
+    const size_t cap = a.part_count / (kC * 9);
+    const size_t max_small = std::min<size_t>((size_t)4096, cap > (size_t)2 * batch ? cap - batch : 1);
+    const int rpw = (int)std::max<size_t>(1, ((size_t)batch * n + max_small - 1) / max_small);
+    const int wpi = (n + rpw - 1) / rpw;
+    const int small_used = batch * wpi;
+    if ((size_t)small_used > cap) return fail(NMG_ERR_STATE, "MFMA backward: one-channel partials exceed the scratch");
+    (void)total;
     // last layer: its weight gradient and the delta of a_{NL-1}
     const uint16_t* a_last = a.acts[(size_t)NL - 2];
     hipLaunchKernelGGL((k_tr_wgrad_small<0>), dim3(small_used), dim3(kThreads), 0, s, a.dout, (const double*)nullptr,
-                       a_last, a.part, n, total, small_len);
+                       a_last, a.part, n, wpi, rpw);
     reduce(NL - 1, kC * 9, small_used);
     uint16_t* dcur = a.d0;
     uint16_t* dnext = a.d1;
@@ -495,7 +487,7 @@ nmg_status smoother_backward_mfma(const Ctx* c, const MfmaBackwardArgs& a, hipSt
     }
     // first layer
     hipLaunchKernelGGL((k_tr_wgrad_small<1>), dim3(small_used), dim3(kThreads), 0, s, a.b, a.nrm2,
-                       (const uint16_t*)dcur, a.part, n, total, small_len);
+                       (const uint16_t*)dcur, a.part, n, wpi, rpw);
     reduce(0, kC * 9, small_used);
     if (a.din0)
         hipLaunchKernelGGL(k_tr_first_din, dim3(gpx, batch), dim3(kThreads), 0, s, (const uint16_t*)dcur,
