@@ -451,11 +451,23 @@ typedef enum {
     NMG_K_COARSE = 4, NMG_K_FPRIME = 5, NMG_K_REFINE = 6, NMG_K_NORM = 7
 } nmg_kernel_kind;
 
-/* Turns HIP-event timing on for the kernel families in kind_mask (bit k =
+/* Turns timing on for the kernel families in kind_mask (bit k =
  * nmg_kernel_kind k; 0 turns it off) and clears the accumulated times.
- * Events are recorded on the caller's stream around each timed launch (as
- * event nodes inside captured solve iterations). */
+ * HIP events are recorded on the caller's stream around each timed launch;
+ * inside captured solve iterations, where events cannot be timed, two
+ * one-wave kernels write the device's real-time counter before and after it. */
 nmg_status nmg_profile_enable(nmg_handle h, int kind_mask);
+
+/* Times only every period-th solve iteration of nmg_solve and the serving
+ * engine (default 1: all of them); the others run without timing launches.
+ * The accumulated launch counts then cover the sampled iterations only.
+ * period < 1: NMG_ERR_ARG. */
+nmg_status nmg_profile_sample(nmg_handle h, int period);
+
+/* The number of right-hand sides still iterating, summed over the solve
+ * iterations that were timed since nmg_profile_enable (each such iteration
+ * runs nu1 + nu2 smoothing steps per level on each of them). */
+nmg_status nmg_profile_rhs(nmg_handle h, long long* rhs_iterations);
 
 /* Restricts timing to the levels in level_mask (bit l = level l; default
  * all levels).  Fewer timed launches mean less timing overhead. */

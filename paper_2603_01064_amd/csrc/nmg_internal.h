@@ -241,6 +241,9 @@ struct Ctx {
     // profiler
     int prof_mask = 0;         // bit k: time kernel family k
     int prof_levels = 0xFFFF;  // bit l: time launches on level l
+    int prof_period = 1;       // time every prof_period-th solve iteration
+    long long prof_iter = 0;   // solve iterations seen since profiling was enabled
+    long long prof_rhs = 0;    // active right-hand sides summed over the timed solve iterations
     struct ProfEv { hipEvent_t a, b; int kind, level; };
     std::vector<ProfEv> prof_pending;
     std::vector<hipEvent_t> prof_pool;
@@ -429,7 +432,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
 size_t request_bytes(const Ctx* c, nmg_precision prec);
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
-                               double rtol, int* active, hipStream_t s);
+                               double rtol, int* active, hipStream_t s, double* part = nullptr);
 template <typename X, typename T>
 nmg_status launch_refine_update(int batch, size_t per, X* x, const T* d, const double* rn2, const int* active,
                                 hipStream_t s);

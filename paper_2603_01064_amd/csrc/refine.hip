@@ -11,18 +11,42 @@ namespace nmg {
 namespace {
 constexpr int kBlock = 256;
 
+// One block per (chunk, right-hand side) with the chunks of the norm
+// partials: block ch covers elements [ch len, (ch + 1) len) of the image,
+// len = ceil(per / kNormChunksPerRhs), and with part it also writes the sum
+// of squares of its outputs (each thread's elements in order, then a fixed
+// tree), the first stage of ||y||^2 for the cycle's first BF16 smoothing
+// step, in the same order as a separate partial-sum pass over y.
 template <typename R, typename T>
 __global__ void __launch_bounds__(kBlock) k_refine_scale(const R* __restrict__ r, T* __restrict__ y,
                                                          const double* __restrict__ rn2, const double* __restrict__ bn2,
-                                                         double tol2, int* __restrict__ active, size_t per) {
-    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const int b = blockIdx.y;
+                                                         double tol2, int* __restrict__ active, size_t per,
+                                                         double* __restrict__ part) {
+    __shared__ double red[kBlock];
+    const int b = blockIdx.y, ch = blockIdx.x;
     const double q = rn2[b];
     const bool act = (q > tol2 * bn2[b]) && isfinite(q);
-    if (e == 0) active[b] = act ? 1 : 0;
-    if (e >= per) return;
+    if (ch == 0 && threadIdx.x == 0) active[b] = act ? 1 : 0;
     const double inv = act ? 1.0 / sqrt(q) : 0.0;
-    y[(size_t)b * per + e] = (T)((double)r[(size_t)b * per + e] * inv);
+    const size_t len = (per + kNormChunksPerRhs - 1) / kNormChunksPerRhs;
+    const size_t e0 = (size_t)ch * len, e1 = e0 + len < per ? e0 + len : per;
+    const R* src = r + (size_t)b * per;
+    T* dst = y + (size_t)b * per;
+    double acc = 0.0;
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        const T v = (T)((double)src[e] * inv);
+        dst[e] = v;
+        const double t = (double)v;
+        acc += t * t;
+    }
+    if (!part) return;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)b * kNormChunksPerRhs + ch] = red[0];
 }
 
 template <typename X, typename T>
@@ -113,9 +137,10 @@ template nmg_status launch_scatter_slots<float>(int, size_t, const float*, doubl
 
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
-                               double rtol, int* active, hipStream_t s) {
-    dim3 grid((unsigned)((per + kBlock - 1) / kBlock), batch);
-    hipLaunchKernelGGL((k_refine_scale<R, T>), grid, dim3(kBlock), 0, s, r, y, rn2, bn2, rtol * rtol, active, per);
+                               double rtol, int* active, hipStream_t s, double* part) {
+    dim3 grid((unsigned)kNormChunksPerRhs, batch);
+    hipLaunchKernelGGL((k_refine_scale<R, T>), grid, dim3(kBlock), 0, s, r, y, rn2, bn2, rtol * rtol, active, per,
+                       part);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -151,11 +176,11 @@ template nmg_status launch_rollout_sub<double>(int, size_t, double*, const doubl
 template nmg_status launch_rollout_sub<float>(int, size_t, float*, const float*, const int*, int, hipStream_t);
 
 template nmg_status launch_refine_scale<double, double>(int, size_t, const double*, double*, const double*,
-                                                        const double*, double, int*, hipStream_t);
+                                                        const double*, double, int*, hipStream_t, double*);
 template nmg_status launch_refine_scale<double, float>(int, size_t, const double*, float*, const double*,
-                                                       const double*, double, int*, hipStream_t);
+                                                       const double*, double, int*, hipStream_t, double*);
 template nmg_status launch_refine_scale<float, float>(int, size_t, const float*, float*, const double*,
-                                                      const double*, double, int*, hipStream_t);
+                                                      const double*, double, int*, hipStream_t, double*);
 template nmg_status launch_refine_update<double, double>(int, size_t, double*, const double*, const double*,
                                                          const int*, hipStream_t);
 template nmg_status launch_refine_update<double, float>(int, size_t, double*, const float*, const double*,

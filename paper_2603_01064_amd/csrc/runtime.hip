@@ -481,11 +481,11 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int part
 
 template <typename T>
 nmg_status run_cycle(Ctx* c, int batch, const double* alpha, const int* ws, const T* y, T* x, bool x_zero,
-                     const nmg_cycle_opts& o, hipStream_t s) {
+                     const nmg_cycle_opts& o, hipStream_t s, int parts_ready = 0) {
     NMG_TRY(ensure_work<T>(c));
     if (o.precision != NMG_MIXED || c->p.smoother_arch == NMG_ARCH_FNO) NMG_TRY(ensure_acts<T>(c));
     CycleArgs<T> a{c, &work_of<T>(c), batch, alpha, ws, o, s};
-    return cycle<T>(a, 0, x, y, x_zero);
+    return cycle<T>(a, 0, x, y, x_zero, parts_ready);
 }
 
 }  // namespace
@@ -847,8 +847,10 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             NMG_TRY(launch_refine_update<double, double>(kk, per, X64, w.lv[0].x, d_rn2, h->active, st));
         } else {
             Work<float>& w = h->w32b;
-            NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st));
-            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st));
+            // the scaling also writes the first stage of ||y||^2 for the cycle's first smoothing step
+            NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st,
+                                                       h->norm_part));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st, kNormChunksPerRhs));
             if (refine_residual_fusable(h, h->w64)) {
                 ProfScope ps(h, st, NMG_K_REFINE, 0);
                 (void)launch_refine_residual<float>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
@@ -860,6 +862,15 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         }
         return residual(kk, st);
     };
+    // sampled timing: iterations off the sampling period run without timing
+    // nodes (their own graph), so the timing adds no launches to them
+    struct MaskGuard {
+        Ctx* c;
+        int saved;
+        ~MaskGuard() { c->prof_mask = saved; }
+    } mask_guard{h, h->prof_mask};
+    if (h->prof_mask && h->prof_period > 1 && (h->prof_iter++ % h->prof_period) != 0) h->prof_mask = 0;
+    if (h->prof_mask) h->prof_rhs += k;
     if (h->use_graphs) {
         std::vector<long long> key = {kb, (long long)o->precision, o->nu1, o->nu2, o->use_fprime, wsd ? 1 : 0,
                                       (long long)h->prof_mask, (long long)h->prof_levels};
@@ -1440,6 +1451,23 @@ nmg_status nmg_profile_enable(nmg_handle h, int on) {
         for (auto& v : row) v = 0.0;
     for (auto& row : h->prof_cnt)
         for (auto& v : row) v = 0;
+    h->prof_rhs = 0;
+    h->prof_iter = 0;
+    return NMG_OK;
+}
+
+nmg_status nmg_profile_rhs(nmg_handle h, long long* rhs_iterations) {
+    NMG_TRY(check_handle(h));
+    if (!rhs_iterations) return fail(NMG_ERR_ARG, "null argument");
+    *rhs_iterations = h->prof_rhs;
+    return NMG_OK;
+}
+
+nmg_status nmg_profile_sample(nmg_handle h, int period) {
+    NMG_TRY(check_handle(h));
+    if (period < 1) return fail(NMG_ERR_ARG, "period must be >= 1");
+    h->prof_period = period;
+    h->prof_iter = 0;
     return NMG_OK;
 }
 

@@ -19,6 +19,20 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// XCD-major numbering of a (gridDim.x, gridDim.y) grid.  Workgroups are
+// dispatched round-robin over the 8 XCDs by linear id; numbering them so that
+// XCD x takes a contiguous range of the (block, image) pairs, in order, puts
+// the neighbouring blocks of one image on one XCD, where the halo rows and
+// columns they share are read from its L2 instead of from memory.  Returns
+// the logical block (bx) and image (by).
+__device__ inline void xcd_major(int& bx, int& by) {
+    const int G = gridDim.x * gridDim.y, i = blockIdx.x + blockIdx.y * gridDim.x;
+    const int xc = i % 8, q = G / 8, rem = G % 8;
+    const int p = xc * q + min(xc, rem) + i / 8;
+    by = p / gridDim.x;
+    bx = p - by * gridDim.x;
+}
+
 // Row pass: tg[b][i][j] = sum_q G[j][q] x[b][i][q]; the same for M into tm.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_rowpass(const T* __restrict__ x, T* __restrict__ tg,
@@ -133,11 +147,12 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r, T*
                                                      int two_d, T scale, double* __restrict__ part) {
     const int rows_c = two_d ? nc : 1;
     const size_t perc = (size_t)rows_c * nc;
-    const int b = blockIdx.y;
+    int bx, b;
+    xcd_major(bx, b);
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
     const T* src = r + (size_t)b * perf;
     double sq = 0.0;
-    for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < perc; e += (size_t)gridDim.x * kBlock) {
+    for (size_t e = (size_t)bx * kBlock + threadIdx.x; e < perc; e += (size_t)gridDim.x * kBlock) {
         const int i = (int)(e / nc), j = (int)(e % nc);
         int ij[3], ii[3];
         T wj[3], wi[3];
@@ -168,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r, T*
             if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+        if (threadIdx.x == 0) part[(size_t)b * gridDim.x + bx] = red[0];
     }
 }
 
@@ -191,9 +206,10 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ ec, T* __restrict__ x, int nf, int nc,
                                                         int two_d) {
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
-    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    int bx, b;
+    xcd_major(bx, b);
+    const size_t e = (size_t)bx * kBlock + threadIdx.x;
     if (e >= perf) return;
-    const int b = blockIdx.y;
     const size_t perc = (size_t)(two_d ? nc : 1) * nc;
     const int p = (int)(e / nf), q = (int)(e % nf);
     const T* src = ec + (size_t)b * perc;
@@ -331,8 +347,8 @@ __global__ void __launch_bounds__(kBlock) k_residual_tiled(
     T* X = sm;
     T* TGs = X + (size_t)XH * XW;
     T* TMs = TGs + (size_t)GH * TW;
-    const int b = blockIdx.y;
-    const int tile = blockIdx.x;
+    int tile, b;
+    xcd_major(tile, b);
     const int i0 = (tile / tiles_x) * TH, j0 = (tile % tiles_x) * TW;
     const size_t per = (size_t)n * n;
     const T* xs = x + (size_t)b * per;
@@ -507,8 +523,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     // corner corrections staged next to the tile (rc x rc each)
     T* cs = TMs + (m_ident ? 0 : MH * TW);
     const int rc2 = rc * rc;
-    const int b = blockIdx.y;
-    const int tile = blockIdx.x;
+    int tile, b;
+    xcd_major(tile, b);
     const int i0 = (tile / tiles_x) * TH, j0 = (tile % tiles_x) * TW;
     const size_t per = (size_t)n * n;
     const T* xs = x + (size_t)b * per;
@@ -811,8 +827,9 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     T* Ms = G + XH * TW;                      // [TH + 4][TW]: row r <-> image row i0 - 1 + r
     T* cs = Ms + (m_ident ? 0 : (TH + 4) * TW);  // corner corrections (rc x rc each)
     const int rc2 = rc * rc;
-    const int b = blockIdx.y;
-    const int i0 = (blockIdx.x / tiles_x) * TH, j0 = (blockIdx.x % tiles_x) * TW;
+    int bx, b;
+    xcd_major(bx, b);
+    const int i0 = (bx / tiles_x) * TH, j0 = (bx % tiles_x) * TW;
     const size_t per = (size_t)n * n;
     const T* tgs = tg + (size_t)b * per;
     const int tid = threadIdx.x;
@@ -916,7 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
             if (tid < h) red[tid] += red[tid + h];
             __syncthreads();
         }
-        if (tid == 0) part[(size_t)b * kNormChunks + blockIdx.x] = red[0];
+        if (tid == 0) part[(size_t)b * kNormChunks + bx] = red[0];
     }
 }
 

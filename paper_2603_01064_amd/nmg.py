@@ -94,6 +94,8 @@ def load_library():
         "nmg_profile_enable": (S, [P, I]),
         "nmg_set_graphs": (S, [P, I]),
         "nmg_profile_levels": (S, [P, I]),
+        "nmg_profile_sample": (S, [P, I]),
+        "nmg_profile_rhs": (S, [P, P]),
         "nmg_serve_submit": (S, [P, ctypes.c_longlong, D, I, P, P]),
         "nmg_serve_step": (S, [P, D, I, ctypes.POINTER(_CycleOpts), P, ctypes.POINTER(ctypes.c_int), P]),
         "nmg_serve_pending": (S, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -485,6 +487,16 @@ class Handle:
         for k in kinds:
             mask |= 1 << self.KERNELS[k]
         _check(_lib.nmg_profile_enable(self.ptr, mask))
+
+    def profile_sample(self, period: int) -> None:
+        """Time only every ``period``-th solve iteration."""
+        _check(_lib.nmg_profile_sample(self.ptr, int(period)))
+
+    def profile_rhs(self) -> int:
+        """Active right-hand sides summed over the timed solve iterations."""
+        v = ctypes.c_longlong(0)
+        _check(_lib.nmg_profile_rhs(self.ptr, ctypes.byref(v)))
+        return v.value
 
     def profile_levels(self, levels=None) -> None:
         """Time only the given levels (None: all levels)."""
