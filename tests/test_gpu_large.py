@@ -3,9 +3,11 @@ at the finest level), alpha = 1e-4, CNN 1-32-32-32-1 smoothers, right-hand
 sides b = sum of 500 Gaussian blobs.  The FP64-residual refinement carries
 the BF16/FP32 cycle to a relative error of 1e-10 against the exact solution
 (the oracle's eigenbasis solve), on the 255^2 crop problem (same stencil in
-grid units, s = 0.04, 5 levels) and on the full 2047^2 grid (s = 0.005, 5
-levels down to 127^2, solved exactly in the eigenbasis of the coarsest
-factors: the trained smoothers cover levels with s/h = 10.24 .. 1.28)."""
+grid units, s = 0.04, 5 levels) and on the full 2047^2 grid: with 5 levels
+down to 127^2, solved exactly in the eigenbasis of the coarsest factors (the
+trained smoothers cover levels with s/h = 10.24 .. 1.28), and with 8 levels
+down to 15^2 (dense Cholesky), levels 5-7 (s/h = 0.64 .. 0.16) smoothed by
+weighted Jacobi."""
 import os
 
 import numpy as np
@@ -22,7 +24,7 @@ WEIGHTS = os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s10.24h
 ALPHA = 1e-4
 
 
-def _handle(n, s, L, B):
+def _handle(n, s, L, B, jacobi_from=None, omega=0.8):
     from paper_2603_01064_amd import nmg
     from paper_2603_01064_amd.train_weights import load_weights
     nmg.load_library()
@@ -31,13 +33,16 @@ def _handle(n, s, L, B):
     h = nmg.setup_hierarchy(nmg.Problem(n=n, s=s, levels=L, max_batch=B, channels=tuple(meta["channels"]), ksize=3))
     deepest = meta["levels"] - 2
     for l in range(L - 1):
-        h.load_smoother_weights(l, 0, [sets[k][min(l, deepest)]])
+        if jacobi_from is not None and l >= jacobi_from:
+            h.set_jacobi_smoother(l, omega)
+        else:
+            h.load_smoother_weights(l, 0, [sets[k][min(l, deepest)]])
     return h, meta["cycle"]
 
 
-def _solve_and_check(n, s, L, B, seed):
+def _solve_and_check(n, s, L, B, seed, jacobi_from=None):
     dev = torch.device("cuda:0")
-    h, cyc = _handle(n, s, L, B)
+    h, cyc = _handle(n, s, L, B, jacobi_from)
     b = torch.tensor(np.stack([inputs.blobs_image(n, seed + i) for i in range(B)]))
     alpha = torch.full((B,), ALPHA, dtype=DT)
     kw = dict(nu1=cyc["nu1"], nu2=cyc["nu2"], use_fprime=cyc["use_fprime"])
@@ -69,3 +74,8 @@ def test_crop_255_error_1e10():
 def test_full_2047_error_1e10():
     print("case large solve 2047x2047 s/h=10.24, 5 levels", flush=True)
     _solve_and_check(2047, 0.005, 5, 2, 46000)
+
+
+def test_full_2047_eight_levels_error_1e10():
+    print("case large solve 2047x2047 s/h=10.24, 8 levels to 15^2, Jacobi on levels 5-7", flush=True)
+    _solve_and_check(2047, 0.005, 8, 2, 46000, jacobi_from=4)
