@@ -434,8 +434,19 @@ def training(nmg, steps=10, warmup=2):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     h.close()
+    # algorithmic network work per step: forward plus backward (data and weight
+    # gradients, 2x the forward) of each level's smoother on its level, for
+    # the batch; the loss transforms, transfers and the activation recompute
+    # are not counted
+    px = sum((((n + 1) >> l) - 1) ** 2 for l in range(L - 1))
+    flop = 3 * FLOP_PER_PX * px * B
+    tflops = flop / (dt / steps) / 1e12
     return {"ms_per_step": round(1e3 * dt / steps, 2), "samples_per_s": round(B * steps / dt, 1), "steps": steps,
-            "batch": B, "grid": n, "levels": L, "mask": "band", "loss_sum_first": first, "loss_sum_last": last}
+            "batch": B, "grid": n, "levels": L, "mask": "band", "loss_sum_first": first, "loss_sum_last": last,
+            "network_gflop_per_step": round(flop / 1e9, 1), "achieved_tflops": round(tflops, 2),
+            "mfma_frac": round(tflops / BF16_PEAK_TFLOPS, 4),
+            "flop_note": "3 x 19,584 FLOP per pixel (forward + backward of the CNN 1-32-32-1) on levels "
+                         "127^2, 63^2, 31^2, 15^2, batch 256; against the dense BF16 MFMA peak"}
 
 
 def _serial_handle(nmg, sets):
@@ -444,13 +455,14 @@ def _serial_handle(nmg, sets):
     for k, ws in enumerate(sets):
         for l in range(LEVELS - 1):
             h1.load_smoother_weights(l, k, [ws[l]])
-    h1.set_graphs(False)
     return h1
 
 
 def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8):
     """Plain FP32 V-cycle solving one right-hand side at a time (no batching,
-    no BF16, no refinement, no graphs) on the first `count` problems of a batch."""
+    no BF16, no refinement) on the first `count` problems of a batch, with the
+    tiled FP32 smoother and captured iteration graphs (one warm-up solve
+    captures them first)."""
     import torch
     dev = torch.device("cuda:0")
     h1 = _serial_handle(nmg, sets)
@@ -461,6 +473,9 @@ def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8
         ws = torch.tensor([wsi], dtype=torch.int32, device=dev)
         b = h1.apply_operator(0, torch.tensor(u[i:i + 1], device=dev), alpha, "fp64")
         probs.append((alpha, ws, b))
+    a0, w0, b0 = probs[0]
+    h1.solve(b0, a0, weight_set=w0, rtol=1e-6, max_cycles=2, nu1=cyc_cfg["nu1"], nu2=cyc_cfg["nu2"],
+             use_fprime=cyc_cfg["use_fprime"], precision="fp32")  # graph capture, coarse factors
     torch.cuda.synchronize()
     lat, cyc_all, ok = [], [], 0
     t0 = time.perf_counter()
@@ -479,7 +494,7 @@ def serial_fp32(nmg, sets, set_alphas, cyc_cfg, alpha_np, u, max_cycles, count=8
     h1.close()
     return {"value": round(count / elapsed, 3), "unit": "solves/s", "p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2), "converged": ok, "solves": count, "cycles": cyc_all,
-            "note": "one request at a time, plain FP32 cycle and FP32 direct-convolution smoother, no graphs"}
+            "note": "one request at a time, plain FP32 cycle, tiled FP32 convolution smoother, captured graphs"}
 
 
 def serving(nmg, h, sets, set_alphas, cyc_cfg, batches, max_cycles, rates=(20.0, 1000.0), low_count=48,
@@ -522,6 +537,7 @@ def serving(nmg, h, sets, set_alphas, cyc_cfg, batches, max_cycles, rates=(20.0,
                 except nmg.NMGError:
                     return -1, -1
 
+            solve_one(0)  # graph capture and coarse factors before the trace
             srep = serve_serially(solve_one, arr)
             h1.close()
             out[f"poisson_{int(rate)}_per_s"]["serial_fp32"] = srep.summary()
@@ -570,8 +586,8 @@ def large_solve(nmg, batch=16, max_cycles=400):
     x = torch.empty_like(b)
     kw = dict(nu1=cyc["nu1"], nu2=cyc["nu2"], use_fprime=cyc["use_fprime"])
     h.solve(b[:1], alpha[:1], rtol=1e-6, max_cycles=max_cycles, precision="mixed", **kw)  # capture, factors
-    # the plain FP32 cycle (FP32 direct-convolution smoother, FP32 residuals) stalls near 2e-5 on this
-    # operator and takes seconds per cycle at this size, so it runs 3 cycles for its per-cycle time
+    # the plain FP32 cycle (tiled FP32 convolution smoother, FP32 residuals) stalls near 2e-5 on this
+    # operator, so it runs 3 cycles for its per-cycle time
     for prec, rtol, cap in (("mixed", 1e-6, max_cycles), ("fp32", 1e-6, 3), ("mixed", 1e-14, max_cycles)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -718,8 +734,6 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
     arr = inputs.poisson_arrivals(rate, count, seed=43000 + int(rate))[:serial_count]
     arr = arr - arr[0]
     serial = [_mixed_handle(nmg, sd, meta, sets, 1) for sd in MIXED_SIDES]
-    for h1 in serial:
-        h1.set_graphs(False)
 
     def solve_one(i):
         h1 = serial[member[i]]
@@ -731,7 +745,10 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
         except nmg.NMGError:
             return -1, -1
 
-    solve_one(0)
+    for mi in range(len(serial)):  # each size's graph capture and factors before the trace
+        first = next((i for i in range(len(member)) if member[i] == mi), None)
+        if first is not None:
+            solve_one(first)
     srep = serve_serially(solve_one, arr)
     for h1 in serial:
         h1.close()

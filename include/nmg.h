@@ -342,9 +342,9 @@ nmg_status nmg_request_bytes(nmg_handle h, nmg_precision precision, size_t* byte
  * size.  Each member handle keeps its hierarchy, weights and iterates on the
  * device and runs its continuous-batching engine (nmg_serve_*) on a stream
  * the pool creates for it (default priority); one pool step advances every
- * member with work by one outer iteration, and a member waits only for its
- * own previous iteration, so different members' iterations overlap on the
- * device.  Requests wait in one FIFO and are admitted while the bytes of
+ * member with work whose previous outer iteration has finished by one more
+ * (waiting for the first to finish when none has), so members iterate at
+ * their own pace and different members' iterations overlap on the device.  Requests wait in one FIFO and are admitted while the bytes of
  * the admitted requests (nmg_request_bytes at the step's precision) stay
  * within hbm_budget_bytes; the head request is always admitted when nothing
  * is in flight.  The pool does not own its handles: they must outlive it and
@@ -364,7 +364,9 @@ nmg_status nmg_pool_add(nmg_pool p, nmg_handle h, int* member_out);
  * in mixed precision, NMG_ERR_NOT_SPD / NMG_ERR_ARG for a bad alpha. */
 nmg_status nmg_pool_submit(nmg_pool p, int member, long long id, double alpha, int weight_set,
                            const double* b_dev, double* x_dev);
-/* Admission, then one outer iteration of every member with work.  Finished
+/* Admission, then one outer iteration of every member with work whose
+ * previous iteration has finished (at least one: the call waits for the
+ * first to finish when none has).  Finished
  * requests are written to done[0..*n_done) with their member index in
  * done_member; latency_ms counts from nmg_pool_submit.  Their solutions are
  * complete in x when the call returns.  capacity must be at least the

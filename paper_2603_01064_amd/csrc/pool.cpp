@@ -4,15 +4,18 @@
 // Every right-hand side is an independent solve (Sec. 2.3), so requests of
 // different sizes and alphas can be in flight together: each member handle
 // runs its own slot engine on its own stream, and a pool step advances every
-// member with work by one outer iteration.  A member's step waits only for
-// its own previous iteration, so the iterations of different members overlap
-// on the device.  Requests wait in one FIFO and enter their member's engine
-// while the request bytes admitted so far (request_bytes of each request's
-// handle) stay within the budget.
+// member whose previous outer iteration has finished by one more (waiting
+// for the first to finish when none has).  Members therefore iterate at
+// their own pace: a small grid is not held to the iteration time of a large
+// one, and the iterations of different members overlap on the device.
+// Requests wait in one FIFO and enter their member's engine while the
+// request bytes admitted so far (request_bytes of each request's handle)
+// stay within the budget.
 
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -23,6 +26,8 @@ struct nmg_pool_ctx {
         nmg_handle h = nullptr;
         hipStream_t s = nullptr;
         hipEvent_t retired = nullptr;
+        hipEvent_t iter_done = nullptr;  // recorded after each of the member's steps
+        bool launched = false;           // iter_done has been recorded
     };
     struct Pending {
         long long id;
@@ -68,6 +73,7 @@ void nmg_pool_destroy(nmg_pool p) {
             (void)hipStreamDestroy(m.s);
         }
         if (m.retired) (void)hipEventDestroy(m.retired);
+        if (m.iter_done) (void)hipEventDestroy(m.iter_done);
         (void)nmg_serve_reset(m.h);  // requests still in flight are abandoned
     }
     delete p;
@@ -83,6 +89,7 @@ nmg_status nmg_pool_add(nmg_pool p, nmg_handle h, int* member_out) {
     m.h = h;
     NMG_HIP(hipStreamCreateWithFlags(&m.s, hipStreamNonBlocking));
     NMG_HIP(hipEventCreateWithFlags(&m.retired, hipEventDisableTiming));
+    NMG_HIP(hipEventCreateWithFlags(&m.iter_done, hipEventDisableTiming));
     p->members.push_back(m);
     *member_out = (int)p->members.size() - 1;
     return NMG_OK;
@@ -130,20 +137,43 @@ nmg_status nmg_pool_step(nmg_pool p, double rtol, int max_cycles, const nmg_cycl
     }
     if (capacity < (int)p->running.size())
         return fail(NMG_ERR_ARG, "result capacity below the requests in flight");
-    // ---- one outer iteration for every member with work; members whose
-    // requests finished wait only for the copy-out of those solutions
-    // every early return below first reports the requests already handed
-    // back in done[0..count), so a failing member never loses finished ones
+    // ---- one outer iteration for every member with work whose previous
+    // iteration has finished (when none has, wait for the first that does);
+    // members whose requests finished wait only for the copy-out of those
+    // solutions.  Every early return below first reports the requests already
+    // handed back in done[0..count), so a failing member never loses finished ones
+    auto has_work = [](const nmg_pool_ctx::Member& m) { return !m.h->eng.queue.empty() || !m.h->eng.slot.empty(); };
+    std::vector<char> ready(p->members.size(), 0);
+    for (bool any_work = true, any_ready = false; any_work && !any_ready;) {
+        any_work = false;
+        for (size_t mi = 0; mi < p->members.size(); ++mi) {
+            auto& m = p->members[mi];
+            if (!has_work(m)) continue;
+            any_work = true;
+            hipError_t q = m.launched ? hipEventQuery(m.iter_done) : hipSuccess;
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return nmg::hip_fail(q, "hipEventQuery(iter_done)", __FILE__, __LINE__);
+            ready[mi] = 1;
+            any_ready = true;
+        }
+        if (any_work && !any_ready) std::this_thread::yield();
+    }
     int count = 0;
     for (size_t mi = 0; mi < p->members.size(); ++mi) {
         auto& m = p->members[mi];
-        if (m.h->eng.queue.empty() && m.h->eng.slot.empty()) continue;
+        if (!ready[mi]) continue;
         std::vector<nmg_request_result> out;
         const nmg_status st = nmg::engine_step(m.h, rtol, max_cycles, o, out, m.s, m.retired);
         if (st < 0) {
             *n_done = count;
             return st;
         }
+        const hipError_t rec = hipEventRecord(m.iter_done, m.s);
+        if (rec != hipSuccess) {
+            *n_done = count;
+            return nmg::hip_fail(rec, "hipEventRecord(iter_done)", __FILE__, __LINE__);
+        }
+        m.launched = true;
         if (out.empty()) continue;
         const hipError_t ev = hipEventSynchronize(m.retired);
         if (ev != hipSuccess) {

@@ -5,9 +5,12 @@
 // with N_theta a bias-free CNN (conv, ReLU, ..., conv), cross-correlation
 // with zero "same" padding.  Weighted Jacobi (Sec. 2.2): h = omega D^{-1} b.
 //
-// This direct convolution keeps one output (pixel, channel) per thread and
-// stages activations through global memory; the fast BF16 path lives in
-// the MFMA smoother.
+// FP64 (and shapes other than 2D 3x3 with 1 or 32 channels) use a direct
+// convolution with one output (pixel, channel) per thread; 2D FP32 layers of
+// the workloads' networks use a tiled kernel (16 x 16 output pixels per
+// workgroup, every output channel of a pixel per thread, input channels and
+// weights staged in LDS).  Activations go through global memory between
+// layers in both; the fast BF16 path lives in the MFMA smoother.
 #include "nmg_internal.h"
 
 namespace nmg {
@@ -63,6 +66,77 @@ __global__ void __launch_bounds__(kBlock) k_conv(const T* __restrict__ in, T* __
     }
 }
 
+// One 2D 3x3 FP32 layer, CIN -> COUT channels: workgroup = 16 x 16 output
+// pixels of one image, thread = one pixel with all COUT accumulators.  The
+// input channels are staged CC at a time as 18 x 18 tiles (zero outside the
+// image) together with their weights ([ci][tap][co], read as broadcasts).
+// The sum runs over input channels in order, taps in row-major order, as the
+// direct kernel's; FIRST scales the sum by 1/||b|| afterwards, LAST writes
+// ||b|| times the (only) output channel to dst, other layers apply ReLU.
+constexpr int kTile = 16;
+
+template <int CIN, int COUT, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kTile * kTile) k_conv3_tiled(const float* __restrict__ in, float* __restrict__ out,
+                                                                const float* __restrict__ wlevel,
+                                                                const int* __restrict__ ws, int nsets, int wcount,
+                                                                int layer_off, int n, int tiles_x, int accumulate,
+                                                                const double* __restrict__ nrm2) {
+    constexpr int H = kTile + 2, CC = CIN < 8 ? CIN : 8;
+    static_assert(CIN % CC == 0 && (!LAST || COUT == 1), "layer shape");
+    __shared__ float xs[CC][H][H];
+    __shared__ __attribute__((aligned(16))) float wsm[CC][9][COUT];
+    const int b = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles_x) * kTile, tx0 = (blockIdx.x % tiles_x) * kTile;
+    const int tid = threadIdx.x, ty = tid / kTile, tx = tid % kTile;
+    // out-of-range set indices are clamped so that a bad index cannot read past the weights
+    const int set = ws ? min(max(ws[b], 0), nsets - 1) : 0;
+    const float* w = wlevel + (size_t)set * wcount + layer_off;  // [COUT][CIN][3][3]
+    const size_t per = (size_t)n * n;
+    const float* src = in + (size_t)b * CIN * per;
+    float acc[COUT];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = 0.f;
+    for (int c0 = 0; c0 < CIN; c0 += CC) {
+        __syncthreads();  // the previous chunk has been read
+        for (int e = tid; e < CC * H * H; e += kTile * kTile) {
+            const int ci = e / (H * H), rem = e - ci * (H * H), r = rem / H, c = rem - r * H;
+            const int gy = ty0 - 1 + r, gx = tx0 - 1 + c;
+            xs[ci][r][c] = (gy >= 0 && gy < n && gx >= 0 && gx < n) ? src[(size_t)(c0 + ci) * per + (size_t)gy * n + gx]
+                                                                     : 0.f;
+        }
+        for (int e = tid; e < CC * 9 * COUT; e += kTile * kTile) {
+            const int co = e % COUT, t = (e / COUT) % 9, ci = e / (9 * COUT);
+            wsm[ci][t][co] = w[((size_t)co * CIN + c0 + ci) * 9 + t];
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ci = 0; ci < CC; ++ci)
+#pragma unroll 3
+            for (int t = 0; t < 9; ++t) {
+                const float x = xs[ci][ty + t / 3][tx + t % 3];
+#pragma unroll
+                for (int co = 0; co < COUT; ++co) acc[co] = fmaf(wsm[ci][t][co], x, acc[co]);
+            }
+    }
+    const int gy = ty0 + ty, gx = tx0 + tx;
+    if (gy >= n || gx >= n) return;
+    const double nb = sqrt(nrm2[b]);
+    if (FIRST) {
+        const float inscale = nb > 0.0 ? (float)(1.0 / nb) : 0.f;
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) acc[co] *= inscale;
+    }
+    const size_t pix = (size_t)gy * n + gx;
+    if (LAST) {
+        const float v = acc[0] * (float)nb;
+        float* d = out + (size_t)b * per + pix;
+        *d = accumulate ? *d + v : v;
+    } else {
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) out[((size_t)b * COUT + co) * per + pix] = acc[co] < 0.f ? 0.f : acc[co];
+    }
+}
+
 // Weighted Jacobi: h = omega b / diag(A_l), diag = alpha m_i m_j + g_i g_j (2D).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_jacobi(const T* __restrict__ bres, T* __restrict__ dst,
@@ -108,6 +182,30 @@ nmg_status launch_conv_smoother(const Ctx* c, int l, int batch, const int* ws, c
         const int cin = c->p.channels[i], cout = c->p.channels[i + 1];
         const int first = i == 0, last = i == nl - 1;
         T* out = last ? dst : bufs[i & 1];
+        if constexpr (sizeof(T) == 4) {
+            // tiled FP32 layers for the shapes of the workloads' networks
+            if (c->p.dim == 2 && c->p.ksize == 3) {
+                const int tiles_x = (n + kTile - 1) / kTile;
+                const dim3 tg((unsigned)(tiles_x * tiles_x), (unsigned)batch);
+                bool done = true;
+                if (cin == 1 && cout == 32 && first && !last)
+                    hipLaunchKernelGGL((k_conv3_tiled<1, 32, true, false>), tg, dim3(kTile * kTile), 0, s, src, out,
+                                       wl, ws, c->p.n_weight_sets, c->wcount, c->layer_off[i], n, tiles_x, 0, nrm2);
+                else if (cin == 32 && cout == 32 && !first && !last)
+                    hipLaunchKernelGGL((k_conv3_tiled<32, 32, false, false>), tg, dim3(kTile * kTile), 0, s, src, out,
+                                       wl, ws, c->p.n_weight_sets, c->wcount, c->layer_off[i], n, tiles_x, 0, nrm2);
+                else if (cin == 32 && cout == 1 && !first && last)
+                    hipLaunchKernelGGL((k_conv3_tiled<32, 1, false, true>), tg, dim3(kTile * kTile), 0, s, src, out,
+                                       wl, ws, c->p.n_weight_sets, c->wcount, c->layer_off[i], n, tiles_x,
+                                       accumulate, nrm2);
+                else
+                    done = false;
+                if (done) {
+                    src = out;
+                    continue;
+                }
+            }
+        }
         dim3 grid(blocks_for(per), last ? 1 : cout, batch);
         hipLaunchKernelGGL(k_conv<T>, grid, dim3(kBlock), 0, s, src, out, wl, ws, c->p.n_weight_sets, c->wcount,
                            c->layer_off[i], cin,
