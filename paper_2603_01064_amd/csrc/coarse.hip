@@ -133,20 +133,34 @@ __global__ void __launch_bounds__(kBlock) k_gram(const double* __restrict__ W, d
     Ainv[(size_t)b * N * N + e] = acc;
 }
 
-// x = Ainv y per right-hand side; Ainv is symmetric, so thread i reads column
-// i (contiguous across threads for each k).
+// x = Ainv y per right-hand side; Ainv is symmetric, so output i reads
+// column i (contiguous across threads for each k).  A workgroup takes 32
+// outputs of one right-hand side and splits the sum over k into 8 slices of
+// consecutive k (one per wave half), added in slice order: 8x shorter
+// dependent chains and N/32 workgroups per right-hand side.
+constexpr int kInvOut = 32, kInvSlices = kBlock / kInvOut;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_inverse_apply(const double* __restrict__ Ainv, const int* __restrict__ fidx,
                                                           const T* __restrict__ y, T* __restrict__ x, int N) {
-    extern __shared__ double yv[];
-    const int b = blockIdx.x;
+    extern __shared__ double yv[];  // N values of y, then kBlock partial sums
+    double* red = yv + N;
+    const int b = blockIdx.y;
     for (int i = threadIdx.x; i < N; i += kBlock) yv[i] = (double)y[(size_t)b * N + i];
     __syncthreads();
     const double* A = Ainv + (size_t)fidx[b] * N * N;
-    for (int i = threadIdx.x; i < N; i += kBlock) {
-        double acc = 0.0;
-        for (int k = 0; k < N; ++k) acc += A[(size_t)k * N + i] * yv[k];
-        x[(size_t)b * N + i] = (T)acc;
+    const int io = threadIdx.x % kInvOut, ks = threadIdx.x / kInvOut;
+    const int i = blockIdx.x * kInvOut + io;
+    const int len = (N + kInvSlices - 1) / kInvSlices, k0 = ks * len, k1 = min(N, k0 + len);
+    double acc = 0.0;
+    if (i < N)
+        for (int k = k0; k < k1; ++k) acc += A[(size_t)k * N + i] * yv[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (ks == 0 && i < N) {
+        double s = red[io];
+        for (int q = 1; q < kInvSlices; ++q) s += red[q * kInvOut + io];
+        x[(size_t)b * N + i] = (T)s;
     }
 }
 
@@ -229,8 +243,8 @@ nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s) {
     const int N = c->nc;
-    hipLaunchKernelGGL(k_inverse_apply<T>, dim3(batch), dim3(kBlock), N * sizeof(double), s, c->cinv,
-                       c->cycle_fidx ? c->cycle_fidx : c->coarse_idx,
+    hipLaunchKernelGGL(k_inverse_apply<T>, dim3((N + kInvOut - 1) / kInvOut, batch), dim3(kBlock),
+                       (N + kBlock) * sizeof(double), s, c->cinv, c->cycle_fidx ? c->cycle_fidx : c->coarse_idx,
                        y, x, N);
     NMG_HIP(hipGetLastError());
     return NMG_OK;

@@ -812,7 +812,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(T* x, T* __restrict__ tg,
 // each thread's rows in order, then a fixed tree over the threads) goes to
 // part[b * kNormChunks + tile], the first stage of ||out||^2 with a partial
 // layout that depends only on the level size.
-template <typename T, int TP>
+template <typename T, int TP, int TW = 64>
 __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg, const T* __restrict__ tm,
                                                        const T* __restrict__ x, const T* __restrict__ y,
                                                        T* __restrict__ out, const double* __restrict__ alpha, int n,
@@ -820,7 +820,10 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
                                                        const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
                                                        const T* __restrict__ mt, int m_ident, int tiles_x,
                                                        double* __restrict__ part = nullptr) {
-    constexpr int TH = 64, TW = 64, OC = 16;  // 4 x 64 threads, 16 rows each
+    // TH x TW tile, TW columns x (TH / OC) row groups of threads: OC = 16 rows
+    // each for 64 columns, 8 for 32 (more, smaller workgroups)
+    constexpr int TH = 64, OC = TH * TW / kBlock;
+    static_assert(OC * kBlock == TH * TW && OC % 4 == 0, "column-pass tile");
     constexpr int XH = TH + TP;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* G = reinterpret_cast<T*>(smem_raw);    // [XH][TW]: row r <-> image row i0 - rg + r
@@ -999,13 +1002,16 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
         bool launched = false;
         // FP32: 128 x 64 tiles (512 threads, 4 waves per SIMD) when they give at
         // least 512 workgroups, else 32 x 32 tiles (256 threads) for more
-        // parallelism at small batches and on coarse levels; FP64: 32 x 32 tiles
+        // parallelism at small batches and on coarse levels (64 x 64 tiles with
+        // 256 threads, measured on level 1 at about 30 right-hand sides, took
+        // 32 us against 21 us); FP64: 32 x 32 tiles
         const bool big = sizeof(T) == 4 && (long)((n + 63) / 64) * ((n + 127) / 128) * batch >= 512;
         auto launch = [&](auto cfg_tag, auto tp_tag) {
             constexpr int TP = decltype(tp_tag)::value;
-            constexpr bool BIG = decltype(cfg_tag)::value;
-            constexpr int TH = BIG ? 128 : 32, TW = BIG ? 64 : 32, OC = BIG ? 8 : 4, NT = BIG ? 512 : 256;
-            constexpr int WPE = BIG ? 4 : 1;
+            constexpr int CFG = decltype(cfg_tag)::value;  // 2: 128 x 64, 0: 32 x 32
+            constexpr int TH = CFG == 2 ? 128 : 32, TW = CFG == 2 ? 64 : 32;
+            constexpr int OC = CFG == 2 ? 8 : 4, NT = CFG == 2 ? 512 : 256;
+            constexpr int WPE = CFG == 2 ? 4 : 1;
             const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
             const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW) +
                                 2 * (size_t)op.rc * op.rc) * sizeof(T);
@@ -1019,11 +1025,11 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             launched = true;
             if constexpr (sizeof(T) == 4) {
                 if (big) {
-                    launch(std::true_type{}, tp_tag);
+                    launch(std::integral_constant<int, 2>{}, tp_tag);
                     return;
                 }
             }
-            launch(std::false_type{}, tp_tag);
+            launch(std::integral_constant<int, 0>{}, tp_tag);
         };
         go(std::integral_constant<int, 4>{});
         go(std::integral_constant<int, 8>{});
@@ -1069,14 +1075,19 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
 // stage of ||r||^2 in the column pass, then the per-image sums.  Returns
 // false (and launches nothing) where the two-launch tile form does not apply
 // or the partials would not fit; the caller then runs the separate kernels.
+// The refinement residual's column pass runs on 64 x 32 tiles (8 rows per
+// thread): twice the workgroups of 64 x 64 tiles at half the LDS each, for a
+// pass that is bound by latency at the batch sizes of a solve's tail.
+constexpr int kRefineTW = 32;
+
 bool refine_residual_fusable(const Ctx* c, const Work<double>& w) {
     const int n = c->n[0];
     const TiledOp<double>& op = w.tiled[0];
-    const int tiles_x = (n + 63) / 64;
+    const int tiles = ((n + kRefineTW - 1) / kRefineTW) * ((n + 63) / 64);
     static const int kTaps[] = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 84, 164};
     bool tp_ok = false;
     for (int t : kTaps) tp_ok = tp_ok || op.rgp == t;
-    return c->p.dim == 2 && op.ok && op.m_ident && tp_ok && tiles_x * tiles_x <= kNormChunks;
+    return c->p.dim == 2 && op.ok && op.m_ident && tp_ok && tiles <= kNormChunks;
 }
 
 template <typename D>
@@ -1085,7 +1096,7 @@ bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double
                             Work<double>& w, hipStream_t s) {
     const int l = 0, n = c->n[l];
     const TiledOp<double>& op = w.tiled[(size_t)l];
-    const int tiles_x = (n + 63) / 64, tiles = tiles_x * tiles_x;
+    const int tiles_x = (n + kRefineTW - 1) / kRefineTW, tiles = tiles_x * ((n + 63) / 64);
     if (!refine_residual_fusable(c, w)) return false;
     bool launched = false;
     auto go = [&](auto tp_tag) {
@@ -1098,8 +1109,8 @@ bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double
                            dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(double), s,
                            x, tg, (double*)nullptr, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n, d, rn2,
                            active);
-        const size_t lds = ((size_t)(64 + TP) * 64 + 2 * (size_t)op.rc * op.rc) * sizeof(double);
-        hipLaunchKernelGGL((k_cols_fixed<double, TP>), dim3(tiles, batch), dim3(kBlock), lds, s, tg,
+        const size_t lds = ((size_t)(64 + TP) * kRefineTW + 2 * (size_t)op.rc * op.rc) * sizeof(double);
+        hipLaunchKernelGGL((k_cols_fixed<double, TP, kRefineTW>), dim3(tiles, batch), dim3(kBlock), lds, s, tg,
                            (const double*)nullptr, x, y, out, alpha, n, 0, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
                            op.m_ident, tiles_x, c->norm_part);
         hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, c->norm_part, nrm2, batch, tiles);
