@@ -252,9 +252,16 @@ def main(argv=None):
                                 done_ms=done)
         return cyc, done, st
 
+    # warm-up with the timing of the timed region switched on, so that the
+    # iteration graphs of both kinds (with and without the timing launches)
+    # are captured before it
+    h.profile_levels([0])
+    h.profile_sample(PROFILE_PERIOD)
+    h.profile_enable(("smoother",))
     for k in range(a.warmup):
         log(f"warmup {k + 1}/{a.warmup}")
         run(batches[k])
+    h.profile_enable(())
     if a.copy_calibration:
         src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -569,10 +569,11 @@ nmg_status factor_alphas(Ctx* h, const std::vector<double>& al, std::vector<int>
 }
 
 namespace {
-// Launch sizes for captured iterations: exact up to 4, then multiples of 4 up
-// to 32 and of 8 beyond (at most 15 graphs for a batch of 64).
+// Launch sizes for captured iterations: exact up to 32, where a solve's tail
+// spends most of its iterations and a padded slot costs as much as a real
+// one, then multiples of 4 (at most 40 graphs for a batch of 64).
 int graph_batch(int k, int B) {
-    int kb = k <= 4 ? k : (k <= 32 ? (k + 3) / 4 * 4 : (k + 7) / 8 * 8);
+    int kb = k <= 32 ? k : (k + 3) / 4 * 4;
     return std::min(kb, B);
 }
 
