@@ -333,7 +333,8 @@ template <typename T>
 nmg_status launch_dense_axis(const T* in, T* out, const T* C, int n, int ny, int batch, int col_axis, int inverse,
                              hipStream_t s);
 template <typename T>
-nmg_status launch_prolong_add(const Ctx* c, int l, int batch, const T* e, T* x, hipStream_t s);
+// x += P e (set: x = P e)
+nmg_status launch_prolong_add(const Ctx* c, int l, int batch, const T* e, T* x, hipStream_t s, bool set = false);
 template <typename T>
 nmg_status launch_axpy(int batch, size_t elems, const T* src, T* dst, int accumulate, hipStream_t s);
 template <typename T>

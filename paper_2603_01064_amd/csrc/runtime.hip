@@ -447,16 +447,16 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int part
         if (a.o.precision == NMG_FP64) return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
         return launch_coarse_apply_inverse<T>(c, a.batch, y, x, a.s);
     }
-    const size_t per = level_elems(c, l);
-    if (x_zero && a.o.nu1 == 0) {
-        NMG_TRY(launch_zero<T>(x, (size_t)a.batch * per, a.s));
-    }
+    // with no pre-smoothing from x = 0, the residual is y itself: y is
+    // restricted directly and the coarse correction sets x (no zero fill, no
+    // residual launch)
+    const bool from_zero = x_zero && a.o.nu1 == 0;
     for (int k = 0; k < a.o.nu1; ++k) {
         NMG_TRY(smooth_step<T>(a, l, x, y, x_zero, k == 0 ? parts_ready : 0));
         x_zero = false;
     }
     LevelBuffers<T>& lb = w.lv[(size_t)l];
-    {
+    if (!from_zero) {
         ProfScope ps(c, a.s, NMG_K_OPERATOR, l);
         NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, lb.b, 0, w, a.s));
     }
@@ -466,14 +466,14 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int part
                            a.o.precision == NMG_MIXED && c->p.smoother_arch != NMG_ARCH_FNO;
     {
         ProfScope ps(c, a.s, NMG_K_RESTRICT, l);
-        NMG_TRY(launch_restrict<T>(c, l, a.batch, lb.b, w.lv[(size_t)l + 1].y, a.s,
+        NMG_TRY(launch_restrict<T>(c, l, a.batch, from_zero ? y : lb.b, w.lv[(size_t)l + 1].y, a.s,
                                    fuse_norm ? c->norm_part : nullptr));
     }
     NMG_TRY(cycle<T>(a, l + 1, w.lv[(size_t)l + 1].x, w.lv[(size_t)l + 1].y, true,
                      fuse_norm ? restrict_norm_parts(c, l) : 0));
     {
         ProfScope ps(c, a.s, NMG_K_PROLONG, l);
-        NMG_TRY(launch_prolong_add<T>(c, l, a.batch, w.lv[(size_t)l + 1].x, x, a.s));
+        NMG_TRY(launch_prolong_add<T>(c, l, a.batch, w.lv[(size_t)l + 1].x, x, a.s, from_zero));
     }
     for (int k = 0; k < a.o.nu2; ++k) NMG_TRY(smooth_step<T>(a, l, x, y, false));
     return NMG_OK;

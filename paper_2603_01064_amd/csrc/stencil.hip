@@ -204,7 +204,7 @@ __device__ inline int interp_taps(int p, int nc, int* idx, T* w) {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ ec, T* __restrict__ x, int nf, int nc,
-                                                        int two_d) {
+                                                        int two_d, int set) {
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
     int bx, b;
     xcd_major(bx, b);
@@ -229,7 +229,10 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ ec
     } else {
         for (int c = 0; c < kq; ++c) acc += wq[c] * src[iq[c]];
     }
-    x[(size_t)b * perf + e] += acc;
+    if (set)
+        x[(size_t)b * perf + e] = acc;
+    else
+        x[(size_t)b * perf + e] += acc;
 }
 
 // Writes the index maps exactly as the transfer kernels compute them.
@@ -1179,11 +1182,11 @@ nmg_status launch_prolong_transpose(const Ctx* c, int l, int batch, const T* g, 
 }
 
 template <typename T>
-nmg_status launch_prolong_add(const Ctx* c, int l, int batch, const T* e, T* x, hipStream_t s) {
+nmg_status launch_prolong_add(const Ctx* c, int l, int batch, const T* e, T* x, hipStream_t s, bool set) {
     const int nf = c->n[l], nc = c->n[l + 1];
     const size_t perf = level_elems(c, l);
     hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(perf), batch), dim3(kBlock), 0, s, e, x, nf, nc,
-                       c->p.dim == 2 ? 1 : 0);
+                       c->p.dim == 2 ? 1 : 0, set ? 1 : 0);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -1227,7 +1230,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
     template nmg_status launch_sumsq_part<T>(const Ctx*, int, size_t, const T*, hipStream_t);                    \
     template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t, double*);            \
     template nmg_status launch_prolong_transpose<T>(const Ctx*, int, int, const T*, T*, hipStream_t);            \
-    template nmg_status launch_prolong_add<T>(const Ctx*, int, int, const T*, T*, hipStream_t);                  \
+    template nmg_status launch_prolong_add<T>(const Ctx*, int, int, const T*, T*, hipStream_t, bool);            \
     template nmg_status launch_axpy<T>(int, size_t, const T*, T*, int, hipStream_t);                             \
     template nmg_status launch_zero<T>(T*, size_t, hipStream_t);
 NMG_INST(float)
