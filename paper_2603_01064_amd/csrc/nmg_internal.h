@@ -215,7 +215,7 @@ struct Ctx {
     // norms and scratch
     double* nrm = nullptr;             // [max_batch] per right-hand-side norms
     double* nrm2 = nullptr;            // [max_batch] second norm slot
-    double* norm_part = nullptr;       // [max_batch][kNormChunksPerRhs] partial sums
+    double* norm_part = nullptr;       // [max_batch][kResidualNormParts] partial sums
     double* x64 = nullptr;             // [max_batch][ny][n] compacted FP64 iterates (solve)
     double* b64 = nullptr;             // [max_batch][ny][n] compacted FP64 right-hand sides (solve)
     double* slot_d = nullptr;          // [3][max_batch] alpha, ||b||^2, ||r||^2 per compacted slot
@@ -312,11 +312,18 @@ size_t level_elems(const Ctx* c, int l);  // ny_l * n_l
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
-// mode 0: out = y - A x ; mode 1: out = A x
+constexpr int kNormChunksPerRhs = 32;
+// at most this many partial sums of ||out||^2 per image from launch_operator
+constexpr int kResidualNormParts = 64;
+// mode 0: out = y - A x ; mode 1: out = A x.  With norm_part and nparts, the
+// FP32 one-launch form also writes partial sums of ||out||^2, one per 32 x 32
+// block of the image, to norm_part[b][*nparts] (fixed order whatever the
+// batch); *nparts = 0 where it does not (other forms, or more blocks than
+// kResidualNormParts)
 template <typename T>
 nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y,
-                           T* out, int mode, Work<T>& w, hipStream_t s);
-constexpr int kNormChunksPerRhs = 32;
+                           T* out, int mode, Work<T>& w, hipStream_t s, double* norm_part = nullptr,
+                           int* nparts = nullptr);
 template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s);
 // first stage only: c->norm_part[b][kNormChunksPerRhs]

@@ -372,34 +372,37 @@ struct CycleArgs {
     hipStream_t s;
 };
 
-// parts_ready > 0: c->norm_part already holds that many partial sums of
-// ||y||^2 per right-hand side (written by the restriction that produced y)
+// parts_ready > 0 (with x_zero): c->norm_part already holds that many partial
+// sums of ||y||^2 per right-hand side (written by the restriction that
+// produced y)
 template <typename T>
 nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int parts_ready = 0) {
     Ctx* c = a.c;
     Work<T>& w = *a.w;
     const size_t per = level_elems(c, l);
     const T* bres = y;
+    // the BF16 smoother takes ||b||^2 as per-image partial sums, which the
+    // FP32 residual writes itself where it can
+    const bool mfma = c->kind[(size_t)l] == 0 && c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
     if (!x_zero) {
         ProfScope ps(c, a.s, NMG_K_OPERATOR, l);
-        NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, w.lv[(size_t)l].b, 0, w, a.s));
+        NMG_TRY(launch_operator<T>(c, l, a.batch, a.alpha, x, y, w.lv[(size_t)l].b, 0, w, a.s,
+                                   mfma ? c->norm_part : nullptr, mfma ? &parts_ready : nullptr));
         bres = w.lv[(size_t)l].b;
     }
     T* target = a.o.use_fprime ? w.lv[(size_t)l].h : x;
     const int acc = a.o.use_fprime ? 0 : (x_zero ? 0 : 1);
     // the BF16 smoother feeds the MFMA filter F' a zero-padded BF16 plane
     // (in the level's first F' scratch buffer) on levels above 64^2
-    const bool mfma_sm = c->kind[(size_t)l] == 0 && c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
     const int n_l = c->n[(size_t)l], np_l = (n_l + 127) / 128 * 128;
-    const bool bf_plane = !c->dbg_fp32_handoff && mfma_sm && a.o.use_fprime && c->p.dim == 2 && n_l > 64 && mfma_smoother_covers(c, l, np_l) &&
+    const bool bf_plane = !c->dbg_fp32_handoff && mfma && a.o.use_fprime && c->p.dim == 2 && n_l > 64 && mfma_smoother_covers(c, l, np_l) &&
                           (size_t)np_l * np_l * 2 <= level_elems(c, l) * sizeof(T);
     if (c->kind[(size_t)l] == 1) {
         ProfScope ps(c, a.s, NMG_K_SMOOTHER, l);
         NMG_TRY(launch_jacobi<T>(c, l, a.batch, a.alpha, c->omega[(size_t)l], bres, target, acc, w, a.s));
     } else {
         // the BF16 kernel adds the per-image partial sums itself
-        const bool mfma = c->p.smoother_arch != NMG_ARCH_FNO && a.o.precision == NMG_MIXED;
-        const bool have_parts = mfma && x_zero && parts_ready > 0;
+        const bool have_parts = mfma && parts_ready > 0;
         const int nparts = have_parts ? parts_ready : kNormChunksPerRhs;
         if (!have_parts) {
             ProfScope ps(c, a.s, NMG_K_NORM, l);
@@ -1002,7 +1005,8 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     c->cache_used.assign((size_t)B, -1);
     NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
-    NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kNormChunksPerRhs));
+    static_assert(kResidualNormParts >= kNormChunksPerRhs, "norm partial rows");
+    NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kResidualNormParts));
 
     NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
     NMG_TRY(dev_alloc(&c->active, (size_t)B));

@@ -505,11 +505,13 @@ __device__ inline void row_corners(const T* row, int off, const T* cs, int rc, i
     for (int o = 0; o < 4; ++o) acc[o] += (j + o < rc) ? cl[o] : cr[o];
 }
 
+constexpr int kNormBlock = 32;  // side of the blocks of the residual's norm partials
+
 template <typename T, int TH, int TW, int TP, int OC, int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) k_residual_fixed(
     const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ out, const double* __restrict__ alpha, int n,
     int mode, const T* __restrict__ tg, int rg, const T* __restrict__ dtl, const T* __restrict__ dbr, int rc,
-    const T* __restrict__ tm, int m_ident, int tiles_x) {
+    const T* __restrict__ tm, int m_ident, int tiles_x, double* __restrict__ part = nullptr) {
     constexpr int XH = TH + TP, XW = TW + TP;     // staged rows / columns (image i0 - rg + r, j0 - rg + c)
     constexpr int CG = TW / 4;                     // row-pass items per row (4 outputs each)
     constexpr int RITEMS = (XH * CG + NT - 1) / NT;
@@ -649,6 +651,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     __syncthreads();
     // ---- column pass and combination
     const T a = (T)alpha[b];
+    // sums of squares of the outputs per 4-row chunk of a column (OC / 4
+    // chunks per item), for the norm partials below
+    static_assert(OC % 4 == 0 && TH % kNormBlock == 0 && TW % kNormBlock == 0, "norm blocks");
+    double sq4[CPT][OC / 4];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q)
+#pragma unroll
+        for (int c4 = 0; c4 < OC / 4; ++c4) sq4[q][c4] = 0.0;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
         const int item = tid + q * NT;
@@ -704,7 +714,45 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
             }
             const T ax = a * mv[o] + (g[o] + corr);
             const size_t idx = (size_t)b * per + (size_t)i * n + j;
-            out[idx] = mode == 0 ? yv[q][o] - ax : ax;
+            const T r = mode == 0 ? yv[q][o] - ax : ax;
+            out[idx] = r;
+            sq4[q][o / 4] += (double)r * (double)r;
+        }
+    }
+    // With part: ||out||^2 partials, one per 32 x 32 block of the image (row
+    // stride (n + 31) / 32), each in one fixed order whatever the tile shape:
+    // the 4-row chunk sums of the block's 8 x 32 (chunk row, column) positions
+    // t = chunk row * 32 + column, added by a binary tree over t.  A 32 x 32
+    // tile holds one block (thread t owns position t), a 128 x 64 tile eight,
+    // so the partials of an image do not depend on the launch's tile shape.
+    if (part) {
+        constexpr int BX = TW / kNormBlock, NB = (TH / kNormBlock) * BX, BP = kNormBlock * kNormBlock / 4;
+        __syncthreads();  // every thread is done with the staged tile
+        double* red = reinterpret_cast<double*>(smem_raw);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int item = tid + q * NT;
+            if (item >= CITEMS) continue;
+            const int ii = (item / TW) * OC, jj = item % TW;
+#pragma unroll
+            for (int c4 = 0; c4 < OC / 4; ++c4) {
+                const int lr = ii + 4 * c4;
+                const int blk = (lr / kNormBlock) * BX + jj / kNormBlock;
+                red[blk * BP + ((lr % kNormBlock) / 4) * kNormBlock + jj % kNormBlock] = sq4[q][c4];
+            }
+        }
+        __syncthreads();
+        for (int h = BP / 2; h > 0; h >>= 1) {
+            for (int e = tid; e < NB * h; e += NT) {
+                const int blk = e / h, t = e - blk * h;
+                red[blk * BP + t] += red[blk * BP + t + h];
+            }
+            __syncthreads();
+        }
+        const int nbx = (n + kNormBlock - 1) / kNormBlock;
+        for (int blk = tid; blk < NB; blk += NT) {
+            const int by = i0 / kNormBlock + blk / BX, bxg = j0 / kNormBlock + blk % BX;
+            if (by < nbx && bxg < nbx) part[(size_t)b * nbx * nbx + (size_t)by * nbx + bxg] = red[blk * BP];
         }
     }
 }
@@ -954,8 +1002,9 @@ constexpr int tile_h() { return 64; }
 
 template <typename T>
 nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y, T* out,
-                           int mode, Work<T>& w, hipStream_t s) {
+                           int mode, Work<T>& w, hipStream_t s, double* norm_part, int* nparts) {
     const int n = c->n[l];
+    if (nparts) *nparts = 0;
     const size_t per = level_elems(c, l);
     const HostLevel& hl = c->host[l];
     const TiledOp<T>& op = w.tiled[(size_t)l];
@@ -1016,11 +1065,19 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
             constexpr int OC = CFG == 2 ? 8 : 4, NT = CFG == 2 ? 512 : 256;
             constexpr int WPE = CFG == 2 ? 4 : 1;
             const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
-            const size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW) +
-                                2 * (size_t)op.rc * op.rc) * sizeof(T);
+            size_t lds = ((size_t)(TH + TP) * (TW + TP) + (op.m_ident ? 0 : (size_t)(TH + 4) * TW) +
+                          2 * (size_t)op.rc * op.rc) * sizeof(T);
+            // the norm partials reuse the tile's LDS: (TH / 32) * (TW / 32) blocks of 256 doubles
+            const int nb = (n + kNormBlock - 1) / kNormBlock;
+            double* part = norm_part && nparts && nb * nb <= kResidualNormParts ? norm_part : nullptr;
+            if (part) {
+                lds = std::max(lds, (size_t)(TH / kNormBlock) * (TW / kNormBlock) * kNormBlock * kNormBlock / 4 *
+                                        sizeof(double));
+                *nparts = nb * nb;
+            }
             hipLaunchKernelGGL((k_residual_fixed<T, TH, TW, TP, OC, NT, WPE>), dim3(tiles_x * tiles_y, batch), dim3(NT),
                                lds, s, x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
-                               op.m_ident, tiles_x);
+                               op.m_ident, tiles_x, part);
         };
         auto go = [&](auto tp_tag) {
             constexpr int TP = decltype(tp_tag)::value;
@@ -1225,7 +1282,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
 
 #define NMG_INST(T)                                                                                              \
     template nmg_status launch_operator<T>(const Ctx*, int, int, const double*, const T*, const T*, T*, int,     \
-                                           Work<T>&, hipStream_t);                                               \
+                                           Work<T>&, hipStream_t, double*, int*);                                \
     template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t);                \
     template nmg_status launch_sumsq_part<T>(const Ctx*, int, size_t, const T*, hipStream_t);                    \
     template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t, double*);            \
