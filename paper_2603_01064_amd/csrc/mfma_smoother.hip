@@ -44,7 +44,10 @@ inline uint16_t f2bf(float f) {
 }
 
 // Activation buffers hold 32 BF16 channels per pixel (64 B) in four chunks of
-// 8 channels; chunk g of pixel (row r, column c) sits at
+// 8 channels, chunk g holding channels 4g .. 4g + 3 and 16 + 4g .. 16 + 4g + 3
+// (what lane group g of a 16x16 MFMA tile over the 32 channels holds, so a
+// lane writes its chunk with one 16-byte store); chunk g of pixel (row r,
+// column c) sits at
 //   (r * P + c) * 64 + ((g ^ ((c >> 1) & 3)) << 4),
 // so any 8 consecutive pixels put a given chunk in 8 distinct 16-byte bank
 // slots and a 16-lane operand read is conflict-free.  The pitch P is a
@@ -57,7 +60,8 @@ __device__ inline int act_addr(int r, int c, int g) { return (r * kP + c) * 64 +
 
 // Packed weight block (uint16 bf16) per (level, set):
 //   first : [nb 2][lane 64][4]          co = nb*16 + lane%16, tap (dy, dx) = (lane/16, j), 0 if dy or dx is 3
-//   hidden: [layer][tap 9][nb 2][lane 64][8]  co = nb*16 + lane%16, ci = 8*(lane/16)+j
+//   hidden: [layer][tap 9][nb 2][lane 64][8]  co = nb*16 + lane%16, ci = 4*(lane/16)+j (j < 4),
+//                                       16+4*(lane/16)+j-4 (j >= 4): the accumulator order
 //   last  : [lane 64][8]                t = lane%16 (0 if >= 9), ci = 4*(lane/16)+j (j < 4),
 //                                       16+4*(lane/16)+j-4 (j >= 4): the accumulator order
 constexpr int kFirstElems = 2 * 64 * 4;
@@ -199,24 +203,18 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
         for (int h = 0; h < NH; ++h) load_hidden(h, h);
     const bf16x8 wl = wload(lane * 16, kFirstElems + NH * kHiddenElems);
     // per-lane constants for 16-aligned pixel groups (column = 16 k + ln): the
-    // operand chunk offsets of pixels ln, ln+1, ln+2 and the output chunk
-    // offsets of channels nb*16 + 4*lg .. +3
+    // operand chunk offsets of pixels ln, ln+1, ln+2; the output chunk of a
+    // lane is its operand chunk of pixel ln (chunk lg)
     const int swz0 = swz(ln, lg), swz1 = swz(ln + 1, lg), swz2 = swz(ln + 2, lg);
     // first-layer record offsets of this lane (tap row dy = min(lane/16, 2)):
     // row groups read pixel ln of a row, column groups row ln of a column
     const int rec_row = (min(lg, 2) * G::RW + ln) * 8;
     const int rec_col = ((ln + min(lg, 2)) * G::RW) * 8;
-    int out_off[2];
-    for (int nb = 0; nb < 2; ++nb) {
-        const int co = nb * 16 + lg * 4;
-        out_off[nb] = swz(ln, co >> 3) + (co & 7) * 2;
-    }
     // first-layer row group k of this wave is group wave + 4 k: row (wave >> 1) + 2 k,
     // pixels (wave & 1) * 16 + ln, so its operand and output addresses are these
     // per-lane bases plus a multiple of k that fits an LDS immediate offset
     const int rec_wave = rec_row + ((wave >> 1) * G::RW + (wave & 1) * 16) * 8;
-    int st_wave[2];
-    for (int nb = 0; nb < 2; ++nb) st_wave[nb] = ((wave >> 1) * kP + (wave & 1) * 16 + ln) * 64 + out_off[nb];
+    const int st_wave = ((wave >> 1) * kP + (wave & 1) * 16 + ln) * 64 + swz0;
 
     const size_t per = (size_t)n * n;
     const float* src = bres + (size_t)img * per;
@@ -320,14 +318,14 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                         const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
                         inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
                     }
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb) {
-                        // row groups start at a multiple of 16 pixels: the swizzle is the lane's
-                        const int co = nb * 16 + lg_t * 4;
-                        char* o = rowg ? bufA + st_wave[nb] + k * (2 * kP * 64)
-                                       : bufA + (ry * kP + rx) * 64 + swz(rx, co >> 3) + (co & 7) * 2;
-                        *reinterpret_cast<uint2*>(o) = inside ? relu_pack4(acc[nb]) : make_uint2(0u, 0u);
-                    }
+                    // the lane's eight channels (4 lg .. 4 lg + 3, 16 + 4 lg .. 16 + 4 lg + 3)
+                    // are chunk lg of the pixel in the order the hidden weights are
+                    // packed: one 16-byte store (row groups start at a multiple of 16
+                    // pixels, so the swizzle is the lane's)
+                    char* o = rowg ? bufA + st_wave + k * (2 * kP * 64) : bufA + (ry * kP + rx) * 64 + swz(rx, lg_t);
+                    const uint2 p0 = inside ? relu_pack4(acc[0]) : make_uint2(0u, 0u);
+                    const uint2 p1 = inside ? relu_pack4(acc[1]) : make_uint2(0u, 0u);
+                    *reinterpret_cast<uint4*>(o) = make_uint4(p0.x, p0.y, p1.x, p1.y);
                 };
                 if constexpr (NL == 3) {
                     // all of a wave's groups are independent: operands first, then the
@@ -455,11 +453,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
                                 const int gy = ty0 - HALO + ry, gx = tx0 - HALO + rx;
                                 inside = gy >= 0 && gy < n && gx >= 0 && gx < n;
                             }
-                            char* o = aout + (ry * kP + rx) * 64;
-                            *reinterpret_cast<uint2*>(o + out_off[0]) =
-                                inside ? relu_pack4(acc[r][0]) : make_uint2(0u, 0u);
-                            *reinterpret_cast<uint2*>(o + out_off[1]) =
-                                inside ? relu_pack4(acc[r][1]) : make_uint2(0u, 0u);
+                            const uint2 p0 = inside ? relu_pack4(acc[r][0]) : make_uint2(0u, 0u);
+                            const uint2 p1 = inside ? relu_pack4(acc[r][1]) : make_uint2(0u, 0u);
+                            *reinterpret_cast<uint4*>(aout + (ry * kP + rx) * 64 + swz0) =
+                                make_uint4(p0.x, p0.y, p1.x, p1.y);
                         }
                     }
                 };
@@ -574,13 +571,17 @@ nmg_status repack_bf16(Ctx* c, int level, int weight_set) {
                 const int co = nb * 16 + lane % 16, dy = lane / 16, dx = j;
                 pk[(size_t)(nb * 64 + lane) * 4 + j] = (dy < 3 && dx < 3) ? f2bf(w1[co * 9 + dy * 3 + dx]) : 0;
             }
+    // hidden layers: K slot (lane/16, j) is the input channel that the previous
+    // layer's accumulators hold there, 4 (lane/16) + j, then 16 + 4 (lane/16) + j - 4
+    // (each layer stores them as one 16-byte chunk per pixel)
     for (int h = 0; h < NH; ++h) {
         const float* wh = w.data() + c->layer_off[1 + h];  // [32][32][3][3]
         for (int t = 0; t < 9; ++t)
             for (int nb = 0; nb < 2; ++nb)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int j = 0; j < 8; ++j) {
-                        const int co = nb * 16 + lane % 16, ci = 8 * (lane / 16) + j;
+                        const int g = lane / 16;
+                        const int co = nb * 16 + lane % 16, ci = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
                         pk[kFirstElems + (size_t)h * kHiddenElems + (size_t)((t * 2 + nb) * 64 + lane) * 8 + j] =
                             f2bf(wh[(co * kC + ci) * 9 + t]);
                     }
