@@ -218,13 +218,19 @@ struct Ctx {
     double* norm_part = nullptr;       // [max_batch][kResidualNormParts] partial sums
     double* x64 = nullptr;             // [max_batch][ny][n] compacted FP64 iterates (solve)
     double* b64 = nullptr;             // [max_batch][ny][n] compacted FP64 right-hand sides (solve)
-    double* slot_d = nullptr;          // [3][max_batch] alpha, ||b||^2, ||r||^2 per compacted slot
-    int* slot_i = nullptr;             // [2][max_batch] weight set, factor index; then [2][max_batch] x 2 move lists
-    // pinned host staging of the engine (rewritten only after a stream sync):
-    // pin_d [3B] slot tables, [B] residual norms, [B] right-hand-side norms;
-    // pin_i [6B] slot tables and move lists; pin_ptr [B] destinations
+    // slot tables, one device block: slot_d [3][max_batch] alpha, ||b||^2,
+    // ||r||^2 per compacted slot, then slot_i [2][max_batch] weight set, factor
+    // index and [2][max_batch] x 2 move lists (slot_i points into slot_d's block)
+    double* slot_d = nullptr;
+    int* slot_i = nullptr;
+    // pinned host staging of the engine (rewritten only after a stream sync),
+    // one block laid out like the device one, so the per-iteration tables go
+    // up in one copy: pin_d [3B] slot tables, pin_i [6B] slot tables and move
+    // lists, then pin_rd [B] residual norms, [B] right-hand-side norms read
+    // back; pin_ptr [B] destinations
     double* pin_d = nullptr;
     int* pin_i = nullptr;
+    double* pin_rd = nullptr;
     double** pin_ptr = nullptr;
     double** xptr_dev = nullptr;       // [max_batch] destinations of finished iterates
     Engine eng;

@@ -712,8 +712,8 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     k = (int)E.slot.size();
     if (k == 0) return NMG_OK;
     // ---- residual norms of every active slot (new ones: ||b||^2)
-    double* rn2 = h->pin_d + 3 * B;
-    double* bn2n = h->pin_d + 4 * B;
+    double* rn2 = h->pin_rd;
+    double* bn2n = h->pin_rd + B;
     NMG_HIP(hipMemcpyAsync(rn2, h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
     if (m > 0)
         NMG_HIP(hipMemcpyAsync(bn2n, (plain32 ? h->nrm : h->nrm2) + (k - m), (size_t)m * sizeof(double),
@@ -814,8 +814,10 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         hi[(size_t)i] = sl.ws;
         hi[(size_t)B + i] = sl.fidx;
     }
-    NMG_HIP(hipMemcpyAsync(h->slot_d, hd, (size_t)3 * B * sizeof(double), hipMemcpyHostToDevice, s));
-    NMG_HIP(hipMemcpyAsync(h->slot_i, hi, (size_t)2 * B * sizeof(int), hipMemcpyHostToDevice, s));
+    // the three double tables and the first two int tables in one transfer
+    // (the host block is laid out like the device one)
+    NMG_HIP(hipMemcpyAsync(h->slot_d, hd, (size_t)3 * B * sizeof(double) + (size_t)2 * B * sizeof(int),
+                           hipMemcpyHostToDevice, s));
     h->cycle_fidx = d_fidx;
     const int* wsd = E.any_ws ? d_ws : nullptr;
     auto residual = [&](int kk, hipStream_t st) -> nmg_status {
@@ -1012,11 +1014,13 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     NMG_TRY(dev_alloc(&c->active, (size_t)B));
     NMG_TRY(dev_alloc(&c->x64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->b64, (size_t)B * level_elems(c.get(), 0)));
-    NMG_TRY(dev_alloc(&c->slot_d, (size_t)3 * B));
-    NMG_TRY(dev_alloc(&c->slot_i, (size_t)6 * B));
+    // 3B doubles, then 6B ints (= 3B doubles' bytes)
+    NMG_TRY(dev_alloc(&c->slot_d, (size_t)6 * B));
+    c->slot_i = reinterpret_cast<int*>(c->slot_d + (size_t)3 * B);
     NMG_HIP(hipMalloc((void**)&c->xptr_dev, (size_t)B * sizeof(double*)));
-    NMG_HIP(hipHostMalloc((void**)&c->pin_d, (size_t)5 * B * sizeof(double), hipHostMallocDefault));
-    NMG_HIP(hipHostMalloc((void**)&c->pin_i, (size_t)6 * B * sizeof(int), hipHostMallocDefault));
+    NMG_HIP(hipHostMalloc((void**)&c->pin_d, (size_t)8 * B * sizeof(double), hipHostMallocDefault));
+    c->pin_i = reinterpret_cast<int*>(c->pin_d + (size_t)3 * B);
+    c->pin_rd = c->pin_d + (size_t)6 * B;
     NMG_HIP(hipHostMalloc((void**)&c->pin_ptr, (size_t)B * sizeof(double*), hipHostMallocDefault));
     NMG_TRY(dev_alloc(&c->r64, (size_t)B * level_elems(c.get(), 0)));
     NMG_TRY(dev_alloc(&c->xs32, (size_t)B * level_elems(c.get(), 0)));
@@ -1079,10 +1083,11 @@ void nmg_destroy(nmg_handle h) {
     dev_free(c->x64);
     dev_free(c->b64);
     dev_free(c->slot_d);
-    dev_free(c->slot_i);
+    c->slot_i = nullptr;
     dev_free(c->xptr_dev);
     if (c->pin_d) (void)hipHostFree(c->pin_d);
-    if (c->pin_i) (void)hipHostFree(c->pin_i);
+    c->pin_i = nullptr;
+    c->pin_rd = nullptr;
     if (c->pin_ptr) (void)hipHostFree(c->pin_ptr);
     dev_free(c->r64);
     dev_free(c->xs32);
