@@ -883,7 +883,22 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     const int rc2 = rc * rc;
     int bx, b;
     xcd_major(bx, b);
-    const int i0 = (bx / tiles_x) * TH, j0 = (bx % tiles_x) * TW;
+    // FP64: tiles numbered column-major, so the tiles that share a column
+    // strip's halo rows (the pass has no horizontal halo) get consecutive
+    // numbers and run together on one XCD, whose L2 serves the overlap; one
+    // 117 KB workgroup per CU sweeping row-major evicts the halo before the
+    // next tile row reads it (2047^2, radius 82: 1.67x the algorithmic bytes
+    // row-major, 1.20x column-major).  FP32 (two workgroups per CU) keeps the
+    // previous tile rows in L2 and does better row-major (1.07x against 1.21x).
+    int i0, j0;
+    if constexpr (sizeof(T) == 8) {
+        const int tiles_y = (n + TH - 1) / TH;
+        i0 = (bx % tiles_y) * TH;
+        j0 = (bx / tiles_y) * TW;
+    } else {
+        i0 = (bx / tiles_x) * TH;
+        j0 = (bx % tiles_x) * TW;
+    }
     const size_t per = (size_t)n * n;
     const T* tgs = tg + (size_t)b * per;
     const int tid = threadIdx.x;
