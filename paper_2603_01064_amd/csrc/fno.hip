@@ -27,6 +27,7 @@ namespace nmg {
 namespace {
 
 constexpr int kBlock = 256;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -479,6 +480,104 @@ __global__ void __launch_bounds__(256) k_fno_layer_out_t2(
     }
 }
 
+// The layer's ks x ks convolution in FP32 on MFMA (float only): an implicit
+// GEMM with the output channel as M (MB blocks of 16), 16 pixels of a row as N
+// and K = 4 input channels at one tap per v_mfma_f32_16x16x4f32 (FP32 inputs,
+// FP32 accumulation: the precision of the VALU kernels, at twice the
+// non-packed VALU rate).  A workgroup owns a 32 x 8 pixel tile of one image
+// and all C output channels; wave w takes rows 2w and 2w + 1, both 16-pixel
+// halves (four N blocks).  Input channels are staged four at a time with the
+// tile's halo (zero outside the image), and their weights from the per-set
+// [ci][tap][co] copy (k_fno_wt).  Epilogue as in k_fno_layer_out_t2:
+// z1 = GELU(spectral part + convolution + bias).
+constexpr int kMW = 32, kMH = 8, kMCI = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fno_wt(const T* __restrict__ wl, size_t stride, size_t w_off, int nsets,
+                                                   int C, int KK, T* __restrict__ out) {
+    const size_t per_set = (size_t)C * KK * C;
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= per_set * nsets) return;
+    const size_t set = e / per_set, r = e - set * per_set;
+    const int ci = (int)(r / ((size_t)KK * C)), t = (int)((r / C) % KK), co = (int)(r % C);
+    out[e] = wl[set * stride + w_off + ((size_t)co * C + ci) * KK + t];
+}
+
+template <int KS, int MB>
+__global__ void __launch_bounds__(256) k_fno_layer_out_mfma(
+    const float* __restrict__ z0, float* __restrict__ z1, const float* __restrict__ sp_plane,
+    const float* __restrict__ wl, size_t stride, size_t w_off, const float* __restrict__ wt,
+    const int* __restrict__ ws, int nsets, int n, int tiles_x) {
+    constexpr int C = 16 * MB, R = KS / 2, KK = KS * KS;
+    constexpr int SW = kMW + 2 * R, SH = kMH + 2 * R;  // staged columns / rows
+    constexpr int IN_E = kMCI * SH * SW;               // staged input floats
+    constexpr int W_E = kMCI * KK * C;                 // staged weight floats
+    __shared__ float tin[IN_E];
+    __shared__ float tw[W_E];
+    const int img = blockIdx.y;
+    const int ty0 = (blockIdx.x / tiles_x) * kMH, tx0 = (blockIdx.x % tiles_x) * kMW;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l16 = lane & 15, kq = lane >> 4;
+    const size_t per = (size_t)n * n;
+    const int set = ws ? min(max(ws[img], 0), nsets - 1) : 0;
+    const float* wts = wt + (size_t)set * C * KK * C;
+    floatx4 acc[4][MB];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // operand bases of this lane: B = staged input of channel kq, row 2 wave
+    // (+ N block row + dy), column l16 (+ 16 x half + dx); A = staged weight of
+    // channel kq, output channel l16 (+ 16 mb), tap 0
+    const int bbase = (kq * SH + 2 * wave) * SW + l16;
+    const int abase = kq * KK * C + l16;
+    for (int c0 = 0; c0 < C; c0 += kMCI) {
+        __syncthreads();  // every wave is done with the previous chunk
+        for (int e = tid; e < IN_E; e += 256) {
+            const int cc = e / (SH * SW), rem = e - cc * (SH * SW), sy = rem / SW, sx = rem - sy * SW;
+            const int gy = ty0 - R + sy, gx = tx0 - R + sx;
+            tin[e] = (gy >= 0 && gy < n && gx >= 0 && gx < n)
+                         ? z0[((size_t)img * C + c0 + cc) * per + (size_t)gy * n + gx]
+                         : 0.f;
+        }
+        const float* wsrc = wts + (size_t)c0 * KK * C;
+        for (int e = tid; e < W_E; e += 256) tw[e] = wsrc[e];
+        __syncthreads();
+#pragma unroll
+        for (int dy = 0; dy < KS; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < KS; ++dx) {
+                float a[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) a[mb] = tw[abase + (dy * KS + dx) * C + 16 * mb];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    const float b = tin[bbase + ((nb >> 1) + dy) * SW + 16 * (nb & 1) + dx];
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb], b, acc[nb][mb], 0, 0, 0);
+                }
+            }
+    }
+    // acc[nb][mb][i]: output channel 16 mb + 4 kq + i of pixel (row 2 wave + (nb >> 1),
+    // column 16 (nb & 1) + l16)
+    const float* bias = set_block(wl, stride, ws, nsets, img) + w_off + (size_t)C * C * KK;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int y = ty0 + 2 * wave + (nb >> 1), x = tx0 + 16 * (nb & 1) + l16;
+        if (y >= n || x >= n) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = 16 * mb + 4 * kq + i;
+                const size_t o = ((size_t)img * C + co) * per + (size_t)y * n + x;
+                z1[o] = gelu(sp_plane[o] + acc[nb][mb][i] + bias[co]);
+            }
+    }
+}
+
 // h = ||b|| (sum_c proj_w[c] z[c] + proj_b), written or accumulated into dst
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fno_project(const T* __restrict__ z, const double* __restrict__ nrm2,
@@ -826,6 +925,10 @@ nmg_status ensure_fno(Ctx* c) {
     NMG_TRY(falloc(&w.fyh, B * C * modes * 2));
     NMG_TRY(falloc(&w.fcd, B * C * ny0 * m * 2));
     NMG_TRY(falloc(&w.fsp, B * C * per0));
+    if (c->p.dim == 2) {
+        const size_t kk = (size_t)c->p.fno_ksize * c->p.fno_ksize;
+        NMG_TRY(falloc(&w.fwt, (size_t)std::max(1, c->p.n_weight_sets) * C * C * kk));
+    }
     (void)n0;
     std::vector<double> tab;
     w.ftab_off.clear();
@@ -928,7 +1031,32 @@ nmg_status launch_fno_smoother(const Ctx* c, int l, int batch, const int* ws, co
             cdp = w.fcd;
         }
         bool done = false;
-        if (t2) {
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32 MFMA for 32 or 64 channels and 3 x 3, 5 x 5, 7 x 7 kernels
+            if (t2 && w.fwt && (C == 32 || C == 64)) {
+                const size_t ww = (size_t)nsets * C * C * d.kk;
+                hipLaunchKernelGGL(k_fno_wt<float>, dim3(blocks_for(ww)), dim3(kBlock), 0, s, wl, stride,
+                                   base + 2 * d.rm, nsets, C, d.kk, w.fwt);
+                const int tiles_x = (n + kMW - 1) / kMW, tiles_y = (n + kMH - 1) / kMH;
+                const dim3 grid((unsigned)(tiles_x * tiles_y), (unsigned)batch);
+                auto go = [&](auto ks_tag, auto mb_tag) {
+                    constexpr int KS = decltype(ks_tag)::value, MB = decltype(mb_tag)::value;
+                    hipLaunchKernelGGL((k_fno_layer_out_mfma<KS, MB>), grid, dim3(256), 0, s, z0, z1, w.fsp, wl,
+                                       stride, base + 2 * d.rm, w.fwt, ws, nsets, n, tiles_x);
+                };
+                auto by_ks = [&](auto mb_tag) {
+                    if (d.ks == 3) go(std::integral_constant<int, 3>{}, mb_tag);
+                    if (d.ks == 5) go(std::integral_constant<int, 5>{}, mb_tag);
+                    if (d.ks == 7) go(std::integral_constant<int, 7>{}, mb_tag);
+                };
+                if (C == 32)
+                    by_ks(std::integral_constant<int, 2>{});
+                else
+                    by_ks(std::integral_constant<int, 4>{});
+                done = true;
+            }
+        }
+        if (!done && t2) {
             const int tiles_x = (n + kFT2 - 1) / kFT2;
             constexpr int CI = sizeof(T) == 4 ? 8 : 4;
             auto go = [&](auto ks_tag) {

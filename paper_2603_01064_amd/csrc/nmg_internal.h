@@ -116,6 +116,7 @@ struct Work {
     T* ftab = nullptr;
     std::vector<size_t> ftab_off;
     T* fsp = nullptr;             // spectral part of a layer's output [B][C][per0]
+    T* fwt = nullptr;             // one layer's convolution weights as [set][ci][tap][co] (2D)
     // FNO training: per-layer activations Z_0..Z_NL, pre-activations, spectra,
     // and the adjoint's work planes
     bool ftr_ready = false;

@@ -309,6 +309,7 @@ void free_work(Ctx* c, Work<T>& w) {
     dev_free(w.fcd);
     dev_free(w.ftab);
     dev_free(w.fsp);
+    dev_free(w.fwt);
     dev_free(w.fmat);
     dev_free(w.ftz);
     dev_free(w.ftp);

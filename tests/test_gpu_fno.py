@@ -43,13 +43,15 @@ def _rel(a, b):
 @pytest.mark.parametrize("dim,n,s,L,arch", [(2, 63, 0.04, 3, (8, 2, 8, 3)), (2, 31, 0.05, 3, (4, 3, 12, 5)),
                                             (1, 127, 0.02, 3, (6, 2, 16, 5)), (2, 63, 0.04, 3, (32, 2, 8, 5)),
                                             (2, 63, 0.04, 3, (16, 2, 6, 3)), (2, 63, 0.04, 3, (16, 1, 6, 7)),
-                                            (2, 31, 0.05, 3, (16, 1, 4, 9))])
+                                            (2, 31, 0.05, 3, (16, 1, 4, 9)), (2, 63, 0.04, 3, (32, 1, 6, 3)),
+                                            (2, 31, 0.05, 3, (32, 1, 4, 7)), (2, 63, 0.04, 3, (64, 1, 6, 3))])
 def test_fno_smoother_every_level(dim, n, s, L, arch):
     """Mode counts clamp on the coarse levels (k_l = min(k, n_l / 2)).  Widths
     that are multiples of 16 run the LDS-tiled 2D layer kernels: 32 x 32
     tiles with 2 x 2 pixels per thread for 3 x 3, 5 x 5 and 7 x 7
-    convolutions, 16 x 16 tiles otherwise (9 x 9 here); the tiles are ragged
-    at 63 and 31."""
+    convolutions, 16 x 16 tiles otherwise (9 x 9 here); in FP32, widths 32
+    and 64 with those three kernel sizes run the MFMA layer kernel (32 x 8
+    tiles); the tiles are ragged at 63 and 31."""
     print(f"case FNO smoother dim={dim} n={n} arch={arch}", flush=True)
     dev = torch.device("cuda:0")
     h, H, params = _setup(dim, n, s, L, arch)
@@ -118,6 +120,29 @@ def test_fno_weight_sets_per_rhs():
         ref = O.fno_smoother(_oracle_params(params[int(ws[i])][0]), dim, arch[2])(H, 0, b[i:i + 1].cpu(),
                                                                                    alpha[i:i + 1].cpu())
         assert _rel(both[i:i + 1].cpu(), ref) < 1e-12
+    h.close()
+
+
+def test_fno_weight_sets_per_rhs_fp32_mfma():
+    """Per-right-hand-side weight sets on the FP32 MFMA layer kernel (width
+    32): each image takes its set's copy of the convolution weights; batched
+    results equal solo runs bit for bit and match the oracle to 1e-5."""
+    print("case FNO per-RHS weight sets, FP32 MFMA layer kernel", flush=True)
+    dev = torch.device("cuda:0")
+    dim, n, s, L, arch = 2, 63, 0.04, 3, (32, 2, 6, 5)
+    h, H, params = _setup(dim, n, s, L, arch, B=3, sets=2, seed=7900)
+    b = torch.randn(3, n, n, dtype=DT, generator=torch.Generator().manual_seed(53)).float().double()
+    alpha = torch.tensor([1e-2, 1e-3, 1e-2], dtype=DT)
+    ws = torch.tensor([1, 0, 1], dtype=torch.int32, device=dev)
+    both = h.apply_smoother(0, b.float().to(dev), alpha.to(dev), weight_set=ws, precision="fp32")
+    for i in range(3):
+        solo = h.apply_smoother(0, b[i:i + 1].float().to(dev), alpha[i:i + 1].to(dev), weight_set=ws[i:i + 1],
+                                precision="fp32")
+        assert torch.equal(solo[0], both[i])
+        ref = O.fno_smoother(_oracle_params(params[int(ws[i])][0]), dim, arch[2])(H, 0, b[i:i + 1], alpha[i:i + 1])
+        err = _rel(both[i:i + 1].cpu().double(), ref)
+        print(f"  rhs {i} set {int(ws[i])}: fp32 rel err {err:.2e}", flush=True)
+        assert err < 1e-5
     h.close()
 
 
