@@ -216,7 +216,7 @@ struct Ctx {
     // norms and scratch
     double* nrm = nullptr;             // [max_batch] per right-hand-side norms
     double* nrm2 = nullptr;            // [max_batch] second norm slot
-    double* norm_part = nullptr;       // [max_batch][kResidualNormParts] partial sums
+    double* norm_part = nullptr;       // [max_batch][max(kResidualNormParts, kNormChunksMax)] partial sums
     double* x64 = nullptr;             // [max_batch][ny][n] compacted FP64 iterates (solve)
     double* b64 = nullptr;             // [max_batch][ny][n] compacted FP64 right-hand sides (solve)
     // slot tables, one device block: slot_d [3][max_batch] alpha, ||b||^2,
@@ -320,6 +320,14 @@ size_t level_elems(const Ctx* c, int l);  // ny_l * n_l
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 constexpr int kNormChunksPerRhs = 32;
+// chunks of the two-stage norm of an image of `per` elements: 32 up to 511^2,
+// more on larger images so that the first stage fills the GPU at small
+// batches; a function of the image size only, so the partial sums (and the
+// norm) do not depend on the batch
+constexpr int kNormChunksMax = 256;
+inline int norm_chunks(size_t per) {
+    return per >= ((size_t)1 << 21) ? 256 : per >= ((size_t)1 << 19) ? 64 : kNormChunksPerRhs;
+}
 // at most this many partial sums of ||out||^2 per image from launch_operator
 constexpr int kResidualNormParts = 64;
 // mode 0: out = y - A x ; mode 1: out = A x.  With norm_part and nparts, the
@@ -333,7 +341,7 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
                            int* nparts = nullptr);
 template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s);
-// first stage only: c->norm_part[b][kNormChunksPerRhs]
+// first stage only: c->norm_part[b][norm_chunks(elems)]
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s);
 template <typename T>

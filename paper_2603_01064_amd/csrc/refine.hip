@@ -13,7 +13,8 @@ constexpr int kBlock = 256;
 
 // One block per (chunk, right-hand side) with the chunks of the norm
 // partials: block ch covers elements [ch len, (ch + 1) len) of the image,
-// len = ceil(per / kNormChunksPerRhs), and with part it also writes the sum
+// len = ceil(per / norm_chunks(per)) (the grid's x size), and with part it
+// also writes the sum
 // of squares of its outputs (each thread's elements in order, then a fixed
 // tree), the first stage of ||y||^2 for the cycle's first BF16 smoothing
 // step, in the same order as a separate partial-sum pass over y.
@@ -23,12 +24,12 @@ __global__ void __launch_bounds__(kBlock) k_refine_scale(const R* __restrict__ r
                                                          double tol2, int* __restrict__ active, size_t per,
                                                          double* __restrict__ part) {
     __shared__ double red[kBlock];
-    const int b = blockIdx.y, ch = blockIdx.x;
+    const int b = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
     const double q = rn2[b];
     const bool act = (q > tol2 * bn2[b]) && isfinite(q);
     if (ch == 0 && threadIdx.x == 0) active[b] = act ? 1 : 0;
     const double inv = act ? 1.0 / sqrt(q) : 0.0;
-    const size_t len = (per + kNormChunksPerRhs - 1) / kNormChunksPerRhs;
+    const size_t len = (per + nch - 1) / nch;
     const size_t e0 = (size_t)ch * len, e1 = e0 + len < per ? e0 + len : per;
     const R* src = r + (size_t)b * per;
     T* dst = y + (size_t)b * per;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_scale(const R* __restrict__ r
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(size_t)b * kNormChunksPerRhs + ch] = red[0];
+    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = red[0];
 }
 
 template <typename X, typename T>
@@ -138,7 +139,7 @@ template nmg_status launch_scatter_slots<float>(int, size_t, const float*, doubl
 template <typename R, typename T>
 nmg_status launch_refine_scale(int batch, size_t per, const R* r, T* y, const double* rn2, const double* bn2,
                                double rtol, int* active, hipStream_t s, double* part) {
-    dim3 grid((unsigned)kNormChunksPerRhs, batch);
+    dim3 grid((unsigned)norm_chunks(per), batch);
     hipLaunchKernelGGL((k_refine_scale<R, T>), grid, dim3(kBlock), 0, s, r, y, rn2, bn2, rtol * rtol, active, per,
                        part);
     NMG_HIP(hipGetLastError());

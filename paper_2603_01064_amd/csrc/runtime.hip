@@ -404,7 +404,7 @@ nmg_status smooth_step(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, in
     } else {
         // the BF16 kernel adds the per-image partial sums itself
         const bool have_parts = mfma && parts_ready > 0;
-        const int nparts = have_parts ? parts_ready : kNormChunksPerRhs;
+        const int nparts = have_parts ? parts_ready : norm_chunks(per);
         if (!have_parts) {
             ProfScope ps(c, a.s, NMG_K_NORM, l);
             if (mfma)
@@ -857,7 +857,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             // the scaling also writes the first stage of ||y||^2 for the cycle's first smoothing step
             NMG_TRY(launch_refine_scale<double, float>(kk, per, R64, w.lv[0].y, d_rn2, d_bn2, rtol, h->active, st,
                                                        h->norm_part));
-            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st, kNormChunksPerRhs));
+            NMG_TRY(run_cycle<float>(h, kk, d_alpha, wsd, w.lv[0].y, w.lv[0].x, true, *o, st, norm_chunks(per)));
             if (refine_residual_fusable(h, h->w64)) {
                 ProfScope ps(h, st, NMG_K_REFINE, 0);
                 (void)launch_refine_residual<float>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
@@ -1008,8 +1008,7 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     c->cache_used.assign((size_t)B, -1);
     NMG_TRY(dev_alloc(&c->nrm, (size_t)B));
     NMG_TRY(dev_alloc(&c->nrm2, (size_t)B));
-    static_assert(kResidualNormParts >= kNormChunksPerRhs, "norm partial rows");
-    NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * kResidualNormParts));
+    NMG_TRY(dev_alloc(&c->norm_part, (size_t)B * std::max(kResidualNormParts, kNormChunksMax)));
 
     NMG_TRY(dev_alloc(&c->hist_dev, (size_t)B));
     NMG_TRY(dev_alloc(&c->active, (size_t)B));
@@ -1213,7 +1212,7 @@ nmg_status nmg_apply_smoother(nmg_handle h, int level, int batch, const double* 
     if (prec == NMG_MIXED && h->p.smoother_arch != NMG_ARCH_FNO) {
         // as in the cycle: the BF16 kernel adds the per-image partial sums itself
         NMG_TRY(launch_sumsq_part<float>(h, batch, per, bb, s));
-        return launch_mfma_smoother(h, level, batch, ws, bb, h->norm_part, kNormChunksPerRhs, oo, 0, h->w32b, s);
+        return launch_mfma_smoother(h, level, batch, ws, bb, h->norm_part, norm_chunks(per), oo, 0, h->w32b, s);
     }
     NMG_TRY(launch_sumsq<float>(h, batch, per, bb, h->nrm, s));
     if (h->p.smoother_arch == NMG_ARCH_FNO) {

@@ -104,8 +104,8 @@ constexpr int kNormChunks = kNormChunksPerRhs;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, double* __restrict__ part, size_t per) {
     __shared__ double red[kBlock];
-    const int b = blockIdx.y, ch = blockIdx.x;
-    const size_t len = (per + kNormChunks - 1) / kNormChunks;
+    const int b = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+    const size_t len = (per + nch - 1) / nch;
     const size_t e0 = (size_t)ch * len, e1 = e0 + len < per ? e0 + len : per;
     const T* p = v + (size_t)b * per;
     double acc = 0.0;
@@ -119,15 +119,16 @@ __global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, 
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(size_t)b * kNormChunks + ch] = red[0];
+    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = red[0];
 }
 
-// nparts partials per right-hand side (row stride kNormChunks), added in order
-__global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch, int nparts) {
+// nparts partials per right-hand side (row stride `stride`), added in order
+__global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch, int nparts,
+                              int stride) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     double acc = 0.0;
-    for (int c = 0; c < nparts; ++c) acc += part[(size_t)b * kNormChunks + c];
+    for (int c = 0; c < nparts; ++c) acc += part[(size_t)b * stride + c];
     out[b] = acc;
 }
 
@@ -1188,7 +1189,8 @@ bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double
         hipLaunchKernelGGL((k_cols_fixed<double, TP, kRefineTW>), dim3(tiles, batch), dim3(kBlock), lds, s, tg,
                            (const double*)nullptr, x, y, out, alpha, n, 0, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
                            op.m_ident, tiles_x, c->norm_part);
-        hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, c->norm_part, nrm2, batch, tiles);
+        hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, c->norm_part, nrm2, batch, tiles,
+                           kNormChunks);
     };
     go(std::integral_constant<int, 8>{});
     go(std::integral_constant<int, 12>{});
@@ -1212,7 +1214,8 @@ template bool launch_refine_residual<double>(const Ctx*, int, const double*, dou
 
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, c->norm_part, elems);
+    hipLaunchKernelGGL(k_sumsq_part<T>, dim3((unsigned)norm_chunks(elems), batch), dim3(kBlock), 0, s, v,
+                       c->norm_part, elems);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -1220,8 +1223,9 @@ nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, 
 template <typename T>
 nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s) {
     double* part = c->norm_part;
-    hipLaunchKernelGGL(k_sumsq_part<T>, dim3(kNormChunks, batch), dim3(kBlock), 0, s, v, part, elems);
-    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch, kNormChunks);
+    const int nch = norm_chunks(elems);
+    hipLaunchKernelGGL(k_sumsq_part<T>, dim3((unsigned)nch, batch), dim3(kBlock), 0, s, v, part, elems);
+    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch, nch, nch);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
