@@ -952,7 +952,11 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
         T w[OC + 4];
 #pragma unroll
         for (int k = 0; k < OC; ++k) w[k] = col[k * TW];
-#pragma unroll
+        // bands beyond 32 padded taps: 16 taps per unrolled body (fully
+        // unrolled, the compiler holds every tap in scalar registers and
+        // spills them: 44 FP64 taps took 204 VGPRs and two waves per SIMD, 164
+        // FP32 taps 256 and one; unrolled four times, 130 and 82)
+#pragma unroll(TP > 32 ? 4 : TP / 4)
         for (int t4 = 0; t4 < TP; t4 += 4) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[OC + k] = col[(t4 + OC + k) * TW];
@@ -1040,11 +1044,16 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
                                dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(T), s,
                                const_cast<T*>(x), tg, tm, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n,
                                (const T*)nullptr, (const double*)nullptr, (const int*)nullptr);
-            const int tiles_x = (n + 63) / 64, tiles_y = (n + 63) / 64;
-            const size_t lds = ((size_t)(64 + TP) * 64 + (op.m_ident ? 0 : (size_t)68 * 64) +
+            // long bands (84 and 164 padded taps): 32-column strips, half the LDS of
+            // 64 columns at the same halo share, so twice the workgroups per CU hide
+            // the staging latency that bounds this pass (every output's taps are
+            // added in the same order either way)
+            constexpr int CW = TP >= 84 ? 32 : 64;
+            const int tiles_x = (n + CW - 1) / CW, tiles_y = (n + 63) / 64;
+            const size_t lds = ((size_t)(64 + TP) * CW + (op.m_ident ? 0 : (size_t)68 * CW) +
                                 2 * (size_t)op.rc * op.rc) * sizeof(T);
-            hipLaunchKernelGGL((k_cols_fixed<T, TP>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, tg, tm,
-                               x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident,
+            hipLaunchKernelGGL((k_cols_fixed<T, TP, CW>), dim3(tiles_x * tiles_y, batch), dim3(kBlock), lds, s, tg,
+                               tm, x, y, out, alpha, n, mode, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident,
                                tiles_x, (double*)nullptr);
         };
         go2(std::integral_constant<int, 8>{});
