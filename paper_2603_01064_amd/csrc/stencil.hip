@@ -1044,11 +1044,12 @@ nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, 
                                dim3(kBlock), ((size_t)kRowsPerBlock * LW + 2 * (size_t)op.rc * op.rc) * sizeof(T), s,
                                const_cast<T*>(x), tg, tm, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm, op.m_ident, n,
                                (const T*)nullptr, (const double*)nullptr, (const int*)nullptr);
-            // long bands (84 and 164 padded taps): 32-column strips, half the LDS of
-            // 64 columns at the same halo share, so twice the workgroups per CU hide
-            // the staging latency that bounds this pass (every output's taps are
-            // added in the same order either way)
-            constexpr int CW = TP >= 84 ? 32 : 64;
+            // FP64 and long bands (84 and 164 padded taps): 32-column strips, half
+            // the LDS and registers of 64 columns at the same halo share, so more
+            // workgroups per CU hide the staging latency that bounds this pass
+            // (FP64 at 64 columns holds 202-251 VGPRs, two waves per SIMD; every
+            // output's taps are added in the same order either way)
+            constexpr int CW = (sizeof(T) == 8 || TP >= 84) ? 32 : 64;
             const int tiles_x = (n + CW - 1) / CW, tiles_y = (n + 63) / 64;
             const size_t lds = ((size_t)(64 + TP) * CW + (op.m_ident ? 0 : (size_t)68 * CW) +
                                 2 * (size_t)op.rc * op.rc) * sizeof(T);
