@@ -919,6 +919,9 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
         if (p->channels[i] < 1 || p->channels[i] > 256) return fail(NMG_ERR_SHAPE, "channel count out of range");
     if (p->ksize < 1 || (p->ksize & 1) == 0 || p->ksize > 15) return fail(NMG_ERR_SHAPE, "ksize must be odd, <= 15");
     if (p->n_weight_sets < 1 || p->n_weight_sets > 64) return fail(NMG_ERR_SHAPE, "n_weight_sets out of range");
+    // the transfer kernels index a level's points with 32-bit integers
+    if (p->n < 1 || (p->dim == 2 ? (long long)p->n * p->n : (long long)p->n) >= (1LL << 31))
+        return fail(NMG_ERR_SHAPE, "n out of range (a level must hold fewer than 2^31 points)");
     std::unique_ptr<nmg_ctx> c(new nmg_ctx());
     c->p = *p;
     std::string err;

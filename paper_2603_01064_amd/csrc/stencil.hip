@@ -153,8 +153,10 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r, T*
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
     const T* src = r + (size_t)b * perf;
     double sq = 0.0;
-    for (size_t e = (size_t)bx * kBlock + threadIdx.x; e < perc; e += (size_t)gridDim.x * kBlock) {
-        const int i = (int)(e / nc), j = (int)(e % nc);
+    // 32-bit indices (a level holds fewer than 2^31 points): a 64-bit division
+    // per point cost more than the point's arithmetic
+    for (int e = bx * kBlock + (int)threadIdx.x; e < (int)perc; e += (int)gridDim.x * kBlock) {
+        const int i = e / nc, j = e - (e / nc) * nc;
         int ij[3], ii[3];
         T wj[3], wi[3];
         restrict_taps<T>(j, ij, wj);
@@ -209,10 +211,10 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ ec
     const size_t perf = (size_t)(two_d ? nf : 1) * nf;
     int bx, b;
     xcd_major(bx, b);
-    const size_t e = (size_t)bx * kBlock + threadIdx.x;
-    if (e >= perf) return;
+    const int e = bx * kBlock + (int)threadIdx.x;  // 32-bit: a level holds fewer than 2^31 points
+    if (e >= (int)perf) return;
     const size_t perc = (size_t)(two_d ? nc : 1) * nc;
-    const int p = (int)(e / nf), q = (int)(e % nf);
+    const int p = e / nf, q = e - (e / nf) * nf;
     const T* src = ec + (size_t)b * perc;
     int iq[2];
     T wq[2];
