@@ -253,53 +253,71 @@ __global__ void __launch_bounds__(kThreads) k_tr_first_din(const uint16_t* __res
 // Weight-gradient partials of a one-channel layer over a run of rows of one
 // image (workgroup g: image g / wpi, rows [(g % wpi) rpw, + rpw)):
 //   FIRST: dW_1[c][t] = sum_p D[p][c] u[p + off(t)],  u = BF16(b / ||b||)
-//   else : dW_l[c][t] = sum_p d_out[p] a[p + off(t)][c]
-// Thread (group k, channel c) sums the nine taps of channel c over columns
-// k, k + 8, ... of each row; the eight groups are then added in order.
+//   else : dW_l[c][t] = sum_q a[q][c] d_out[q - off(t)]  (q = p + off(t))
+// Both are sum_p A[p][c] B[p][t] with A the 32-channel BF16 record at p and B
+// the one-channel plane shifted by the tap, taken on the FP32 MFMA
+// (v_mfma_f32_16x16x4f32: M = 16 channels, N = the 9 taps padded to 16, K =
+// four pixels of a row), with the FP32 products of the plain loop.  The four
+// waves take every fourth quad of a row, each with two accumulator sets
+// (alternate quads), added in a fixed order at the end.
 // part[blockIdx.x][c * 9 + t] (the layer's [Cout][Cin][3][3] order).
-constexpr int kSmallGroups = kThreads / kC;  // 8
-
 template <int FIRST>
 __global__ void __launch_bounds__(kThreads) k_tr_wgrad_small(const float* __restrict__ plane,
                                                              const double* __restrict__ nrm2,
                                                              const uint16_t* __restrict__ rec,
                                                              float* __restrict__ part, int n, int wpi, int rpw) {
-    __shared__ float red[kSmallGroups][kC * 9];
-    const int c = threadIdx.x % kC, k = threadIdx.x / kC;
+    __shared__ floatx4 red[kThreads / 64][2][64];
     const int img = blockIdx.x / wpi;
     const int y0 = (blockIdx.x % wpi) * rpw, y1 = y0 + rpw < n ? y0 + rpw : n;
     const size_t base = (size_t)img * n * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;  // A: channel m of pixel kq; B: tap m of pixel kq
     float sc = 0.f;
     if constexpr (FIRST) {
         const double nb = sqrt(nrm2[img]);
         sc = nb > 0.0 ? (float)(1.0 / nb) : 0.f;
     }
-    float acc[9];
+    const bool tap_ok = m < 9;
+    const int dy = m / 3 - 1, dx = m % 3 - 1;
+    const int sy = FIRST ? dy : -dy, sx = FIRST ? dx : -dx;  // B reads the plane at p + (sy, sx)
+    const int nq = (n + 3) / 4;
+    floatx4 acc[2][2];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
-    for (int y = y0; y < y1; ++y) {
-#pragma unroll 2
-        for (int x = k; x < n; x += kSmallGroups) {
-            const size_t p = base + (size_t)y * n + x;
-            const float gv = FIRST ? bf2f(rec[p * kC + c]) : plane[p];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-                const bool in = yy >= 0 && yy < n && xx >= 0 && xx < n;
-                const size_t q = base + (size_t)yy * n + xx;
-                float v = 0.f;
-                if (in) v = FIRST ? round_bf(plane[q] * sc) : bf2f(rec[q * kC + c]);
-                acc[t] += gv * v;
-            }
+    for (int u = 0; u < 2; ++u)
+        for (int cb = 0; cb < 2; ++cb) acc[u][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto quad = [&](int y, int xq, floatx4* ac) {
+        const int x = 4 * xq + kq;
+        const bool px = x < n;
+        const size_t p = base + (size_t)y * n + x;
+        const float a0 = px ? bf2f(rec[p * kC + m]) : 0.f;
+        const float a1 = px ? bf2f(rec[p * kC + 16 + m]) : 0.f;
+        const int yy = y + sy, xx = x + sx;
+        float bv = 0.f;
+        if (px && tap_ok && yy >= 0 && yy < n && xx >= 0 && xx < n) {
+            const float v = plane[base + (size_t)yy * n + xx];
+            bv = FIRST ? round_bf(v * sc) : v;
         }
+        ac[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, ac[0], 0, 0, 0);
+        ac[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, ac[1], 0, 0, 0);
+    };
+    for (int y = y0; y < y1; ++y) {
+        int xq = wave;
+        for (; xq + 4 < nq; xq += 8) {
+            quad(y, xq, acc[0]);
+            quad(y, xq + 4, acc[1]);
+        }
+        if (xq < nq) quad(y, xq, acc[0]);
     }
 #pragma unroll
-    for (int t = 0; t < 9; ++t) red[k][c * 9 + t] = acc[t];
+    for (int cb = 0; cb < 2; ++cb) red[wave][cb][lane] = acc[0][cb] + acc[1][cb];
     __syncthreads();
-    for (int q = threadIdx.x; q < kC * 9; q += kThreads) {
-        float s = 0.f;
-        for (int j = 0; j < kSmallGroups; ++j) s += red[j][q];
-        part[(size_t)blockIdx.x * (kC * 9) + q] = s;
+    // D lane l: channel 16 cb + 4 (l >> 4) + i, tap l & 15
+    for (int e = threadIdx.x; e < 2 * 64 * 4; e += kThreads) {
+        const int cb = e >> 8, l = (e >> 2) & 63, i = e & 3;
+        float v = 0.f;
+        for (int w = 0; w < kThreads / 64; ++w) v += red[w][cb][l][i];
+        const int c = cb * 16 + 4 * (l >> 4) + i, t = l & 15;
+        if (t < 9) part[(size_t)blockIdx.x * (kC * 9) + c * 9 + t] = v;
     }
 }
 
