@@ -48,6 +48,7 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 // thread 4 x 4 of it, over K chunks of 16 staged in LDS.  apply_mask scales
 // output (r, c) by the ramp sqrt(max(r, c) / n).
 constexpr int kGT = 64, kGK = 16;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_axis_gemm(const T* __restrict__ A, const T* __restrict__ B,
@@ -60,6 +61,16 @@ __global__ void __launch_bounds__(kBlock) k_axis_gemm(const T* __restrict__ A, c
     const T* Ab = A + (size_t)img * a_img;
     const T* Bb = B + (size_t)img * b_img;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    // FP32 on the MFMA (v_mfma_f32_16x16x4f32): wave w takes the 32 x 32
+    // quarter (w >> 1, w & 1) of the tile as 2 x 2 blocks of 16 x 16; FP64 on
+    // the VALU, 4 x 4 outputs per thread
+    constexpr bool kMfma = std::is_same<T, float>::value;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    floatx4 macc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) macc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     T acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -82,21 +93,56 @@ __global__ void __launch_bounds__(kBlock) k_axis_gemm(const T* __restrict__ A, c
             }
         }
         __syncthreads();
+        if constexpr (kMfma) {
+            // A[m][k] = As[k][row], lane (m = lane & 15, k = lane >> 4); B[k][n] = Bs[k][col]
 #pragma unroll
-        for (int k = 0; k < kGK; ++k) {
-            T a[4], b[4];
+            for (int k4 = 0; k4 < kGK; k4 += 4) {
+                const int k = k4 + (lane >> 4);
+                float a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+                for (int i = 0; i < 2; ++i) a[i] = As[k][(wave >> 1) * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+                for (int j = 0; j < 2; ++j) b[j] = Bs[k][(wave & 1) * 32 + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < 2; ++j)
+                        macc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], macc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kGK; ++k) {
+                T a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            }
         }
         __syncthreads();
     }
     T* o = out + (size_t)img * n * n;
+    if constexpr (kMfma) {
+        // D lane: row 4 (lane >> 4) + q, column lane & 15 of each block
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + (wave >> 1) * 32 + i * 16 + 4 * (lane >> 4) + q;
+                    const int c = c0 + (wave & 1) * 32 + j * 16 + (lane & 15);
+                    if (r >= n || c >= n) continue;
+                    T v = macc[i][j][q];
+                    if (apply_mask) v *= (T)sqrt((double)(r > c ? r : c) / (double)n);
+                    o[(size_t)r * n + c] = v;
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = r0 + ty * 4 + i;
