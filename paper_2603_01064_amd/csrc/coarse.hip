@@ -200,13 +200,72 @@ __global__ void __launch_bounds__(kET * kET) k_eig_stage(const TA* __restrict__ 
     C[(size_t)b * n * n + (size_t)i * n + j] = (TC)acc;
 }
 
+// The whole eigenbasis solve of one right-hand side in one workgroup for
+// coarsest grids up to 32 x 32: V, y and the intermediate in LDS, the same
+// four products as k_eig_stage (FP64, ascending k, the same division), so
+// the result is the same; one launch instead of four.
+constexpr int kEigSmall = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V, const double* __restrict__ lam,
+                                                   const double* __restrict__ alpha, const T* __restrict__ y,
+                                                   T* __restrict__ x, int n) {
+    __shared__ double sV[kEigSmall * kEigSmall], sA[kEigSmall * kEigSmall], sB[kEigSmall * kEigSmall];
+    __shared__ double sl[kEigSmall];
+    const int b = blockIdx.x, nn = n * n;
+    const double a = alpha[b];
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        sV[e] = V[e];
+        sA[e] = (double)y[(size_t)b * nn + e];
+    }
+    for (int i = threadIdx.x; i < n; i += 256) sl[i] = lam[i];
+    __syncthreads();
+    // T1 = V^T y
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        const int i = e / n, j = e - (e / n) * n;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += sV[k * n + i] * sA[k * n + j];
+        sB[e] = acc;
+    }
+    __syncthreads();
+    // T2 = (T1 V) / (alpha + lam_i lam_j)
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        const int i = e / n, j = e - (e / n) * n;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += sB[i * n + k] * sV[k * n + j];
+        sA[e] = acc / (a + sl[i] * sl[j]);
+    }
+    __syncthreads();
+    // T3 = V T2
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        const int i = e / n, j = e - (e / n) * n;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += sV[i * n + k] * sA[k * n + j];
+        sB[e] = acc;
+    }
+    __syncthreads();
+    // x = T3 V^T
+    for (int e = threadIdx.x; e < nn; e += 256) {
+        const int i = e / n, j = e - (e / n) * n;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += sB[i * n + k] * sV[j * n + k];
+        x[(size_t)b * nn + e] = (T)acc;
+    }
+}
+
 }  // namespace
 
 // x = V [(V^T y V) / (alpha + lam_i lam_j)] V^T per right-hand side: four
-// batched products through the FP64 stage scratch.
+// batched products through the FP64 stage scratch, or one workgroup per
+// right-hand side for coarsest grids up to 32 x 32.
 template <typename T>
 nmg_status launch_eig_coarse(const Ctx* c, int batch, const double* alpha, const T* y, T* x, hipStream_t s) {
     const int n = c->n[(size_t)c->L - 1];
+    if (n <= kEigSmall) {
+        hipLaunchKernelGGL((k_eig_small<T>), dim3(batch), dim3(256), 0, s, c->eigV, c->eigLam, alpha, y, x, n);
+        NMG_HIP(hipGetLastError());
+        return NMG_OK;
+    }
     const size_t nn = (size_t)n * n;
     const int tiles = (n + kET - 1) / kET;
     const dim3 grid(tiles * tiles, 1, batch), block(kET * kET);

@@ -933,12 +933,16 @@ nmg_status nmg_setup_hierarchy(const nmg_problem* p, nmg_handle* out) {
     c->ny0 = p->dim == 2 ? p->n : 1;
     const int nl = c->n.back();
     c->nc = p->dim == 2 ? nl * nl : nl;
-    if (c->nc > 1024) {
-        if (p->dim != 2 || nl > 511)
-            return fail(NMG_ERR_SHAPE, "coarsest grid too large (dense factor up to 1024 unknowns; in 2D the "
-                                       "eigenbasis solve up to 511^2)");
-        c->eig_coarse = true;
-    }
+    // 2D: the coarsest operator alpha M (x) M + G (x) G is solved exactly in the
+    // eigenbasis of the pencil (G, M), which does not depend on alpha: no
+    // factorization per alpha (a dense Cholesky and inverse of the 225 x 225
+    // operator of a 15^2 grid took 6.6 ms per new alpha, which a serving
+    // stream with a new alpha per request paid on every admission), and the
+    // solve is four n x n products per right-hand side.  1D: dense factors.
+    if (c->nc > 1024 && (p->dim != 2 || nl > 511))
+        return fail(NMG_ERR_SHAPE, "coarsest grid too large (dense factor up to 1024 unknowns; in 2D the "
+                                   "eigenbasis solve up to 511^2)");
+    c->eig_coarse = p->dim == 2;
     // smoother layout
     const int kk = p->dim == 2 ? p->ksize * p->ksize : p->ksize;
     c->wcount = 0;
