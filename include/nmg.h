@@ -7,7 +7,7 @@
  * Gaussian kernel (paper Sec. 2.1; 2D Kronecker form K2 = K (x) K of Sec. 4.2)
  * by V-cycles whose smoothers are learned per-level CNNs (Algorithms 2-4),
  * with full-weighting restriction, linear interpolation, Galerkin coarse
- * operators (Algorithm 1) and a Cholesky solve on the coarsest grid.
+ * operators (Algorithm 1) and an exact solve on the coarsest grid.
  *
  * Conventions shared by every entry point
  *  - Grids have n = 2^k - 1 interior points per axis, mesh h = 1/(n+1),
@@ -144,10 +144,10 @@ typedef struct {
  * banded factor G_1 = K^T K, the Galerkin factors M_l, G_l of
  * A_l = alpha M_l (x) M_l + G_l (x) G_l, device copies and workspaces for
  * max_batch right-hand sides.  Synchronises.  *out receives the handle.
- * The exact coarsest solve of Algorithm 1 is a dense FP64 Cholesky factor
- * per alpha when n_L^dim <= 1024.  In 2D, larger coarsest grids (n_L up to
- * 511) are solved exactly in the simultaneous eigenbasis V of (M_L, G_L),
- * computed once on the host: x = V [(V^T y V) / (alpha + lam_i lam_j)] V^T,
+ * The exact coarsest solve of Algorithm 1: in 2D (coarsest n_L up to 511)
+ * in the simultaneous eigenbasis V of (M_L, G_L), computed once on the host
+ * and independent of alpha: x = V [(V^T y V) / (alpha + lam_i lam_j)] V^T;
+ * in 1D a dense FP64 Cholesky factor per alpha (n_L <= 1024),
  * four FP64 products per right-hand side and nothing to factor per alpha.
  * Errors: NMG_ERR_SHAPE (n not 2^k-1, too many levels, coarsest grid too
  * large, bad channels), NMG_ERR_ARG, NMG_ERR_OOM, NMG_ERR_HIP. */
@@ -176,15 +176,16 @@ nmg_status nmg_get_smoother_weights(nmg_handle h, int level, int weight_set,
  * level `level` (omega > 0), in place of the neural smoother. */
 nmg_status nmg_set_jacobi_smoother(nmg_handle h, int level, double omega);
 
-/* Coarse factorisation for the right-hand sides b < batch: for every
- * distinct alpha[b] forms A_L = alpha M_L (x) M_L + G_L (x) G_L and its FP64
- * Cholesky factor (Algorithm 1, exact coarsest solve), plus the FP64 inverse
- * used by FP32 / mixed cycles.  Factors are cached per alpha value (up to
- * max_batch of them), so repeated alphas cost nothing.  alpha: device
+/* Coarse preparation for the right-hand sides b < batch.  1D: for every
+ * distinct alpha[b] forms A_L = alpha M_L + G_L and its FP64 Cholesky factor
+ * (Algorithm 1, exact coarsest solve), plus the FP64 inverse used by FP32 /
+ * mixed cycles; factors are cached per alpha value (up to max_batch of
+ * them), so repeated alphas cost nothing.  2D: the eigenbasis solve needs no
+ * factor, and this only checks the alphas.  alpha: device
  * double[batch].  Must precede nmg_vcycle for these right-hand sides
  * (nmg_solve calls it itself).  Synchronises; NMG_ERR_ARG for alpha <= 0 or
- * non-finite, NMG_ERR_NOT_SPD if a pivot is not positive or alpha is at
- * or below the floor of NMG_OP_KERNEL. */
+ * non-finite, NMG_ERR_NOT_SPD if a pivot is not positive (1D) or alpha is
+ * at or below the operator's floor. */
 nmg_status nmg_prepare(nmg_handle h, int batch, const double* alpha_dev, void* stream);
 
 /* ---- operators ---------------------------------------------------------- */
@@ -239,7 +240,7 @@ nmg_status nmg_apply_fprime_noalloc(nmg_handle h, int level, int batch, const fl
 /* x <- MG(x, y): one V(nu1, nu2) cycle on the finest level with initial
  * guess x (Algorithm 1 skeleton with the neural smoothing step
  * b = y - A x, h = ||b|| N(b/||b||), x += F'(h) of Algorithms 2-4, Galerkin
- * coarse levels, Cholesky coarsest solve).  x, y: device, double for
+ * coarse levels, exact coarsest solve).  x, y: device, double for
  * NMG_FP64, float otherwise.  weight_set_dev: device int[batch] choosing the
  * smoother set per right-hand side, or NULL for set 0 (indices outside
  * [0, n_weight_sets) are clamped into it).  Requires nmg_prepare for the

@@ -114,7 +114,7 @@ def test_operator_every_level(dim, n, s, L, form):
     h.close()
 
 
-def test_one_level_is_coarse_cholesky_solve():
+def test_one_level_is_the_exact_coarse_solve():
     print("case L=1 direct solve 15x15", flush=True)
     dev = _dev()
     n, s = 15, 0.05
@@ -454,15 +454,17 @@ def test_solve_fp64_history_matches_oracle_and_dense_solution():
 
 
 # --------------------------------------------------------------------------
-# Exact coarsest solve in the eigenbasis (coarsest grids above 1024 unknowns)
+# Exact coarsest solve in the eigenbasis (every 2D coarsest grid; one
+# workgroup per right-hand side up to 32^2, four batched products above)
 # --------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("n,s,L", [(63, 0.04, 1), (255, 0.04, 3), (127, 0.03, 2)])
+@pytest.mark.parametrize("n,s,L", [(63, 0.04, 1), (255, 0.04, 3), (127, 0.03, 2), (31, 0.05, 1), (63, 0.04, 2)])
 def test_eigenbasis_coarse_solve(n, s, L):
-    """Coarsest grids of 63^2 and 127^2 unknowns take the eigenbasis solve: the
-    one-level case against the oracle's dense Cholesky solve, and FP64 neural
-    V-cycles against the oracle's cycle, alphas 1e-2 / 1e-4 in one batch."""
+    """Coarsest grids of 31^2 (one workgroup per right-hand side), 63^2 and
+    127^2 unknowns (four batched products) in the eigenbasis: the one-level
+    case against the oracle's dense Cholesky solve, and FP64 neural V-cycles
+    against the oracle's cycle, alphas 1e-2 / 1e-4 in one batch."""
     print(f"case eigenbasis coarse n={n} L={L}", flush=True)
     dev = _dev()
     alpha = torch.tensor([1e-2, 1e-4], dtype=DT)
