@@ -356,7 +356,8 @@ def main(argv=None):
         res["large_solve"] = large_solve(nmg)
     if not a.no_mixed_sizes and os.path.exists(MIXED_WEIGHTS):
         log("serving: grid sides 64..1024 through one pool")
-        res["serving_mixed_sizes"] = mixed_sizes_serving(nmg, count=a.mixed_requests, max_cycles=a.max_cycles)
+        res["serving_mixed_sizes"] = mixed_sizes_serving(nmg, count=a.mixed_requests, max_cycles=a.max_cycles,
+                                                         serial=not a.no_serial_baseline)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(meta, sets, host[a.warmup])
@@ -676,7 +677,7 @@ def _mixed_handle(nmg, side, meta, sets, max_batch):
 
 
 def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, serial_count=40, max_cycles=200,
-                        budget=2 << 30):
+                        budget=2 << 30, serial=True):
     """Serving stream of 2D solves with grid side uniform over 64..1024,
     s = 2.5 grid spacings, alpha log-uniform in [1e-5, 1e-2], box-image
     right-hand sides and Poisson arrivals, through one pool (one handle per
@@ -740,6 +741,10 @@ def mixed_sizes_serving(nmg, rates=(50.0, 100.0, 200.0, 400.0), count=300, seria
         log(f"mixed-size serving at {rate:g}/s: {summ['solves_per_s']} solves/s, p50 {summ['p50_ms']} ms, "
             f"p99 {summ['p99_ms']} ms, converged {summ['converged']}/{summ['requests']}")
     pool.close()
+    if not serial:
+        for h in handles:
+            h.close()
+        return out
     # the serial plain-FP32 solver on the first requests of the lowest rate
     rate = min(rates)
     arr = inputs.poisson_arrivals(rate, count, seed=43000 + int(rate))[:serial_count]
