@@ -232,6 +232,29 @@ __global__ void __launch_bounds__(64 * WAVES) k_fprime_tiled(const uint16_t* __r
     };
 #pragma unroll
     for (int t = 0; t < KCH; ++t) fetch(t);
+    // STAGE 1 adds into x: this thread's values of x are loaded now (behind
+    // the first operand steps, ahead of the refills), so their latency
+    // overlaps the products.  Element k is row j = tid / CB + k NTH / CB,
+    // column I0 + tid % CB; x is read through a buffer resource and an element
+    // outside the image takes an out-of-range offset, which reads zero.  With
+    // 16 waves (128 registers per lane) the values would not fit beside the
+    // operand ring, so that shape reads x in the epilogue instead.
+    constexpr bool kPrefetchX = STAGE == 1 && NTH <= 512;
+    constexpr int EPT = STAGE == 1 ? NP * CB / NTH : 1;
+    static_assert(STAGE == 0 || (NP * CB % NTH == 0 && NTH % CB == 0), "F' output elements per thread");
+    float xv[kPrefetchX ? EPT : 1];
+    if constexpr (kPrefetchX) {
+        const __amdgpu_buffer_rsrc_t xres = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<float*>(out) + (size_t)img * n * n, (short)0, n * n * 4, 0x00020000);
+        const int xi = I0 + tid % CB;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int j = tid / CB + k * (NTH / CB);
+            const bool ok = accumulate && j < n && xi < n;
+            xv[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                  xres, ok ? (j * n + xi) * 4 : (int)0x80000000, 0, 0));
+        }
+    }
     *reinterpret_cast<uint4*>(Ls + tid * 16) = ar0;
     if constexpr (APT == 2) *reinterpret_cast<uint4*>(Ls + (tid + NTH) * 16) = ar1;
     __syncthreads();
@@ -318,13 +341,17 @@ __global__ void __launch_bounds__(64 * WAVES) k_fprime_tiled(const uint16_t* __r
                 *reinterpret_cast<floatx4*>(O + (wrow + nt * 16 + ln) * OPITCH + mt * 16 + lg * 4) = acc[mt][nt];
         __syncthreads();
         float* xb = reinterpret_cast<float*>(out) + (size_t)img * n * n;
-#pragma unroll 4
-        for (int e = tid; e < NP * CB; e += NTH) {
-            const int j = e / CB, i = e % CB;
+        const int i = tid % CB;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int j = tid / CB + k * (NTH / CB);
             if (j < n && I0 + i < n) {
                 const float v = O[j * OPITCH + i];
                 float* d = xb + (size_t)j * n + I0 + i;
-                *d = accumulate ? *d + v : v;
+                if constexpr (kPrefetchX)
+                    *d = accumulate ? xv[k] + v : v;
+                else
+                    *d = accumulate ? *d + v : v;
             }
         }
     }
@@ -388,13 +415,32 @@ __global__ void __launch_bounds__(kSmallThreads) k_fprime_small(const float* __r
         const float v1 = (i < n && k + 1 < n) ? src[(size_t)i * n + k + 1] : 0.f;
         *reinterpret_cast<uint32_t*>(buf[0] + off(i, k >> 3) + (k & 7) * 2) = pack_bf16(v0, v1);
     }
+    // the values of dst this wave's last-pass outputs add to, loaded now so
+    // their latency overlaps the four passes (output tile t of pass 3 is
+    // rows 16 (t / NT) + 4 lg .. + 3, column 16 (t % NT) + ln)
+    constexpr int TPW = (NT * NT + WAVES - 1) / WAVES;  // output tiles per wave
+    float* dimg = dst + (size_t)b * n * n;
+    float dv[TPW][4];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = wave + u * WAVES;
+        const int i = (t % NT) * 16 + ln;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = (t / NT) * 16 + lg * 4 + q;
+            dv[u][q] = (accumulate && t < NT * NT && i < n && j < n) ? dimg[(size_t)j * n + i] : 0.f;
+        }
+    }
     __syncthreads();
 #pragma unroll 1
     for (int pass = 0; pass < 4; ++pass) {
         const char* M = mats[pass < 2 ? 0 : 1];
         const char* cur = buf[pass & 1];
         char* nxt = buf[(pass + 1) & 1];
-        for (int t = wave; t < NT * NT; t += WAVES) {
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int t = wave + u * WAVES;
+            if (t >= NT * NT) break;
             const int tj = t / NT, ti = t % NT;  // output rows j (M), columns i (N)
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -414,8 +460,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_fprime_small(const float* __r
                     // next pass reads row j, column i
                     *reinterpret_cast<uint16_t*>(nxt + off(j, i >> 3) + (i & 7) * 2) = (uint16_t)pack_bf16(v, 0.f);
                 } else if (i < n && j < n) {
-                    float* o = dst + (size_t)b * n * n + (size_t)j * n + i;
-                    *o = accumulate ? *o + v : v;
+                    dimg[(size_t)j * n + i] = accumulate ? dv[u][q] + v : v;
                 }
             }
         }
