@@ -27,7 +27,7 @@ METRIC = "V-cycle solves/s to 1e-6 rel. residual, 256^2 batch 64; p50/p99 solve 
 N, S, LEVELS, BATCH = 255, 0.01, 5, 64
 CHANNELS = (1, 32, 32, 1)
 ALPHAS = (1e-2, 1e-3, 1e-4)
-PROFILE_PERIOD = 4  # the smoother roofline times every 4th solve iteration
+PROFILE_PERIOD = 8  # the smoother roofline times every 8th solve iteration
 FLOP_PER_PX = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)  # 19,584: three 3x3 layers
 # smoother input plane read + output plane written (FP32), plus a read of the
 # output when it accumulates into x (no F')

@@ -508,9 +508,16 @@ nmg_status nmg_debug_factor(nmg_handle h, int level, int which, double* out, int
  *     path of nmg_apply_fprime) instead of receiving the zero-padded BF16
  *     plane the smoother writes directly on levels above 64^2.  Both give
  *     bit-identical iterates.  Value 0 (default) restores the direct plane.
+ *   NMG_DEBUG_SEPARATE_RESTRICT, value 1: 2D cycles without pre-smoothing
+ *     (nu1 = 0, Algorithm 4's restriction of y from x = 0) restrict level by
+ *     level, one launch each, and solve the coarsest level in its own
+ *     launch, instead of taking the restrictions onto grids of at most
+ *     64 x 64 (and the coarsest eigenbasis solve up to 32 x 32) in one
+ *     launch.  Both give bit-identical iterates.  Value 0 (default) restores
+ *     the single launch.
  * Takes effect for cycles launched afterwards (captured solve graphs are
  * dropped).  NMG_ERR_ARG for an unknown option. */
-typedef enum { NMG_DEBUG_FP32_HANDOFF = 1 } nmg_debug_opt;
+typedef enum { NMG_DEBUG_FP32_HANDOFF = 1, NMG_DEBUG_SEPARATE_RESTRICT = 2 } nmg_debug_opt;
 nmg_status nmg_debug_option(nmg_handle h, int option, int value);
 
 #ifdef __cplusplus

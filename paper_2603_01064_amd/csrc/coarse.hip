@@ -206,22 +206,21 @@ __global__ void __launch_bounds__(kET * kET) k_eig_stage(const TA* __restrict__ 
 // the result is the same; one launch instead of four.
 constexpr int kEigSmall = 32;
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V, const double* __restrict__ lam,
-                                                   const double* __restrict__ alpha, const T* __restrict__ y,
-                                                   T* __restrict__ x, int n) {
-    __shared__ double sV[kEigSmall * kEigSmall], sA[kEigSmall * kEigSmall], sB[kEigSmall * kEigSmall];
-    __shared__ double sl[kEigSmall];
-    const int b = blockIdx.x, nn = n * n;
-    const double a = alpha[b];
-    for (int e = threadIdx.x; e < nn; e += 256) {
+// The one-workgroup eigenbasis solve of one right-hand side (NTH threads):
+// y(e) gives element e of y, x receives the n x n solution.  sV, sA, sB hold
+// kEigSmall^2 doubles each, sl kEigSmall.
+template <int NTH, typename T, typename YF>
+__device__ inline void eig_small_solve(const double* __restrict__ V, const double* __restrict__ lam, double a, YF y,
+                                       T* __restrict__ x, int n, double* sV, double* sA, double* sB, double* sl) {
+    const int nn = n * n;
+    for (int e = threadIdx.x; e < nn; e += NTH) {
         sV[e] = V[e];
-        sA[e] = (double)y[(size_t)b * nn + e];
+        sA[e] = y(e);
     }
-    for (int i = threadIdx.x; i < n; i += 256) sl[i] = lam[i];
+    for (int i = threadIdx.x; i < n; i += NTH) sl[i] = lam[i];
     __syncthreads();
     // T1 = V^T y
-    for (int e = threadIdx.x; e < nn; e += 256) {
+    for (int e = threadIdx.x; e < nn; e += NTH) {
         const int i = e / n, j = e - (e / n) * n;
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += sV[k * n + i] * sA[k * n + j];
@@ -229,7 +228,7 @@ __global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V,
     }
     __syncthreads();
     // T2 = (T1 V) / (alpha + lam_i lam_j)
-    for (int e = threadIdx.x; e < nn; e += 256) {
+    for (int e = threadIdx.x; e < nn; e += NTH) {
         const int i = e / n, j = e - (e / n) * n;
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += sB[i * n + k] * sV[k * n + j];
@@ -237,7 +236,7 @@ __global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V,
     }
     __syncthreads();
     // T3 = V T2
-    for (int e = threadIdx.x; e < nn; e += 256) {
+    for (int e = threadIdx.x; e < nn; e += NTH) {
         const int i = e / n, j = e - (e / n) * n;
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += sV[i * n + k] * sA[k * n + j];
@@ -245,11 +244,111 @@ __global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V,
     }
     __syncthreads();
     // x = T3 V^T
-    for (int e = threadIdx.x; e < nn; e += 256) {
+    for (int e = threadIdx.x; e < nn; e += NTH) {
         const int i = e / n, j = e - (e / n) * n;
         double acc = 0.0;
         for (int k = 0; k < n; ++k) acc += sB[i * n + k] * sV[j * n + k];
-        x[(size_t)b * nn + e] = (T)acc;
+        x[e] = (T)acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V, const double* __restrict__ lam,
+                                                   const double* __restrict__ alpha, const T* __restrict__ y,
+                                                   T* __restrict__ x, int n) {
+    __shared__ double sV[kEigSmall * kEigSmall], sA[kEigSmall * kEigSmall], sB[kEigSmall * kEigSmall];
+    __shared__ double sl[kEigSmall];
+    const int b = blockIdx.x;
+    const size_t nn = (size_t)n * n;
+    const T* yb = y + b * nn;
+    eig_small_solve<256>(V, lam, alpha[b], [&](int e) { return (double)yb[e]; }, x + b * nn, n, sV, sA, sB, sl);
+}
+
+// Restriction chain.  A cycle without pre-smoothing from x = 0 restricts its
+// right-hand side through every level before any other work
+// (y_{k+1} = R y_k).  From the first level whose restricted grids all fit
+// in LDS, one workgroup per right-hand side takes the remaining
+// restrictions in one launch: the first reads y_{k0} from global memory,
+// each later one the grid the previous one left in LDS, and every y_k is
+// written out (the post-smoothing residuals read them).  With the
+// eigenbasis coarse solve on a grid of at most kEigSmall^2 points, the
+// coarsest solve follows in the same workgroup.  Each point is the 3 x 3
+// full weighting of the single-level restriction, in its order (weighted
+// row sums, then their weighted sum), and the solve is the one of
+// k_eig_small, so the values are those of the separate launches.
+constexpr int kChainThreads = 1024;
+constexpr int kChainUnroll = 4;  // outputs per thread whose loads are in flight together
+
+template <typename T>
+__device__ inline T restrict_point(const T* __restrict__ src, int nf, int i, int j) {
+    const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T* row = src + (2 * i + a) * nf;
+        T ra = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ra += w[c] * row[2 * j + c];
+        acc += w[a] * ra;
+    }
+    return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kChainThreads) k_restrict_chain(RestrictChain<T> ch, const double* __restrict__ V,
+                                                                  const double* __restrict__ lam,
+                                                                  const double* __restrict__ alpha) {
+    __shared__ T bufA[kChainMax * kChainMax], bufB[(kChainMax / 2) * (kChainMax / 2)];
+    __shared__ double sV[kEigSmall * kEigSmall], sA[kEigSmall * kEigSmall], sB[kEigSmall * kEigSmall];
+    __shared__ double sl[kEigSmall];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    // first restriction: y_{k0} (global) -> y_{k0 + 1}; the outputs of a
+    // thread past the grid recompute its last point (their loads stay in
+    // bounds and issue with the others) and store nothing
+    {
+        const int nf = ch.n[0], nc = ch.n[1], ncc = nc * nc;
+        const T* src = ch.y[0] + (size_t)b * nf * nf;
+        T* dst = ch.y[1] + (size_t)b * ncc;
+        for (int e0 = 0; e0 < ncc; e0 += kChainThreads * kChainUnroll) {
+            T v[kChainUnroll];
+#pragma unroll
+            for (int u = 0; u < kChainUnroll; ++u) {
+                const int e = min(e0 + u * kChainThreads + tid, ncc - 1);
+                const int i = e / nc, j = e - (e / nc) * nc;
+                v[u] = restrict_point(src, nf, i, j);
+            }
+#pragma unroll
+            for (int u = 0; u < kChainUnroll; ++u) {
+                const int e = e0 + u * kChainThreads + tid;
+                if (e < ncc) {
+                    bufA[e] = v[u];
+                    dst[e] = v[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // later restrictions, LDS to LDS (levels alternate between the buffers)
+    T* cur = bufA;
+    T* nxt = bufB;
+    for (int k = 1; k + 1 < ch.levels; ++k) {
+        const int nf = ch.n[k], nc = ch.n[k + 1], ncc = nc * nc;
+        T* dst = ch.y[k + 1] + (size_t)b * ncc;
+        for (int e = tid; e < ncc; e += kChainThreads) {
+            const int i = e / nc, j = e - (e / nc) * nc;
+            const T v = restrict_point(cur, nf, i, j);
+            nxt[e] = v;
+            dst[e] = v;
+        }
+        __syncthreads();
+        T* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (ch.x_coarse) {
+        const int n = ch.n[ch.levels - 1];
+        eig_small_solve<kChainThreads>(V, lam, alpha[b], [&](int e) { return (double)cur[e]; },
+                                       ch.x_coarse + (size_t)b * n * n, n, sV, sA, sB, sl);
     }
 }
 
@@ -287,6 +386,27 @@ nmg_status launch_eig_coarse(const Ctx* c, int batch, const double* alpha, const
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
+template <typename T>
+nmg_status launch_restrict_chain(const Ctx* c, int batch, const double* alpha, const RestrictChain<T>& ch,
+                                 hipStream_t s) {
+    if (ch.levels < 2 || ch.levels > kChainLevels) return fail(NMG_ERR_ARG, "restriction chain: level count");
+    for (int k = 0; k + 1 < ch.levels; ++k)
+        if (ch.n[k + 1] != (ch.n[k] - 1) / 2 || ch.n[k + 1] < 1 || (k == 0 && 2 * ch.n[1] + 1 > ch.n[0]))
+            return fail(NMG_ERR_SHAPE, "restriction chain: grid sizes do not halve");
+    if (ch.n[1] > kChainMax) return fail(NMG_ERR_SHAPE, "restriction chain: restricted grid exceeds the LDS buffers");
+    if (ch.x_coarse && (!c->eig_coarse || ch.n[ch.levels - 1] > kEigSmall))
+        return fail(NMG_ERR_STATE, "restriction chain: the coarsest solve needs the small eigenbasis form");
+    hipLaunchKernelGGL((k_restrict_chain<T>), dim3(batch), dim3(kChainThreads), 0, s, ch, c->eigV, c->eigLam, alpha);
+    NMG_HIP(hipGetLastError());
+    return NMG_OK;
+}
+template nmg_status launch_restrict_chain<float>(const Ctx*, int, const double*, const RestrictChain<float>&,
+                                                 hipStream_t);
+template nmg_status launch_restrict_chain<double>(const Ctx*, int, const double*, const RestrictChain<double>&,
+                                                  hipStream_t);
+
+int eig_small_max() { return kEigSmall; }
+
 template nmg_status launch_eig_coarse<float>(const Ctx*, int, const double*, const float*, float*, hipStream_t);
 template nmg_status launch_eig_coarse<double>(const Ctx*, int, const double*, const double*, double*, hipStream_t);
 

@@ -182,6 +182,7 @@ struct Ctx {
     float* adam_v = nullptr;
     std::vector<int> adam_step;        // per set
     bool dbg_fp32_handoff = false;     // nmg_debug_option NMG_DEBUG_FP32_HANDOFF
+    bool dbg_separate_restrict = false;  // nmg_debug_option NMG_DEBUG_SEPARATE_RESTRICT
     uint16_t* dctbf = nullptr;         // BF16 DCT-II matrices C and C^T per level (padded)
     std::vector<size_t> dctbf_off;
     float* ramp = nullptr;             // sqrt(k / n_l) per level (F' mask)
@@ -424,6 +425,23 @@ bool coarse_eigenbasis(const Band& M, const Band& G, std::vector<double>& V, std
                        std::string& err);
 template <typename T>
 nmg_status launch_eig_coarse(const Ctx* c, int batch, const double* alpha, const T* y, T* x, hipStream_t s);
+// Restriction chain (2D): y[k + 1] = R y[k] for k = 0 .. levels - 2 in one
+// launch, one workgroup per right-hand side, and, with x_coarse, the
+// eigenbasis solve of the last grid into x_coarse.  n[1] <= kChainMax; with
+// x_coarse the last side is at most eig_small_max().
+constexpr int kChainLevels = 8;
+constexpr int kChainMax = 64;
+template <typename T>
+struct RestrictChain {
+    int levels = 0;                   // grids in the chain: the level read and every level below it
+    int n[kChainLevels] = {};         // their sides
+    T* y[kChainLevels] = {};          // right-hand sides (y[0] read, the others written)
+    T* x_coarse = nullptr;            // coarsest solution when the solve is fused, else null
+};
+template <typename T>
+nmg_status launch_restrict_chain(const Ctx* c, int batch, const double* alpha, const RestrictChain<T>& ch,
+                                 hipStream_t s);
+int eig_small_max();
 nmg_status launch_coarse_inverse(Ctx* c, int count, const int* slots, hipStream_t s);
 template <typename T>
 nmg_status launch_coarse_apply_inverse(const Ctx* c, int batch, const T* y, T* x, hipStream_t s);

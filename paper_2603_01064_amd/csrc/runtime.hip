@@ -371,7 +371,28 @@ struct CycleArgs {
     const int* ws;
     nmg_cycle_opts o;
     hipStream_t s;
+    int chain_from = -1;     // level whose restriction chain produced every coarser y (-1: none)
+    bool chain_eig = false;  // the chain also solved the coarsest level
 };
+
+// A cycle without pre-smoothing from x = 0 may restrict from level l down
+// in one launch (launch_restrict_chain): 2D, the grids below l small enough
+// for its LDS buffers, and sizes that halve.
+template <typename T>
+bool chain_restrict(const Ctx* c, int l, RestrictChain<T>& ch, Work<T>& w, const T* y) {
+    if (c->dbg_separate_restrict || c->p.dim != 2 || l + 1 > c->L - 1 || c->L - l > kChainLevels) return false;
+    if (c->n[(size_t)l + 1] > kChainMax) return false;
+    for (int k = l; k + 1 < c->L; ++k)
+        if (c->n[(size_t)k + 1] != (c->n[(size_t)k] - 1) / 2 || c->n[(size_t)k + 1] < 1) return false;
+    ch.levels = c->L - l;
+    for (int k = 0; k < ch.levels; ++k) {
+        ch.n[k] = c->n[(size_t)(l + k)];
+        ch.y[k] = k == 0 ? const_cast<T*>(y) : w.lv[(size_t)(l + k)].y;
+    }
+    const bool eig = c->eig_coarse && c->n[(size_t)c->L - 1] <= eig_small_max();
+    ch.x_coarse = eig ? w.lv[(size_t)c->L - 1].x : nullptr;
+    return true;
+}
 
 // parts_ready > 0 (with x_zero): c->norm_part already holds that many partial
 // sums of ||y||^2 per right-hand side (written by the restriction that
@@ -446,6 +467,7 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int part
     Ctx* c = a.c;
     Work<T>& w = *a.w;
     if (l == c->L - 1) {
+        if (a.chain_eig) return NMG_OK;  // solved by the restriction chain
         ProfScope ps(c, a.s, NMG_K_COARSE, l);
         if (c->eig_coarse) return launch_eig_coarse<T>(c, a.batch, a.alpha, y, x, a.s);
         if (a.o.precision == NMG_FP64) return launch_coarse_solve<T>(c, a.batch, y, x, a.s);
@@ -468,10 +490,17 @@ nmg_status cycle(CycleArgs<T>& a, int l, T* x, const T* y, bool x_zero, int part
     // level starts with a BF16 neural smoothing step on it
     const bool fuse_norm = l + 1 < c->L - 1 && a.o.nu1 > 0 && c->kind[(size_t)l + 1] == 0 &&
                            a.o.precision == NMG_MIXED && c->p.smoother_arch != NMG_ARCH_FNO;
-    {
+    if (!(from_zero && a.chain_from >= 0 && l > a.chain_from)) {  // else the chain restricted this level
         ProfScope ps(c, a.s, NMG_K_RESTRICT, l);
-        NMG_TRY(launch_restrict<T>(c, l, a.batch, from_zero ? y : lb.b, w.lv[(size_t)l + 1].y, a.s,
-                                   fuse_norm ? c->norm_part : nullptr));
+        RestrictChain<T> ch;
+        if (from_zero && !fuse_norm && chain_restrict<T>(c, l, ch, w, y)) {
+            NMG_TRY(launch_restrict_chain<T>(c, a.batch, a.alpha, ch, a.s));
+            a.chain_from = l;
+            a.chain_eig = ch.x_coarse != nullptr;
+        } else {
+            NMG_TRY(launch_restrict<T>(c, l, a.batch, from_zero ? y : lb.b, w.lv[(size_t)l + 1].y, a.s,
+                                       fuse_norm ? c->norm_part : nullptr));
+        }
     }
     NMG_TRY(cycle<T>(a, l + 1, w.lv[(size_t)l + 1].x, w.lv[(size_t)l + 1].y, true,
                      fuse_norm ? restrict_norm_parts(c, l) : 0));
@@ -1443,8 +1472,12 @@ nmg_status nmg_debug_transfer_map(nmg_handle h, int level, int kind, int32_t* id
 
 nmg_status nmg_debug_option(nmg_handle h, int option, int value) {
     NMG_TRY(check_handle(h));
-    if (option != NMG_DEBUG_FP32_HANDOFF) return fail(NMG_ERR_ARG, "unknown debug option");
-    h->dbg_fp32_handoff = value != 0;
+    if (option == NMG_DEBUG_FP32_HANDOFF)
+        h->dbg_fp32_handoff = value != 0;
+    else if (option == NMG_DEBUG_SEPARATE_RESTRICT)
+        h->dbg_separate_restrict = value != 0;
+    else
+        return fail(NMG_ERR_ARG, "unknown debug option");
     NMG_HIP(hipDeviceSynchronize());
     release_graphs(h);
     return NMG_OK;

@@ -474,7 +474,7 @@ class Handle:
                "norm": 7}
 
     def debug_option(self, option: int, value: int) -> None:
-        """``nmg_debug_option`` (1 = NMG_DEBUG_FP32_HANDOFF)."""
+        """``nmg_debug_option`` (1 = NMG_DEBUG_FP32_HANDOFF, 2 = NMG_DEBUG_SEPARATE_RESTRICT)."""
         _check(_lib.nmg_debug_option(self.ptr, int(option), int(value)))
 
     def set_graphs(self, enable: bool) -> None:

@@ -4,6 +4,8 @@ the V-cycle (FP64: 1e-12 relative, FP32: 1e-5 relative, norm-wise per cycle).
 Every case prints its name before touching the GPU so a failure is
 attributable from the log alone.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -16,6 +18,7 @@ pytestmark = pytest.mark.gpu
 DT = torch.float64
 FP64_TOL = 1e-12
 FP32_TOL = 1e-5
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _nmg():
@@ -327,6 +330,57 @@ def test_vcycle_fp32_2d():
     print("case vcycle fp32 2D 63", flush=True)
     errs = _cycle_case(2, 63, 0.04, 4, (1, 8, 8, 1), 3, 1, 1, True, [1e-2, 1e-3], 3, prec="fp32")
     assert max(errs) < FP32_TOL, errs
+
+
+@pytest.mark.parametrize("n,L,prec", [(255, 5, "mixed"), (127, 4, "mixed"), (511, 4, "mixed"), (63, 3, "fp32"),
+                                      (127, 4, "fp64")])
+def test_restriction_chain_equals_separate_launches(n, L, prec):
+    """Without pre-smoothing (nu1 = 0) a cycle restricts its right-hand side
+    through every level first; onto grids of at most 64^2 those restrictions,
+    and the coarsest eigenbasis solve up to 32^2, run as one launch.  A solve
+    (every level from x = 0) and two V-cycles from a nonzero x (the chain
+    starts below the finest level) are compared bit for bit with the
+    level-by-level launches (NMG_DEBUG_SEPARATE_RESTRICT), which the other
+    parity tests cover.  511^2 with four levels ends on 63^2: the chain
+    covers the last restriction only and the coarsest solve stays separate."""
+    print(f"case restriction chain n={n} L={L} {prec}", flush=True)
+    from paper_2603_01064_amd.train_weights import load_weights
+    dev = _dev()
+    B = 3
+    # the shipped smoothers for s = 2.5 h (trained on 255^2; deeper levels
+    # reuse the deepest set), one set per alpha
+    meta, sets = load_weights(os.path.join(ROOT, "paper_2603_01064_amd", "weights", "grid255_s2.5h.npz"))
+    h = _nmg().setup_hierarchy(_nmg().Problem(n=n, s=2.5 / (n + 1), levels=L, max_batch=B, channels=(1, 32, 32, 1),
+                                              ksize=3, n_weight_sets=len(sets)))
+    for k, ws in enumerate(sets):
+        for l in range(L - 1):
+            h.load_smoother_weights(l, k, [ws[min(l, meta["levels"] - 2)]])
+    alpha = torch.tensor([1e-2, 1e-3, 1e-4], dtype=DT).to(dev)
+    wsel = torch.tensor([0, 1, 2], dtype=torch.int32).to(dev)
+    h.prepare(alpha)
+    g = torch.Generator().manual_seed(81)
+    b = torch.randn(B, n, n, dtype=DT, generator=g)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x0 = (0.1 * torch.randn(B, n, n, dtype=DT, generator=g)).to(dt)
+    fp = prec != "fp32"
+    res = []
+    for sep in (0, 1):
+        h.debug_option(2, sep)
+        xs, cyc, _, _ = h.solve(b.to(dev), alpha, weight_set=wsel, rtol=1e-6, max_cycles=40, nu1=0, nu2=3,
+                                use_fprime=fp, precision=prec)
+        xv = x0.clone().to(dev)
+        for _ in range(2):
+            h.vcycle(b.to(dt).to(dev), xv, alpha, weight_set=wsel, nu1=0, nu2=3, use_fprime=fp, precision=prec)
+        torch.cuda.synchronize()
+        res.append((xs.cpu(), np.asarray(cyc).copy(), xv.cpu()))
+    h.debug_option(2, 0)
+    h.close()
+    (s0, c0, v0), (s1, c1, v1) = res
+    print(f"  cycles {c0.tolist()} / {c1.tolist()}; differing solve {int((s0 != s1).sum())}, "
+          f"cycle {int((v0 != v1).sum())} of {s0.numel()}", flush=True)
+    assert bool(torch.isfinite(s0).all()) and float(v0.abs().max()) > 0
+    assert np.array_equal(c0, c1)
+    assert torch.equal(s0, s1) and torch.equal(v0, v1)
 
 
 def test_vcycle_1d_ten_cycles_fp64_and_fp32():
