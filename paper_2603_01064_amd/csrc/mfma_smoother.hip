@@ -219,17 +219,6 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
     const size_t per = (size_t)n * n;
     const float* src = bres + (size_t)img * per;
     float* out = dst + (size_t)img * per;
-    // ||b||^2: given, or the sum of this image's partial sums in their order
-    double nb2;
-    if (nparts > 0) {
-        nb2 = 0.0;
-        for (int i = 0; i < nparts; ++i) nb2 += nrm2[(size_t)img * nparts + i];
-    } else {
-        nb2 = nrm2[img];
-    }
-    const float nbf = (float)sqrt(nb2);
-    const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
-
     // input values of this thread's first-layer records (three per record),
     // loaded one tile ahead so the global latency overlaps the layers.  The
     // image is read through a buffer resource: a load whose offset lies past
@@ -255,7 +244,21 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N
             }
         }
     };
+    // (issued before the norm's loads below, so the two latencies overlap)
     load_records(wgi, tid);
+
+    // ||b||^2: given, or the sum of this image's partial sums in their order
+    double nb2;
+    if (nparts > 0) {
+        nb2 = 0.0;
+        // (unrolled: sixteen partials are loaded together; the sum keeps its order)
+#pragma unroll 16
+        for (int i = 0; i < nparts; ++i) nb2 += nrm2[(size_t)img * nparts + i];
+    } else {
+        nb2 = nrm2[img];
+    }
+    const float nbf = (float)sqrt(nb2);
+    const float inv = nb2 > 0.0 ? (float)(1.0 / sqrt(nb2)) : 0.f;
 
     for (int tile = wgi; tile < tiles_per_img; tile += gridDim.x) {
         // per-tile copies of the lane indices: the per-lane index arithmetic of

@@ -340,8 +340,10 @@ template <typename T>
 nmg_status launch_operator(const Ctx* c, int l, int batch, const double* alpha, const T* x, const T* y,
                            T* out, int mode, Work<T>& w, hipStream_t s, double* norm_part = nullptr,
                            int* nparts = nullptr);
+// mirror (optional): the sums also into pinned host memory (see k_sumsq_final)
 template <typename T>
-nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s);
+nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s,
+                        double* mirror = nullptr);
 // first stage only: c->norm_part[b][norm_chunks(elems)]
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s);
@@ -378,7 +380,7 @@ bool refine_residual_fusable(const Ctx* c, const Work<double>& w);
 template <typename D>
 bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double* x, const D* d,
                             const double* rn2, const int* active, const double* y, double* out, double* nrm2,
-                            Work<double>& w, hipStream_t s);
+                            Work<double>& w, hipStream_t s, double* mirror = nullptr);
 // Mixed-precision backward of the CNN smoother on MFMA (train_mfma.hip):
 // buffers and weights of one level and weight set.
 struct MfmaBackwardArgs {

@@ -716,9 +716,9 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             NMG_TRY(launch_convert<double, float>(B64 + off, B32 + off, cnt, s));
             NMG_HIP(hipMemcpyAsync(R32 + off, B32 + off, cnt * sizeof(float), hipMemcpyDeviceToDevice, s));
             NMG_TRY(launch_zero<float>(X32 + off, cnt, s));
-            NMG_TRY(launch_sumsq<float>(h, m, per, R32 + off, h->nrm2 + k, s));
+            NMG_TRY(launch_sumsq<float>(h, m, per, R32 + off, h->nrm2 + k, s, h->pin_rd + k));
         } else {
-            NMG_TRY(launch_sumsq<double>(h, m, per, B64 + off, h->nrm2 + k, s));
+            NMG_TRY(launch_sumsq<double>(h, m, per, B64 + off, h->nrm2 + k, s, h->pin_rd + k));
             NMG_HIP(hipMemcpyAsync(R64 + off, B64 + off, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
             NMG_TRY(launch_zero<double>(X64 + off, cnt, s));
         }
@@ -741,10 +741,13 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
     }
     k = (int)E.slot.size();
     if (k == 0) return NMG_OK;
-    // ---- residual norms of every active slot (new ones: ||b||^2)
+    // ---- residual norms of every active slot (new ones: ||b||^2).  Every
+    // launch that writes h->nrm2 in this engine (the admission above, the
+    // residual of each iteration) also writes the sums into pinned host
+    // memory at the same index, so they are read there once the stream's
+    // work is done
     double* rn2 = h->pin_rd;
     double* bn2n = h->pin_rd + B;
-    NMG_HIP(hipMemcpyAsync(rn2, h->nrm2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
     if (m > 0)
         NMG_HIP(hipMemcpyAsync(bn2n, (plain32 ? h->nrm : h->nrm2) + (k - m), (size_t)m * sizeof(double),
                                hipMemcpyDeviceToHost, s));
@@ -854,10 +857,10 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         ProfScope ps(h, st, NMG_K_REFINE, 0);
         if (plain32) {
             NMG_TRY(launch_operator<float>(h, 0, kk, d_alpha, X32, B32, R32, 0, h->w32b, st));
-            NMG_TRY(launch_sumsq<float>(h, kk, per, R32, h->nrm2, st));
+            NMG_TRY(launch_sumsq<float>(h, kk, per, R32, h->nrm2, st, h->pin_rd));
         } else {
             NMG_TRY(launch_operator<double>(h, 0, kk, d_alpha, X64, B64, R64, 0, h->w64, st));
-            NMG_TRY(launch_sumsq<double>(h, kk, per, R64, h->nrm2, st));
+            NMG_TRY(launch_sumsq<double>(h, kk, per, R64, h->nrm2, st, h->pin_rd));
         }
         return NMG_OK;
     };
@@ -876,7 +879,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             if (refine_residual_fusable(h, h->w64)) {
                 ProfScope ps(h, st, NMG_K_REFINE, 0);
                 (void)launch_refine_residual<double>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
-                                                  h->nrm2, h->w64, st);
+                                                  h->nrm2, h->w64, st, h->pin_rd);
                 NMG_HIP(hipGetLastError());
                 return NMG_OK;
             }
@@ -890,7 +893,7 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             if (refine_residual_fusable(h, h->w64)) {
                 ProfScope ps(h, st, NMG_K_REFINE, 0);
                 (void)launch_refine_residual<float>(h, kk, d_alpha, X64, w.lv[0].x, d_rn2, h->active, B64, R64,
-                                                  h->nrm2, h->w64, st);
+                                                  h->nrm2, h->w64, st, h->pin_rd);
                 NMG_HIP(hipGetLastError());
                 return NMG_OK;
             }

@@ -123,13 +123,22 @@ __global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, 
 }
 
 // nparts partials per right-hand side (row stride `stride`), added in order
+// mirror (optional): the same sums into pinned host memory, made visible at
+// system scope, so the host reads them after the stream's work without a copy
 __global__ void k_sumsq_final(const double* __restrict__ part, double* __restrict__ out, int batch, int nparts,
-                              int stride) {
+                              int stride, double* __restrict__ mirror = nullptr) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     double acc = 0.0;
+    // (unrolled: the loads of eight partials are in flight together; the
+    // sum keeps its ascending order)
+#pragma unroll 8
     for (int c = 0; c < nparts; ++c) acc += part[(size_t)b * stride + c];
     out[b] = acc;
+    if (mirror) {
+        mirror[b] = acc;
+        __threadfence_system();
+    }
 }
 
 // Full weighting: coarse node i reads fine nodes 2i, 2i+1, 2i+2 (1/4, 1/2, 1/4).
@@ -1181,7 +1190,7 @@ bool refine_residual_fusable(const Ctx* c, const Work<double>& w) {
 template <typename D>
 bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double* x, const D* d,
                             const double* rn2, const int* active, const double* y, double* out, double* nrm2,
-                            Work<double>& w, hipStream_t s) {
+                            Work<double>& w, hipStream_t s, double* mirror) {
     const int l = 0, n = c->n[l];
     const TiledOp<double>& op = w.tiled[(size_t)l];
     const int tiles_x = (n + kRefineTW - 1) / kRefineTW, tiles = tiles_x * ((n + 63) / 64);
@@ -1202,7 +1211,7 @@ bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double
                            (const double*)nullptr, x, y, out, alpha, n, 0, op.tg, op.rg, op.dtl, op.dbr, op.rc, op.tm,
                            op.m_ident, tiles_x, c->norm_part);
         hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, c->norm_part, nrm2, batch, tiles,
-                           kNormChunks);
+                           kNormChunks, mirror);
     };
     go(std::integral_constant<int, 8>{});
     go(std::integral_constant<int, 12>{});
@@ -1220,9 +1229,11 @@ bool launch_refine_residual(const Ctx* c, int batch, const double* alpha, double
     return launched;
 }
 template bool launch_refine_residual<float>(const Ctx*, int, const double*, double*, const float*, const double*,
-                                            const int*, const double*, double*, double*, Work<double>&, hipStream_t);
+                                            const int*, const double*, double*, double*, Work<double>&, hipStream_t,
+                                            double*);
 template bool launch_refine_residual<double>(const Ctx*, int, const double*, double*, const double*, const double*,
-                                             const int*, const double*, double*, double*, Work<double>&, hipStream_t);
+                                             const int*, const double*, double*, double*, Work<double>&, hipStream_t,
+                                             double*);
 
 template <typename T>
 nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, hipStream_t s) {
@@ -1233,11 +1244,12 @@ nmg_status launch_sumsq_part(const Ctx* c, int batch, size_t elems, const T* v, 
 }
 
 template <typename T>
-nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s) {
+nmg_status launch_sumsq(const Ctx* c, int batch, size_t elems, const T* v, double* out, hipStream_t s,
+                        double* mirror) {
     double* part = c->norm_part;
     const int nch = norm_chunks(elems);
     hipLaunchKernelGGL(k_sumsq_part<T>, dim3((unsigned)nch, batch), dim3(kBlock), 0, s, v, part, elems);
-    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch, nch, nch);
+    hipLaunchKernelGGL(k_sumsq_final, dim3((batch + 63) / 64), dim3(64), 0, s, part, out, batch, nch, nch, mirror);
     NMG_HIP(hipGetLastError());
     return NMG_OK;
 }
@@ -1314,7 +1326,7 @@ nmg_status launch_convert(const A* src, B* dst, size_t count, hipStream_t s) {
 #define NMG_INST(T)                                                                                              \
     template nmg_status launch_operator<T>(const Ctx*, int, int, const double*, const T*, const T*, T*, int,     \
                                            Work<T>&, hipStream_t, double*, int*);                                \
-    template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t);                \
+    template nmg_status launch_sumsq<T>(const Ctx*, int, size_t, const T*, double*, hipStream_t, double*);                \
     template nmg_status launch_sumsq_part<T>(const Ctx*, int, size_t, const T*, hipStream_t);                    \
     template nmg_status launch_restrict<T>(const Ctx*, int, int, const T*, T*, hipStream_t, double*);            \
     template nmg_status launch_prolong_transpose<T>(const Ctx*, int, int, const T*, T*, hipStream_t);            \
