@@ -34,6 +34,8 @@ __global__ void __launch_bounds__(kBlock) k_refine_scale(const R* __restrict__ r
     const R* src = r + (size_t)b * per;
     T* dst = y + (size_t)b * per;
     double acc = 0.0;
+    // (unrolled: a thread's loads are in flight together; its sum keeps its order)
+#pragma unroll 8
     for (size_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
         const T v = (T)((double)src[e] * inv);
         dst[e] = v;

@@ -815,17 +815,44 @@ __global__ void __launch_bounds__(kBlock) k_rows_fixed(T* x, T* __restrict__ tg,
         static_assert(kRowsPerBlock * 64 == kBlock, "one wave per staged row");
         for (int q0 = 0; q0 * 64 < LW; q0 += 8) {
             T v[8];
+            D dv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int c = lane + 64 * (q0 + u), gj = c - rg;
                 v[u] = (c < LW && gi < n && gj >= 0 && gj < n) ? src[gj] : (T)0;
+            }
+            // the corrections are loaded together with x (all sixteen loads
+            // in flight) before any of them is used: through a buffer
+            // resource over this image, where an element outside the row
+            // takes an out-of-range offset and reads zero (no branch per load)
+            if (upd && per * sizeof(D) < 0x7FFFFFFFu) {
+                const __amdgpu_buffer_rsrc_t dres = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<D*>(dcorr + (size_t)b * per), (short)0, (int)(per * sizeof(D)), 0x00020000);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = lane + 64 * (q0 + u), gj = c - rg;
+                    const bool ok = c < LW && gi < n && gj >= 0 && gj < n;
+                    const int off = ok ? (int)((roff + gj) * sizeof(D)) : (int)0x80000000;
+                    if constexpr (sizeof(D) == 4) {
+                        dv[u] = __builtin_bit_cast(D, __builtin_amdgcn_raw_buffer_load_b32(dres, off, 0, 0));
+                    } else {
+                        const auto w = __builtin_amdgcn_raw_buffer_load_b64(dres, off, 0, 0);
+                        __builtin_memcpy(&dv[u], &w, sizeof(D));
+                    }
+                }
+            } else if (upd) {  // images of 2 GiB and more: plain loads
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = lane + 64 * (q0 + u), gj = c - rg;
+                    dv[u] = (c < LW && gi < n && gj >= 0 && gj < n) ? dcorr[(size_t)b * per + roff + gj] : (D)0;
+                }
             }
             if (upd) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int c = lane + 64 * (q0 + u), gj = c - rg;
                     if (c < LW && gi < n && gj >= 0 && gj < n) {
-                        v[u] += rho * (T)dcorr[(size_t)b * per + roff + gj];
+                        v[u] += rho * (T)dv[u];
                         src[gj] = v[u];
                     }
                 }
