@@ -5,6 +5,7 @@
 // right-hand sides get a zero input (hence a zero correction) and are left
 // unchanged.
 #include "nmg_internal.h"
+#include "tree_sum.h"
 
 namespace nmg {
 
@@ -45,11 +46,8 @@ __global__ void __launch_bounds__(kBlock) k_refine_scale(const R* __restrict__ r
     if (!part) return;
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = red[0];
+    const double tot = tree_sum<kBlock, kBlock>(red, threadIdx.x);
+    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = tot;
 }
 
 template <typename X, typename T>

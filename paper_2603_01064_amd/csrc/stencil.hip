@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "nmg_internal.h"
+#include "tree_sum.h"
 
 namespace nmg {
 
@@ -115,11 +116,8 @@ __global__ void __launch_bounds__(kBlock) k_sumsq_part(const T* __restrict__ v, 
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = red[0];
+    const double tot = tree_sum<kBlock, kBlock>(red, threadIdx.x);
+    if (threadIdx.x == 0) part[(size_t)b * nch + ch] = tot;
 }
 
 // nparts partials per right-hand side (row stride `stride`), added in order
@@ -191,11 +189,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r, T*
         __shared__ double red[kBlock];
         red[threadIdx.x] = sq;
         __syncthreads();
-        for (int h = kBlock / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(size_t)b * gridDim.x + bx] = red[0];
+        const double tot = tree_sum<kBlock, kBlock>(red, threadIdx.x);
+        if (threadIdx.x == 0) part[(size_t)b * gridDim.x + bx] = tot;
     }
 }
 
@@ -754,7 +749,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
             }
         }
         __syncthreads();
-        for (int h = BP / 2; h > 0; h >>= 1) {
+        // the tree levels h >= 64 through LDS; the last six in one wave per
+        // block by cross-lane shifts (the same pairs in the same order)
+        for (int h = BP / 2; h >= 64; h >>= 1) {
             for (int e = tid; e < NB * h; e += NT) {
                 const int blk = e / h, t = e - blk * h;
                 red[blk * BP + t] += red[blk * BP + t + h];
@@ -762,9 +759,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
             __syncthreads();
         }
         const int nbx = (n + kNormBlock - 1) / kNormBlock;
-        for (int blk = tid; blk < NB; blk += NT) {
+        const int wv = tid >> 6, ln = tid & 63;
+        for (int blk = wv; blk < NB; blk += NT / 64) {
+            double v = red[blk * BP + ln];
+#pragma unroll
+            for (int h = 32; h > 0; h >>= 1) v += __shfl_down(v, h, 64);
             const int by = i0 / kNormBlock + blk / BX, bxg = j0 / kNormBlock + blk % BX;
-            if (by < nbx && bxg < nbx) part[(size_t)b * nbx * nbx + (size_t)by * nbx + bxg] = red[blk * BP];
+            if (ln == 0 && by < nbx && bxg < nbx) part[(size_t)b * nbx * nbx + (size_t)by * nbx + bxg] = v;
         }
     }
 }
@@ -1041,11 +1042,8 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = sq;
         __syncthreads();
-        for (int h = kBlock / 2; h > 0; h >>= 1) {
-            if (tid < h) red[tid] += red[tid + h];
-            __syncthreads();
-        }
-        if (tid == 0) part[(size_t)b * kNormChunks + bx] = red[0];
+        const double tot = tree_sum<kBlock, kBlock>(red, tid);
+        if (tid == 0) part[(size_t)b * kNormChunks + bx] = tot;
     }
 }
 
