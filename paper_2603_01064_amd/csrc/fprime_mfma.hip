@@ -243,6 +243,23 @@ __global__ void __launch_bounds__(64 * WAVES) k_fprime_tiled(const uint16_t* __r
     constexpr int EPT = STAGE == 1 ? NP * CB / NTH : 1;
     static_assert(STAGE == 0 || (NP * CB % NTH == 0 && NTH % CB == 0), "F' output elements per thread");
     float xv[kPrefetchX ? EPT : 1];
+    // STAGE 0 scales its outputs by the ramp mask: the ramp values of this
+    // thread's outputs are loaded here too (output (mt, nt, q) is row
+    // j = wrow + 16 nt + ln, column i = I0 + 16 mt + 4 lg + q, and takes
+    // ramp[max(i, j)], zero outside the grid)
+    constexpr bool kPrefetchRamp = STAGE == 0 && NTH <= 512;
+    float rv[kPrefetchRamp ? MT : 1][kPrefetchRamp ? NT : 1][4];
+    if constexpr (kPrefetchRamp) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = I0 + mt * 16 + lg * 4 + q, j = wrow + nt * 16 + ln;
+                    rv[mt][nt][q] = (i < n && j < n) ? ramp[i > j ? i : j] : 0.f;
+                }
+    }
     if constexpr (kPrefetchX) {
         const __amdgpu_buffer_rsrc_t xres = __builtin_amdgcn_make_buffer_rsrc(
             reinterpret_cast<float*>(out) + (size_t)img * n * n, (short)0, n * n * 4, 0x00020000);
@@ -325,7 +342,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_fprime_tiled(const uint16_t* __r
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int i = ib + q;
-                    v[q] = (i < n && j < n) ? acc[mt][nt][q] * ramp[i > j ? i : j] : 0.f;
+                    if constexpr (kPrefetchRamp)
+                        v[q] = (i < n && j < n) ? acc[mt][nt][q] * rv[mt][nt][q] : 0.f;
+                    else
+                        v[q] = (i < n && j < n) ? acc[mt][nt][q] * ramp[i > j ? i : j] : 0.f;
                 }
                 // four consecutive columns share one 16-byte group of the tile
                 uint16_t* dst = reinterpret_cast<uint16_t*>(out) + (size_t)img * NP * NP + tiled_off(NP, j, ib);
