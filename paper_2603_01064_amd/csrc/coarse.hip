@@ -208,16 +208,18 @@ constexpr int kEigSmall = 32;
 
 // The one-workgroup eigenbasis solve of one right-hand side (NTH threads):
 // y(e) gives element e of y, x receives the n x n solution.  sV, sA, sB hold
-// kEigSmall^2 doubles each, sl kEigSmall.
-template <int NTH, typename T, typename YF>
+// kEigSmall^2 doubles each, sl kEigSmall.  With STAGED, sV and sl already
+// hold V and the eigenvalues.
+template <int NTH, bool STAGED = false, typename T, typename YF>
 __device__ inline void eig_small_solve(const double* __restrict__ V, const double* __restrict__ lam, double a, YF y,
                                        T* __restrict__ x, int n, double* sV, double* sA, double* sB, double* sl) {
     const int nn = n * n;
     for (int e = threadIdx.x; e < nn; e += NTH) {
-        sV[e] = V[e];
+        if constexpr (!STAGED) sV[e] = V[e];
         sA[e] = y(e);
     }
-    for (int i = threadIdx.x; i < n; i += NTH) sl[i] = lam[i];
+    if constexpr (!STAGED)
+        for (int i = threadIdx.x; i < n; i += NTH) sl[i] = lam[i];
     __syncthreads();
     // T1 = V^T y
     for (int e = threadIdx.x; e < nn; e += NTH) {
@@ -277,6 +279,7 @@ __global__ void __launch_bounds__(256) k_eig_small(const double* __restrict__ V,
 // row sums, then their weighted sum), and the solve is the one of
 // k_eig_small, so the values are those of the separate launches.
 constexpr int kChainThreads = 1024;
+static_assert(kEigSmall * kEigSmall <= kChainThreads, "one V element per thread");
 constexpr int kChainUnroll = 4;  // outputs per thread whose loads are in flight together
 
 template <typename T>
@@ -302,6 +305,12 @@ __global__ void __launch_bounds__(kChainThreads) k_restrict_chain(RestrictChain<
     __shared__ double sV[kEigSmall * kEigSmall], sA[kEigSmall * kEigSmall], sB[kEigSmall * kEigSmall];
     __shared__ double sl[kEigSmall];
     const int b = blockIdx.x, tid = threadIdx.x;
+    // the coarsest solve's V and eigenvalues: loaded first (one element per
+    // thread, n^2 <= kChainThreads), stored to LDS after the first restriction
+    const int nL = ch.n[ch.levels - 1];
+    const bool solve = ch.x_coarse != nullptr;
+    const double vv = (solve && tid < nL * nL) ? V[tid] : 0.0;
+    const double lv = (solve && tid < nL) ? lam[tid] : 0.0;
     // first restriction: y_{k0} (global) -> y_{k0 + 1}; the outputs of a
     // thread past the grid recompute its last point (their loads stay in
     // bounds and issue with the others) and store nothing
@@ -327,6 +336,8 @@ __global__ void __launch_bounds__(kChainThreads) k_restrict_chain(RestrictChain<
             }
         }
     }
+    if (solve && tid < nL * nL) sV[tid] = vv;
+    if (solve && tid < nL) sl[tid] = lv;
     __syncthreads();
     // later restrictions, LDS to LDS (levels alternate between the buffers)
     T* cur = bufA;
@@ -345,11 +356,9 @@ __global__ void __launch_bounds__(kChainThreads) k_restrict_chain(RestrictChain<
         cur = nxt;
         nxt = t;
     }
-    if (ch.x_coarse) {
-        const int n = ch.n[ch.levels - 1];
-        eig_small_solve<kChainThreads>(V, lam, alpha[b], [&](int e) { return (double)cur[e]; },
-                                       ch.x_coarse + (size_t)b * n * n, n, sV, sA, sB, sl);
-    }
+    if (solve)
+        eig_small_solve<kChainThreads, true>(V, lam, alpha[b], [&](int e) { return (double)cur[e]; },
+                                             ch.x_coarse + (size_t)b * nL * nL, nL, sV, sA, sB, sl);
 }
 
 }  // namespace
