@@ -542,10 +542,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
     const T* xs = x + (size_t)b * per;
     const int tid = threadIdx.x;
     const T* taps = tg;
-    for (int e = threadIdx.x; e < rc2; e += NT) {
-        cs[e] = dtl[e];
-        cs[rc2 + e] = dbr[e];
-    }
+    // corner corrections into LDS; called between the first staging batch's
+    // loads and its stores, so their loads are in flight with the tile's
+    auto copy_corners = [&]() {
+        for (int e = threadIdx.x; e < rc2; e += NT) {
+            cs[e] = dtl[e];
+            cs[rc2 + e] = dbr[e];
+        }
+    };
     // ---- stage the tile with its halo (zero outside the grid); every load of
     // a thread is issued before the first LDS store
     {
@@ -568,6 +572,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
                     v[u][k] = (row_in && c < XW && gj >= 0 && gj < n) ? src[gj] : (T)0;
                 }
             }
+            if (u0 == 0) copy_corners();
 #pragma unroll
             for (int u = 0; u < SB; ++u) {
                 const int r = ty + WAVES * (u0 + u);
@@ -942,24 +947,36 @@ __global__ void __launch_bounds__(kBlock) k_cols_fixed(const T* __restrict__ tg,
     const size_t per = (size_t)n * n;
     const T* tgs = tg + (size_t)b * per;
     const int tid = threadIdx.x;
-    for (int e = tid; e < rc2; e += kBlock) {
-        cs[e] = dtl[e];
-        cs[rc2 + e] = dbr[e];
-    }
-    // staging in batches of 8 loads per thread in flight
-    for (int e0 = tid; e0 < XH * TW; e0 += 8 * kBlock) {
-        T v[8];
+    // staging in batches of 16 loads per thread in flight (one batch for the
+    // 44-tap band); the corner corrections go to LDS between the first
+    // batch's loads and stores
+    constexpr int SBT = 16;
+    bool corners = false;
+    for (int e0 = tid; e0 < XH * TW; e0 += SBT * kBlock) {
+        T v[SBT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < SBT; ++u) {
             const int e = e0 + u * kBlock;
             const int r = e / TW, c = e - r * TW;
             const int gi = i0 - rg + r, gj = j0 + c;
             v[u] = (e < XH * TW && gi >= 0 && gi < n && gj < n) ? tgs[(size_t)gi * n + gj] : (T)0;
         }
+        if (!corners) {
+            corners = true;
+            for (int e = tid; e < rc2; e += kBlock) {
+                cs[e] = dtl[e];
+                cs[rc2 + e] = dbr[e];
+            }
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < SBT; ++u)
             if (e0 + u * kBlock < XH * TW) G[e0 + u * kBlock] = v[u];
     }
+    if (!corners)  // (a thread without a staging batch)
+        for (int e = tid; e < rc2; e += kBlock) {
+            cs[e] = dtl[e];
+            cs[rc2 + e] = dbr[e];
+        }
     if (!m_ident) {
         const T* tms = tm + (size_t)b * per;
         for (int e = tid; e < (TH + 4) * TW; e += kBlock) {
