@@ -422,24 +422,37 @@ __global__ void __launch_bounds__(kSmallThreads) k_fprime_small(const float* __r
     const int ln = lane & 15, lg = lane >> 4;
     const float* src = in + (size_t)b * n * n;
     auto off = [](int r, int ch) { return r * RB + ((ch ^ (r & SW)) << 4); };
-    // C and C^T (rows of the padded tables), the ramp, and H as BF16 (zero beyond n)
-    for (int e = tid; e < 2 * NP * CPR; e += kSmallThreads) {
+    // C and C^T (rows of the padded tables), the ramp, and H as BF16 (zero
+    // beyond n): every global load of a thread is issued before its first
+    // LDS store
+    constexpr int MI = (2 * NP * CPR + kSmallThreads - 1) / kSmallThreads;  // table chunks per thread
+    constexpr int HI = (NP * NP / 2 + kSmallThreads - 1) / kSmallThreads;   // H pairs per thread
+    uint4 mv[MI];
+    float hv[HI][2];
+#pragma unroll
+    for (int u = 0; u < MI; ++u) {
+        const int e = tid + u * kSmallThreads;
         const int m = e / (NP * CPR), r = (e / CPR) % NP, ch = e % CPR;
         const uint16_t* M = m == 0 ? C : Ct;
-        *reinterpret_cast<uint4*>(mats[m] + off(r, ch)) = *reinterpret_cast<const uint4*>(M + (size_t)r * mstride + ch * 8);
+        mv[u] = e < 2 * NP * CPR ? *reinterpret_cast<const uint4*>(M + (size_t)r * mstride + ch * 8) : make_uint4(0, 0, 0, 0);
     }
-    if (tid < NP) rp[tid] = tid < n ? ramp[tid] : 0.f;
-    for (int e = tid; e < NP * NP / 2; e += kSmallThreads) {
+#pragma unroll
+    for (int u = 0; u < HI; ++u) {
+        const int e = tid + u * kSmallThreads;
         const int i = e / (NP / 2), k = (e % (NP / 2)) * 2;
-        const float v0 = (i < n && k < n) ? src[(size_t)i * n + k] : 0.f;
-        const float v1 = (i < n && k + 1 < n) ? src[(size_t)i * n + k + 1] : 0.f;
-        *reinterpret_cast<uint32_t*>(buf[0] + off(i, k >> 3) + (k & 7) * 2) = pack_bf16(v0, v1);
+        const bool ok = e < NP * NP / 2;
+        hv[u][0] = (ok && i < n && k < n) ? src[(size_t)i * n + k] : 0.f;
+        hv[u][1] = (ok && i < n && k + 1 < n) ? src[(size_t)i * n + k + 1] : 0.f;
     }
-    // the values of dst this wave's last-pass outputs add to, loaded now so
-    // their latency overlaps the four passes (output tile t of pass 3 is
-    // rows 16 (t / NT) + 4 lg .. + 3, column 16 (t % NT) + ln)
+    const float rpv = (tid < NP && tid < n) ? ramp[tid] : 0.f;
+    // the values of dst this wave's last-pass outputs add to, loaded with
+    // the rest (output tile t of pass 3 is rows 16 (t / NT) + 4 lg .. + 3,
+    // column 16 (t % NT) + ln) through a buffer resource over the image: an
+    // element outside it takes an out-of-range offset and reads zero, so the
+    // loads need no branch and issue together
     constexpr int TPW = (NT * NT + WAVES - 1) / WAVES;  // output tiles per wave
     float* dimg = dst + (size_t)b * n * n;
+    const __amdgpu_buffer_rsrc_t dres = __builtin_amdgcn_make_buffer_rsrc(dimg, (short)0, n * n * 4, 0x00020000);
     float dv[TPW][4];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
@@ -448,8 +461,24 @@ __global__ void __launch_bounds__(kSmallThreads) k_fprime_small(const float* __r
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = (t / NT) * 16 + lg * 4 + q;
-            dv[u][q] = (accumulate && t < NT * NT && i < n && j < n) ? dimg[(size_t)j * n + i] : 0.f;
+            const bool ok = accumulate && t < NT * NT && i < n && j < n;
+            dv[u][q] = __builtin_bit_cast(float,
+                                          __builtin_amdgcn_raw_buffer_load_b32(dres, ok ? (j * n + i) * 4 : (int)0x80000000, 0, 0));
         }
+    }
+#pragma unroll
+    for (int u = 0; u < MI; ++u) {
+        const int e = tid + u * kSmallThreads;
+        const int m = e / (NP * CPR), r = (e / CPR) % NP, ch = e % CPR;
+        if (e < 2 * NP * CPR) *reinterpret_cast<uint4*>(mats[m] + off(r, ch)) = mv[u];
+    }
+    if (tid < NP) rp[tid] = rpv;
+#pragma unroll
+    for (int u = 0; u < HI; ++u) {
+        const int e = tid + u * kSmallThreads;
+        const int i = e / (NP / 2), k = (e % (NP / 2)) * 2;
+        if (e < NP * NP / 2)
+            *reinterpret_cast<uint32_t*>(buf[0] + off(i, k >> 3) + (k & 7) * 2) = pack_bf16(hv[u][0], hv[u][1]);
     }
     __syncthreads();
 #pragma unroll 1
