@@ -793,16 +793,6 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         h->pin_ptr[nfin] = sl.x;
         ++nfin;
     }
-    if (nfin > 0) {
-        NMG_HIP(hipMemcpyAsync(d_pairs, hi + 2 * B, (size_t)nfin * sizeof(int), hipMemcpyHostToDevice, s));
-        NMG_HIP(hipMemcpyAsync(h->xptr_dev, h->pin_ptr, (size_t)nfin * sizeof(double*),
-                               hipMemcpyHostToDevice, s));
-        if (plain32)
-            NMG_TRY(launch_scatter_ptrs<float>(nfin, per, X32, h->xptr_dev, d_pairs, s));
-        else
-            NMG_TRY(launch_scatter_ptrs<double>(nfin, per, X64, h->xptr_dev, d_pairs, s));
-        if (retired) NMG_HIP(hipEventRecord(retired, s));
-    }
     // ---- refill the finished slots below nkeep from active slots at or above it
     int nmoves = 0;
     {
@@ -818,27 +808,13 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
             --src;
         }
     }
-    if (nmoves > 0) {
-        NMG_HIP(hipMemcpyAsync(d_moves, hi + 4 * B, (size_t)2 * nmoves * sizeof(int), hipMemcpyHostToDevice,
-                               s));
-        if (plain32)
-            NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
-        else
-            NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
-    }
     E.slot.resize((size_t)nkeep);
     k = nkeep;
-    if (k == 0) {
-        E.precision = -1;
-        E.any_ws = false;
-        NMG_HIP(hipStreamSynchronize(s));
-        return NMG_OK;
-    }
-    // ---- one outer iteration on kb >= k slots (a fixed set of launch sizes,
-    // so a few captured graphs serve every active count); slots k..kb-1 carry
-    // slot 0's parameters with a zero residual norm, which the cycle treats as
-    // converged (zero input, no update)
-    const int kb = h->use_graphs ? graph_batch(k, B) : k;
+    // ---- the next outer iteration runs on kb >= k slots (a fixed set of
+    // launch sizes, so a few captured graphs serve every active count); slots
+    // k..kb-1 carry slot 0's parameters with a zero residual norm, which the
+    // cycle treats as converged (zero input, no update)
+    const int kb = k == 0 ? 0 : (h->use_graphs ? graph_batch(k, B) : k);
     for (int i = 0; i < kb; ++i) {
         const EngineSlot& sl = E.slot[(size_t)(i < k ? i : 0)];
         hd[(size_t)i] = sl.alpha;
@@ -847,10 +823,33 @@ nmg_status engine_step(Ctx* h, double rtol, int max_cycles, const nmg_cycle_opts
         hi[(size_t)i] = sl.ws;
         hi[(size_t)B + i] = sl.fidx;
     }
-    // the three double tables and the first two int tables in one transfer
-    // (the host block is laid out like the device one)
-    NMG_HIP(hipMemcpyAsync(h->slot_d, hd, (size_t)3 * B * sizeof(double) + (size_t)2 * B * sizeof(int),
-                           hipMemcpyHostToDevice, s));
+    // one transfer for the slot tables, the finished slots and the slot
+    // moves (the host block is laid out like the device one); the finished
+    // iterates are copied out before the moves overwrite their slots
+    if (kb > 0 || nfin > 0 || nmoves > 0)
+        NMG_HIP(hipMemcpyAsync(h->slot_d, hd, (size_t)3 * B * sizeof(double) + (size_t)6 * B * sizeof(int),
+                               hipMemcpyHostToDevice, s));
+    if (nfin > 0) {
+        NMG_HIP(hipMemcpyAsync(h->xptr_dev, h->pin_ptr, (size_t)nfin * sizeof(double*),
+                               hipMemcpyHostToDevice, s));
+        if (plain32)
+            NMG_TRY(launch_scatter_ptrs<float>(nfin, per, X32, h->xptr_dev, d_pairs, s));
+        else
+            NMG_TRY(launch_scatter_ptrs<double>(nfin, per, X64, h->xptr_dev, d_pairs, s));
+        if (retired) NMG_HIP(hipEventRecord(retired, s));
+    }
+    if (nmoves > 0) {
+        if (plain32)
+            NMG_TRY(launch_move_slots<float>(nmoves, per, X32, B32, R32, d_moves, s));
+        else
+            NMG_TRY(launch_move_slots<double>(nmoves, per, X64, B64, R64, d_moves, s));
+    }
+    if (k == 0) {
+        E.precision = -1;
+        E.any_ws = false;
+        NMG_HIP(hipStreamSynchronize(s));
+        return NMG_OK;
+    }
     h->cycle_fidx = d_fidx;
     const int* wsd = E.any_ws ? d_ws : nullptr;
     auto residual = [&](int kk, hipStream_t st) -> nmg_status {
